@@ -1,0 +1,360 @@
+/*
+ * Plain FP64 CPU oracle of the 2D3V implicit-FDTD PIC step.
+ *
+ * TEST INFRASTRUCTURE ONLY: the slow, obviously correct reference the GPU
+ * library is checked against. Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg load it. Shares no code with the GPU library.
+ *
+ * Paper: Ikeya & Matsumoto, PASJ 2015 (arXiv:1412.2480). Each function cites
+ * the passage it follows; the layout and units are described in oracle.h.
+ * Written for clarity, not speed: loops run over fixed windows that contain
+ * the shape supports, and zero weights are simply added.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static inline int wrapi(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
+static inline int64_t at(int nx, int ny, int i, int j) {
+  return (int64_t)wrapi(j, ny) * nx + wrapi(i, nx);
+}
+
+/* B-spline of degree p (p = 1: linear, 2: quadratic, 3: cubic); the paper's
+ * first- and second-order shape functions (Sec. 3.2-3.3) are p = 1 and 2. */
+double ora_shape(int order, double d) {
+  double a = fabs(d);
+  switch (order) {
+    case 1:
+      return a < 1.0 ? 1.0 - a : 0.0;
+    case 2:
+      if (a < 0.5) return 0.75 - a * a;
+      if (a < 1.5) return 0.5 * (1.5 - a) * (1.5 - a);
+      return 0.0;
+    case 3:
+      if (a < 1.0) return (4.0 - 6.0 * a * a + 3.0 * a * a * a) / 6.0;
+      if (a < 2.0) return (2.0 - a) * (2.0 - a) * (2.0 - a) / 6.0;
+      return 0.0;
+    default:
+      return 0.0;
+  }
+}
+
+/* staggered offsets (in cells) of Ex, Ey, Ez, Bx, By, Bz on the Yee grid */
+static const double STAG_X[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
+static const double STAG_Y[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
+
+/* Momentum-conserving gather (Sec. 1; Sec. 3 first paragraph): field value at
+ * the particle = sum over the component's own grid points of
+ * F(i+sx, j+sy) * S(X - i - sx) * S(Y - j - sy). The window i in
+ * [ix-2, ix+2] contains the support of every order for both staggers. */
+void ora_gather(int nx, int ny, int order, const double* const* f6,
+                int64_t np, const int32_t* ix, const int32_t* iy,
+                const double* fx, const double* fy, double* out6) {
+  for (int64_t k = 0; k < np; ++k) {
+    for (int c = 0; c < 6; ++c) {
+      double sum = 0.0;
+      for (int j = iy[k] - 2; j <= iy[k] + 2; ++j) {
+        double wy = ora_shape(order, (double)(iy[k] - j) + fy[k] - STAG_Y[c]);
+        for (int i = ix[k] - 2; i <= ix[k] + 2; ++i) {
+          double wx = ora_shape(order, (double)(ix[k] - i) + fx[k] - STAG_X[c]);
+          sum += f6[c][at(nx, ny, i, j)] * wx * wy;
+        }
+      }
+      out6[(int64_t)c * np + k] = sum;
+    }
+  }
+}
+
+/* Relativistic Boris push, c = 1:
+ *   u-  = u + (q dt/2m) E
+ *   t   = (q dt/(2m gamma-)) B,  gamma- = sqrt(1 + |u-|^2)
+ *   s   = 2 t/(1 + |t|^2)
+ *   u'  = u- + u- x t
+ *   u+  = u- + u' x s
+ *   u   = u+ + (q dt/2m) E                                                   */
+void ora_boris(int64_t np, double qdt_2m, const double* e3, const double* b3,
+               double* ux, double* uy, double* uz) {
+  for (int64_t k = 0; k < np; ++k) {
+    double ex = e3[k], ey = e3[np + k], ez = e3[2 * np + k];
+    double bx = b3[k], by = b3[np + k], bz = b3[2 * np + k];
+    double umx = ux[k] + qdt_2m * ex;
+    double umy = uy[k] + qdt_2m * ey;
+    double umz = uz[k] + qdt_2m * ez;
+    double gm = sqrt(1.0 + umx * umx + umy * umy + umz * umz);
+    double tx = qdt_2m * bx / gm, ty = qdt_2m * by / gm, tz = qdt_2m * bz / gm;
+    double t2 = tx * tx + ty * ty + tz * tz;
+    double sx = 2.0 * tx / (1.0 + t2), sy = 2.0 * ty / (1.0 + t2), sz = 2.0 * tz / (1.0 + t2);
+    double upx = umx + (umy * tz - umz * ty);
+    double upy = umy + (umz * tx - umx * tz);
+    double upz = umz + (umx * ty - umy * tx);
+    double uplx = umx + (upy * sz - upz * sy);
+    double uply = umy + (upz * sx - upx * sz);
+    double uplz = umz + (upx * sy - upy * sx);
+    ux[k] = uplx + qdt_2m * ex;
+    uy[k] = uply + qdt_2m * ey;
+    uz[k] = uplz + qdt_2m * ez;
+  }
+}
+
+/* advance one coordinate held as cell + offset by a displacement of less
+ * than one cell; an offset that rounds to exactly 1 moves to the next cell */
+static void advance(int32_t* cell, double* off, double disp) {
+  double f = *off + disp;
+  int32_t c = *cell;
+  if (f >= 1.0) {
+    f -= 1.0;
+    c += 1;
+  } else if (f < 0.0) {
+    f += 1.0;
+    c -= 1;
+  }
+  if (f >= 1.0) {
+    f -= 1.0;
+    c += 1;
+  }
+  *cell = c;
+  *off = f;
+}
+
+void ora_move(int64_t np, double dt, double dx, double dy,
+              const double* ux, const double* uy, const double* uz,
+              int32_t* ix, int32_t* iy, double* fx, double* fy) {
+  for (int64_t k = 0; k < np; ++k) {
+    double g = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
+    advance(&ix[k], &fx[k], dt * ux[k] / (g * dx));
+    advance(&iy[k], &fy[k], dt * uy[k] / (g * dy));
+  }
+}
+
+/* Esirkepov (2001) charge-conserving deposit in 2D with a z velocity:
+ * with node shapes S0 (old position) and S1 (new), DS = S1 - S0,
+ *   Wx = DSx (S0y + DSy/2),  Wy = DSy (S0x + DSx/2),
+ *   Wz = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3,
+ *   Jx(i+1/2, j) = -(q/(dy dt)) sum_{i' <= i} Wx(i', j)
+ *   Jy(i, j+1/2) = -(q/(dx dt)) sum_{j' <= j} Wy(i, j')
+ *   Jz(i, j)     =  q vz Wz(i, j)/(dx dy).
+ * The window of 6 nodes per axis, [i0-2, i0+3], holds both supports for all
+ * orders because a particle moves less than one cell per step. */
+void ora_deposit(int nx, int ny, int order, double dx, double dy, double dt,
+                 double q, int64_t np,
+                 const int32_t* ix0, const int32_t* iy0, const double* fx0, const double* fy0,
+                 const int32_t* ix1, const int32_t* iy1, const double* fx1, const double* fy1,
+                 const double* ux, const double* uy, const double* uz,
+                 double* jx, double* jy, double* jz) {
+  enum { W = 6 };
+  for (int64_t k = 0; k < np; ++k) {
+    double s0x[W], s1x[W], dsx[W], s0y[W], s1y[W], dsy[W];
+    int bi = ix0[k] - 2, bj = iy0[k] - 2;
+    for (int a = 0; a < W; ++a) {
+      int i = bi + a, j = bj + a;
+      s0x[a] = ora_shape(order, (double)(ix0[k] - i) + fx0[k]);
+      s1x[a] = ora_shape(order, (double)(ix1[k] - i) + fx1[k]);
+      s0y[a] = ora_shape(order, (double)(iy0[k] - j) + fy0[k]);
+      s1y[a] = ora_shape(order, (double)(iy1[k] - j) + fy1[k]);
+      dsx[a] = s1x[a] - s0x[a];
+      dsy[a] = s1y[a] - s0y[a];
+    }
+    double g = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
+    double vz = uz[k] / g;
+    double cx = -q / (dy * dt), cy = -q / (dx * dt), cz = q * vz / (dx * dy);
+    for (int b = 0; b < W; ++b) {
+      double acc = 0.0;
+      for (int a = 0; a < W; ++a) {
+        acc += dsx[a] * (s0y[b] + 0.5 * dsy[b]);
+        jx[at(nx, ny, bi + a, bj + b)] += cx * acc;
+      }
+    }
+    for (int a = 0; a < W; ++a) {
+      double acc = 0.0;
+      for (int b = 0; b < W; ++b) {
+        acc += dsy[b] * (s0x[a] + 0.5 * dsx[a]);
+        jy[at(nx, ny, bi + a, bj + b)] += cy * acc;
+      }
+    }
+    for (int b = 0; b < W; ++b)
+      for (int a = 0; a < W; ++a) {
+        double wz = s0x[a] * s0y[b] + 0.5 * dsx[a] * s0y[b] + 0.5 * s0x[a] * dsy[b] +
+                    dsx[a] * dsy[b] / 3.0;
+        jz[at(nx, ny, bi + a, bj + b)] += cz * wz;
+      }
+  }
+}
+
+void ora_wrap_periodic(int nx, int ny, int64_t np, int32_t* ix, int32_t* iy) {
+  for (int64_t k = 0; k < np; ++k) {
+    ix[k] = wrapi(ix[k], nx);
+    iy[k] = wrapi(iy[k], ny);
+  }
+}
+
+/* 5-point Laplacian of a periodic array at (i, j) */
+static double lap(int nx, int ny, double dx, double dy, const double* f, int i, int j) {
+  double c = f[at(nx, ny, i, j)];
+  return (f[at(nx, ny, i + 1, j)] - 2.0 * c + f[at(nx, ny, i - 1, j)]) / (dx * dx) +
+         (f[at(nx, ny, i, j + 1)] - 2.0 * c + f[at(nx, ny, i, j - 1)]) / (dy * dy);
+}
+
+/* curl with forward differences, evaluated at the B points (Eq. (5)):
+ * (cE F)x(i, j+1/2) = dFz/dy, (cE F)y(i+1/2, j) = -dFz/dx,
+ * (cE F)z(i+1/2, j+1/2) = dFy/dx - dFx/dy, for F co-located with E */
+static void curl_e(int nx, int ny, double dx, double dy, const double* const* f, int i, int j,
+                   double* out3) {
+  out3[0] = (f[2][at(nx, ny, i, j + 1)] - f[2][at(nx, ny, i, j)]) / dy;
+  out3[1] = -(f[2][at(nx, ny, i + 1, j)] - f[2][at(nx, ny, i, j)]) / dx;
+  out3[2] = (f[1][at(nx, ny, i + 1, j)] - f[1][at(nx, ny, i, j)]) / dx -
+            (f[0][at(nx, ny, i, j + 1)] - f[0][at(nx, ny, i, j)]) / dy;
+}
+
+/* curl with backward differences, evaluated at the E points (Eq. (6)):
+ * (cB F)x(i+1/2, j) = dFz/dy, (cB F)y(i, j+1/2) = -dFz/dx,
+ * (cB F)z(i, j) = dFy/dx - dFx/dy, for F co-located with B */
+static void curl_b(int nx, int ny, double dx, double dy, const double* const* f, int i, int j,
+                   double* out3) {
+  out3[0] = (f[2][at(nx, ny, i, j)] - f[2][at(nx, ny, i, j - 1)]) / dy;
+  out3[1] = -(f[2][at(nx, ny, i, j)] - f[2][at(nx, ny, i - 1, j)]) / dx;
+  out3[2] = (f[1][at(nx, ny, i, j)] - f[1][at(nx, ny, i - 1, j)]) / dx -
+            (f[0][at(nx, ny, i, j)] - f[0][at(nx, ny, i, j - 1)]) / dy;
+}
+
+/* Eq. (7) right-hand side, c = 1:
+ * b = theta dt^2 (L B^n + 4 pi curl J^{n+1/2}) - dt curl E^n */
+void ora_rhs(int nx, int ny, double dx, double dy, double dt, double theta,
+             const double* const* e3, const double* const* b3, const double* const* j3,
+             double* const* b_out) {
+  const double four_pi = 4.0 * M_PI;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double cj[3], ce[3];
+      curl_e(nx, ny, dx, dy, j3, i, j, cj);
+      curl_e(nx, ny, dx, dy, e3, i, j, ce);
+      for (int c = 0; c < 3; ++c) {
+        double lb = lap(nx, ny, dx, dy, b3[c], i, j);
+        b_out[c][at(nx, ny, i, j)] = theta * dt * dt * (lb + four_pi * cj[c]) - dt * ce[c];
+      }
+    }
+}
+
+/* the operator of Eq. (7): A = 1 - (theta c dt)^2 L */
+void ora_apply_A(int nx, int ny, double dx, double dy, double dt, double theta,
+                 const double* x, double* y) {
+  double a = (theta * dt) * (theta * dt);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      y[at(nx, ny, i, j)] = x[at(nx, ny, i, j)] - a * lap(nx, ny, dx, dy, x, i, j);
+}
+
+static double dot(int64_t n, const double* a, const double* b) {
+  double s = 0.0;
+  for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+  return s;
+}
+
+/* Conjugate gradient (Hestenes-Stiefel) on the symmetric positive definite
+ * A of Eq. (7); the paper solves Eq. (7) by CG (Sec. 2, citing Hoshino 2013). */
+int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
+           const double* b, double* x, double rtol, int maxit, double* relres) {
+  int64_t n = (int64_t)nx * ny;
+  double bnorm = sqrt(dot(n, b, b));
+  if (bnorm == 0.0) {
+    memset(x, 0, sizeof(double) * n);
+    if (relres) *relres = 0.0;
+    return 0;
+  }
+  double* r = malloc(sizeof(double) * n);
+  double* p = malloc(sizeof(double) * n);
+  double* q = malloc(sizeof(double) * n);
+  ora_apply_A(nx, ny, dx, dy, dt, theta, x, q);
+  for (int64_t k = 0; k < n; ++k) {
+    r[k] = b[k] - q[k];
+    p[k] = r[k];
+  }
+  double rr = dot(n, r, r);
+  int it = 0;
+  while (it < maxit && sqrt(rr) > rtol * bnorm) {
+    ora_apply_A(nx, ny, dx, dy, dt, theta, p, q);
+    double alpha = rr / dot(n, p, q);
+    for (int64_t k = 0; k < n; ++k) {
+      x[k] += alpha * p[k];
+      r[k] -= alpha * q[k];
+    }
+    double rr_new = dot(n, r, r);
+    double beta = rr_new / rr;
+    for (int64_t k = 0; k < n; ++k) p[k] = r[k] + beta * p[k];
+    rr = rr_new;
+    ++it;
+  }
+  if (relres) {
+    ora_apply_A(nx, ny, dx, dy, dt, theta, x, q);
+    for (int64_t k = 0; k < n; ++k) r[k] = b[k] - q[k];
+    *relres = sqrt(dot(n, r, r)) / bnorm;
+  }
+  free(r);
+  free(p);
+  free(q);
+  return it;
+}
+
+/* Eqs. (5)-(6) with dB known:
+ * E^{n+1} = E^n + dt curl_B(B^n + theta dB) - 4 pi dt J^{n+1/2}, B^{n+1} = B^n + dB */
+void ora_update(int nx, int ny, double dx, double dy, double dt, double theta,
+                double* const* e3, double* const* b3, const double* const* db3,
+                const double* const* j3) {
+  int64_t n = (int64_t)nx * ny;
+  double* bt[3];
+  for (int c = 0; c < 3; ++c) {
+    bt[c] = malloc(sizeof(double) * n);
+    for (int64_t k = 0; k < n; ++k) bt[c][k] = b3[c][k] + theta * db3[c][k];
+  }
+  const double four_pi = 4.0 * M_PI;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double cb[3];
+      curl_b(nx, ny, dx, dy, (const double* const*)bt, i, j, cb);
+      for (int c = 0; c < 3; ++c) {
+        int64_t k = at(nx, ny, i, j);
+        e3[c][k] += dt * cb[c] - four_pi * dt * j3[c][k];
+      }
+    }
+  for (int c = 0; c < 3; ++c) {
+    for (int64_t k = 0; k < n; ++k) b3[c][k] += db3[c][k];
+    free(bt[c]);
+  }
+}
+
+void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
+                const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
+                double* rho) {
+  for (int64_t k = 0; k < np; ++k)
+    for (int j = iy[k] - 2; j <= iy[k] + 3; ++j) {
+      double wy = ora_shape(order, (double)(iy[k] - j) + fy[k]);
+      for (int i = ix[k] - 2; i <= ix[k] + 3; ++i) {
+        double wx = ora_shape(order, (double)(ix[k] - i) + fx[k]);
+        rho[at(nx, ny, i, j)] += q * wx * wy / (dx * dy);
+      }
+    }
+}
+
+void ora_div_e(int nx, int ny, double dx, double dy, const double* ex, const double* ey,
+               double* out) {
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      out[at(nx, ny, i, j)] = (ex[at(nx, ny, i, j)] - ex[at(nx, ny, i - 1, j)]) / dx +
+                              (ey[at(nx, ny, i, j)] - ey[at(nx, ny, i, j - 1)]) / dy;
+}
+
+void ora_div_b(int nx, int ny, double dx, double dy, const double* bx, const double* by,
+               double* out) {
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i)
+      out[at(nx, ny, i, j)] = (bx[at(nx, ny, i + 1, j)] - bx[at(nx, ny, i, j)]) / dx +
+                              (by[at(nx, ny, i, j + 1)] - by[at(nx, ny, i, j)]) / dy;
+}
+
+double ora_kinetic(int64_t np, double m, const double* ux, const double* uy, const double* uz) {
+  double s = 0.0;
+  for (int64_t k = 0; k < np; ++k)
+    s += m * (sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]) - 1.0);
+  return s;
+}

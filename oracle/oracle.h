@@ -1,0 +1,111 @@
+/*
+ * Plain FP64 CPU oracle of the 2D3V implicit-FDTD PIC step.
+ *
+ * TEST INFRASTRUCTURE ONLY. This library is the slow, obviously correct
+ * reference the GPU library is checked against. Only the test suite, the
+ * smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * GPU product path never does. It shares no source with the GPU library.
+ *
+ * Paper: Ikeya & Matsumoto, PASJ 2015 (arXiv:1412.2480).
+ *
+ * Grid (standard 2D Yee layout; the paper's Fig. 1 is not reproduced, so the
+ * textbook arrangement is taken): nx*ny cells, row-major arrays [ny][nx],
+ * index k = j*nx + i, periodic in both directions.
+ *   Ex(i+1/2, j)   Ey(i, j+1/2)   Ez(i, j)
+ *   Bx(i, j+1/2)   By(i+1/2, j)   Bz(i+1/2, j+1/2)
+ *   Jx, Jy, Jz co-located with Ex, Ey, Ez; rho at nodes (i, j).
+ * Units: Gaussian with c = 1 (Maxwell equations of Sec. 2, Eqs. (1)-(2)).
+ *
+ * Particles: cell index (ix, iy) and in-cell offset (fx, fy) in [0, 1), so
+ * the position in cell units is X = ix + fx; momentum u = gamma v (ux, uy, uz)
+ * at the half step n-1/2, position at step n (leapfrog implied by J^{n+1/2}
+ * in Eq. (6)).
+ */
+#ifndef PIC_ORACLE_H
+#define PIC_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* B-spline shape of degree `order` (1, 2 or 3), evaluated at distance d in
+ * cell units; shared by gather and charge assignment (Sec. 1, Sec. 3). */
+double ora_shape(int order, double d);
+
+/* Momentum-conserving gather (Sec. 1 and Sec. 3, citing Birdsall & Langdon
+ * ch. 8): every field component is interpolated from its own staggered
+ * points with the same order-p shape in x and y as the charge assignment.
+ * f6 = {Ex, Ey, Ez, Bx, By, Bz}, each [ny][nx]. out6[c*np + k]. */
+void ora_gather(int nx, int ny, int order, const double* const* f6,
+                int64_t np, const int32_t* ix, const int32_t* iy,
+                const double* fx, const double* fy, double* out6);
+
+/* Relativistic Boris rotation (the paper names no pusher; read as the
+ * standard Boris scheme, with gamma from the half-kicked momentum).
+ * qdt_2m = q*dt/(2m). e3/b3 point at per-particle Ex..Ez and Bx..Bz columns
+ * (stride np). Updates ux, uy, uz in place from n-1/2 to n+1/2. */
+void ora_boris(int64_t np, double qdt_2m, const double* e3, const double* b3,
+               double* ux, double* uy, double* uz);
+
+/* Position advance x^{n+1} = x^n + dt u^{n+1/2}/gamma (2D; z untracked).
+ * Writes the unwrapped new cell index and offset. */
+void ora_move(int64_t np, double dt, double dx, double dy,
+              const double* ux, const double* uy, const double* uz,
+              int32_t* ix, int32_t* iy, double* fx, double* fy);
+
+/* Esirkepov (2001) density-decomposition current deposit of J^{n+1/2} from
+ * the displacement (ix0+fx0, iy0+fy0) -> (ix1+fx1, iy1+fy1), cited in Sec. 1
+ * and Sec. 3. Adds into jx, jy, jz ([ny][nx], periodic wrap). */
+void ora_deposit(int nx, int ny, int order, double dx, double dy, double dt,
+                 double q, int64_t np,
+                 const int32_t* ix0, const int32_t* iy0, const double* fx0, const double* fy0,
+                 const int32_t* ix1, const int32_t* iy1, const double* fx1, const double* fy1,
+                 const double* ux, const double* uy, const double* uz,
+                 double* jx, double* jy, double* jz);
+
+/* Periodic wrap of cell indices into [0, nx) x [0, ny). */
+void ora_wrap_periodic(int nx, int ny, int64_t np, int32_t* ix, int32_t* iy);
+
+/* Right-hand side of Eq. (7) on each B component's own grid:
+ * b = theta dt^2 (L B^n + 4 pi curl_E J) - dt curl_E E^n. */
+void ora_rhs(int nx, int ny, double dx, double dy, double dt, double theta,
+             const double* const* e3, const double* const* b3, const double* const* j3,
+             double* const* b_out);
+
+/* Apply A = I - (theta dt)^2 L (5-point Laplacian, periodic). */
+void ora_apply_A(int nx, int ny, double dx, double dy, double dt, double theta,
+                 const double* x, double* y);
+
+/* Plain unpreconditioned conjugate gradient for A x = b (Eq. (7) is solved
+ * by CG in the paper, Sec. 2). Starts from the x passed in. Stops when
+ * ||r||_2 <= rtol ||b||_2 (recursive residual) or after maxit iterations.
+ * Returns the iteration count; *relres receives ||b - A x||_2 / ||b||_2
+ * recomputed from scratch (0 when b = 0). */
+int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
+           const double* b, double* x, double rtol, int maxit, double* relres);
+
+/* Field update from Eqs. (5)-(6) given dB = B^{n+1} - B^n:
+ * E^{n+1} = E^n + dt curl_B(B^n + theta dB) - 4 pi dt J;  B^{n+1} = B^n + dB. */
+void ora_update(int nx, int ny, double dx, double dy, double dt, double theta,
+                double* const* e3, double* const* b3, const double* const* db3,
+                const double* const* j3);
+
+/* Charge density at nodes, rho(i,j) += q S(X-i) S(Y-j)/(dx dy). */
+void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
+                const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
+                double* rho);
+
+/* Discrete divergences: divE at nodes (backward differences of Ex, Ey),
+ * divB at cell centres (forward differences of Bx, By). */
+void ora_div_e(int nx, int ny, double dx, double dy, const double* ex, const double* ey, double* out);
+void ora_div_b(int nx, int ny, double dx, double dy, const double* bx, const double* by, double* out);
+
+/* sum m (gamma - 1) over particles */
+double ora_kinetic(int64_t np, double m, const double* ux, const double* uy, const double* uz);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
