@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the PIC hot path on one MI355X.
+
+Workload (default): periodic 1024 x 256 grid, dx = 0.1 c/omega_pe, pair plasma
+at gamma0 = 40 with T = 0.01 m c^2, 64 particles/cell/species (33,554,432
+particles), cubic (order-3) shape, CFL 1.0, theta = 0.6, field CG to 1e-8.
+One step = gather + Boris push + move + Esirkepov deposit of every particle,
+tile re-binning, the current reduction and the implicit field solve (RHS of
+Eq. (7), CG, update of Eqs. (5)-(6)).
+
+The timed form is the FP32 particle path (FP64 fields and CG); the plain FP64
+form is timed on the same GPU beside it. Inputs are synthetic (seeded
+Maxwell-Juettner load) and resident in HBM before the timed region.
+
+Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic HBM bytes per particle-step: read + write of the particle state
+BYTES_PER_PARTICLE = {"fp32": 2 * (4 + 5 * 4), "fp64": 2 * (4 + 5 * 8)}
+HBM_PEAK_GBS = 8000.0
+
+CONFIGS = {
+    # name: nx, ny, ppc, gamma0, order, cfl, theta
+    "c2": dict(nx=1024, ny=256, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
+               label="periodic 1024x256, pair gamma0=40, 64 ppc/species, order 3, "
+                     "CFL 1.0, theta 0.6"),
+    "c1": dict(nx=64, ny=64, ppc=16, gamma0=20.0, order=1, cfl=1.0, theta=0.6,
+               label="periodic 64x64, pair gamma0=20, 16 ppc/species, order 1, "
+                     "CFL 1.0, theta 0.6"),
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_sim(pic, cfg, load, precision, tile, cg_blocks=0):
+    from synth import loads
+    Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
+    run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
+                       [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8, cg_maxit=200)
+    sim = pic.Sim([run], pic.make_options(precision, tile=tile, diag_every=0,
+                                          cg_blocks=cg_blocks))
+    for s in range(2):
+        d = load[s]
+        sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    return sim
+
+
+def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0):
+    sim = make_sim(pic, cfg, load, precision, tile, cg_blocks)
+    n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
+    if warmup:
+        sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    rc = sim.step_async(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if rc not in (0,):
+        raise RuntimeError(f"pic_step returned {pic.STATUS.get(rc, rc)}")
+    tim = sim.get_timing()
+    st = sim.step(0)
+    sim.timing(False)
+    sim.close()
+    ms = (t1 - t0) * 1e3 / steps
+    push = tim["push"]
+    push_ms = push["ms"] / max(1, push["launches"])
+    return dict(ms_per_step=ms, particle_steps_per_s=n_part / (ms * 1e-3),
+                push_ms=push_ms, field_solve_ms=tim["field_solve"]["ms"] / max(1, steps),
+                rebin_ms=tim["rebin"]["ms"] / max(1, steps),
+                current_sum_ms=tim["current_sum"]["ms"] / max(1, steps),
+                cg_iters=st[0]["iters"], n_particles=n_part)
+
+
+def cpu_baseline(cfg, seconds=15.0):
+    """The FP64 oracle on a 4-row strip of the same workload (same grid width,
+    ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
+    import oracle
+    from synth import loads
+    nx, ny = cfg["nx"], 4
+    Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
+    ld = loads.pair_plasma_cells(nx, ny, cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
+    sp = [oracle.Particles(d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"], q, Q)
+          for d, q in zip(ld, (-Q, Q))]
+    sim = oracle.Sim(nx, ny, 0.1, 0.1, cfg["cfl"], cfg["theta"], cfg["order"], sp)
+    n = sum(p.n for p in sp)
+    sim.step()
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds or steps < 2:
+        sim.step()
+        steps += 1
+    dt = time.perf_counter() - t0
+    return dict(value=n * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{nx}x{ny} strip of the workload ({n} particles), {steps} whole "
+                       f"steps after 1 warm-up step, 1 thread, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cg-blocks", type=int, default=0, help="field-solve work-groups (0 = auto)")
+    ap.add_argument("--sweep-cg", default="", help="comma list of cg_blocks to time (FP32 form)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+              f"(asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1412_2480_amd as pic
+    from synth import loads
+
+    cfg = CONFIGS[args.config]
+    tile = tuple(int(v) for v in args.tile.split("x"))
+    log(f"bench: generating load {cfg['label']}")
+    t0 = time.perf_counter()
+    load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
+    log(f"bench: load ready in {time.perf_counter() - t0:.1f} s")
+
+    if args.sweep_cg:
+        for nb in [int(v) for v in args.sweep_cg.split(",")]:
+            r = time_form(pic, torch, cfg, load, "fp32", tile, 10, 2, nb)
+            log(f"bench: cg_blocks={nb}: field solve {r['field_solve_ms']:.3f} ms/step, "
+                f"iters {r['cg_iters']}")
+    log("bench: FP32 form")
+    fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks)
+    log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step")
+    plain = None
+    if not args.no_fp64:
+        log("bench: FP64 form")
+        plain = time_form(pic, torch, cfg, load, "fp64", tile, args.steps, args.warmup,
+                          args.cg_blocks)
+        log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
+    del load
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: oracle CPU baseline")
+        cpu = cpu_baseline(cfg, args.cpu_seconds)
+
+    n_part = fast["n_particles"]
+    achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
+    line = {
+        "metric": "particle-steps/s (whole step, FP32 particle path) + field-solve ms/step",
+        "value": fast["particle_steps_per_s"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": fast["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 particles, f64 fields/CG",
+        "data": "synthetic (seeded Maxwell-Juettner pair plasma)",
+        "config": {"workload": cfg["label"], "particles": n_part, "cells": cfg["nx"] * cfg["ny"],
+                   "tile": list(tile), "cg_rtol": 1e-8},
+        "field_solve_ms_per_step": fast["field_solve_ms"],
+        "cg_iters_last_step": fast["cg_iters"],
+        "breakdown_ms": {k: fast[k] for k in ("push_ms", "rebin_ms", "current_sum_ms",
+                                              "field_solve_ms")},
+        "plain_fp64": None if plain is None else {
+            "particle_steps_per_s": plain["particle_steps_per_s"],
+            "ms_per_step": plain["ms_per_step"],
+            "field_solve_ms_per_step": plain["field_solve_ms"],
+            "push_ms": plain["push_ms"],
+            "fp32_speedup": plain["ms_per_step"] / fast["ms_per_step"],
+        },
+        "roofline": {"bound": "hbm", "kernel": "fused particle push (gather+Boris+move+deposit)",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
+                     "avg_launch_ms": fast["push_ms"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

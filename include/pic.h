@@ -1,0 +1,201 @@
+/*
+ * pic.h -- C-ABI of the MI355X (gfx950) library for the data-parallel hot path
+ * of the 2D3V relativistic PIC method of Ikeya & Matsumoto, "Stability Property
+ * of Numerical Cherenkov Radiation and its Application to Relativistic Shock
+ * Simulations", PASJ 2015 (arXiv:1412.2480).
+ *
+ * One time step, as the paper states the problem (Sec. 2, Eqs. (5)-(7), and the
+ * PIC ingredients named in Sec. 1 and Sec. 3):
+ *   1. momentum-conserving gather of E^n, B^n to x^n with the order-p shape,
+ *   2. relativistic Boris push u^{n-1/2} -> u^{n+1/2}, move x^n -> x^{n+1},
+ *   3. Esirkepov density-decomposition deposit of J^{n+1/2},
+ *   4. implicit theta-weighted field solve: CG for dB of Eq. (7), then the
+ *      update of Eqs. (5)-(6).
+ *
+ * Conventions
+ *   Units: Gaussian, c = 1. dt = cfl * dx (cfl is the paper's sigma, Sec. 3.1).
+ *   Grid: nx*ny cells, arrays row-major [ny][nx] (index j*nx + i), standard 2D
+ *   Yee staggering: Ex(i+1/2,j) Ey(i,j+1/2) Ez(i,j) Bx(i,j+1/2) By(i+1/2,j)
+ *   Bz(i+1/2,j+1/2); J co-located with E; rho at nodes.
+ *   Particles: cell index (ix, iy) plus in-cell offset (fx, fy) in [0, 1), so
+ *   x = (ix + fx) dx; momentum u = gamma v; positions at integer steps,
+ *   momenta at half steps.
+ *
+ * Ownership: the caller allocates one device workspace of
+ * pic_plan_info.workspace_bytes (e.g. a torch uint8 tensor) and owns a HIP
+ * stream; both must outlive the context. The library allocates no device
+ * memory; it only keeps host-side bookkeeping in the opaque context. Host arrays
+ * passed in are borrowed for the duration of the call and copied.
+ *
+ * Errors: every call returns an int32 status (PIC_OK = 0, negative on error);
+ * no exception crosses the ABI. pic_last_error() gives a message. EINVAL
+ * leaves the state unchanged. Kernel faults surface at the next call that
+ * synchronises (pic_sync, pic_diag, reads, the end of pic_step).
+ * Threading: one context per host thread; all work is ordered on the
+ * context's stream.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_MAX_SPECIES 2
+#define PIC_MAX_RUNS 256
+
+enum pic_status {
+  PIC_OK = 0,
+  PIC_E_INVAL = -1,    /* bad argument or descriptor */
+  PIC_E_NOMEM = -2,    /* workspace smaller than the plan requires */
+  PIC_E_HIP = -3,      /* HIP runtime error */
+  PIC_E_NOCONV = -4,   /* CG hit cg_maxit; the best iterate was applied */
+  PIC_E_CAPACITY = -5, /* a tile's particle slots or exchange buffers overflowed */
+  PIC_E_NAN = -6,      /* non-finite value found by a diagnostic */
+  PIC_E_STATE = -7     /* calls out of order (e.g. deposit before gather_push) */
+};
+
+enum pic_bc { PIC_BC_PERIODIC = 0 };
+enum pic_precision { PIC_FP64 = 0, PIC_FP32_FAST = 1 };
+enum pic_solver { PIC_SOLVER_CG = 0 };
+enum pic_field_id {
+  PIC_EX = 0, PIC_EY, PIC_EZ, PIC_BX, PIC_BY, PIC_BZ, PIC_JX, PIC_JY, PIC_JZ, PIC_RHO
+};
+
+typedef struct pic_species_desc {
+  double q;           /* macro-particle charge (Gaussian units) */
+  double m;           /* macro-particle mass */
+  double ppc;         /* expected particles per cell, sizes the tile slots */
+} pic_species_desc;
+
+/* One simulation. All runs of a context share precision and tile shape. */
+typedef struct pic_run_desc {
+  int32_t nx, ny;        /* cells; each >= 8 and <= 32767 */
+  double dx, dy;         /* cell sizes (c/omega_pe) */
+  double cfl;            /* sigma = c dt/dx, 0 < sigma <= 1 (Esirkepov needs < 1 cell/step) */
+  double theta;          /* implicitness factor of Eqs. (5)-(6), 0.5 <= theta <= 1 */
+  int32_t shape_order;   /* B-spline degree 1, 2 or 3 */
+  int32_t bc;            /* PIC_BC_PERIODIC (both directions) */
+  int32_t n_species;     /* 1 .. PIC_MAX_SPECIES */
+  pic_species_desc species[PIC_MAX_SPECIES];
+  double cg_rtol;        /* relative residual target of the field CG (e.g. 1e-8) */
+  int32_t cg_maxit;      /* iteration cap of the field CG (e.g. 200) */
+} pic_run_desc;
+
+typedef struct pic_options {
+  int32_t precision;     /* PIC_FP64 or PIC_FP32_FAST (particles in FP32, fields FP64) */
+  int32_t solver;        /* PIC_SOLVER_CG */
+  int32_t tile_x, tile_y;/* tile shape in cells; 0 picks a default */
+  double slack;          /* extra tile slots over ppc*cells (default 0.25 if <= 0) */
+  double exchange_frac;  /* inbox/hole slots per tile as a fraction of tile slots (0.25) */
+  int32_t diag_every;    /* record energies every n steps into the history (0 = never) */
+  int32_t history_cap;   /* history records kept per run (ring buffer) */
+  int32_t cg_blocks;     /* work-groups of the persistent field solve; 0 = automatic */
+} pic_options;
+
+typedef struct pic_plan_info {
+  uint64_t workspace_bytes;
+  int32_t tile_x, tile_y;
+  int32_t n_tiles;                         /* over all runs */
+  int32_t tile_slots[PIC_MAX_SPECIES];     /* particle slots per tile per species */
+  int32_t exchange_slots;                  /* inbox/hole slots per tile per species */
+  int64_t particle_slots[PIC_MAX_SPECIES]; /* total slots per species */
+  int64_t n_cells;                         /* over all runs */
+} pic_plan_info;
+
+typedef struct pic_solve_stats {
+  int32_t iters[3];      /* CG iterations per B component */
+  double relres[3];      /* recursive relative residual ||r||/||b|| at exit */
+  double bnorm[3];       /* ||b||_2 of Eq. (7)'s right-hand side */
+} pic_solve_stats;
+
+typedef struct pic_diag_out {
+  int64_t step;          /* step index n of the record */
+  double t;              /* n dt */
+  double W_E, W_B;       /* field energies at step n: sum |F|^2 dx dy/(8 pi) */
+  double W_K_minus;      /* sum m (gamma - 1) at n - 1/2 */
+  double W_K_plus;       /* sum m (gamma - 1) at n + 1/2 */
+  int32_t cg_iters[3];
+  double cg_relres[3];
+  int64_t n_particles[PIC_MAX_SPECIES];
+} pic_diag_out;
+
+typedef struct pic_timing_out {
+  /* accumulated device time (ms) and launch counts per kernel class since
+     timing was switched on: 0 particle push (fused or split), 1 deposit
+     (split path), 2 rebin, 3 current reduction, 4 field RHS, 5 CG,
+     6 field update, 7 diagnostics */
+  double ms[8];
+  int64_t launches[8];
+} pic_timing_out;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Validate runs/options and size the workspace (host only, no HIP calls). */
+int32_t pic_plan(const pic_run_desc* runs, int32_t n_runs, const pic_options* opt,
+                 pic_plan_info* out);
+
+/* Create a context on the caller's workspace and stream (hipStream_t passed
+ * as void*; NULL is the default stream). Fields start at zero, as in the
+ * paper's runs (Sec. 3, first paragraph); particle counts start at zero. */
+int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* opt,
+                 void* d_workspace, size_t ws_bytes, void* hip_stream, pic_ctx** out);
+
+/* Replace the particles of (run, species) with n host particles: cell index
+ * (ix, iy), offset (fx, fy) in [0, 1) and momentum (ux, uy, uz) at n - 1/2.
+ * Particle k gets id k. PIC_E_CAPACITY if a tile's slots overflow (state unchanged). */
+int32_t pic_load_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t n,
+                           const int32_t* ix, const int32_t* iy, const double* fx,
+                           const double* fy, const double* ux, const double* uy,
+                           const double* uz);
+
+/* Copy the particles of (run, species) to the host, ordered by id, with
+ * n_out = count (at most cap). Any output pointer may be NULL. */
+int32_t pic_read_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t cap,
+                           int32_t* ix, int32_t* iy, double* fx, double* fy, double* ux,
+                           double* uy, double* uz, int64_t* n_out);
+
+/* Field arrays of one run, [ny][nx] FP64 at their Yee positions. Setting E or B
+ * also refreshes the FP32 copy used by the fast particle path. PIC_RHO is
+ * computed on demand from the particles (read only). */
+int32_t pic_set_field(pic_ctx* ctx, int32_t run, int32_t id, const double* host);
+int32_t pic_get_field(pic_ctx* ctx, int32_t run, int32_t id, double* host);
+
+/* Split step, for parity checks. gather_push: gather, Boris push and move of
+ * every particle of every run, keeping x^n (Sec. 1, Sec. 3). deposit:
+ * Esirkepov deposit of J^{n+1/2} from x^n -> x^{n+1}, periodic wrap and tile
+ * re-binning. field_solve: RHS of Eq. (7), CG for dB, update of Eqs. (5)-(6).
+ * stats may be NULL or point at n_runs entries. */
+int32_t pic_gather_push(pic_ctx* ctx);
+int32_t pic_deposit(pic_ctx* ctx);
+int32_t pic_field_solve(pic_ctx* ctx, pic_solve_stats* stats);
+
+/* nsteps fused steps (gather+push+move+deposit in one kernel per tile, then
+ * re-binning, the current reduction and the field solve). Synchronises once at
+ * the end to report overflow and CG status. last: NULL or n_runs entries. */
+int32_t pic_step(pic_ctx* ctx, int32_t nsteps, pic_solve_stats* last);
+
+/* Diagnostics of the current state of one run (synchronises): energies of
+ * the last recorded step plus particle counts. gauss/divb (nullable) receive
+ * max |div E - 4 pi rho| and max |div B| over the grid. */
+int32_t pic_diag(pic_ctx* ctx, int32_t run, pic_diag_out* out, double* gauss, double* divb);
+
+/* History records collected every diag_every steps (oldest first). */
+int32_t pic_history(pic_ctx* ctx, int32_t run, pic_diag_out* out, int32_t cap, int32_t* n_out);
+
+/* Event timing per kernel class (on the context stream). */
+int32_t pic_timing(pic_ctx* ctx, int32_t on);
+int32_t pic_get_timing(pic_ctx* ctx, pic_timing_out* out);
+
+int32_t pic_sync(pic_ctx* ctx);
+int32_t pic_destroy(pic_ctx* ctx);
+const char* pic_last_error(const pic_ctx* ctx);
+const char* pic_status_str(int32_t status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,316 @@
+"""MI355X (gfx950) hot path of the implicit-FDTD relativistic PIC method of
+Ikeya & Matsumoto, PASJ 2015 (arXiv:1412.2480).
+
+This module is a thin ctypes binding of libpic.so (C-ABI in include/pic.h):
+it only marshals arguments. PyTorch provides the device workspace and the
+stream; every step of the method runs in the library's HIP kernels. There is
+no CPU fallback: importing works without the library, but creating a Sim
+raises if libpic.so is missing or no GPU is visible.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_MAX_SPECIES = 2
+PIC_FP64, PIC_FP32_FAST = 0, 1
+PIC_SOLVER_CG = 0
+PIC_BC_PERIODIC = 0
+FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
+             "rho": 9}
+STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
+          -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
+EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_read_particles", "pic_set_field",
+           "pic_get_field", "pic_gather_push", "pic_deposit", "pic_field_solve", "pic_step",
+           "pic_diag", "pic_history", "pic_timing", "pic_get_timing", "pic_sync", "pic_destroy",
+           "pic_last_error", "pic_status_str"]
+
+
+class SpeciesDesc(ctypes.Structure):
+    _fields_ = [("q", ctypes.c_double), ("m", ctypes.c_double), ("ppc", ctypes.c_double)]
+
+
+class RunDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+                ("cfl", ctypes.c_double), ("theta", ctypes.c_double),
+                ("shape_order", ctypes.c_int32), ("bc", ctypes.c_int32),
+                ("n_species", ctypes.c_int32),
+                ("species", SpeciesDesc * PIC_MAX_SPECIES),
+                ("cg_rtol", ctypes.c_double), ("cg_maxit", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("solver", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("slack", ctypes.c_double), ("exchange_frac", ctypes.c_double),
+                ("diag_every", ctypes.c_int32), ("history_cap", ctypes.c_int32),
+                ("cg_blocks", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("workspace_bytes", ctypes.c_uint64), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("tile_slots", ctypes.c_int32 * PIC_MAX_SPECIES),
+                ("exchange_slots", ctypes.c_int32),
+                ("particle_slots", ctypes.c_int64 * PIC_MAX_SPECIES),
+                ("n_cells", ctypes.c_int64)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32 * 3), ("relres", ctypes.c_double * 3),
+                ("bnorm", ctypes.c_double * 3)]
+
+
+class DiagOut(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("W_E", ctypes.c_double),
+                ("W_B", ctypes.c_double), ("W_K_minus", ctypes.c_double),
+                ("W_K_plus", ctypes.c_double), ("cg_iters", ctypes.c_int32 * 3),
+                ("cg_relres", ctypes.c_double * 3),
+                ("n_particles", ctypes.c_int64 * PIC_MAX_SPECIES)]
+
+
+class TimingOut(ctypes.Structure):
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+
+
+TIMING_CLASSES = ["push", "deposit", "rebin", "current_sum", "rhs", "field_solve", "update", "diag"]
+
+_lib = None
+
+
+def lib():
+    """Load libpic.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        L.pic_plan.argtypes = [P(RunDesc), ctypes.c_int32, P(Options), P(PlanInfo)]
+        L.pic_init.argtypes = [P(RunDesc), ctypes.c_int32, P(Options), ctypes.c_void_p,
+                               ctypes.c_size_t, ctypes.c_void_p, P(ctypes.c_void_p)]
+        L.pic_load_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64] + [ctypes.c_void_p] * 7
+        L.pic_read_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int64] + [ctypes.c_void_p] * 7 + \
+                                        [P(ctypes.c_int64)]
+        L.pic_set_field.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p]
+        L.pic_get_field.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p]
+        L.pic_gather_push.argtypes = [ctypes.c_void_p]
+        L.pic_deposit.argtypes = [ctypes.c_void_p]
+        L.pic_field_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.pic_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
+        L.pic_diag.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(DiagOut), ctypes.c_void_p,
+                               ctypes.c_void_p]
+        L.pic_history.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int32, P(ctypes.c_int32)]
+        L.pic_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.pic_get_timing.argtypes = [ctypes.c_void_p, P(TimingOut)]
+        L.pic_sync.argtypes = [ctypes.c_void_p]
+        L.pic_destroy.argtypes = [ctypes.c_void_p]
+        L.pic_last_error.argtypes = [ctypes.c_void_p]
+        L.pic_last_error.restype = ctypes.c_char_p
+        L.pic_status_str.argtypes = [ctypes.c_int32]
+        L.pic_status_str.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name not in ("pic_last_error", "pic_status_str"):
+                getattr(L, name).restype = ctypes.c_int32
+        _lib = L
+    return _lib
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_maxit=200):
+    """species: list of (q, m, ppc)."""
+    d = RunDesc()
+    d.nx, d.ny = int(nx), int(ny)
+    d.dx = float(dx)
+    d.dy = float(dx if dy is None else dy)
+    d.cfl, d.theta = float(cfl), float(theta)
+    d.shape_order = int(order)
+    d.bc = PIC_BC_PERIODIC
+    d.n_species = len(species)
+    for k, (q, m, ppc) in enumerate(species):
+        d.species[k].q, d.species[k].m, d.species[k].ppc = float(q), float(m), float(ppc)
+    d.cg_rtol, d.cg_maxit = float(cg_rtol), int(cg_maxit)
+    return d
+
+
+def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
+                 diag_every=0, history_cap=1, cg_blocks=0):
+    o = Options()
+    o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
+    o.solver = PIC_SOLVER_CG
+    o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
+    o.slack, o.exchange_frac = float(slack), float(exchange_frac)
+    o.diag_every, o.history_cap = int(diag_every), int(history_cap)
+    o.cg_blocks = int(cg_blocks)
+    return o
+
+
+def plan(runs, options):
+    arr = (RunDesc * len(runs))(*runs)
+    info = PlanInfo()
+    rc = lib().pic_plan(arr, len(runs), ctypes.byref(options), ctypes.byref(info))
+    if rc != 0:
+        raise PicError(rc, "pic_plan rejected the configuration")
+    return info
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data
+
+
+class Sim:
+    """A context of one or more runs on the current torch CUDA (HIP) device."""
+
+    def __init__(self, runs, options, device=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the PIC library has no CPU path")
+        self.L = lib()
+        self.runs = list(runs)
+        self.options = options
+        self.info = plan(self.runs, options)
+        self.device = torch.device("cuda" if device is None else device)
+        self.workspace = torch.empty(int(self.info.workspace_bytes), dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = torch.cuda.current_stream(self.device)
+        arr = (RunDesc * len(self.runs))(*self.runs)
+        ctx = ctypes.c_void_p()
+        rc = self.L.pic_init(arr, len(self.runs), ctypes.byref(options),
+                             ctypes.c_void_p(self.workspace.data_ptr()),
+                             int(self.info.workspace_bytes),
+                             ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
+        if rc != 0:
+            raise PicError(rc, "pic_init failed")
+        self.ctx = ctx
+
+    def _check(self, rc, what, allow=()):
+        if rc != 0 and rc not in allow:
+            raise PicError(rc, f"{what}: {self.L.pic_last_error(self.ctx).decode()}")
+        return rc
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None and self.ctx.value:
+            self.L.pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- data
+    def load_particles(self, run, species, ix, iy, fx, fy, ux, uy, uz):
+        a = [np.ascontiguousarray(v, dtype=t) for v, t in
+             ((ix, np.int32), (iy, np.int32), (fx, np.float64), (fy, np.float64),
+              (ux, np.float64), (uy, np.float64), (uz, np.float64))]
+        n = a[0].size
+        self._check(self.L.pic_load_particles(self.ctx, run, species, n, *[_ptr(v) for v in a]),
+                    "load_particles")
+
+    def read_particles(self, run, species, cap):
+        out = dict(ix=np.empty(cap, np.int32), iy=np.empty(cap, np.int32),
+                   fx=np.empty(cap), fy=np.empty(cap), ux=np.empty(cap), uy=np.empty(cap),
+                   uz=np.empty(cap))
+        n = ctypes.c_int64(0)
+        self._check(self.L.pic_read_particles(self.ctx, run, species, cap,
+                                              *[_ptr(out[k]) for k in
+                                                ("ix", "iy", "fx", "fy", "ux", "uy", "uz")],
+                                              ctypes.byref(n)), "read_particles")
+        return {k: v[:n.value] for k, v in out.items()}
+
+    def get_field(self, run, name):
+        d = self.runs[run]
+        out = np.empty((d.ny, d.nx))
+        self._check(self.L.pic_get_field(self.ctx, run, FIELD_IDS[name], _ptr(out)), "get_field")
+        return out
+
+    def set_field(self, run, name, arr):
+        a = np.ascontiguousarray(arr, dtype=np.float64)
+        d = self.runs[run]
+        assert a.shape == (d.ny, d.nx)
+        self._check(self.L.pic_set_field(self.ctx, run, FIELD_IDS[name], _ptr(a)), "set_field")
+
+    # ---- step calls
+    def gather_push(self):
+        self._check(self.L.pic_gather_push(self.ctx), "gather_push")
+
+    def deposit(self):
+        self._check(self.L.pic_deposit(self.ctx), "deposit")
+
+    def _stats(self, st):
+        return [dict(iters=list(s.iters), relres=list(s.relres), bnorm=list(s.bnorm)) for s in st]
+
+    def field_solve(self, allow_noconv=False):
+        st = (SolveStats * len(self.runs))()
+        self._check(self.L.pic_field_solve(self.ctx, st), "field_solve",
+                    allow=(-4,) if allow_noconv else ())
+        return self._stats(st)
+
+    def step(self, n=1, allow_noconv=False):
+        st = (SolveStats * len(self.runs))()
+        self._check(self.L.pic_step(self.ctx, int(n), st), "step",
+                    allow=(-4,) if allow_noconv else ())
+        return self._stats(st)
+
+    def step_async(self, n=1):
+        """Enqueue n steps; returns the status without reading anything back
+        except the end-of-call overflow and CG checks."""
+        return self.L.pic_step(self.ctx, int(n), None)
+
+    def sync(self):
+        self._check(self.L.pic_sync(self.ctx), "sync")
+
+    # ---- diagnostics
+    @staticmethod
+    def _rec(o):
+        return dict(step=o.step, t=o.t, W_E=o.W_E, W_B=o.W_B, W_K_minus=o.W_K_minus,
+                    W_K_plus=o.W_K_plus, cg_iters=list(o.cg_iters),
+                    cg_relres=list(o.cg_relres), n_particles=list(o.n_particles))
+
+    def diag(self, run=0, divergences=False):
+        o = DiagOut()
+        g = ctypes.c_double(0.0)
+        d = ctypes.c_double(0.0)
+        self._check(self.L.pic_diag(self.ctx, run, ctypes.byref(o),
+                                    ctypes.byref(g) if divergences else None,
+                                    ctypes.byref(d) if divergences else None), "diag")
+        r = self._rec(o)
+        if divergences:
+            r["gauss_max"], r["divb_max"] = g.value, d.value
+        return r
+
+    def history(self, run=0):
+        cap = max(1, self.options.history_cap)
+        out = (DiagOut * cap)()
+        n = ctypes.c_int32(0)
+        self._check(self.L.pic_history(self.ctx, run, out, cap, ctypes.byref(n)), "history")
+        return [self._rec(out[k]) for k in range(n.value)]
+
+    def timing(self, on=True):
+        self._check(self.L.pic_timing(self.ctx, 1 if on else 0), "timing")
+
+    def get_timing(self):
+        t = TimingOut()
+        self._check(self.L.pic_get_timing(self.ctx, ctypes.byref(t)), "get_timing")
+        return {name: dict(ms=t.ms[k], launches=t.launches[k])
+                for k, name in enumerate(TIMING_CLASSES)}
+
+
+def exported_symbols():
+    return list(EXPORTS)

@@ -1,0 +1,993 @@
+// C-ABI of the PIC hot-path library (declared in include/pic.h): planning,
+// workspace carving, particle/field transfer, step sequencing, diagnostics
+// and event timing. All device work is issued on the caller's stream; the
+// device memory is the caller's workspace.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic.h"
+#include "pic_dev.h"
+#include "pic_launch.h"
+
+namespace {
+
+constexpr int kMaxCgBlocks = 4096;
+constexpr int kDivBlocks = 512;
+constexpr int kTimingClasses = 8;
+
+struct Bump {
+  uint8_t* base;
+  size_t off = 0;
+  explicit Bump(uint8_t* b) : base(b) {}
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+struct Tiling {
+  int TX, TY, TXA, TYA;
+  std::vector<int> ntx, nty, tile0;
+  std::vector<long long> cell0;
+  int n_tiles;
+  long long n_cells, max_cells;
+};
+
+int tiles_along(int n, int T, int* widest) {
+  if (n <= T) {
+    *widest = n;
+    return 1;
+  }
+  const int rem = n % T;
+  if (rem == 0) {
+    *widest = T;
+    return n / T;
+  }
+  if (rem < 3) {
+    *widest = T + rem;
+    return n / T;
+  }
+  *widest = T;
+  return n / T + 1;
+}
+
+}  // namespace
+
+struct pic_ctx {
+  std::vector<pic_run_desc> runs;
+  pic_options opt{};
+  pic_plan_info plan{};
+  Tiling tl;
+  hipStream_t stream = nullptr;
+  uint8_t* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool fast = false;
+  bool split = true;
+  std::vector<DevRun> hruns;
+  DevRun* d_runs = nullptr;
+  int* d_tile_run = nullptr;
+  DevState<float> sf{};
+  DevState<double> sd{};
+  FieldArgs fa{};
+  double* d_stats = nullptr;
+  double* d_history = nullptr;
+  double* d_rho = nullptr;
+  double* d_divpart = nullptr;
+  int* d_err = nullptr;
+  int phase = 0;
+  long long step = 0;
+  long long diag_count = 0;
+  std::vector<long long> hist_step;  // steps recorded (host mirror)
+  int threads = 256;
+  std::string err;
+  // timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of start event)
+  double t_ms[kTimingClasses] = {};
+  long long t_n[kTimingClasses] = {};
+};
+
+namespace {
+
+int fail(pic_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIPCHK(ctx, expr)                                                          \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ctx, PIC_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::string* msg) {
+  if (!runs || n_runs < 1 || n_runs > PIC_MAX_RUNS) {
+    *msg = "n_runs out of range";
+    return PIC_E_INVAL;
+  }
+  if (!o) {
+    *msg = "options missing";
+    return PIC_E_INVAL;
+  }
+  if (o->precision != PIC_FP64 && o->precision != PIC_FP32_FAST) {
+    *msg = "precision must be PIC_FP64 or PIC_FP32_FAST";
+    return PIC_E_INVAL;
+  }
+  if (o->solver != PIC_SOLVER_CG) {
+    *msg = "unknown solver";
+    return PIC_E_INVAL;
+  }
+  for (int r = 0; r < n_runs; ++r) {
+    const pic_run_desc& d = runs[r];
+    char buf[160];
+    auto bad = [&](const char* what) {
+      snprintf(buf, sizeof buf, "run %d: %s", r, what);
+      *msg = buf;
+      return PIC_E_INVAL;
+    };
+    if (d.nx < 8 || d.ny < 8 || d.nx > 32767 || d.ny > 32767) return bad("nx, ny must be in [8, 32767]");
+    if (!(d.dx > 0) || !(d.dy > 0)) return bad("dx, dy must be positive");
+    if (!(d.cfl > 0) || d.cfl > 1.0) return bad("cfl must be in (0, 1]");
+    if (d.cfl * d.dx > d.dy * (1.0 + 1e-12)) return bad("dt must not exceed dy (one cell per step)");
+    if (!(d.theta >= 0.5) || d.theta > 1.0) return bad("theta must be in [0.5, 1]");
+    if (d.shape_order < 1 || d.shape_order > 3) return bad("shape_order must be 1, 2 or 3");
+    if (d.bc != PIC_BC_PERIODIC) return bad("only periodic boundaries are supported");
+    if (d.n_species < 1 || d.n_species > PIC_MAX_SPECIES) return bad("n_species out of range");
+    for (int s = 0; s < d.n_species; ++s)
+      if (!(d.species[s].m > 0) || !std::isfinite(d.species[s].q) || !(d.species[s].ppc >= 0))
+        return bad("species needs m > 0, finite q, ppc >= 0");
+    if (!(d.cg_rtol > 0) || d.cg_maxit < 1) return bad("cg_rtol > 0 and cg_maxit >= 1 required");
+  }
+  return PIC_OK;
+}
+
+void make_tiling(const pic_run_desc* runs, int n_runs, const pic_options* o, Tiling* t) {
+  t->TX = o->tile_x > 0 ? o->tile_x : 16;
+  t->TY = o->tile_y > 0 ? o->tile_y : 16;
+  t->TXA = t->TYA = 0;
+  t->ntx.resize(n_runs);
+  t->nty.resize(n_runs);
+  t->tile0.resize(n_runs);
+  t->cell0.resize(n_runs);
+  int nt = 0;
+  long long nc = 0, mc = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    int wx, wy;
+    t->ntx[r] = tiles_along(runs[r].nx, t->TX, &wx);
+    t->nty[r] = tiles_along(runs[r].ny, t->TY, &wy);
+    t->TXA = std::max(t->TXA, wx);
+    t->TYA = std::max(t->TYA, wy);
+    t->tile0[r] = nt;
+    t->cell0[r] = nc;
+    nt += t->ntx[r] * t->nty[r];
+    const long long cells = (long long)runs[r].nx * runs[r].ny;
+    nc += cells;
+    mc = std::max(mc, cells);
+  }
+  t->n_tiles = nt;
+  t->n_cells = nc;
+  t->max_cells = mc;
+}
+
+// Carve (or, with base == nullptr, size) the workspace.
+template <typename R>
+size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
+             bool split, int hist_cap, pic_ctx* c, DevState<R>* st) {
+  Bump b(base);
+  const long long nc = tl.n_cells;
+  const size_t plane = (size_t)(tl.TXA + 5) * (tl.TYA + 5);
+  DevRun* d_runs = b.take<DevRun>(n_runs);
+  int* tile_run = b.take<int>(tl.n_tiles);
+  double *E[3], *B[3], *J[3];
+  for (int k = 0; k < 3; ++k) E[k] = b.take<double>(nc);
+  for (int k = 0; k < 3; ++k) B[k] = b.take<double>(nc);
+  for (int k = 0; k < 3; ++k) J[k] = b.take<double>(nc);
+  float* Ef[6] = {};
+  if (fast)
+    for (int k = 0; k < 6; ++k) Ef[k] = b.take<float>(nc);
+  double *x[3], *r[3], *p0[3], *p1[3], *q[3];
+  for (int k = 0; k < 3; ++k) {
+    x[k] = b.take<double>(nc);
+    r[k] = b.take<double>(nc);
+    p0[k] = b.take<double>(nc);
+    p1[k] = b.take<double>(nc);
+    q[k] = b.take<double>(nc);
+  }
+  double* part = b.take<double>((size_t)kMaxCgBlocks * 10);
+  int* g_active = b.take<int>(2);
+  double* stats = b.take<double>((size_t)n_runs * 9);
+  double* history = b.take<double>((size_t)n_runs * hist_cap * PIC_REC_WORDS);
+  int* err = b.take<int>(1);
+  double* wk_part = b.take<double>((size_t)tl.n_tiles * PIC_MAXS * 2);
+  double* rho = b.take<double>(tl.max_cells);
+  double* divpart = b.take<double>((size_t)kDivBlocks * 2);
+  R* patch[3];
+  for (int k = 0; k < 3; ++k) patch[k] = b.take<R>((size_t)tl.n_tiles * plane);
+  DevState<R> s{};
+  for (int sp = 0; sp < PIC_MAXS; ++sp) {
+    const size_t slots = (size_t)tl.n_tiles * pl.tile_slots[sp];
+    const size_t ex = (size_t)tl.n_tiles * pl.exchange_slots;
+    if (pl.tile_slots[sp] == 0) continue;
+    s.cell[sp] = b.take<int>(slots);
+    s.ox[sp] = b.take<R>(slots);
+    s.oy[sp] = b.take<R>(slots);
+    s.ux[sp] = b.take<R>(slots);
+    s.uy[sp] = b.take<R>(slots);
+    s.uz[sp] = b.take<R>(slots);
+    s.id[sp] = b.take<int>(slots);
+    s.cnt[sp] = b.take<int>(tl.n_tiles);
+    s.in_cnt[sp] = b.take<int>(tl.n_tiles);
+    s.in_cell[sp] = b.take<int>(ex);
+    s.in_ox[sp] = b.take<R>(ex);
+    s.in_oy[sp] = b.take<R>(ex);
+    s.in_ux[sp] = b.take<R>(ex);
+    s.in_uy[sp] = b.take<R>(ex);
+    s.in_uz[sp] = b.take<R>(ex);
+    s.in_id[sp] = b.take<int>(ex);
+    s.hole[sp] = b.take<int>(ex);
+    s.hole_cnt[sp] = b.take<int>(tl.n_tiles);
+    s.rb_scr[sp] = b.take<int>(ex);
+    if (split) {
+      s.old_cell[sp] = b.take<int>(slots);
+      s.old_ox[sp] = b.take<R>(slots);
+      s.old_oy[sp] = b.take<R>(slots);
+    }
+  }
+  const size_t total = (b.off + 255) & ~size_t(255);
+  if (!base) return total;
+
+  s.n_runs = n_runs;
+  s.n_tiles = tl.n_tiles;
+  s.TX = tl.TX;
+  s.TY = tl.TY;
+  s.TXA = tl.TXA;
+  s.TYA = tl.TYA;
+  s.PW = tl.TXA + 5;
+  s.PH = tl.TYA + 5;
+  for (int sp = 0; sp < PIC_MAXS; ++sp) s.tile_slots[sp] = pl.tile_slots[sp];
+  s.ex_slots = pl.exchange_slots;
+  s.runs = d_runs;
+  s.tile_run = tile_run;
+  for (int k = 0; k < 3; ++k) {
+    s.E[k] = E[k];
+    s.B[k] = B[k];
+    s.J[k] = J[k];
+  }
+  for (int k = 0; k < 6; ++k) s.Ef[k] = Ef[k];
+  for (int k = 0; k < 3; ++k) s.patch[k] = patch[k];
+  s.wk_part = wk_part;
+  s.err = err;
+  *st = s;
+
+  FieldArgs& f = c->fa;
+  f.n_runs = n_runs;
+  f.runs = d_runs;
+  for (int k = 0; k < 3; ++k) {
+    f.E[k] = E[k];
+    f.B[k] = B[k];
+    f.J[k] = J[k];
+    f.x[k] = x[k];
+    f.r[k] = r[k];
+    f.p0[k] = p0[k];
+    f.p1[k] = p1[k];
+    f.q[k] = q[k];
+  }
+  for (int k = 0; k < 6; ++k) f.Ef[k] = Ef[k];
+  f.part = part;
+  f.g_active = g_active;
+  f.stats = stats;
+  f.wk_part = wk_part;
+  f.history = history;
+  f.hist_cap = hist_cap;
+  c->d_runs = d_runs;
+  c->d_tile_run = tile_run;
+  c->d_stats = stats;
+  c->d_history = history;
+  c->d_rho = rho;
+  c->d_divpart = divpart;
+  c->d_err = err;
+  return total;
+}
+
+int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_plan_info* out,
+              Tiling* tl, std::string* msg) {
+  int rc = validate(runs, n_runs, o, msg);
+  if (rc) return rc;
+  make_tiling(runs, n_runs, o, tl);
+  const bool fast = o->precision == PIC_FP32_FAST;
+  const size_t rsz = fast ? 4 : 8;
+  const size_t plane = (size_t)(tl->TXA + 5) * (tl->TYA + 5);
+  const size_t smem = (6 + 3) * plane * rsz;
+  if (smem > 64 * 1024) {
+    *msg = "tile too large for LDS (fields + currents exceed 64 KiB)";
+    return PIC_E_INVAL;
+  }
+  pic_plan_info p{};
+  p.tile_x = tl->TX;
+  p.tile_y = tl->TY;
+  p.n_tiles = tl->n_tiles;
+  p.n_cells = tl->n_cells;
+  const double slack = o->slack > 0 ? o->slack : 0.25;
+  const double exf = o->exchange_frac > 0 ? o->exchange_frac : 0.25;
+  int max_species = 0;
+  for (int r = 0; r < n_runs; ++r) max_species = std::max(max_species, runs[r].n_species);
+  for (int s = 0; s < PIC_MAX_SPECIES; ++s) {
+    double ppc = 0;
+    for (int r = 0; r < n_runs; ++r)
+      if (s < runs[r].n_species) ppc = std::max(ppc, runs[r].species[s].ppc);
+    if (s >= max_species) {
+      p.tile_slots[s] = 0;
+      continue;
+    }
+    double want = std::ceil(ppc * tl->TXA * tl->TYA * (1.0 + slack));
+    long long slots = std::max(64LL, ((long long)want + 63) / 64 * 64);
+    if (slots > (1LL << 30)) {
+      *msg = "tile slots exceed 2^30";
+      return PIC_E_INVAL;
+    }
+    p.tile_slots[s] = (int)slots;
+    p.particle_slots[s] = slots * tl->n_tiles;
+  }
+  int ts = std::max(p.tile_slots[0], p.tile_slots[1]);
+  p.exchange_slots = std::max(64, (int)(std::ceil(ts * exf) + 63) / 64 * 64);
+  const int hist_cap = o->history_cap > 0 ? o->history_cap : 1;
+  const bool split = true;
+  p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, hist_cap, nullptr,
+                                          (DevState<float>*)nullptr)
+                           : carve<double>(nullptr, *tl, p, n_runs, false, split, hist_cap,
+                                           nullptr, (DevState<double>*)nullptr);
+  *out = p;
+  return PIC_OK;
+}
+
+// ---------------------------------------------------------------- timing
+void t_begin(pic_ctx* c, int cls) {
+  if (!c->timing) return;
+  if (c->ev_used + 2 > c->ev_pool.size()) {
+    for (int k = 0; k < 256; ++k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return;
+      c->ev_pool.push_back(e);
+    }
+  }
+  (void)hipEventRecord(c->ev_pool[c->ev_used], c->stream);
+  c->ev_marks.push_back({cls, c->ev_used});
+  c->ev_used += 2;
+}
+void t_end(pic_ctx* c) {
+  if (!c->timing || c->ev_marks.empty()) return;
+  (void)hipEventRecord(c->ev_pool[c->ev_marks.back().second + 1], c->stream);
+}
+void t_resolve(pic_ctx* c) {
+  if (c->ev_marks.empty()) return;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto& m : c->ev_marks) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev_pool[m.second], c->ev_pool[m.second + 1]) == hipSuccess) {
+      c->t_ms[m.first] += ms;
+      c->t_n[m.first] += 1;
+    }
+  }
+  c->ev_marks.clear();
+  c->ev_used = 0;
+}
+
+// ---------------------------------------------------------------- device steps
+template <typename R>
+DevState<R>& state(pic_ctx* c);
+template <>
+DevState<float>& state<float>(pic_ctx* c) { return c->sf; }
+template <>
+DevState<double>& state<double>(pic_ctx* c) { return c->sd; }
+
+bool diag_step(pic_ctx* c) {
+  return c->opt.diag_every > 0 && (c->step % c->opt.diag_every) == 0;
+}
+
+template <typename R>
+int launch_particles(pic_ctx* c, int mode, int diag) {
+  t_begin(c, mode == PIC_MODE_DEPOSIT ? 1 : 0);
+  hipError_t e = pic_launch_particles<R>(state<R>(c), mode, diag, c->threads, c->stream);
+  t_end(c);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("particle kernel: ") + hipGetErrorString(e));
+  return PIC_OK;
+}
+
+template <typename R>
+int launch_exchange(pic_ctx* c) {
+  int ns = 0;
+  for (auto& r : c->runs) ns = std::max(ns, r.n_species);
+  t_begin(c, 2);
+  hipError_t e = pic_launch_rebin<R>(state<R>(c), ns, c->stream);
+  t_end(c);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("rebin: ") + hipGetErrorString(e));
+  t_begin(c, 3);
+  e = pic_launch_current_sum<R>(state<R>(c), c->tl.max_cells, c->stream);
+  t_end(c);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("current sum: ") + hipGetErrorString(e));
+  return PIC_OK;
+}
+
+int launch_field(pic_ctx* c, int diag) {
+  FieldArgs a = c->fa;
+  a.diag = diag;
+  a.step = c->step;
+  a.hist_slot = (int)(c->diag_count % std::max(1, c->opt.history_cap));
+  t_begin(c, 5);
+  hipError_t e = pic_launch_field_solve(a, c->stream);
+  t_end(c);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("field solve: ") + hipGetErrorString(e));
+  if (diag) {
+    c->hist_step.push_back(c->step);
+    c->diag_count += 1;
+  }
+  return PIC_OK;
+}
+
+int read_stats(pic_ctx* c, pic_solve_stats* out) {
+  const int n = (int)c->runs.size();
+  std::vector<double> h((size_t)n * 9);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_stats, h.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  int rc = PIC_OK;
+  for (int r = 0; r < n; ++r) {
+    for (int k = 0; k < 3; ++k) {
+      const int it = (int)h[r * 9 + k];
+      const double rel = h[r * 9 + 3 + k];
+      if (out) {
+        out[r].iters[k] = it;
+        out[r].relres[k] = rel;
+        out[r].bnorm[k] = h[r * 9 + 6 + k];
+      }
+      if (!std::isfinite(rel)) rc = PIC_E_NAN;
+      else if (it >= c->runs[r].cg_maxit && rel > c->runs[r].cg_rtol && rc == PIC_OK)
+        rc = PIC_E_NOCONV;
+    }
+  }
+  if (rc == PIC_E_NOCONV) c->err = "field CG reached cg_maxit";
+  if (rc == PIC_E_NAN) c->err = "non-finite CG residual";
+  return rc;
+}
+
+int check_err(pic_ctx* c) {
+  int h = 0;
+  HIPCHK(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "particle exchange overflow (bits 0x%x); raise slack/exchange_frac", h);
+    return fail(c, PIC_E_CAPACITY, buf);
+  }
+  return PIC_OK;
+}
+
+template <typename R>
+int do_gather_push(pic_ctx* c) {
+  return launch_particles<R>(c, PIC_MODE_PUSH, diag_step(c) ? 1 : 0);
+}
+template <typename R>
+int do_deposit(pic_ctx* c) {
+  int rc = launch_particles<R>(c, PIC_MODE_DEPOSIT, 0);
+  if (rc) return rc;
+  return launch_exchange<R>(c);
+}
+template <typename R>
+int do_step(pic_ctx* c) {
+  const int diag = diag_step(c) ? 1 : 0;
+  int rc = launch_particles<R>(c, PIC_MODE_FUSED, diag);
+  if (rc) return rc;
+  rc = launch_exchange<R>(c);
+  if (rc) return rc;
+  rc = launch_field(c, diag);
+  if (rc) return rc;
+  c->step += 1;
+  return PIC_OK;
+}
+
+template <typename R>
+int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const int32_t* iy,
+              const double* fx, const double* fy, const double* ux, const double* uy,
+              const double* uz) {
+  const pic_run_desc& d = c->runs[run];
+  const Tiling& tl = c->tl;
+  const int ntx = tl.ntx[run], nty = tl.nty[run], nt = ntx * nty;
+  const int slots = c->plan.tile_slots[s];
+  if (n > (int64_t)INT32_MAX) return fail(c, PIC_E_INVAL, "too many particles for int32 ids");
+  std::vector<int> tile_of(n);
+  std::vector<int> count(nt, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    if (ix[k] < 0 || ix[k] >= d.nx || iy[k] < 0 || iy[k] >= d.ny || !(fx[k] >= 0.0) ||
+        !(fx[k] < 1.0) || !(fy[k] >= 0.0) || !(fy[k] < 1.0) || !std::isfinite(ux[k]) ||
+        !std::isfinite(uy[k]) || !std::isfinite(uz[k]))
+      return fail(c, PIC_E_INVAL, "particle outside the grid, offset outside [0,1) or non-finite u");
+    const int tx = std::min(ix[k] / tl.TX, ntx - 1);
+    const int ty = std::min(iy[k] / tl.TY, nty - 1);
+    tile_of[k] = ty * ntx + tx;
+    if (++count[tile_of[k]] > slots)
+      return fail(c, PIC_E_CAPACITY, "tile slots exceeded while loading; raise slack or ppc");
+  }
+  // Slot order inside a tile interleaves cells (the r-th particle of every
+  // cell before the (r+1)-th of any), so the lanes of a wavefront deposit into
+  // different cells instead of contending for the same LDS addresses.
+  std::vector<int64_t> start(nt + 1, 0);
+  for (int t = 0; t < nt; ++t) start[t + 1] = start[t] + count[t];
+  std::vector<int64_t> order(n);
+  std::vector<uint32_t> rank_in_cell(n);
+  {
+    std::vector<int> seen((size_t)d.nx * d.ny, 0);
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (int64_t k = 0; k < n; ++k) {
+      rank_in_cell[k] = (uint32_t)seen[(size_t)iy[k] * d.nx + ix[k]]++;
+      order[pos[tile_of[k]]++] = k;
+    }
+    const int cells_per_tile = tl.TXA * tl.TYA;
+    for (int t = 0; t < nt; ++t) {
+      auto key = [&](int64_t k) {
+        const int tx = std::min(ix[k] / tl.TX, ntx - 1), ty = std::min(iy[k] / tl.TY, nty - 1);
+        const int lc = (iy[k] - ty * tl.TY) * tl.TXA + (ix[k] - tx * tl.TX);
+        return (uint64_t)rank_in_cell[k] * cells_per_tile + lc;
+      };
+      std::sort(order.begin() + start[t], order.begin() + start[t + 1],
+                [&](int64_t a, int64_t b) { return key(a) < key(b); });
+    }
+  }
+  const size_t tot = (size_t)nt * slots;
+  std::vector<int> hcell(tot, -1), hid(tot, 0);
+  std::vector<R> hox(tot, R(0)), hoy(tot, R(0)), hux(tot, R(0)), huy(tot, R(0)), huz(tot, R(0));
+  std::vector<int> fill(nt, 0);
+  for (int64_t kk = 0; kk < n; ++kk) {
+    const int64_t k = order[kk];
+    const int t = tile_of[k];
+    const size_t o = (size_t)t * slots + fill[t]++;
+    hcell[o] = (iy[k] << 16) | ix[k];
+    hox[o] = (R)fx[k];
+    hoy[o] = (R)fy[k];
+    // an offset that rounds up to 1 in FP32 moves to the next cell
+    if (hox[o] >= R(1)) { hox[o] = R(0); hcell[o] = (iy[k] << 16) | ((ix[k] + 1) % d.nx); }
+    if (hoy[o] >= R(1)) { hoy[o] = R(0); hcell[o] = ((((hcell[o] >> 16) + 1) % d.ny) << 16) | (hcell[o] & 0xffff); }
+    hux[o] = (R)ux[k];
+    huy[o] = (R)uy[k];
+    huz[o] = (R)uz[k];
+    hid[o] = (int)k;
+  }
+  DevState<R>& st = state<R>(c);
+  const size_t b0 = (size_t)tl.tile0[run] * slots;
+  hipStream_t S = c->stream;
+  HIPCHK(c, hipMemcpyAsync(st.cell[s] + b0, hcell.data(), tot * sizeof(int), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.ox[s] + b0, hox.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.oy[s] + b0, hoy.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.ux[s] + b0, hux.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.uy[s] + b0, huy.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.uz[s] + b0, huz.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.id[s] + b0, hid.data(), tot * sizeof(int), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(st.cnt[s] + tl.tile0[run], count.data(), nt * sizeof(int),
+                           hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipStreamSynchronize(S));
+  return PIC_OK;
+}
+
+template <typename R>
+int read_impl(pic_ctx* c, int run, int s, int64_t cap, int32_t* ix, int32_t* iy, double* fx,
+              double* fy, double* ux, double* uy, double* uz, int64_t* n_out) {
+  const Tiling& tl = c->tl;
+  const int nt = tl.ntx[run] * tl.nty[run];
+  const int slots = c->plan.tile_slots[s];
+  const size_t tot = (size_t)nt * slots;
+  DevState<R>& st = state<R>(c);
+  const size_t b0 = (size_t)tl.tile0[run] * slots;
+  std::vector<int> hcell(tot), hid(tot), count(nt);
+  std::vector<R> hox(tot), hoy(tot), hux(tot), huy(tot), huz(tot);
+  hipStream_t S = c->stream;
+  HIPCHK(c, hipMemcpyAsync(count.data(), st.cnt[s] + tl.tile0[run], nt * sizeof(int), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(hcell.data(), st.cell[s] + b0, tot * sizeof(int), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(hox.data(), st.ox[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(hoy.data(), st.oy[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(hux.data(), st.ux[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(huy.data(), st.uy[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(huz.data(), st.uz[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipMemcpyAsync(hid.data(), st.id[s] + b0, tot * sizeof(int), hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipStreamSynchronize(S));
+  int64_t n = 0;
+  for (int t = 0; t < nt; ++t) n += count[t];
+  *n_out = n;
+  if (n > cap) return fail(c, PIC_E_INVAL, "output capacity smaller than the particle count");
+  std::vector<char> seen(n, 0);
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < count[t]; ++k) {
+      const size_t o = (size_t)t * slots + k;
+      const int id = hid[o];
+      if (id < 0 || id >= n || seen[id] || hcell[o] < 0)
+        return fail(c, PIC_E_STATE, "particle store inconsistent (duplicate/missing id or hole)");
+      seen[id] = 1;
+      if (ix) ix[id] = hcell[o] & 0xffff;
+      if (iy) iy[id] = hcell[o] >> 16;
+      if (fx) fx[id] = (double)hox[o];
+      if (fy) fy[id] = (double)hoy[o];
+      if (ux) ux[id] = (double)hux[o];
+      if (uy) uy[id] = (double)huy[o];
+      if (uz) uz[id] = (double)huz[o];
+    }
+  return PIC_OK;
+}
+
+}  // namespace
+
+namespace {
+
+double* field_ptr(pic_ctx* c, int id) {
+  const FieldArgs& f = c->fa;
+  if (id >= PIC_EX && id <= PIC_EZ) return f.E[id - PIC_EX];
+  if (id >= PIC_BX && id <= PIC_BZ) return f.B[id - PIC_BX];
+  if (id >= PIC_JX && id <= PIC_JZ) return f.J[id - PIC_JX];
+  return nullptr;
+}
+
+template <typename R>
+int rho_impl(pic_ctx* c, int run) {
+  hipError_t e = pic_launch_particles<R>(state<R>(c), 3, 0, 256, c->stream);
+  if (e == hipSuccess)
+    e = pic_launch_charge_sum<R>(state<R>(c), run,
+                                 (long long)c->runs[run].nx * c->runs[run].ny, c->d_rho, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("charge: ") + hipGetErrorString(e));
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pic_plan(const pic_run_desc* runs, int32_t n_runs, const pic_options* opt,
+                 pic_plan_info* out) {
+  if (!out) return PIC_E_INVAL;
+  Tiling tl;
+  std::string msg;
+  return plan_impl(runs, n_runs, opt, out, &tl, &msg);
+}
+
+int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* opt,
+                 void* d_workspace, size_t ws_bytes, void* hip_stream, pic_ctx** out) {
+  if (!out) return PIC_E_INVAL;
+  *out = nullptr;
+  pic_ctx* c = new pic_ctx();
+  std::string msg;
+  int rc = plan_impl(runs, n_runs, opt, &c->plan, &c->tl, &msg);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  if (!d_workspace || ws_bytes < c->plan.workspace_bytes) {
+    delete c;
+    return PIC_E_NOMEM;
+  }
+  c->runs.assign(runs, runs + n_runs);
+  c->opt = *opt;
+  if (c->opt.history_cap <= 0) c->opt.history_cap = 1;
+  c->stream = (hipStream_t)hip_stream;
+  c->ws = (uint8_t*)d_workspace;
+  c->ws_bytes = ws_bytes;
+  c->fast = opt->precision == PIC_FP32_FAST;
+  if (c->fast)
+    carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->opt.history_cap, c, &c->sf);
+  else
+    carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->opt.history_cap, c, &c->sd);
+
+  // CG work-groups: as many as can be co-resident, split over runs by cells
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+    delete c;
+    return PIC_E_HIP;
+  }
+  int maxb = pic_field_solve_max_blocks(n_cu);
+  if (maxb < n_runs) {
+    delete c;
+    return PIC_E_HIP;
+  }
+  maxb = std::min(maxb, kMaxCgBlocks);
+  if (opt->cg_blocks > 0) maxb = std::max(n_runs, std::min(maxb, (int)opt->cg_blocks));
+  long long want = 0;
+  for (int r = 0; r < n_runs; ++r) want += ((long long)runs[r].nx * runs[r].ny + 255) / 256;
+  const int total = (int)std::min<long long>(maxb, std::max<long long>(want, n_runs));
+  c->hruns.resize(n_runs);
+  int blk = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    const pic_run_desc& d = runs[r];
+    DevRun& h = c->hruns[r];
+    memset(&h, 0, sizeof h);
+    h.nx = d.nx;
+    h.ny = d.ny;
+    h.order = d.shape_order;
+    h.nspecies = d.n_species;
+    h.ntx = c->tl.ntx[r];
+    h.nty = c->tl.nty[r];
+    h.tile0 = c->tl.tile0[r];
+    h.cell0 = c->tl.cell0[r];
+    h.dx = d.dx;
+    h.dy = d.dy;
+    h.dt = d.cfl * d.dx;
+    h.theta = d.theta;
+    h.cg_rtol = d.cg_rtol;
+    h.cg_maxit = d.cg_maxit;
+    for (int s = 0; s < d.n_species; ++s) {
+      h.q[s] = d.species[s].q;
+      h.m[s] = d.species[s].m;
+    }
+    const long long cells = (long long)d.nx * d.ny;
+    long long nb = (long long)((double)total * cells / (double)c->tl.n_cells);
+    nb = std::max<long long>(1, std::min<long long>(nb, (cells + 255) / 256));
+    const int left = total - blk - (n_runs - 1 - r);
+    nb = std::min<long long>(nb, left);
+    if (r == n_runs - 1) nb = std::max<long long>(1, std::min<long long>((cells + 255) / 256, left));
+    h.cg_blk_lo = blk;
+    h.cg_blk_hi = blk + (int)nb;
+    blk += (int)nb;
+  }
+  c->fa.n_blocks = blk;
+  std::vector<int> tile_run(c->tl.n_tiles);
+  for (int r = 0; r < n_runs; ++r)
+    for (int t = 0; t < c->tl.ntx[r] * c->tl.nty[r]; ++t) tile_run[c->tl.tile0[r] + t] = r;
+
+  hipStream_t S = c->stream;
+  hipError_t e = hipMemsetAsync(c->ws, 0, c->plan.workspace_bytes, S);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_runs, c->hruns.data(), sizeof(DevRun) * n_runs, hipMemcpyHostToDevice, S);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c->d_tile_run, tile_run.data(), sizeof(int) * tile_run.size(),
+                       hipMemcpyHostToDevice, S);
+  if (e == hipSuccess) e = hipStreamSynchronize(S);
+  if (e != hipSuccess) {
+    delete c;
+    return PIC_E_HIP;
+  }
+  *out = c;
+  return PIC_OK;
+}
+
+int32_t pic_load_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n, const int32_t* ix,
+                           const int32_t* iy, const double* fx, const double* fy, const double* ux,
+                           const double* uy, const double* uz) {
+  if (!c) return PIC_E_INVAL;
+  if (run < 0 || run >= (int)c->runs.size() || species < 0 ||
+      species >= c->runs[run].n_species || n < 0 || (n > 0 && (!ix || !iy || !fx || !fy || !ux || !uy || !uz)))
+    return fail(c, PIC_E_INVAL, "bad run/species/arguments");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "load during a split step");
+  return c->fast ? load_impl<float>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz)
+                 : load_impl<double>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz);
+}
+
+int32_t pic_read_particles(pic_ctx* c, int32_t run, int32_t species, int64_t cap, int32_t* ix,
+                           int32_t* iy, double* fx, double* fy, double* ux, double* uy,
+                           double* uz, int64_t* n_out) {
+  if (!c || !n_out) return PIC_E_INVAL;
+  if (run < 0 || run >= (int)c->runs.size() || species < 0 || species >= c->runs[run].n_species)
+    return fail(c, PIC_E_INVAL, "bad run/species");
+  return c->fast ? read_impl<float>(c, run, species, cap, ix, iy, fx, fy, ux, uy, uz, n_out)
+                 : read_impl<double>(c, run, species, cap, ix, iy, fx, fy, ux, uy, uz, n_out);
+}
+
+int32_t pic_get_field(pic_ctx* c, int32_t run, int32_t id, double* host) {
+  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_RHO)
+    return fail(c, PIC_E_INVAL, "bad run/field/pointer");
+  const long long n = (long long)c->runs[run].nx * c->runs[run].ny;
+  const double* src;
+  if (id == PIC_RHO) {
+    int rc = c->fast ? rho_impl<float>(c, run) : rho_impl<double>(c, run);
+    if (rc) return rc;
+    src = c->d_rho;
+  } else {
+    src = field_ptr(c, id) + c->tl.cell0[run];
+  }
+  HIPCHK(c, hipMemcpyAsync(host, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_set_field(pic_ctx* c, int32_t run, int32_t id, const double* host) {
+  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_JZ)
+    return fail(c, PIC_E_INVAL, "bad run/field/pointer");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "set_field during a split step");
+  const long long n = (long long)c->runs[run].nx * c->runs[run].ny;
+  const long long o = c->tl.cell0[run];
+  HIPCHK(c, hipMemcpyAsync(field_ptr(c, id) + o, host, n * sizeof(double), hipMemcpyHostToDevice,
+                           c->stream));
+  if (c->fast && id <= PIC_BZ) {
+    std::vector<float> h(n);
+    for (long long k = 0; k < n; ++k) h[k] = (float)host[k];
+    HIPCHK(c, hipMemcpyAsync(c->fa.Ef[id] + o, h.data(), n * sizeof(float), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_gather_push(pic_ctx* c) {
+  if (!c) return PIC_E_INVAL;
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "gather_push needs a completed step");
+  int rc = c->fast ? do_gather_push<float>(c) : do_gather_push<double>(c);
+  if (rc == PIC_OK) c->phase = 1;
+  return rc;
+}
+
+int32_t pic_deposit(pic_ctx* c) {
+  if (!c) return PIC_E_INVAL;
+  if (c->phase != 1) return fail(c, PIC_E_STATE, "deposit must follow gather_push");
+  int rc = c->fast ? do_deposit<float>(c) : do_deposit<double>(c);
+  if (rc == PIC_OK) c->phase = 2;
+  return rc;
+}
+
+int32_t pic_field_solve(pic_ctx* c, pic_solve_stats* stats) {
+  if (!c) return PIC_E_INVAL;
+  if (c->phase != 2) return fail(c, PIC_E_STATE, "field_solve must follow deposit");
+  int rc = launch_field(c, diag_step(c) ? 1 : 0);
+  if (rc) return rc;
+  c->phase = 0;
+  c->step += 1;
+  rc = check_err(c);
+  if (rc) return rc;
+  return read_stats(c, stats);
+}
+
+int32_t pic_step(pic_ctx* c, int32_t nsteps, pic_solve_stats* last) {
+  if (!c || nsteps < 0) return PIC_E_INVAL;
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "pic_step during a split step");
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = c->fast ? do_step<float>(c) : do_step<double>(c);
+    if (rc) return rc;
+  }
+  int rc = check_err(c);
+  if (rc) return rc;
+  return read_stats(c, last);
+}
+
+int32_t pic_history(pic_ctx* c, int32_t run, pic_diag_out* out, int32_t cap, int32_t* n_out) {
+  if (!c || !n_out || run < 0 || run >= (int)c->runs.size()) return PIC_E_INVAL;
+  const int hc = c->opt.history_cap;
+  const long long have = std::min<long long>(c->diag_count, hc);
+  std::vector<double> h((size_t)hc * PIC_REC_WORDS);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_history + (size_t)run * hc * PIC_REC_WORDS,
+                           h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  const long long first = c->diag_count - have;
+  int n = 0;
+  for (long long k = first; k < c->diag_count && n < cap; ++k, ++n) {
+    const double* r = h.data() + (size_t)(k % hc) * PIC_REC_WORDS;
+    pic_diag_out& o = out[n];
+    memset(&o, 0, sizeof o);
+    o.step = (int64_t)r[0];
+    o.t = r[1];
+    o.W_E = r[2];
+    o.W_B = r[3];
+    o.W_K_minus = r[4];
+    o.W_K_plus = r[5];
+    for (int q = 0; q < 3; ++q) {
+      o.cg_iters[q] = (int)r[6 + q];
+      o.cg_relres[q] = r[9 + q];
+    }
+  }
+  *n_out = n;
+  return PIC_OK;
+}
+
+int32_t pic_diag(pic_ctx* c, int32_t run, pic_diag_out* out, double* gauss, double* divb) {
+  if (!c || run < 0 || run >= (int)c->runs.size()) return PIC_E_INVAL;
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "diag during a split step");
+  int rc = PIC_OK;
+  if (out) {
+    memset(out, 0, sizeof *out);
+    if (c->diag_count > 0) {
+      int n = 0;
+      std::vector<pic_diag_out> all(std::min<long long>(c->diag_count, c->opt.history_cap));
+      rc = pic_history(c, run, all.data(), (int)all.size(), &n);
+      if (rc) return rc;
+      if (n > 0) *out = all[n - 1];
+    } else {
+      out->step = -1;
+    }
+    const Tiling& tl = c->tl;
+    const int nt = tl.ntx[run] * tl.nty[run];
+    for (int s = 0; s < c->runs[run].n_species; ++s) {
+      std::vector<int> cnt(nt);
+      int* src = c->fast ? c->sf.cnt[s] : c->sd.cnt[s];
+      HIPCHK(c, hipMemcpyAsync(cnt.data(), src + tl.tile0[run], nt * sizeof(int),
+                               hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      long long tot = 0;
+      for (int v : cnt) tot += v;
+      out->n_particles[s] = tot;
+    }
+  }
+  if (gauss || divb) {
+    rc = c->fast ? rho_impl<float>(c, run) : rho_impl<double>(c, run);
+    if (rc) return rc;
+    const double* E[3] = {c->fa.E[0], c->fa.E[1], c->fa.E[2]};
+    const double* B[3] = {c->fa.B[0], c->fa.B[1], c->fa.B[2]};
+    hipError_t e = pic_launch_divergences(c->d_runs, run,
+                                          (long long)c->runs[run].nx * c->runs[run].ny, E, B,
+                                          c->d_rho, c->d_divpart, kDivBlocks, c->stream);
+    if (e != hipSuccess) return fail(c, PIC_E_HIP, hipGetErrorString(e));
+    std::vector<double> h(kDivBlocks * 2);
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->d_divpart, h.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double g = 0, d = 0;
+    for (int b = 0; b < kDivBlocks; ++b) {
+      if (h[2 * b] > g || std::isnan(h[2 * b])) g = h[2 * b];
+      if (h[2 * b + 1] > d || std::isnan(h[2 * b + 1])) d = h[2 * b + 1];
+    }
+    if (gauss) *gauss = g;
+    if (divb) *divb = d;
+    if (std::isnan(g) || std::isnan(d)) return fail(c, PIC_E_NAN, "non-finite field divergence");
+  }
+  if (out && (!std::isfinite(out->W_E) || !std::isfinite(out->W_B) ||
+              !std::isfinite(out->W_K_plus)))
+    return fail(c, PIC_E_NAN, "non-finite energy");
+  return rc;
+}
+
+int32_t pic_timing(pic_ctx* c, int32_t on) {
+  if (!c) return PIC_E_INVAL;
+  t_resolve(c);
+  c->timing = on != 0;
+  for (int k = 0; k < kTimingClasses; ++k) {
+    c->t_ms[k] = 0;
+    c->t_n[k] = 0;
+  }
+  return PIC_OK;
+}
+
+int32_t pic_get_timing(pic_ctx* c, pic_timing_out* out) {
+  if (!c || !out) return PIC_E_INVAL;
+  t_resolve(c);
+  for (int k = 0; k < kTimingClasses; ++k) {
+    out->ms[k] = c->t_ms[k];
+    out->launches[k] = c->t_n[k];
+  }
+  return PIC_OK;
+}
+
+int32_t pic_sync(pic_ctx* c) {
+  if (!c) return PIC_E_INVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return check_err(c);
+}
+
+int32_t pic_destroy(pic_ctx* c) {
+  if (!c) return PIC_OK;
+  (void)hipStreamSynchronize(c->stream);
+  for (auto e : c->ev_pool) (void)hipEventDestroy(e);
+  delete c;
+  return PIC_OK;
+}
+
+const char* pic_last_error(const pic_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+const char* pic_status_str(int32_t s) {
+  switch (s) {
+    case PIC_OK: return "PIC_OK";
+    case PIC_E_INVAL: return "PIC_E_INVAL";
+    case PIC_E_NOMEM: return "PIC_E_NOMEM";
+    case PIC_E_HIP: return "PIC_E_HIP";
+    case PIC_E_NOCONV: return "PIC_E_NOCONV";
+    case PIC_E_CAPACITY: return "PIC_E_CAPACITY";
+    case PIC_E_NAN: return "PIC_E_NAN";
+    case PIC_E_STATE: return "PIC_E_STATE";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

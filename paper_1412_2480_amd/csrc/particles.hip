@@ -1,0 +1,728 @@
+// Particle loop of the implicit-FDTD PIC method of Ikeya & Matsumoto
+// (PASJ 2015): momentum-conserving gather with order-p B-spline shapes,
+// relativistic Boris push, move, and Esirkepov (2001) density-decomposition
+// deposit of J^{n+1/2} (Sec. 1 and Sec. 3 name these ingredients; Eq. (6)
+// puts J at the half step).
+//
+// Layout: particles are kept sorted by cell tile (TX x TY cells). One
+// work-group owns one tile: it stages the tile's E and B (+ guard nodes) in
+// LDS, pushes every particle of every species of the tile, accumulates the
+// current of the tile (+ guard nodes) in LDS, and writes that patch out whole.
+// A second pass sums the overlapping patches node by node in a fixed order
+// (no global atomics on J). Particles that leave their tile are appended to
+// the destination tile's inbox (slots reserved once per wavefront and
+// destination); the re-binning kernel then fills the holes they left.
+#include <math.h>
+
+#include <type_traits>
+
+#include "pic_dev.h"
+#include "pic_launch.h"
+
+namespace {
+
+constexpr int G = PIC_GUARD_LO;
+constexpr double kFourPi = 12.566370614359172953850573533118;
+
+enum { MODE_FUSED = PIC_MODE_FUSED, MODE_PUSH = PIC_MODE_PUSH, MODE_DEPOSIT = PIC_MODE_DEPOSIT,
+       MODE_CHARGE = 3 };
+
+// largest displacement per step, in cells: the Esirkepov window assumes a
+// particle crosses at most one cell boundary per axis per step
+template <typename R> __device__ __forceinline__ R max_disp();
+template <> __device__ __forceinline__ float max_disp<float>() { return 1.0f - 0x1p-20f; }
+template <> __device__ __forceinline__ double max_disp<double>() { return 1.0 - 0x1p-40; }
+
+// B-spline weights of degree P for a point at offset t (in cells) from node 0
+// of the component's grid, t in [-1/2, 1). Returns the first node index
+// (relative to node 0) and the P+1 non-trivial weights.
+template <int P, typename R>
+__device__ __forceinline__ int bspline_weights(R t, R (&w)[P + 1]) {
+  if constexpr (P == 1) {
+    const int fl = t < R(0) ? -1 : 0;
+    const R d = t - R(fl);
+    w[0] = R(1) - d;
+    w[1] = d;
+    return fl;
+  } else if constexpr (P == 2) {
+    const int r = t >= R(0.5) ? 1 : 0;     // nearest node
+    const R d = t - R(r);                  // in [-1/2, 1/2)
+    const R a = R(0.5) - d, b = R(0.5) + d;
+    w[0] = R(0.5) * a * a;
+    w[1] = R(0.75) - d * d;
+    w[2] = R(0.5) * b * b;
+    return r - 1;
+  } else {
+    const int fl = t < R(0) ? -1 : 0;
+    const R d = t - R(fl);                 // in [0, 1)
+    const R d2 = d * d, d3 = d2 * d, e = R(1) - d;
+    const R sixth = R(1) / R(6);
+    w[0] = e * e * e * sixth;
+    w[1] = (R(4) - R(6) * d2 + R(3) * d3) * sixth;
+    w[2] = (R(1) + R(3) * d + R(3) * d2 - R(3) * d3) * sixth;
+    w[3] = d3 * sixth;
+    return fl - 1;
+  }
+}
+
+// sum_{jj,ii} F(x0+ii, y0+jj) wx[ii] wy[jj] from an LDS plane with pitch PW
+template <int P, typename R, typename F>
+__device__ __forceinline__ R interp(const F* f, int PW, int x0, int y0, const R (&wx)[P + 1],
+                                    const R (&wy)[P + 1]) {
+  R s = R(0);
+#pragma unroll
+  for (int jj = 0; jj <= P; ++jj) {
+    const F* row = f + (y0 + jj) * PW + x0;
+    R acc = R(0);
+#pragma unroll
+    for (int ii = 0; ii <= P; ++ii) acc += R(row[ii]) * wx[ii];
+    s += acc * wy[jj];
+  }
+  return s;
+}
+
+// advance an in-cell offset by a displacement of at most one cell; returns
+// the cell change; an offset that rounds to exactly 1 moves to the next cell
+template <typename R>
+__device__ __forceinline__ int advance(R& f, R disp) {
+  R g = f + disp;
+  int d = 0;
+  if (g >= R(1)) {
+    g -= R(1);
+    d = 1;
+  } else if (g < R(0)) {
+    g += R(1);
+    d = -1;
+  }
+  if (g >= R(1)) {
+    g -= R(1);
+    d += 1;
+  }
+  f = g;
+  return d;
+}
+
+// node shapes of the Esirkepov window (P + 3 nodes starting one node before
+// the old support): old weights sit at window index 1, new weights at
+// index a1 = dc + first1 - first0 + 1, which is 0, 1 or 2
+template <int P, typename R>
+__device__ __forceinline__ void window_shapes(const R (&w0)[P + 1], const R (&w1)[P + 1], int a1,
+                                              R (&S0)[P + 3], R (&DS)[P + 3]) {
+#pragma unroll
+  for (int a = 0; a < P + 3; ++a) {
+    const R s0 = (a >= 1 && a - 1 <= P) ? w0[a - 1 < 0 ? 0 : (a - 1 > P ? P : a - 1)] : R(0);
+    const R v0 = (a <= P) ? w1[a > P ? P : a] : R(0);
+    const R v1 = (a >= 1 && a - 1 <= P) ? w1[a - 1 < 0 ? 0 : (a - 1 > P ? P : a - 1)] : R(0);
+    const R v2 = (a >= 2 && a - 2 <= P) ? w1[a - 2 < 0 ? 0 : (a - 2 > P ? P : a - 2)] : R(0);
+    const R s1 = a1 == 0 ? v0 : (a1 == 1 ? v1 : v2);
+    S0[a] = s0;
+    DS[a] = s1 - s0;
+  }
+}
+
+// reserve slots in counters[key] for every lane with want set, one atomic per
+// wavefront and distinct key; returns the lane's slot (or -1)
+__device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
+  const int lane = __lane_id();
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  int slot = -1;
+  bool pending = want;
+  while (true) {
+    const unsigned long long m = __ballot(pending);
+    if (m == 0ull) break;
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    const int k = __shfl(key, leader);
+    const bool mine = pending && key == k;
+    const unsigned long long mm = __ballot(mine);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[k], __popcll(mm));
+    base = __shfl(base, leader);
+    if (mine) {
+      slot = base + __popcll(mm & below);
+      pending = false;
+    }
+  }
+  return slot;
+}
+
+template <typename R, typename F, int P, int MODE>
+__device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
+                          int x0, int y0, int tw, int th, const F* sF, R* sJ, int* s_holes,
+                          int diag, double (&wk)[PIC_MAXS][2]) {
+  constexpr int W = P + 3;
+  const int PW = st.PW, PH = st.PH;
+  const int plane = PW * PH;
+  const R dt = R(run.dt);
+  const R dtdx = R(run.dt / run.dx), dtdy = R(run.dt / run.dy);
+  const R lim = max_disp<R>();
+
+  for (int s = 0; s < run.nspecies; ++s) {
+    const int n = st.cnt[s][tile];
+    const long long base = (long long)tile * st.tile_slots[s];
+    const R qdt_2m = R(run.q[s] * run.dt / (2.0 * run.m[s]));
+    const R cjx = R(-run.q[s] / (run.dy * run.dt));
+    const R cjy = R(-run.q[s] / (run.dx * run.dt));
+    const R cjz = R(run.q[s] / (run.dx * run.dy));
+    const double mass = run.m[s];
+    for (int k0 = 0; k0 < n; k0 += blockDim.x) {
+      const int k = k0 + threadIdx.x;
+      const bool active = k < n;
+      bool leave = false;
+      int dest = 0;
+      int gcell = 0;
+      R fx1 = R(0), fy1 = R(0), ux = R(0), uy = R(0), uz = R(0);
+      int pid = 0;
+      if (active) {
+        const long long idx = base + k;
+        int cell0, dcx = 0, dcy = 0;
+        R fx, fy;
+        if constexpr (MODE == MODE_DEPOSIT) {
+          cell0 = st.old_cell[s][idx];
+          fx = st.old_ox[s][idx];
+          fy = st.old_oy[s][idx];
+          const int c1 = st.cell[s][idx];
+          fx1 = st.ox[s][idx];
+          fy1 = st.oy[s][idx];
+          ux = st.ux[s][idx];
+          uy = st.uy[s][idx];
+          uz = st.uz[s][idx];
+          dcx = pic_cell_ix(c1) - pic_cell_ix(cell0);
+          dcy = pic_cell_iy(c1) - pic_cell_iy(cell0);
+          if (dcx > 1) dcx -= run.nx;
+          if (dcx < -1) dcx += run.nx;
+          if (dcy > 1) dcy -= run.ny;
+          if (dcy < -1) dcy += run.ny;
+        } else {
+          cell0 = st.cell[s][idx];
+          fx = st.ox[s][idx];
+          fy = st.oy[s][idx];
+          ux = st.ux[s][idx];
+          uy = st.uy[s][idx];
+          uz = st.uz[s][idx];
+        }
+        const int lx = pic_cell_ix(cell0) - x0;
+        const int ly = pic_cell_iy(cell0) - y0;
+        R w0x[P + 1], w0y[P + 1];
+        const int f0x = bspline_weights<P, R>(fx, w0x);
+        const int f0y = bspline_weights<P, R>(fy, w0y);
+
+        if constexpr (MODE == MODE_CHARGE) {
+          const R cq = R(run.q[s] / (run.dx * run.dy));
+          const int ax0 = lx + f0x + G, ay0 = ly + f0y + G;
+#pragma unroll
+          for (int b = 0; b <= P; ++b)
+#pragma unroll
+            for (int a = 0; a <= P; ++a)
+              atomicAdd(&sJ[(ay0 + b) * PW + ax0 + a], cq * w0x[a] * w0y[b]);
+        }
+
+        if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
+          // ---- gather (each component from its own staggered points)
+          R whx[P + 1], why[P + 1];
+          const int fhx = bspline_weights<P, R>(fx - R(0.5), whx);
+          const int fhy = bspline_weights<P, R>(fy - R(0.5), why);
+          const int gx0 = lx + f0x + G, gy0 = ly + f0y + G;
+          const int gxh = lx + fhx + G, gyh = ly + fhy + G;
+          const R ex = interp<P, R, F>(sF + 0 * plane, PW, gxh, gy0, whx, w0y);
+          const R ey = interp<P, R, F>(sF + 1 * plane, PW, gx0, gyh, w0x, why);
+          const R ez = interp<P, R, F>(sF + 2 * plane, PW, gx0, gy0, w0x, w0y);
+          const R bx = interp<P, R, F>(sF + 3 * plane, PW, gx0, gyh, w0x, why);
+          const R by = interp<P, R, F>(sF + 4 * plane, PW, gxh, gy0, whx, w0y);
+          const R bz = interp<P, R, F>(sF + 5 * plane, PW, gxh, gyh, whx, why);
+          if (diag)
+            wk[s][0] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
+                                     (double)uz * uz) - 1.0);
+          // ---- relativistic Boris push u^{n-1/2} -> u^{n+1/2}
+          const R umx = ux + qdt_2m * ex, umy = uy + qdt_2m * ey, umz = uz + qdt_2m * ez;
+          const R gm = sqrt(R(1) + umx * umx + umy * umy + umz * umz);
+          const R tf = qdt_2m / gm;
+          const R tx_ = tf * bx, ty_ = tf * by, tz_ = tf * bz;
+          const R sf = R(2) / (R(1) + tx_ * tx_ + ty_ * ty_ + tz_ * tz_);
+          const R sx = sf * tx_, sy = sf * ty_, sz = sf * tz_;
+          const R upx = umx + (umy * tz_ - umz * ty_);
+          const R upy = umy + (umz * tx_ - umx * tz_);
+          const R upz = umz + (umx * ty_ - umy * tx_);
+          ux = umx + (upy * sz - upz * sy) + qdt_2m * ex;
+          uy = umy + (upz * sx - upx * sz) + qdt_2m * ey;
+          uz = umz + (upx * sy - upy * sx) + qdt_2m * ez;
+          // ---- move x^n -> x^{n+1}
+          const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+          if (diag) wk[s][1] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
+                                              (double)uz * uz) - 1.0);
+          R dx_ = ux * ig * dtdx, dy_ = uy * ig * dtdy;
+          dx_ = dx_ > lim ? lim : (dx_ < -lim ? -lim : dx_);
+          dy_ = dy_ > lim ? lim : (dy_ < -lim ? -lim : dy_);
+          fx1 = fx;
+          fy1 = fy;
+          dcx = advance(fx1, dx_);
+          dcy = advance(fy1, dy_);
+        }
+
+        if constexpr (MODE == MODE_PUSH) {
+          st.old_cell[s][idx] = cell0;
+          st.old_ox[s][idx] = fx;
+          st.old_oy[s][idx] = fy;
+          const int ix1 = pic_wrap(pic_cell_ix(cell0) + dcx, run.nx);
+          const int iy1 = pic_wrap(pic_cell_iy(cell0) + dcy, run.ny);
+          st.cell[s][idx] = pic_cell_pack(ix1, iy1);
+          st.ox[s][idx] = fx1;
+          st.oy[s][idx] = fy1;
+          st.ux[s][idx] = ux;
+          st.uy[s][idx] = uy;
+          st.uz[s][idx] = uz;
+        }
+
+        if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
+          // ---- Esirkepov deposit of J^{n+1/2} into the LDS patch
+          R w1x[P + 1], w1y[P + 1];
+          const int f1x = bspline_weights<P, R>(fx1, w1x);
+          const int f1y = bspline_weights<P, R>(fy1, w1y);
+          int a1x = dcx + f1x - f0x + 1, a1y = dcy + f1y - f0y + 1;
+          a1x = a1x < 0 ? 0 : (a1x > 2 ? 2 : a1x);
+          a1y = a1y < 0 ? 0 : (a1y > 2 ? 2 : a1y);
+          R S0x[W], DSx[W], S0y[W], DSy[W];
+          window_shapes<P, R>(w0x, w1x, a1x, S0x, DSx);
+          window_shapes<P, R>(w0y, w1y, a1y, S0y, DSy);
+          const int ax0 = lx + f0x - 1 + G, ay0 = ly + f0y - 1 + G;
+          const R vz = uz / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+          R* jx = sJ;
+          R* jy = sJ + plane;
+          R* jz = sJ + 2 * plane;
+#pragma unroll
+          for (int b = 0; b < W; ++b) {
+            const R wy = S0y[b] + R(0.5) * DSy[b];
+            R acc = R(0);
+#pragma unroll
+            for (int a = 0; a < W - 1; ++a) {
+              acc += DSx[a] * wy;
+              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], cjx * acc);
+            }
+          }
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            const R wx = S0x[a] + R(0.5) * DSx[a];
+            R acc = R(0);
+#pragma unroll
+            for (int b = 0; b < W - 1; ++b) {
+              acc += DSy[b] * wx;
+              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], cjy * acc);
+            }
+          }
+          const R czv = cjz * vz;
+#pragma unroll
+          for (int b = 0; b < W; ++b)
+#pragma unroll
+            for (int a = 0; a < W; ++a) {
+              const R wz = S0x[a] * S0y[b] + R(0.5) * DSx[a] * S0y[b] +
+                           R(0.5) * S0x[a] * DSy[b] + DSx[a] * DSy[b] * (R(1) / R(3));
+              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], czv * wz);
+            }
+
+          // ---- tile membership after the move
+          const int lx1 = lx + dcx, ly1 = ly + dcy;
+          const int ix1 = pic_wrap(x0 + lx1, run.nx), iy1 = pic_wrap(y0 + ly1, run.ny);
+          gcell = pic_cell_pack(ix1, iy1);
+          int dest_t = tile;
+          if (lx1 < 0 || lx1 >= tw || ly1 < 0 || ly1 >= th) {
+            int ttx = tx + (lx1 < 0 ? -1 : (lx1 >= tw ? 1 : 0));
+            int tty = ty + (ly1 < 0 ? -1 : (ly1 >= th ? 1 : 0));
+            ttx = ttx < 0 ? run.ntx - 1 : (ttx >= run.ntx ? 0 : ttx);
+            tty = tty < 0 ? run.nty - 1 : (tty >= run.nty ? 0 : tty);
+            dest_t = run.tile0 + tty * run.ntx + ttx;
+          }
+          if (dest_t == tile) {
+            if constexpr (MODE == MODE_FUSED) {
+              st.cell[s][idx] = gcell;
+              st.ox[s][idx] = fx1;
+              st.oy[s][idx] = fy1;
+              st.ux[s][idx] = ux;
+              st.uy[s][idx] = uy;
+              st.uz[s][idx] = uz;
+            }
+          } else {
+            leave = true;
+            dest = dest_t;
+            pid = st.id[s][idx];
+            st.cell[s][idx] = -1;   // hole marker for the re-binning pass
+          }
+        }
+      }
+      if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
+        const int slot = wave_reserve(leave, dest, st.in_cnt[s]);
+        if (leave) {
+          if (slot < st.ex_slots) {
+            const long long o = (long long)dest * st.ex_slots + slot;
+            st.in_cell[s][o] = gcell;
+            st.in_ox[s][o] = fx1;
+            st.in_oy[s][o] = fy1;
+            st.in_ux[s][o] = ux;
+            st.in_uy[s][o] = uy;
+            st.in_uz[s][o] = uz;
+            st.in_id[s][o] = pid;
+          } else {
+            atomicOr(st.err, PIC_ERRBIT_INBOX);
+          }
+          const int h = atomicAdd(&s_holes[s], 1);
+          if (h < st.ex_slots)
+            st.hole[s][(long long)tile * st.ex_slots + h] = k;
+          else
+            atomicOr(st.err, PIC_ERRBIT_HOLES);
+        }
+      }
+    }
+  }
+}
+
+template <typename R, typename F, int MODE>
+__global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
+  // XCD-aware order: consecutive tiles go to the same XCD
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= st.n_tiles) return;
+  const int ri = st.tile_run[tile];
+  const DevRun& run = st.runs[ri];
+  const int lt = tile - run.tile0;
+  const int tx = lt % run.ntx, ty = lt / run.ntx;
+  const int x0 = tx * st.TX, y0 = ty * st.TY;
+  const int tw = pic_tile_width(tx, st.TX, run.ntx, run.nx);
+  const int th = pic_tile_width(ty, st.TY, run.nty, run.ny);
+  const int PW = st.PW, PH = st.PH, plane = PW * PH;
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  F* sF = reinterpret_cast<F*>(smem_raw);
+  const size_t fbytes = (MODE == MODE_FUSED || MODE == MODE_PUSH) ? 6 * plane * sizeof(F) : 0;
+  R* sJ = reinterpret_cast<R*>(smem_raw + fbytes);
+  const int nj = (MODE == MODE_PUSH) ? 0 : (MODE == MODE_CHARGE ? 1 : 3);
+  __shared__ int s_holes[PIC_MAXS];
+  __shared__ double s_red[4][PIC_MAXS * 2];
+
+  if (threadIdx.x < PIC_MAXS) s_holes[threadIdx.x] = 0;
+  if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
+    for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+      const int ly = e / PW - G, lx = e % PW - G;
+      const bool in = lx <= tw + PIC_GUARD_HI - 1 && ly <= th + PIC_GUARD_HI - 1;
+      const long long g = run.cell0 + (long long)pic_wrap(y0 + ly, run.ny) * run.nx +
+                          pic_wrap(x0 + lx, run.nx);
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        F v = F(0);
+        if (in) {
+          if constexpr (sizeof(F) == 4)
+            v = st.Ef[c][g];
+          else
+            v = (c < 3) ? st.E[c][g] : st.B[c - 3][g];
+        }
+        sF[c * plane + e] = v;
+      }
+    }
+  }
+  for (int e = threadIdx.x; e < nj * plane; e += blockDim.x) sJ[e] = R(0);
+  __syncthreads();
+
+  double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
+  switch (run.order) {
+    case 1:
+      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      break;
+    case 2:
+      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      break;
+    default:
+      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      break;
+  }
+  __syncthreads();
+
+  if constexpr (MODE != MODE_PUSH) {
+    for (int c = 0; c < nj; ++c) {
+      R* out = st.patch[c] + (size_t)tile * plane;
+      for (int e = threadIdx.x; e < plane; e += blockDim.x) out[e] = sJ[c * plane + e];
+    }
+  }
+  if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
+    if (threadIdx.x < run.nspecies) st.hole_cnt[threadIdx.x][tile] = s_holes[threadIdx.x];
+  }
+  if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
+    if (diag) {
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+      for (int s = 0; s < PIC_MAXS; ++s)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          double v = wk[s][h];
+          for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+          if (lane == 0) s_red[wave][s * 2 + h] = v;
+        }
+      __syncthreads();
+      if (threadIdx.x < PIC_MAXS * 2) {
+        double v = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += s_red[w][threadIdx.x];
+        st.wk_part[(size_t)tile * PIC_MAXS * 2 + threadIdx.x] = v;
+      }
+    }
+  }
+}
+
+// block-wide exclusive prefix of a predicate (blockDim multiple of 64, <= 1024)
+__device__ __forceinline__ int block_prefix(bool pred, int* s_wave, int& total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const unsigned long long m = __ballot(pred);
+  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const int in_wave = __popcll(m & below);
+  if (lane == 0) s_wave[wave] = __popcll(m);
+  __syncthreads();
+  int off = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const int c = s_wave[w];
+    if (w < wave) off += c;
+    tot += c;
+  }
+  __syncthreads();
+  total = tot;
+  return off + in_wave;
+}
+
+// Re-binning: arrivals fill the holes left by departures; if more particles
+// left than arrived, live particles from the tail of the segment fill the
+// remaining holes below the new count.
+template <typename R>
+__global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= st.n_tiles) return;
+  const int s = blockIdx.y;
+  const int run_i = st.tile_run[tile];
+  if (s >= st.runs[run_i].nspecies) return;
+  __shared__ int s_wave[16];
+  const int ex = st.ex_slots;
+  const int cap = st.tile_slots[s];
+  const int C = st.cnt[s][tile];
+  int H = st.hole_cnt[s][tile];
+  int A = st.in_cnt[s][tile];
+  H = H > ex ? ex : H;
+  A = A > ex ? ex : A;
+  const int N = C - H + A;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    st.in_cnt[s][tile] = 0;
+    st.hole_cnt[s][tile] = 0;
+  }
+  if (N > cap) {
+    if (threadIdx.x == 0) {
+      atomicOr(st.err, PIC_ERRBIT_TILE);
+      st.cnt[s][tile] = C - H;   // state is no longer consistent; run is flagged
+    }
+    return;
+  }
+  int* holes = st.hole[s] + (long long)tile * ex;
+  int* scr = st.rb_scr[s] + (long long)tile * ex;
+  const long long base = (long long)tile * cap;
+  // phase 1: stable in-place compaction of holes with index < N
+  int h_low = 0;
+  for (int c0 = 0; c0 < H; c0 += blockDim.x) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < H ? holes[i] : 0x7fffffff;
+    int tot;
+    const int pos = block_prefix(i < H && v < N, s_wave, tot);
+    if (i < H && v < N) holes[h_low + pos] = v;
+    h_low += tot;
+    __syncthreads();
+  }
+  // phase 2: live particles in the tail [N, C) (only when more left than arrived)
+  int L = 0;
+  if (H > A) {
+    for (int c0 = N; c0 < C; c0 += blockDim.x) {
+      const int i = c0 + threadIdx.x;
+      const bool live = i < C && st.cell[s][base + i] != -1;
+      int tot;
+      const int pos = block_prefix(live, s_wave, tot);
+      if (live) scr[L + pos] = i;
+      L += tot;
+    }
+    __syncthreads();
+  }
+  // phase 3: move sources (inbox, then tail) into targets (low holes, then append)
+  const int n_targets = h_low + (A > H ? A - H : 0);
+  for (int k = threadIdx.x; k < n_targets; k += blockDim.x) {
+    const long long dst = base + (k < h_low ? holes[k] : C + (k - h_low));
+    if (k < A) {
+      const long long o = (long long)tile * ex + k;
+      st.cell[s][dst] = st.in_cell[s][o];
+      st.ox[s][dst] = st.in_ox[s][o];
+      st.oy[s][dst] = st.in_oy[s][o];
+      st.ux[s][dst] = st.in_ux[s][o];
+      st.uy[s][dst] = st.in_uy[s][o];
+      st.uz[s][dst] = st.in_uz[s][o];
+      st.id[s][dst] = st.in_id[s][o];
+    } else {
+      const long long src = base + scr[k - A];
+      st.cell[s][dst] = st.cell[s][src];
+      st.ox[s][dst] = st.ox[s][src];
+      st.oy[s][dst] = st.oy[s][src];
+      st.ux[s][dst] = st.ux[s][src];
+      st.uy[s][dst] = st.uy[s][src];
+      st.uz[s][dst] = st.uz[s][src];
+      st.id[s][dst] = st.id[s][src];
+    }
+  }
+  if (threadIdx.x == 0) st.cnt[s][tile] = N;
+}
+
+// Sum of the overlapping tile patches at every node, in a fixed tile order.
+template <typename R>
+__global__ void __launch_bounds__(256) k_current_sum(DevState<R> st, int ncomp, double* out0,
+                                                     int only_run) {
+  const int ri = only_run >= 0 ? only_run : blockIdx.y;
+  const DevRun& run = st.runs[ri];
+  const long long ncell = (long long)run.nx * run.ny;
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ncell) return;
+  const int i = (int)(k % run.nx), j = (int)(k / run.nx);
+  const int TX = st.TX, TY = st.TY, PW = st.PW, plane = PW * st.PH;
+  const int tx = pic_tile_of(i, TX, run.ntx), ty = pic_tile_of(j, TY, run.nty);
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int dy = -1; dy <= 1; ++dy) {
+    int t_y = ty + dy, oy;
+    if (t_y < 0) { t_y = run.nty - 1; oy = t_y * TY - run.ny; }
+    else if (t_y >= run.nty) { t_y = 0; oy = run.ny; }
+    else oy = t_y * TY;
+    const int hy = pic_tile_width(t_y, TY, run.nty, run.ny);
+    const int ly = j - oy;
+    if (ly < -G || ly > hy + PIC_GUARD_HI - 1) continue;
+    for (int dx = -1; dx <= 1; ++dx) {
+      int t_x = tx + dx, ox;
+      if (t_x < 0) { t_x = run.ntx - 1; ox = t_x * TX - run.nx; }
+      else if (t_x >= run.ntx) { t_x = 0; ox = run.nx; }
+      else ox = t_x * TX;
+      const int hx = pic_tile_width(t_x, TX, run.ntx, run.nx);
+      const int lx = i - ox;
+      if (lx < -G || lx > hx + PIC_GUARD_HI - 1) continue;
+      const size_t off = (size_t)(run.tile0 + t_y * run.ntx + t_x) * plane +
+                         (size_t)(ly + G) * PW + (lx + G);
+      for (int c = 0; c < ncomp; ++c) acc[c] += (double)st.patch[c][off];
+    }
+  }
+  const long long g = run.cell0 + k;
+  if (out0) {
+    out0[k] = acc[0];
+  } else {
+    for (int c = 0; c < ncomp; ++c) st.J[c][g] = acc[c];
+  }
+}
+
+__global__ void __launch_bounds__(256)
+k_divergences(const DevRun* runs, int ri, const double* ex, const double* ey,
+              const double* bx, const double* by, const double* rho, double* part) {
+  const DevRun& run = runs[ri];
+  const long long ncell = (long long)run.nx * run.ny;
+  double g = 0.0, d = 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
+       k += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(k % run.nx), j = (int)(k / run.nx);
+    const long long c0 = run.cell0;
+    const long long kk = c0 + k;
+    const long long xm = c0 + (long long)j * run.nx + pic_wrap(i - 1, run.nx);
+    const long long ym = c0 + (long long)pic_wrap(j - 1, run.ny) * run.nx + i;
+    const long long xp = c0 + (long long)j * run.nx + pic_wrap(i + 1, run.nx);
+    const long long yp = c0 + (long long)pic_wrap(j + 1, run.ny) * run.nx + i;
+    const double dive = (ex[kk] - ex[xm]) / run.dx + (ey[kk] - ey[ym]) / run.dy;
+    const double gr = fabs(dive - kFourPi * rho[k]);
+    const double divb = fabs((bx[xp] - bx[kk]) / run.dx + (by[yp] - by[kk]) / run.dy);
+    g = (gr > g || gr != gr) ? gr : g;
+    d = (divb > d || divb != divb) ? divb : d;
+  }
+  __shared__ double sg[256], sd[256];
+  sg[threadIdx.x] = g;
+  sd[threadIdx.x] = d;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      const double a = sg[threadIdx.x + off], b = sd[threadIdx.x + off];
+      if (a > sg[threadIdx.x] || a != a) sg[threadIdx.x] = a;
+      if (b > sd[threadIdx.x] || b != b) sd[threadIdx.x] = b;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[blockIdx.x * 2 + 0] = sg[0];
+    part[blockIdx.x * 2 + 1] = sd[0];
+  }
+}
+
+inline int grid_tiles(int n_tiles) { return ((n_tiles + 7) / 8) * 8; }
+
+}  // namespace
+
+template <typename R>
+size_t pic_particle_smem(const DevState<R>& st, int mode) {
+  using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
+  const size_t plane = (size_t)st.PW * st.PH;
+  size_t b = 0;
+  if (mode == MODE_FUSED || mode == MODE_PUSH) b += 6 * plane * sizeof(F);
+  if (mode == MODE_FUSED || mode == MODE_DEPOSIT) b += 3 * plane * sizeof(R);
+  if (mode == MODE_CHARGE) b += plane * sizeof(R);
+  return b;
+}
+
+template <typename R>
+hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int threads,
+                                hipStream_t s) {
+  using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
+  const size_t smem = pic_particle_smem(st, mode);
+  const dim3 grid(grid_tiles(st.n_tiles)), block(threads);
+  switch (mode) {
+    case MODE_FUSED:
+      k_particles<R, F, MODE_FUSED><<<grid, block, smem, s>>>(st, diag);
+      break;
+    case MODE_PUSH:
+      k_particles<R, F, MODE_PUSH><<<grid, block, smem, s>>>(st, diag);
+      break;
+    case MODE_DEPOSIT:
+      k_particles<R, F, MODE_DEPOSIT><<<grid, block, smem, s>>>(st, diag);
+      break;
+    default:
+      k_particles<R, F, MODE_CHARGE><<<grid, block, smem, s>>>(st, 0);
+      break;
+  }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s) {
+  k_rebin<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), 0, s>>>(st);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pic_launch_current_sum(const DevState<R>& st, long long max_cells, hipStream_t s) {
+  const dim3 grid((unsigned)((max_cells + 255) / 256), st.n_runs);
+  k_current_sum<R><<<grid, dim3(256), 0, s>>>(st, 3, nullptr, -1);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pic_launch_charge_sum(const DevState<R>& st, int run, long long ncell, double* rho,
+                                 hipStream_t s) {
+  k_current_sum<R><<<dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s>>>(st, 1, rho, run);
+  return hipGetLastError();
+}
+
+hipError_t pic_launch_divergences(const DevRun* runs, int run, long long ncell,
+                                  const double* const* E, const double* const* B,
+                                  const double* rho, double* partial_max, int n_blocks,
+                                  hipStream_t s) {
+  k_divergences<<<dim3(n_blocks), dim3(256), 0, s>>>(runs, run, E[0], E[1], B[0], B[1], rho,
+                                                     partial_max);
+  return hipGetLastError();
+}
+
+template size_t pic_particle_smem<float>(const DevState<float>&, int);
+template size_t pic_particle_smem<double>(const DevState<double>&, int);
+template hipError_t pic_launch_particles<float>(const DevState<float>&, int, int, int, hipStream_t);
+template hipError_t pic_launch_particles<double>(const DevState<double>&, int, int, int, hipStream_t);
+template hipError_t pic_launch_rebin<float>(const DevState<float>&, int, hipStream_t);
+template hipError_t pic_launch_rebin<double>(const DevState<double>&, int, hipStream_t);
+template hipError_t pic_launch_current_sum<float>(const DevState<float>&, long long, hipStream_t);
+template hipError_t pic_launch_current_sum<double>(const DevState<double>&, long long, hipStream_t);
+template hipError_t pic_launch_charge_sum<float>(const DevState<float>&, int, long long, double*, hipStream_t);
+template hipError_t pic_launch_charge_sum<double>(const DevState<double>&, int, long long, double*, hipStream_t);

@@ -1,0 +1,52 @@
+// Host-side launch interfaces between the C-ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pic_dev.h"
+
+#define PIC_REC_WORDS 16   // doubles per history record
+
+struct FieldArgs {
+  int n_runs, n_blocks, diag;
+  const DevRun* runs;
+  double* E[3];
+  double* B[3];
+  double* J[3];
+  float* Ef[6];            // FP32 copies (null pointers in the FP64 form)
+  double* x[3];            // dB
+  double* r[3];
+  double* p0[3];
+  double* p1[3];
+  double* q[3];
+  double* part;            // per-block partial sums
+  int* g_active;           // two active-component counters
+  double* stats;           // [run][9]: iters, relres, ||b||
+  const double* wk_part;   // [tile][species][2] kinetic partials
+  double* history;         // [run][hist_cap][PIC_REC_WORDS]
+  int hist_cap, hist_slot;
+  long long step;
+};
+
+int pic_field_solve_max_blocks(int n_cu);
+hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s);
+
+enum PicParticleMode { PIC_MODE_FUSED = 0, PIC_MODE_PUSH = 1, PIC_MODE_DEPOSIT = 2 };
+
+template <typename R>
+hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int threads,
+                                hipStream_t s);
+template <typename R>
+hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s);
+template <typename R>
+hipError_t pic_launch_current_sum(const DevState<R>& st, long long max_cells, hipStream_t s);
+template <typename R>
+hipError_t pic_launch_charge_sum(const DevState<R>& st, int run, long long ncell, double* rho,
+                                 hipStream_t s);
+template <typename R>
+size_t pic_particle_smem(const DevState<R>& st, int mode);
+
+hipError_t pic_launch_divergences(const DevRun* runs, int run, long long ncell,
+                                  const double* const* E, const double* const* B,
+                                  const double* rho, double* partial_max, int n_blocks,
+                                  hipStream_t s);

@@ -170,3 +170,40 @@ def macro_charge(gamma0, dx, dy, ppc):
     omega_pe = sqrt(4 pi n0 e^2 / (m gamma0)) is one and c = 1 (Sec. 4's
     normalisation, with n0 the lab density of one species)."""
     return gamma0 * dx * dy / (4.0 * math.pi * ppc)
+
+
+def pair_plasma_cells(nx, ny, ppc, gamma0, T, seed, direction=+1, chunk=1 << 20, workers=None):
+    """Same load as pair_plasma, returned as cell index + in-cell offset
+    (exact: offset = the uniform draw) and generated in parallel chunks.
+
+    Returns a list of two dicts with ix, iy (int32), fx, fy, ux, uy, uz (float64).
+    """
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    n = nx * ny * ppc
+    out = [dict(ix=np.empty(n, np.int32), iy=np.empty(n, np.int32), fx=np.empty(n),
+                fy=np.empty(n), ux=np.empty(n), uy=np.empty(n), uz=np.empty(n))
+           for _ in range(2)]
+    pos = Stream(seed, TAG_POS)
+
+    def work(k0):
+        k1 = min(n, k0 + chunk)
+        items = np.arange(k0, k1, dtype=np.int64)
+        cell = items // ppc
+        r0, r1 = pos.uniforms(items, 0)
+        for s in range(2):
+            o = out[s]
+            o["ix"][k0:k1] = cell % nx
+            o["iy"][k0:k1] = cell // nx
+            o["fx"][k0:k1] = r0
+            o["fy"][k0:k1] = r1
+            ux, uy, uz = drifting_mj(seed, s, k1 - k0, T, gamma0, direction, first_item=k0)
+            o["ux"][k0:k1] = ux
+            o["uy"][k0:k1] = uy
+            o["uz"][k0:k1] = uz
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(work, range(0, n, chunk)))
+    return out

@@ -1,0 +1,68 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every function that
+include/pic.h declares, and its host-only planner validates descriptors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1412_2480_amd as pic
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "pic.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(pic_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = pic.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(names) == sorted(pic.exported_symbols())
+
+
+def test_status_strings():
+    L = pic.lib()
+    assert L.pic_status_str(0) == b"PIC_OK"
+    assert L.pic_status_str(-5) == b"PIC_E_CAPACITY"
+
+
+def _run(**kw):
+    base = dict(nx=64, ny=64, dx=0.1, cfl=1.0, theta=0.6, order=1,
+                species=[(-1e-3, 1e-3, 16), (1e-3, 1e-3, 16)])
+    base.update(kw)
+    return pic.run_desc(base["nx"], base["ny"], base["dx"], base["cfl"], base["theta"],
+                        base["order"], base["species"])
+
+
+def test_plan_sizes_workspace():
+    info = pic.plan([_run()], pic.make_options("fp64"))
+    assert info.workspace_bytes > 64 * 64 * 8 * 24
+    assert info.n_tiles == 16 and info.tile_slots[0] >= 16 * 256
+    fast = pic.plan([_run()], pic.make_options("fp32"))
+    assert fast.workspace_bytes < info.workspace_bytes
+
+
+@pytest.mark.parametrize("bad", [dict(theta=0.4), dict(theta=1.2), dict(cfl=1.5),
+                                 dict(order=4), dict(nx=4), dict(dx=-1.0)])
+def test_plan_rejects_invalid(bad):
+    with pytest.raises(pic.PicError) as ei:
+        pic.plan([_run(**bad)], pic.make_options("fp64"))
+    assert ei.value.code == -1
+
+
+def test_plan_ragged_tiles():
+    # 34 = 16 + 18 (a 2-cell tail joins the last tile), 40 = 16 + 16 + 8
+    info = pic.plan([_run(nx=34, ny=40)], pic.make_options("fp64", tile=(16, 16)))
+    assert info.n_tiles == 2 * 3
+
+
+def test_plan_batched_runs():
+    runs = [_run(nx=128, ny=64), _run(nx=512, ny=128, order=3)]
+    info = pic.plan(runs, pic.make_options("fp32"))
+    assert info.n_tiles == 8 * 4 + 32 * 8
+    assert info.n_cells == 128 * 64 + 512 * 128
