@@ -18,6 +18,7 @@
 namespace {
 
 constexpr int kMaxCgBlocks = 4096;
+constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kTimingClasses = 8;
 
@@ -197,24 +198,28 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   float* Ef[6] = {};
   if (fast)
     for (int k = 0; k < 6; ++k) Ef[k] = b.take<float>(nc);
-  double *x[3], *r[3], *p0[3], *p1[3], *q[3];
+  double *x[3], *pp[3], *r0[3], *r1[3], *w0[3], *w1[3], *s0[3], *s1[3];
   for (int k = 0; k < 3; ++k) {
     x[k] = b.take<double>(nc);
-    r[k] = b.take<double>(nc);
-    p0[k] = b.take<double>(nc);
-    p1[k] = b.take<double>(nc);
-    q[k] = b.take<double>(nc);
+    pp[k] = b.take<double>(nc);
+    r0[k] = b.take<double>(nc);
+    r1[k] = b.take<double>(nc);
+    w0[k] = b.take<double>(nc);
+    w1[k] = b.take<double>(nc);
+    s0[k] = b.take<double>(nc);
+    s1[k] = b.take<double>(nc);
   }
-  double* part = b.take<double>((size_t)kMaxCgBlocks * 10);
-  int* g_active = b.take<int>(2);
+  double* part = b.take<double>((size_t)kMaxCgBlocks * 16);
+  int* g_active = b.take<int>(4);
+  unsigned* bar = b.take<unsigned>(64);
   double* stats = b.take<double>((size_t)n_runs * 9);
   double* history = b.take<double>((size_t)n_runs * hist_cap * PIC_REC_WORDS);
   int* err = b.take<int>(1);
   double* wk_part = b.take<double>((size_t)tl.n_tiles * PIC_MAXS * 2);
   double* rho = b.take<double>(tl.max_cells);
   double* divpart = b.take<double>((size_t)kDivBlocks * 2);
-  R* patch[3];
-  for (int k = 0; k < 3; ++k) patch[k] = b.take<R>((size_t)tl.n_tiles * plane);
+  double* patch[3];
+  for (int k = 0; k < 3; ++k) patch[k] = b.take<double>((size_t)tl.n_tiles * plane);
   DevState<R> s{};
   for (int sp = 0; sp < PIC_MAXS; ++sp) {
     const size_t slots = (size_t)tl.n_tiles * pl.tile_slots[sp];
@@ -279,14 +284,19 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     f.B[k] = B[k];
     f.J[k] = J[k];
     f.x[k] = x[k];
-    f.r[k] = r[k];
-    f.p0[k] = p0[k];
-    f.p1[k] = p1[k];
-    f.q[k] = q[k];
+    f.p[k] = pp[k];
+    f.r0[k] = r0[k];
+    f.r1[k] = r1[k];
+    f.w0[k] = w0[k];
+    f.w1[k] = w1[k];
+    f.s0[k] = s0[k];
+    f.s1[k] = s1[k];
   }
   for (int k = 0; k < 6; ++k) f.Ef[k] = Ef[k];
   f.part = part;
   f.g_active = g_active;
+  f.bar = bar;
+  f.err = err;
   f.stats = stats;
   f.wk_part = wk_part;
   f.history = history;
@@ -309,7 +319,7 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   const bool fast = o->precision == PIC_FP32_FAST;
   const size_t rsz = fast ? 4 : 8;
   const size_t plane = (size_t)(tl->TXA + 5) * (tl->TYA + 5);
-  const size_t smem = (6 + 3) * plane * rsz;
+  const size_t smem = plane * (6 * rsz + 3 * sizeof(double));
   if (smem > 64 * 1024) {
     *msg = "tile too large for LDS (fields + currents exceed 64 KiB)";
     return PIC_E_INVAL;
@@ -697,9 +707,13 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     return PIC_E_HIP;
   }
   maxb = std::min(maxb, kMaxCgBlocks);
-  if (opt->cg_blocks > 0) maxb = std::max(n_runs, std::min(maxb, (int)opt->cg_blocks));
+  // grid-barrier latency grows with the number of work-groups (about 30 ns
+  // each), so the default keeps the persistent grid small
+  const int cap = opt->cg_blocks > 0 ? opt->cg_blocks : kDefaultCgBlocks;
+  maxb = std::max(n_runs, std::min(maxb, cap));
   long long want = 0;
-  for (int r = 0; r < n_runs; ++r) want += ((long long)runs[r].nx * runs[r].ny + 255) / 256;
+  for (int r = 0; r < n_runs; ++r)
+    want += ((long long)runs[r].nx * runs[r].ny + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
   const int total = (int)std::min<long long>(maxb, std::max<long long>(want, n_runs));
   c->hruns.resize(n_runs);
   int blk = 0;
@@ -727,10 +741,11 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     }
     const long long cells = (long long)d.nx * d.ny;
     long long nb = (long long)((double)total * cells / (double)c->tl.n_cells);
-    nb = std::max<long long>(1, std::min<long long>(nb, (cells + 255) / 256));
+    const long long need = (cells + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
+    nb = std::max<long long>(1, std::min<long long>(nb, need));
     const int left = total - blk - (n_runs - 1 - r);
     nb = std::min<long long>(nb, left);
-    if (r == n_runs - 1) nb = std::max<long long>(1, std::min<long long>((cells + 255) / 256, left));
+    if (r == n_runs - 1) nb = std::max<long long>(1, std::min<long long>(need, left));
     h.cg_blk_lo = blk;
     h.cg_blk_hi = blk + (int)nb;
     blk += (int)nb;

@@ -5,29 +5,39 @@
 //   Eqs. (5)-(6): E^{n+1} = E^n + c dt curl(B^n + theta dB) - 4 pi dt J,
 //                 B^{n+1} = B^n + dB.
 //
-// One persistent, cooperatively launched kernel per step does all of it for
-// every run of the context: each run owns a contiguous range of work-groups,
-// the three B components are solved together (three independent CG
-// recurrences sharing one stencil sweep), and grid-wide barriers separate the
-// phases. All arithmetic is FP64; block reductions are deterministic and are
-// summed across a run's blocks in a fixed order, so every block of a run holds
+// One persistent kernel per step does all of it for every run of the
+// context: each run owns a contiguous range of work-groups, the three B
+// components are solved together (three independent CG recurrences sharing
+// one stencil sweep), and grid-wide barriers separate the phases. All
+// arithmetic is FP64; block reductions are deterministic and are summed
+// across a run's blocks in a fixed order, so every block of a run holds
 // bit-identical CG scalars.
 //
-// Phases: P0 right-hand side (+ field-energy partials) | per iteration
-// {A: p = r + beta p_old, q = A p, <p,q>} | {B: x += alpha p, r -= alpha q,
-// <r,r>} | E update | B update and FP32 field copy ("|" = grid barrier).
-#include <hip/hip_cooperative_groups.h>
+// The CG recurrence is the Chronopoulos-Gear form (Chronopoulos & Gear 1989):
+// it produces the iterates of CG in exact arithmetic but needs a single global
+// reduction, <r,r> and <Ar,r> together, per iteration. The residual at a
+// neighbour, r_{k+1} = r_k - alpha_k (w_k + beta_k s_{k-1}), is recomputed
+// from the previous iteration's buffers, so each iteration is one sweep and
+// one barrier:
+//   p_k = r_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}   (s = A p)
+//   x_{k+1} = x_k + alpha_k p_k, r_{k+1} = r_k - alpha_k s_k, w_{k+1} = A r_{k+1}
+//   gamma = <r,r>, delta = <w,r>, beta = gamma_{k+1}/gamma_k,
+//   alpha_{k+1} = gamma_{k+1} / (delta_{k+1} - beta_{k+1} gamma_{k+1}/alpha_k).
+//
+// Phases ("|" = grid barrier): P0 right-hand side and field-energy partials |
+// P1 w_0 = A r_0, <r,r>, <w,r> | iterations | E update | B update and FP32
+// field copy.
 #include <math.h>
 
 #include "pic_dev.h"
 #include "pic_launch.h"
 
-namespace cg = cooperative_groups;
-
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = PIC_CG_THREADS;
+constexpr int kWaves = kThreads / 64;
 constexpr double kFourPi = 12.566370614359172953850573533118;
+constexpr long kSpinLimit = 1L << 26;   // about seconds of polling: a stalled grid errors out
 
 struct Loc {
   long long base;   // cell0 of the run
@@ -36,6 +46,37 @@ struct Loc {
 
 __device__ __forceinline__ long long lidx(const Loc& L, int i, int j) {
   return L.base + (long long)pic_wrap(j, L.ny) * L.nx + pic_wrap(i, L.nx);
+}
+
+// Grid barrier: every block makes its writes visible (release fence), arrives
+// on one counter, and polls the generation word with relaxed loads; one
+// acquire fence follows. Relaxed polling avoids a cache invalidation per poll.
+// A block that polls for longer than kSpinLimit raises an error bit and
+// continues, so a grid that cannot complete still terminates.
+__device__ __forceinline__ void grid_barrier(unsigned* cnt, unsigned* gen, unsigned nb,
+                                             unsigned& my_gen, int* err) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned g = my_gen;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == nb - 1) {
+      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      long spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > kSpinLimit) {
+          atomicOr(err, PIC_ERRBIT_BARRIER);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    my_gen = g + 1;
+  }
+  __syncthreads();
 }
 
 // deterministic block reduction of N doubles; result valid in all threads
@@ -52,10 +93,24 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* sm) {
 #pragma unroll
   for (int k = 0; k < N; ++k) {
     double s = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) s += sm[w * N + k];
+    for (int w = 0; w < kWaves; ++w) s += sm[w * N + k];
     v[k] = s;
   }
   __syncthreads();
+}
+
+// Sum of the per-block partials (N values each, stride 8) of one run,
+// computed cooperatively by the block: thread t adds partials blo+t,
+// blo+t+kThreads, ... in order, then the fixed reduction tree of block_sum.
+template <int N>
+__device__ __forceinline__ void run_sum(const double* part, int blo, int bhi, double (&s)[N],
+                                        double* sm) {
+#pragma unroll
+  for (int k = 0; k < N; ++k) s[k] = 0.0;
+  for (int b = blo + (int)threadIdx.x; b < bhi; b += kThreads)
+#pragma unroll
+    for (int k = 0; k < N; ++k) s[k] += part[(size_t)b * 8 + k];
+  block_sum<N>(s, sm);
 }
 
 // curl with forward differences at the B points (Eq. (5)), F co-located with E
@@ -75,28 +130,9 @@ __device__ __forceinline__ double lap5(const Loc& L, const double* f, int i, int
          (f[lidx(L, i, j + 1)] - 2.0 * c + f[lidx(L, i, j - 1)]) * idy2;
 }
 
-// Sum of the per-block partials of one run, computed cooperatively by the
-// block: thread t adds partials blo+t, blo+t+256, ... in order, then a fixed
-// reduction tree combines the threads. Every block of the run obtains the
-// same bits.
-__device__ __forceinline__ void run_sum3(const double* part, int blo, int bhi, double s[3],
-                                         double* sm) {
-  double v[3] = {0.0, 0.0, 0.0};
-  for (int b = blo + (int)threadIdx.x; b < bhi; b += kThreads) {
-    v[0] += part[(size_t)b * 4 + 0];
-    v[1] += part[(size_t)b * 4 + 1];
-    v[2] += part[(size_t)b * 4 + 2];
-  }
-  block_sum<3>(v, sm);
-  s[0] = v[0];
-  s[1] = v[1];
-  s[2] = v[2];
-}
-
 __global__ void __launch_bounds__(kThreads)
 k_field_solve(FieldArgs a) {
-  cg::grid_group grid = cg::this_grid();
-  __shared__ double sm[(kThreads / 64) * 4];
+  __shared__ double sm[kWaves * 8];
   __shared__ int s_run;
 
   if (threadIdx.x == 0) {
@@ -108,7 +144,6 @@ k_field_solve(FieldArgs a) {
   const int run = s_run;
   const DevRun& R = a.runs[run];
   const int blo = R.cg_blk_lo, bhi = R.cg_blk_hi;
-  const bool mine = (int)blockIdx.x >= blo && (int)blockIdx.x < bhi;
   const int lb = blockIdx.x - blo, nb = bhi - blo;
   const bool leader = (int)blockIdx.x == blo;
   const Loc L{R.cell0, R.nx, R.ny};
@@ -119,83 +154,125 @@ k_field_solve(FieldArgs a) {
   const double ax = (th * dt) * (th * dt) * idx2, ay = (th * dt) * (th * dt) * idy2;
   const int stride = nb * kThreads;
   const int first = lb * kThreads + (int)threadIdx.x;
-  double* const part_pq = a.part;
-  double* const part_rr = a.part + (size_t)a.n_blocks * 4;
-  double* const part_en = a.part + (size_t)a.n_blocks * 8;
+  const unsigned nblocks = gridDim.x;
+  // the generation word persists across launches; it cannot move before every
+  // block has arrived at the first barrier, so all blocks read the same value
+  unsigned my_gen = __hip_atomic_load(a.bar + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // per-block partial sums, two halves of [block][8] used alternately
+  double* const part0 = a.part;
+  double* const part1 = a.part + (size_t)a.n_blocks * 8;
+  // A v at (i, j) for a vector given by a functor of the linear index
+  auto applyA = [&](auto&& v, long long g, long long gxp, long long gxm, long long gyp,
+                    long long gym) {
+    const double c = v(g);
+    return c - ax * (v(gxp) - 2.0 * c + v(gxm)) - ay * (v(gyp) - 2.0 * c + v(gym));
+  };
 
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.g_active[0] = 0;
-    a.g_active[1] = 0;
-  }
-
-  // ---- P0: right-hand side of Eq. (7); x = 0, r = p = b; <b,b>; energies
+  // ---- P0: right-hand side of Eq. (7) into r (x = 0, so r = b); energies
   {
-    double acc[3] = {0.0, 0.0, 0.0};
     double en[2] = {0.0, 0.0};
-    if (mine) {
-      for (int k = first; k < ncell; k += stride) {
-        const int j = k / R.nx, i = k - j * R.nx;
-        double cj[3], ce[3];
-        curl_fwd(L, a.J, i, j, idx_, idy_, cj);
-        curl_fwd(L, a.E, i, j, idx_, idy_, ce);
-        const long long g = L.base + k;
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      double cj[3], ce[3];
+      curl_fwd(L, a.J, i, j, idx_, idy_, cj);
+      curl_fwd(L, a.E, i, j, idx_, idy_, ce);
+      const long long g = L.base + k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
+        a.r0[c][g] = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        a.x[c][g] = 0.0;
+      }
+      if (a.diag) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
-          const double b = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
-          a.x[c][g] = 0.0;
-          a.r[c][g] = b;
-          a.p0[c][g] = b;   // p_old of iteration 0 (beta = 0 there)
-          acc[c] += b * b;
-        }
-        if (a.diag) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double e = a.E[c][g], bb = a.B[c][g];
-            en[0] += e * e;
-            en[1] += bb * bb;
-          }
+          const double e = a.E[c][g], bb = a.B[c][g];
+          en[0] += e * e;
+          en[1] += bb * bb;
         }
       }
     }
-    block_sum<3>(acc, sm);
     block_sum<2>(en, sm);
     if (threadIdx.x == 0) {
-      double* pp = part_rr + (size_t)blockIdx.x * 4;
-      pp[0] = acc[0]; pp[1] = acc[1]; pp[2] = acc[2];
-      part_en[(size_t)blockIdx.x * 2 + 0] = en[0];
-      part_en[(size_t)blockIdx.x * 2 + 1] = en[1];
+      part0[(size_t)blockIdx.x * 8 + 6] = en[0];
+      part0[(size_t)blockIdx.x * 8 + 7] = en[1];
     }
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.g_active[0] = 0;
   }
-  grid.sync();
+  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
 
-  double bn2[3], rr[3], rr_old[3] = {1.0, 1.0, 1.0};
-  bool act[3] = {true, true, true};
-  int iters[3] = {0, 0, 0};
-  int it = 0;
-  for (;; ++it) {
-    // ---- phase A: residual norms, convergence, p and q = A p, <p,q>
-    {
-      double s[3];
-      run_sum3(part_rr, blo, bhi, s, sm);
+  // ---- P1: w0 = A r0; gamma0 = <r0,r0>, delta0 = <w0,r0>; s_{-1} = 0, p_{-1} = 0
+  {
+    double d[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      const long long g = L.base + k;
+      const long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+      const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
+#pragma unroll
       for (int c = 0; c < 3; ++c) {
-        if (it == 0) bn2[c] = s[c];
-        if (act[c]) rr[c] = s[c];   // inactive components keep their last norm
+        const double* rc = a.r0[c];
+        const double w = applyA([&](long long q) { return rc[q]; }, g, gxp, gxm, gyp, gym);
+        const double r = rc[g];
+        a.w0[c][g] = w;
+        a.s0[c][g] = 0.0;
+        a.p[c][g] = 0.0;
+        d[c] += r * r;
+        d[3 + c] += w * r;
       }
     }
-    int nact = 0;
+    block_sum<6>(d, sm);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 6; ++k) part1[(size_t)blockIdx.x * 8 + k] = d[k];
+  }
+  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
+  double we_tot = 0.0, wb_tot = 0.0;
+  if (leader && a.diag) {
+    // energies of step n (partials written before the first barrier; the
+    // iterations below never write words 6 and 7)
+    double e2[2];
+    run_sum<2>(part0 + 6, blo, bhi, e2, sm);
+    we_tot = e2[0];
+    wb_tot = e2[1];
+  }
+
+  double gam[3], alpha[3], beta[3], bn2[3];
+  bool act[3];
+  int iters[3] = {0, 0, 0};
+  {
+    double s[6];
+    run_sum<6>(part1, blo, bhi, s, sm);
     for (int c = 0; c < 3; ++c) {
-      act[c] = it < R.cg_maxit && bn2[c] > 0.0 && sqrt(rr[c]) > R.cg_rtol * sqrt(bn2[c]);
-      nact += act[c];
-      if (act[c]) iters[c] = it + 1;
+      bn2[c] = s[c];
+      gam[c] = s[c];
+      beta[c] = 0.0;
+      alpha[c] = s[3 + c] > 0.0 ? s[c] / s[3 + c] : 0.0;
+      act[c] = R.cg_maxit > 0 && bn2[c] > 0.0;
     }
-    if (leader && threadIdx.x == 0) atomicAdd(&a.g_active[it & 1], nact);
-    double* const* pold = (it & 1) ? a.p1 : a.p0;
-    double* const* pnew = (it & 1) ? a.p0 : a.p1;
-    double beta[3];
-    for (int c = 0; c < 3; ++c) beta[c] = (it == 0 || !act[c]) ? 0.0 : rr[c] / rr_old[c];
-    double pq[3] = {0.0, 0.0, 0.0};
-    if (mine && nact > 0) {
+  }
+
+  // Pass `it` writes partials into half it&1 and counts active runs in
+  // g_active[it % 3]; block 0 clears the counter of the next pass before the
+  // barrier (its previous readers finished two barriers earlier).
+  for (int it = 0;; ++it) {
+    // all blocks of all runs take the same number of passes; a run whose
+    // components have all converged sweeps nothing
+    bool any = false;
+    for (int c = 0; c < 3; ++c) {
+      act[c] = act[c] && it < R.cg_maxit && sqrt(gam[c]) > R.cg_rtol * sqrt(bn2[c]);
+      if (act[c]) iters[c] = it + 1;
+      any |= act[c];
+    }
+    if (leader && threadIdx.x == 0) atomicAdd(&a.g_active[it % 3], any ? 1 : 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.g_active[(it + 1) % 3] = 0;
+    double* const* rc = (it & 1) ? a.r1 : a.r0;
+    double* const* rn = (it & 1) ? a.r0 : a.r1;
+    double* const* wc = (it & 1) ? a.w1 : a.w0;
+    double* const* wn = (it & 1) ? a.w0 : a.w1;
+    double* const* sc = (it & 1) ? a.s1 : a.s0;   // s_{k-1}
+    double* const* sn = (it & 1) ? a.s0 : a.s1;   // s_k
+    double d[6] = {0, 0, 0, 0, 0, 0};
+    if (any) {
       for (int k = first; k < ncell; k += stride) {
         const int j = k / R.nx, i = k - j * R.nx;
         const long long g = L.base + k;
@@ -204,59 +281,45 @@ k_field_solve(FieldArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           if (!act[c]) continue;
-          const double* rc = a.r[c];
-          const double* po = pold[c];
-          const double bc = beta[c];
-          const double p = rc[g] + bc * po[g];
-          const double pxp = rc[gxp] + bc * po[gxp], pxm = rc[gxm] + bc * po[gxm];
-          const double pyp = rc[gyp] + bc * po[gyp], pym = rc[gym] + bc * po[gym];
-          const double q = p - ax * (pxp - 2.0 * p + pxm) - ay * (pyp - 2.0 * p + pym);
-          pnew[c][g] = p;
-          a.q[c][g] = q;
-          pq[c] += p * q;
+          const double* r_ = rc[c];
+          const double* w_ = wc[c];
+          const double* s_ = sc[c];
+          const double al = alpha[c], be = beta[c];
+          // r_{k+1} at any point from the previous buffers
+          auto rnext = [&](long long q) { return r_[q] - al * (w_[q] + be * s_[q]); };
+          const double sk = w_[g] + be * s_[g];
+          const double pk = r_[g] + be * a.p[c][g];
+          const double r1 = r_[g] - al * sk;
+          const double w1 = applyA(rnext, g, gxp, gxm, gyp, gym);
+          a.p[c][g] = pk;
+          sn[c][g] = sk;
+          a.x[c][g] += al * pk;
+          rn[c][g] = r1;
+          wn[c][g] = w1;
+          d[c] += r1 * r1;
+          d[3 + c] += w1 * r1;
         }
       }
     }
-    block_sum<3>(pq, sm);
-    if (threadIdx.x == 0) {
-      double* pp = part_pq + (size_t)blockIdx.x * 4;
-      pp[0] = pq[0]; pp[1] = pq[1]; pp[2] = pq[2];
-    }
-    for (int c = 0; c < 3; ++c) rr_old[c] = rr[c];
-    grid.sync();
-
-    // ---- phase B: step length, x and r updates, <r,r>
-    const int total = __hip_atomic_load(&a.g_active[it & 1], __ATOMIC_RELAXED,
+    double* const pw = (it & 1) ? part1 : part0;
+    block_sum<6>(d, sm);
+    if (threadIdx.x == 0)
+      for (int k = 0; k < 6; ++k) pw[(size_t)blockIdx.x * 8 + k] = d[k];
+    grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
+    const int total = __hip_atomic_load(&a.g_active[it % 3], __ATOMIC_RELAXED,
                                         __HIP_MEMORY_SCOPE_AGENT);
     if (total == 0) break;
-    if (leader && threadIdx.x == 0) a.g_active[(it + 1) & 1] = 0;
-    double alpha[3];
-    {
-      double s[3];
-      run_sum3(part_pq, blo, bhi, s, sm);
-      for (int c = 0; c < 3; ++c) alpha[c] = act[c] ? rr[c] / s[c] : 0.0;
+    double s[6];
+    run_sum<6>(pw, blo, bhi, s, sm);
+    for (int c = 0; c < 3; ++c) {
+      if (!act[c]) continue;
+      const double gnew = s[c], dnew = s[3 + c];
+      const double bnew = gnew / gam[c];
+      const double den = dnew - bnew * gnew / alpha[c];
+      beta[c] = bnew;
+      alpha[c] = den != 0.0 ? gnew / den : 0.0;
+      gam[c] = gnew;
     }
-    double rn[3] = {0.0, 0.0, 0.0};
-    if (mine && nact > 0) {
-      for (int k = first; k < ncell; k += stride) {
-        const long long g = L.base + k;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (!act[c]) continue;
-          const double p = pnew[c][g];
-          a.x[c][g] += alpha[c] * p;
-          const double r = a.r[c][g] - alpha[c] * a.q[c][g];
-          a.r[c][g] = r;
-          rn[c] += r * r;
-        }
-      }
-    }
-    block_sum<3>(rn, sm);
-    if (threadIdx.x == 0) {
-      double* pp = part_rr + (size_t)blockIdx.x * 4;
-      pp[0] = rn[0]; pp[1] = rn[1]; pp[2] = rn[2];
-    }
-    grid.sync();
   }
 
   // ---- per-run record: CG statistics and energies of step n
@@ -264,15 +327,10 @@ k_field_solve(FieldArgs a) {
     double* st = a.stats + (size_t)run * 9;
     for (int c = 0; c < 3; ++c) {
       st[c] = (double)iters[c];
-      st[3 + c] = bn2[c] > 0.0 ? sqrt(rr[c] / bn2[c]) : 0.0;
+      st[3 + c] = bn2[c] > 0.0 ? sqrt(gam[c] / bn2[c]) : 0.0;
       st[6 + c] = sqrt(bn2[c]);
     }
     if (a.diag) {
-      double we = 0.0, wb = 0.0;
-      for (int b = blo; b < bhi; ++b) {   // one thread, once per step
-        we += part_en[(size_t)b * 2 + 0];
-        wb += part_en[(size_t)b * 2 + 1];
-      }
       double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
       const int nt = R.ntx * R.nty;
       for (int t = R.tile0; t < R.tile0 + nt; ++t)
@@ -284,8 +342,8 @@ k_field_solve(FieldArgs a) {
       double* rec = a.history + ((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS;
       rec[0] = (double)a.step;
       rec[1] = (double)a.step * dt;
-      rec[2] = we * cellv;
-      rec[3] = wb * cellv;
+      rec[2] = we_tot * cellv;
+      rec[3] = wb_tot * cellv;
       rec[4] = wk[0][0] + wk[1][0];
       rec[5] = wk[0][1] + wk[1][1];
       for (int c = 0; c < 3; ++c) {
@@ -296,39 +354,35 @@ k_field_solve(FieldArgs a) {
   }
 
   // ---- E update, Eq. (6): E += dt curl_B(B^n + theta dB) - 4 pi dt J
-  if (mine) {
-    for (int k = first; k < ncell; k += stride) {
-      const int j = k / R.nx, i = k - j * R.nx;
-      const long long g = L.base + k;
-      const long long gxm = lidx(L, i - 1, j), gym = lidx(L, i, j - 1);
-      const double bz = a.B[2][g] + th * a.x[2][g];
-      const double bz_ym = a.B[2][gym] + th * a.x[2][gym];
-      const double bz_xm = a.B[2][gxm] + th * a.x[2][gxm];
-      const double by = a.B[1][g] + th * a.x[1][g];
-      const double by_xm = a.B[1][gxm] + th * a.x[1][gxm];
-      const double bx = a.B[0][g] + th * a.x[0][g];
-      const double bx_ym = a.B[0][gym] + th * a.x[0][gym];
-      const double cx = (bz - bz_ym) * idy_;
-      const double cy = -(bz - bz_xm) * idx_;
-      const double cz = (by - by_xm) * idx_ - (bx - bx_ym) * idy_;
-      a.E[0][g] += dt * cx - kFourPi * dt * a.J[0][g];
-      a.E[1][g] += dt * cy - kFourPi * dt * a.J[1][g];
-      a.E[2][g] += dt * cz - kFourPi * dt * a.J[2][g];
-    }
+  for (int k = first; k < ncell; k += stride) {
+    const int j = k / R.nx, i = k - j * R.nx;
+    const long long g = L.base + k;
+    const long long gxm = lidx(L, i - 1, j), gym = lidx(L, i, j - 1);
+    const double bz = a.B[2][g] + th * a.x[2][g];
+    const double bz_ym = a.B[2][gym] + th * a.x[2][gym];
+    const double bz_xm = a.B[2][gxm] + th * a.x[2][gxm];
+    const double by = a.B[1][g] + th * a.x[1][g];
+    const double by_xm = a.B[1][gxm] + th * a.x[1][gxm];
+    const double bx = a.B[0][g] + th * a.x[0][g];
+    const double bx_ym = a.B[0][gym] + th * a.x[0][gym];
+    const double cx = (bz - bz_ym) * idy_;
+    const double cy = -(bz - bz_xm) * idx_;
+    const double cz = (by - by_xm) * idx_ - (bx - bx_ym) * idy_;
+    a.E[0][g] += dt * cx - kFourPi * dt * a.J[0][g];
+    a.E[1][g] += dt * cy - kFourPi * dt * a.J[1][g];
+    a.E[2][g] += dt * cz - kFourPi * dt * a.J[2][g];
   }
-  grid.sync();
+  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
   // ---- B update, Eq. (5) through dB; FP32 copies for the fast particle path
-  if (mine) {
-    for (int k = first; k < ncell; k += stride) {
-      const long long g = L.base + k;
+  for (int k = first; k < ncell; k += stride) {
+    const long long g = L.base + k;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double bnew = a.B[c][g] + a.x[c][g];
-        a.B[c][g] = bnew;
-        if (a.Ef[0]) {
-          a.Ef[3 + c][g] = (float)bnew;
-          a.Ef[c][g] = (float)a.E[c][g];
-        }
+    for (int c = 0; c < 3; ++c) {
+      const double bnew = a.B[c][g] + a.x[c][g];
+      a.B[c][g] = bnew;
+      if (a.Ef[0]) {
+        a.Ef[3 + c][g] = (float)bnew;
+        a.Ef[c][g] = (float)a.E[c][g];
       }
     }
   }

@@ -147,7 +147,7 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
 
 template <typename R, typename F, int P, int MODE>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
-                          int x0, int y0, int tw, int th, const F* sF, R* sJ, int* s_holes,
+                          int x0, int y0, int tw, int th, const F* sF, double* sJ, int* s_holes,
                           int diag, double (&wk)[PIC_MAXS][2]) {
   constexpr int W = P + 3;
   const int PW = st.PW, PH = st.PH;
@@ -213,7 +213,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           for (int b = 0; b <= P; ++b)
 #pragma unroll
             for (int a = 0; a <= P; ++a)
-              atomicAdd(&sJ[(ay0 + b) * PW + ax0 + a], cq * w0x[a] * w0y[b]);
+              atomicAdd(&sJ[(ay0 + b) * PW + ax0 + a], (double)(cq * w0x[a] * w0y[b]));
         }
 
         if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
@@ -285,9 +285,9 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           window_shapes<P, R>(w0y, w1y, a1y, S0y, DSy);
           const int ax0 = lx + f0x - 1 + G, ay0 = ly + f0y - 1 + G;
           const R vz = uz / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
-          R* jx = sJ;
-          R* jy = sJ + plane;
-          R* jz = sJ + 2 * plane;
+          double* jx = sJ;
+          double* jy = sJ + plane;
+          double* jz = sJ + 2 * plane;
 #pragma unroll
           for (int b = 0; b < W; ++b) {
             const R wy = S0y[b] + R(0.5) * DSy[b];
@@ -295,7 +295,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) {
               acc += DSx[a] * wy;
-              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], cjx * acc);
+              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], (double)(cjx * acc));
             }
           }
 #pragma unroll
@@ -305,7 +305,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) {
               acc += DSy[b] * wx;
-              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], cjy * acc);
+              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], (double)(cjy * acc));
             }
           }
           const R czv = cjz * vz;
@@ -315,7 +315,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             for (int a = 0; a < W; ++a) {
               const R wz = S0x[a] * S0y[b] + R(0.5) * DSx[a] * S0y[b] +
                            R(0.5) * S0x[a] * DSy[b] + DSx[a] * DSy[b] * (R(1) / R(3));
-              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], czv * wz);
+              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], (double)(czv * wz));
             }
 
           // ---- tile membership after the move
@@ -391,7 +391,9 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   F* sF = reinterpret_cast<F*>(smem_raw);
   const size_t fbytes = (MODE == MODE_FUSED || MODE == MODE_PUSH) ? 6 * plane * sizeof(F) : 0;
-  R* sJ = reinterpret_cast<R*>(smem_raw + fbytes);
+  // currents accumulate in FP64 LDS in both forms: on gfx950 an FP64 LDS
+  // atomic add retires about 20x faster than an FP32 one
+  double* sJ = reinterpret_cast<double*>(smem_raw + fbytes);
   const int nj = (MODE == MODE_PUSH) ? 0 : (MODE == MODE_CHARGE ? 1 : 3);
   __shared__ int s_holes[PIC_MAXS];
   __shared__ double s_red[4][PIC_MAXS * 2];
@@ -416,7 +418,7 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
       }
     }
   }
-  for (int e = threadIdx.x; e < nj * plane; e += blockDim.x) sJ[e] = R(0);
+  for (int e = threadIdx.x; e < nj * plane; e += blockDim.x) sJ[e] = 0.0;
   __syncthreads();
 
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
@@ -435,7 +437,7 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
 
   if constexpr (MODE != MODE_PUSH) {
     for (int c = 0; c < nj; ++c) {
-      R* out = st.patch[c] + (size_t)tile * plane;
+      double* out = st.patch[c] + (size_t)tile * plane;
       for (int e = threadIdx.x; e < plane; e += blockDim.x) out[e] = sJ[c * plane + e];
     }
   }
@@ -659,8 +661,8 @@ size_t pic_particle_smem(const DevState<R>& st, int mode) {
   const size_t plane = (size_t)st.PW * st.PH;
   size_t b = 0;
   if (mode == MODE_FUSED || mode == MODE_PUSH) b += 6 * plane * sizeof(F);
-  if (mode == MODE_FUSED || mode == MODE_DEPOSIT) b += 3 * plane * sizeof(R);
-  if (mode == MODE_CHARGE) b += plane * sizeof(R);
+  if (mode == MODE_FUSED || mode == MODE_DEPOSIT) b += 3 * plane * sizeof(double);
+  if (mode == MODE_CHARGE) b += plane * sizeof(double);
   return b;
 }
 

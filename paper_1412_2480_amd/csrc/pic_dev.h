@@ -18,6 +18,7 @@
 #define PIC_ERRBIT_INBOX 1      // destination inbox full
 #define PIC_ERRBIT_HOLES 2      // hole list full
 #define PIC_ERRBIT_TILE 4       // tile slots full after re-binning
+#define PIC_ERRBIT_BARRIER 8    // a grid barrier timed out
 
 struct DevRun {
   int nx, ny, order, nspecies;
@@ -74,7 +75,7 @@ struct DevState {
   R* old_ox[PIC_MAXS];
   R* old_oy[PIC_MAXS];
 
-  R* patch[3];                    // per-tile current patches [tile][PH][PW]
+  double* patch[3];               // per-tile current patches [tile][PH][PW] (FP64)
   double* wk_part;                // [tile][species][2] kinetic energy partials
   int* err;                       // error bits
 };

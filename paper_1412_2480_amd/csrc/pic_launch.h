@@ -7,6 +7,8 @@
 
 #define PIC_REC_WORDS 16   // doubles per history record
 
+#define PIC_CG_THREADS 512    // work-group size of the persistent field solve
+
 struct FieldArgs {
   int n_runs, n_blocks, diag;
   const DevRun* runs;
@@ -15,12 +17,17 @@ struct FieldArgs {
   double* J[3];
   float* Ef[6];            // FP32 copies (null pointers in the FP64 form)
   double* x[3];            // dB
-  double* r[3];
-  double* p0[3];
-  double* p1[3];
-  double* q[3];
-  double* part;            // per-block partial sums
-  int* g_active;           // two active-component counters
+  double* p[3];
+  double* r0[3];           // r, w = A r and s = A p, double-buffered
+  double* r1[3];
+  double* w0[3];
+  double* w1[3];
+  double* s0[3];
+  double* s1[3];
+  double* part;            // per-block partial sums, 2 x [block][8]
+  int* g_active;           // active-run counters (3)
+  unsigned* bar;           // grid barrier: counter at [0], generation at [32]
+  int* err;                // error bits
   double* stats;           // [run][9]: iters, relres, ||b||
   const double* wk_part;   // [tile][species][2] kinetic partials
   double* history;         // [run][hist_cap][PIC_REC_WORDS]
