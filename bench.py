@@ -48,7 +48,7 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0):
     run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
                        [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8, cg_maxit=200)
     sim = pic.Sim([run], pic.make_options(precision, tile=tile, diag_every=0,
-                                          cg_blocks=cg_blocks))
+                                          cg_blocks=cg_blocks, track_ids=False))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])

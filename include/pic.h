@@ -94,6 +94,9 @@ typedef struct pic_options {
   int32_t diag_every;    /* record energies every n steps into the history (0 = never) */
   int32_t history_cap;   /* history records kept per run (ring buffer) */
   int32_t cg_blocks;     /* work-groups of the persistent field solve; 0 = automatic */
+  int32_t track_ids;     /* 1: particles carry ids and reads return them ordered by id;
+                            0: no ids (8 B less traffic per particle-step), reads return
+                            storage order */
 } pic_options;
 
 typedef struct pic_plan_info {
@@ -152,8 +155,9 @@ int32_t pic_load_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t n
                            const double* fy, const double* ux, const double* uy,
                            const double* uz);
 
-/* Copy the particles of (run, species) to the host, ordered by id, with
- * n_out = count (at most cap). Any output pointer may be NULL. */
+/* Copy the particles of (run, species) to the host, with n_out = count (at
+ * most cap), ordered by id when ids are tracked (storage order otherwise).
+ * Any output pointer may be NULL. */
 int32_t pic_read_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t cap,
                            int32_t* ix, int32_t* iy, double* fx, double* fy, double* ux,
                            double* uy, double* uz, int64_t* n_out);

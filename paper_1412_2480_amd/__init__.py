@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("slack", ctypes.c_double), ("exchange_frac", ctypes.c_double),
                 ("diag_every", ctypes.c_int32), ("history_cap", ctypes.c_int32),
-                ("cg_blocks", ctypes.c_int32)]
+                ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -149,7 +149,7 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 
 
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
-                 diag_every=0, history_cap=1, cg_blocks=0):
+                 diag_every=0, history_cap=1, cg_blocks=0, track_ids=True):
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
     o.solver = PIC_SOLVER_CG
@@ -157,6 +157,7 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)
     o.cg_blocks = int(cg_blocks)
+    o.track_ids = 1 if track_ids else 0
     return o
 
 

@@ -73,6 +73,7 @@ struct pic_ctx {
   size_t ws_bytes = 0;
   bool fast = false;
   bool split = true;
+  bool ids = true;
   std::vector<DevRun> hruns;
   DevRun* d_runs = nullptr;
   int* d_tile_run = nullptr;
@@ -185,7 +186,7 @@ void make_tiling(const pic_run_desc* runs, int n_runs, const pic_options* o, Til
 // Carve (or, with base == nullptr, size) the workspace.
 template <typename R>
 size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
-             bool split, int hist_cap, pic_ctx* c, DevState<R>* st) {
+             bool split, bool ids, int hist_cap, pic_ctx* c, DevState<R>* st) {
   Bump b(base);
   const long long nc = tl.n_cells;
   const size_t plane = (size_t)(tl.TXA + 5) * (tl.TYA + 5);
@@ -231,8 +232,19 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     s.ux[sp] = b.take<R>(slots);
     s.uy[sp] = b.take<R>(slots);
     s.uz[sp] = b.take<R>(slots);
-    s.id[sp] = b.take<int>(slots);
+    s.ncell[sp] = b.take<int>(slots);
+    s.nox[sp] = b.take<R>(slots);
+    s.noy[sp] = b.take<R>(slots);
+    s.nux[sp] = b.take<R>(slots);
+    s.nuy[sp] = b.take<R>(slots);
+    s.nuz[sp] = b.take<R>(slots);
+    if (ids) {
+      s.id[sp] = b.take<int>(slots);
+      s.nid[sp] = b.take<int>(slots);
+      s.in_id[sp] = b.take<int>(ex);
+    }
     s.cnt[sp] = b.take<int>(tl.n_tiles);
+    s.stay_cnt[sp] = b.take<int>(tl.n_tiles);
     s.in_cnt[sp] = b.take<int>(tl.n_tiles);
     s.in_cell[sp] = b.take<int>(ex);
     s.in_ox[sp] = b.take<R>(ex);
@@ -240,10 +252,6 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     s.in_ux[sp] = b.take<R>(ex);
     s.in_uy[sp] = b.take<R>(ex);
     s.in_uz[sp] = b.take<R>(ex);
-    s.in_id[sp] = b.take<int>(ex);
-    s.hole[sp] = b.take<int>(ex);
-    s.hole_cnt[sp] = b.take<int>(tl.n_tiles);
-    s.rb_scr[sp] = b.take<int>(ex);
     if (split) {
       s.old_cell[sp] = b.take<int>(slots);
       s.old_ox[sp] = b.take<R>(slots);
@@ -354,9 +362,10 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   p.exchange_slots = std::max(64, (int)(std::ceil(ts * exf) + 63) / 64 * 64);
   const int hist_cap = o->history_cap > 0 ? o->history_cap : 1;
   const bool split = true;
-  p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, hist_cap, nullptr,
-                                          (DevState<float>*)nullptr)
-                           : carve<double>(nullptr, *tl, p, n_runs, false, split, hist_cap,
+  const bool ids = o->track_ids != 0;
+  p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, ids, hist_cap,
+                                          nullptr, (DevState<float>*)nullptr)
+                           : carve<double>(nullptr, *tl, p, n_runs, false, split, ids, hist_cap,
                                            nullptr, (DevState<double>*)nullptr);
   *out = p;
   return PIC_OK;
@@ -415,6 +424,20 @@ int launch_particles(pic_ctx* c, int mode, int diag) {
   return PIC_OK;
 }
 
+// the next buffer (stayers + arrivals) becomes the current one
+template <typename R>
+void swap_buffers(DevState<R>& st) {
+  for (int s = 0; s < PIC_MAXS; ++s) {
+    std::swap(st.cell[s], st.ncell[s]);
+    std::swap(st.ox[s], st.nox[s]);
+    std::swap(st.oy[s], st.noy[s]);
+    std::swap(st.ux[s], st.nux[s]);
+    std::swap(st.uy[s], st.nuy[s]);
+    std::swap(st.uz[s], st.nuz[s]);
+    std::swap(st.id[s], st.nid[s]);
+  }
+}
+
 template <typename R>
 int launch_exchange(pic_ctx* c) {
   int ns = 0;
@@ -423,6 +446,7 @@ int launch_exchange(pic_ctx* c) {
   hipError_t e = pic_launch_rebin<R>(state<R>(c), ns, c->stream);
   t_end(c);
   if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("rebin: ") + hipGetErrorString(e));
+  swap_buffers(state<R>(c));
   t_begin(c, 3);
   e = pic_launch_current_sum<R>(state<R>(c), c->tl.max_cells, c->stream);
   t_end(c);
@@ -476,9 +500,13 @@ int check_err(pic_ctx* c) {
   int h = 0;
   HIPCHK(c, hipMemcpyAsync(&h, c->d_err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (h & PIC_ERRBIT_BARRIER)
+    return fail(c, PIC_E_HIP, "field-solve grid barrier timed out (work-groups not co-resident)");
   if (h) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "particle exchange overflow (bits 0x%x); raise slack/exchange_frac", h);
+    char buf[160];
+    snprintf(buf, sizeof buf,
+             "particle exchange overflow (bits 0x%x: 1 inbox, 4 tile slots); raise slack or "
+             "exchange_frac", h);
     return fail(c, PIC_E_CAPACITY, buf);
   }
   return PIC_OK;
@@ -582,7 +610,8 @@ int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const in
   HIPCHK(c, hipMemcpyAsync(st.ux[s] + b0, hux.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
   HIPCHK(c, hipMemcpyAsync(st.uy[s] + b0, huy.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
   HIPCHK(c, hipMemcpyAsync(st.uz[s] + b0, huz.data(), tot * sizeof(R), hipMemcpyHostToDevice, S));
-  HIPCHK(c, hipMemcpyAsync(st.id[s] + b0, hid.data(), tot * sizeof(int), hipMemcpyHostToDevice, S));
+  if (st.id[s])
+    HIPCHK(c, hipMemcpyAsync(st.id[s] + b0, hid.data(), tot * sizeof(int), hipMemcpyHostToDevice, S));
   HIPCHK(c, hipMemcpyAsync(st.cnt[s] + tl.tile0[run], count.data(), nt * sizeof(int),
                            hipMemcpyHostToDevice, S));
   HIPCHK(c, hipStreamSynchronize(S));
@@ -608,17 +637,19 @@ int read_impl(pic_ctx* c, int run, int s, int64_t cap, int32_t* ix, int32_t* iy,
   HIPCHK(c, hipMemcpyAsync(hux.data(), st.ux[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
   HIPCHK(c, hipMemcpyAsync(huy.data(), st.uy[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
   HIPCHK(c, hipMemcpyAsync(huz.data(), st.uz[s] + b0, tot * sizeof(R), hipMemcpyDeviceToHost, S));
-  HIPCHK(c, hipMemcpyAsync(hid.data(), st.id[s] + b0, tot * sizeof(int), hipMemcpyDeviceToHost, S));
+  if (st.id[s])
+    HIPCHK(c, hipMemcpyAsync(hid.data(), st.id[s] + b0, tot * sizeof(int), hipMemcpyDeviceToHost, S));
   HIPCHK(c, hipStreamSynchronize(S));
   int64_t n = 0;
   for (int t = 0; t < nt; ++t) n += count[t];
   *n_out = n;
   if (n > cap) return fail(c, PIC_E_INVAL, "output capacity smaller than the particle count");
   std::vector<char> seen(n, 0);
+  int64_t seq = 0;
   for (int t = 0; t < nt; ++t)
     for (int k = 0; k < count[t]; ++k) {
       const size_t o = (size_t)t * slots + k;
-      const int id = hid[o];
+      const int id = st.id[s] ? hid[o] : (int)seq++;   // storage order without ids
       if (id < 0 || id >= n || seen[id] || hcell[o] < 0)
         return fail(c, PIC_E_STATE, "particle store inconsistent (duplicate/missing id or hole)");
       seen[id] = 1;
@@ -689,10 +720,13 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   c->ws = (uint8_t*)d_workspace;
   c->ws_bytes = ws_bytes;
   c->fast = opt->precision == PIC_FP32_FAST;
+  c->ids = opt->track_ids != 0;
   if (c->fast)
-    carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->opt.history_cap, c, &c->sf);
+    carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->ids, c->opt.history_cap, c,
+                 &c->sf);
   else
-    carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->opt.history_cap, c, &c->sd);
+    carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap, c,
+                  &c->sd);
 
   // CG work-groups: as many as can be co-resident, split over runs by cells
   int dev = 0, n_cu = 0;

@@ -9,9 +9,12 @@
 // LDS, pushes every particle of every species of the tile, accumulates the
 // current of the tile (+ guard nodes) in LDS, and writes that patch out whole.
 // A second pass sums the overlapping patches node by node in a fixed order
-// (no global atomics on J). Particles that leave their tile are appended to
-// the destination tile's inbox (slots reserved once per wavefront and
-// destination); the re-binning kernel then fills the holes they left.
+// (no global atomics on J). The particle store is double-buffered: particles
+// that stay in their tile are written compacted into the next buffer (one LDS
+// atomic per wavefront), particles that leave are appended to the
+// destination tile's inbox (one global atomic per wavefront and
+// destination), and the re-binning kernel appends each inbox after the tile's
+// stayers. Every write is contiguous.
 #include <math.h>
 
 #include <type_traits>
@@ -147,7 +150,7 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
 
 template <typename R, typename F, int P, int MODE>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
-                          int x0, int y0, int tw, int th, const F* sF, double* sJ, int* s_holes,
+                          int x0, int y0, int tw, int th, const F* sF, double* sJ, int* s_stay,
                           int diag, double (&wk)[PIC_MAXS][2]) {
   constexpr int W = P + 3;
   const int PW = st.PW, PH = st.PH;
@@ -330,24 +333,33 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             tty = tty < 0 ? run.nty - 1 : (tty >= run.nty ? 0 : tty);
             dest_t = run.tile0 + tty * run.ntx + ttx;
           }
-          if (dest_t == tile) {
-            if constexpr (MODE == MODE_FUSED) {
-              st.cell[s][idx] = gcell;
-              st.ox[s][idx] = fx1;
-              st.oy[s][idx] = fy1;
-              st.ux[s][idx] = ux;
-              st.uy[s][idx] = uy;
-              st.uz[s][idx] = uz;
-            }
-          } else {
+          if (dest_t != tile) {
             leave = true;
             dest = dest_t;
-            pid = st.id[s][idx];
-            st.cell[s][idx] = -1;   // hole marker for the re-binning pass
           }
+          if (st.id[s]) pid = st.id[s][idx];
         }
       }
       if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
+        // stayers: compacted into the next buffer of this tile
+        const bool stay = active && !leave;
+        const unsigned long long m = __ballot(stay);
+        int wbase = 0;
+        if (__lane_id() == 0 && m) wbase = atomicAdd(&s_stay[s], __popcll(m));
+        wbase = __shfl(wbase, 0);
+        if (stay) {
+          const int lane = __lane_id();
+          const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+          const long long o = base + wbase + __popcll(m & below);
+          st.ncell[s][o] = gcell;
+          st.nox[s][o] = fx1;
+          st.noy[s][o] = fy1;
+          st.nux[s][o] = ux;
+          st.nuy[s][o] = uy;
+          st.nuz[s][o] = uz;
+          if (st.nid[s]) st.nid[s][o] = pid;
+        }
+        // leavers: appended to the destination tile's inbox
         const int slot = wave_reserve(leave, dest, st.in_cnt[s]);
         if (leave) {
           if (slot < st.ex_slots) {
@@ -358,15 +370,10 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             st.in_ux[s][o] = ux;
             st.in_uy[s][o] = uy;
             st.in_uz[s][o] = uz;
-            st.in_id[s][o] = pid;
+            if (st.in_id[s]) st.in_id[s][o] = pid;
           } else {
             atomicOr(st.err, PIC_ERRBIT_INBOX);
           }
-          const int h = atomicAdd(&s_holes[s], 1);
-          if (h < st.ex_slots)
-            st.hole[s][(long long)tile * st.ex_slots + h] = k;
-          else
-            atomicOr(st.err, PIC_ERRBIT_HOLES);
         }
       }
     }
@@ -395,10 +402,10 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   // atomic add retires about 20x faster than an FP32 one
   double* sJ = reinterpret_cast<double*>(smem_raw + fbytes);
   const int nj = (MODE == MODE_PUSH) ? 0 : (MODE == MODE_CHARGE ? 1 : 3);
-  __shared__ int s_holes[PIC_MAXS];
+  __shared__ int s_stay[PIC_MAXS];
   __shared__ double s_red[4][PIC_MAXS * 2];
 
-  if (threadIdx.x < PIC_MAXS) s_holes[threadIdx.x] = 0;
+  if (threadIdx.x < PIC_MAXS) s_stay[threadIdx.x] = 0;
   if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
     for (int e = threadIdx.x; e < plane; e += blockDim.x) {
       const int ly = e / PW - G, lx = e % PW - G;
@@ -424,13 +431,13 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
   switch (run.order) {
     case 1:
-      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
       break;
     case 2:
-      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
       break;
     default:
-      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_holes, diag, wk);
+      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
       break;
   }
   __syncthreads();
@@ -442,7 +449,7 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
     }
   }
   if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
-    if (threadIdx.x < run.nspecies) st.hole_cnt[threadIdx.x][tile] = s_holes[threadIdx.x];
+    if (threadIdx.x < run.nspecies) st.stay_cnt[threadIdx.x][tile] = s_stay[threadIdx.x];
   }
   if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
     if (diag) {
@@ -465,109 +472,39 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   }
 }
 
-// block-wide exclusive prefix of a predicate (blockDim multiple of 64, <= 1024)
-__device__ __forceinline__ int block_prefix(bool pred, int* s_wave, int& total) {
-  const int lane = __lane_id(), wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-  const unsigned long long m = __ballot(pred);
-  const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  const int in_wave = __popcll(m & below);
-  if (lane == 0) s_wave[wave] = __popcll(m);
-  __syncthreads();
-  int off = 0, tot = 0;
-  for (int w = 0; w < nw; ++w) {
-    const int c = s_wave[w];
-    if (w < wave) off += c;
-    tot += c;
-  }
-  __syncthreads();
-  total = tot;
-  return off + in_wave;
-}
-
-// Re-binning: arrivals fill the holes left by departures; if more particles
-// left than arrived, live particles from the tail of the segment fill the
-// remaining holes below the new count.
+// Re-binning: the tile's inbox is appended after its stayers in the next
+// buffer (contiguous reads and writes); the new count is stayers + arrivals.
 template <typename R>
 __global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
   const int per = gridDim.x / 8;
   const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (tile >= st.n_tiles) return;
   const int s = blockIdx.y;
-  const int run_i = st.tile_run[tile];
-  if (s >= st.runs[run_i].nspecies) return;
-  __shared__ int s_wave[16];
+  if (s >= st.runs[st.tile_run[tile]].nspecies) return;
   const int ex = st.ex_slots;
   const int cap = st.tile_slots[s];
-  const int C = st.cnt[s][tile];
-  int H = st.hole_cnt[s][tile];
+  const int S = st.stay_cnt[s][tile];
   int A = st.in_cnt[s][tile];
-  H = H > ex ? ex : H;
   A = A > ex ? ex : A;
-  const int N = C - H + A;
-  __syncthreads();
+  if (S + A > cap) {
+    if (threadIdx.x == 0) atomicOr(st.err, PIC_ERRBIT_TILE);
+    A = cap - S;   // state is no longer consistent; the run is flagged
+  }
+  const long long base = (long long)tile * cap + S;
+  const long long ib = (long long)tile * ex;
+  for (int k = threadIdx.x; k < A; k += blockDim.x) {
+    st.ncell[s][base + k] = st.in_cell[s][ib + k];
+    st.nox[s][base + k] = st.in_ox[s][ib + k];
+    st.noy[s][base + k] = st.in_oy[s][ib + k];
+    st.nux[s][base + k] = st.in_ux[s][ib + k];
+    st.nuy[s][base + k] = st.in_uy[s][ib + k];
+    st.nuz[s][base + k] = st.in_uz[s][ib + k];
+    if (st.nid[s]) st.nid[s][base + k] = st.in_id[s][ib + k];
+  }
   if (threadIdx.x == 0) {
+    st.cnt[s][tile] = S + A;
     st.in_cnt[s][tile] = 0;
-    st.hole_cnt[s][tile] = 0;
   }
-  if (N > cap) {
-    if (threadIdx.x == 0) {
-      atomicOr(st.err, PIC_ERRBIT_TILE);
-      st.cnt[s][tile] = C - H;   // state is no longer consistent; run is flagged
-    }
-    return;
-  }
-  int* holes = st.hole[s] + (long long)tile * ex;
-  int* scr = st.rb_scr[s] + (long long)tile * ex;
-  const long long base = (long long)tile * cap;
-  // phase 1: stable in-place compaction of holes with index < N
-  int h_low = 0;
-  for (int c0 = 0; c0 < H; c0 += blockDim.x) {
-    const int i = c0 + threadIdx.x;
-    const int v = i < H ? holes[i] : 0x7fffffff;
-    int tot;
-    const int pos = block_prefix(i < H && v < N, s_wave, tot);
-    if (i < H && v < N) holes[h_low + pos] = v;
-    h_low += tot;
-    __syncthreads();
-  }
-  // phase 2: live particles in the tail [N, C) (only when more left than arrived)
-  int L = 0;
-  if (H > A) {
-    for (int c0 = N; c0 < C; c0 += blockDim.x) {
-      const int i = c0 + threadIdx.x;
-      const bool live = i < C && st.cell[s][base + i] != -1;
-      int tot;
-      const int pos = block_prefix(live, s_wave, tot);
-      if (live) scr[L + pos] = i;
-      L += tot;
-    }
-    __syncthreads();
-  }
-  // phase 3: move sources (inbox, then tail) into targets (low holes, then append)
-  const int n_targets = h_low + (A > H ? A - H : 0);
-  for (int k = threadIdx.x; k < n_targets; k += blockDim.x) {
-    const long long dst = base + (k < h_low ? holes[k] : C + (k - h_low));
-    if (k < A) {
-      const long long o = (long long)tile * ex + k;
-      st.cell[s][dst] = st.in_cell[s][o];
-      st.ox[s][dst] = st.in_ox[s][o];
-      st.oy[s][dst] = st.in_oy[s][o];
-      st.ux[s][dst] = st.in_ux[s][o];
-      st.uy[s][dst] = st.in_uy[s][o];
-      st.uz[s][dst] = st.in_uz[s][o];
-      st.id[s][dst] = st.in_id[s][o];
-    } else {
-      const long long src = base + scr[k - A];
-      st.cell[s][dst] = st.cell[s][src];
-      st.ox[s][dst] = st.ox[s][src];
-      st.oy[s][dst] = st.oy[s][src];
-      st.ux[s][dst] = st.ux[s][src];
-      st.uy[s][dst] = st.uy[s][src];
-      st.uz[s][dst] = st.uz[s][src];
-      st.id[s][dst] = st.id[s][src];
-    }
-  }
-  if (threadIdx.x == 0) st.cnt[s][tile] = N;
 }
 
 // Sum of the overlapping tile patches at every node, in a fixed tile order.

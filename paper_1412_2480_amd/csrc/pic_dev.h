@@ -16,7 +16,6 @@
 
 // error bits raised by kernels (read back by the host)
 #define PIC_ERRBIT_INBOX 1      // destination inbox full
-#define PIC_ERRBIT_HOLES 2      // hole list full
 #define PIC_ERRBIT_TILE 4       // tile slots full after re-binning
 #define PIC_ERRBIT_BARRIER 8    // a grid barrier timed out
 
@@ -47,7 +46,10 @@ struct DevState {
   double* J[3];
   float* Ef[6];                   // FP32 copy of Ex..Bz for the fast path
 
-  // particle store (per species)
+  // particle store (per species), double-buffered: the particle kernel reads
+  // the current arrays and writes the particles that stay in their tile,
+  // compacted, into the next arrays; re-binning appends the arrivals there
+  // and the host swaps the two sets. id arrays are null when ids are off.
   int* cell[PIC_MAXS];            // (iy << 16) | ix, run-local cell
   R* ox[PIC_MAXS];
   R* oy[PIC_MAXS];
@@ -55,9 +57,17 @@ struct DevState {
   R* uy[PIC_MAXS];
   R* uz[PIC_MAXS];
   int* id[PIC_MAXS];
-  int* cnt[PIC_MAXS];             // live particles per tile
+  int* ncell[PIC_MAXS];
+  R* nox[PIC_MAXS];
+  R* noy[PIC_MAXS];
+  R* nux[PIC_MAXS];
+  R* nuy[PIC_MAXS];
+  R* nuz[PIC_MAXS];
+  int* nid[PIC_MAXS];
+  int* cnt[PIC_MAXS];             // live particles per tile (current arrays)
+  int* stay_cnt[PIC_MAXS];        // particles kept in the tile by the last pass
 
-  // exchange between tiles
+  // exchange between tiles: inbox of each destination tile
   int* in_cnt[PIC_MAXS];
   int* in_cell[PIC_MAXS];
   R* in_ox[PIC_MAXS];
@@ -66,9 +76,6 @@ struct DevState {
   R* in_uy[PIC_MAXS];
   R* in_uz[PIC_MAXS];
   int* in_id[PIC_MAXS];
-  int* hole[PIC_MAXS];
-  int* hole_cnt[PIC_MAXS];
-  int* rb_scr[PIC_MAXS];
 
   // split path: positions before the move
   int* old_cell[PIC_MAXS];

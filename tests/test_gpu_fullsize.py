@@ -1,0 +1,116 @@
+"""Parity at the benchmark's full size (periodic 1024 x 256, pair plasma at
+gamma0 = 40, 64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32
+particle path, the tile shape bench.py times) on outputs the FP64 oracle can
+compute piecewise: a sample of particles pushed one by one, the current on
+sampled node boxes from the particles that can reach them, and the field
+solve on the whole grid from the GPU's own current."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from pic_cases import relerr
+
+pytestmark = pytest.mark.gpu
+
+NX, NY, PPC, G0, ORDER, DX = 1024, 256, 64, 40.0, 3, 0.1
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+def test_fullsize_fp32_step_sampled_parity():
+    import paper_1412_2480_amd as pic
+    from synth import loads
+    _say("fullsize: generating load")
+    Q = loads.macro_charge(G0, DX, DX, PPC)
+    ld = loads.pair_plasma_cells(NX, NY, PPC, G0, 0.01, seed=0)
+    run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 16)))
+    for s in range(2):
+        d = ld[s]
+        sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    n = NX * NY * PPC
+    del ld
+    _say("fullsize: 3 warm steps")
+    sim.step(3)   # fields grow from noise so the push below is not trivial
+    F0 = {k: sim.get_field(0, k) for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    P0 = [sim.read_particles(0, s, n) for s in range(2)]
+    _say("fullsize: one measured step")
+    sim.step(1)
+    J1 = [sim.get_field(0, k) for k in ("Jx", "Jy", "Jz")]
+    F1 = {k: sim.get_field(0, k) for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    P1 = [sim.read_particles(0, s, n) for s in range(2)]
+    sim.close()
+    dt = DX
+    # the GPU gathers from an FP32 copy of the FP64 fields
+    fields32 = [F0[k].astype(np.float32).astype(np.float64)
+                for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")]
+    rng = np.random.default_rng(0)
+
+    # ---- sampled particles pushed one by one
+    for s, q in enumerate((-Q, Q)):
+        idx = rng.choice(n, 4000, replace=False)
+        p = oracle.Particles(P0[s]["ix"][idx], P0[s]["iy"][idx], P0[s]["fx"][idx],
+                             P0[s]["fy"][idx], P0[s]["ux"][idx], P0[s]["uy"][idx],
+                             P0[s]["uz"][idx], q, Q)
+        f = oracle.gather(NX, NY, ORDER, fields32, p)
+        oracle.boris(p, dt, f[0:3], f[3:6])
+        oracle.move(p, dt, DX, DX)
+        oracle.wrap(NX, NY, p)
+        u = np.stack([P1[s]["ux"][idx], P1[s]["uy"][idx], P1[s]["uz"][idx]])
+        ur = np.stack([p.ux, p.uy, p.uz])
+        mom = np.abs(u - ur).max() / np.abs(ur).max()
+        X = P1[s]["ix"][idx] + P1[s]["fx"][idx]
+        Xr = p.ix + p.fx
+        pos = np.abs((X - Xr + NX / 2) % NX - NX / 2).max()
+        _say(f"  species {s}: momentum err {mom:.2e}, position err {pos:.2e} cells")
+        assert mom <= 2e-6 and pos <= 1e-5
+
+    # ---- current on sampled 8x8 node boxes from every particle within reach
+    jscale = None
+    for b in range(4):
+        i0 = int(rng.integers(8, NX - 16))
+        j0 = int(rng.integers(8, NY - 16))
+        Jr = [np.zeros((NY, NX)) for _ in range(3)]
+        count = np.zeros((NY, NX))
+        for s, q in enumerate((-Q, Q)):
+            sel = ((P0[s]["ix"] >= i0 - 5) & (P0[s]["ix"] < i0 + 13) &
+                   (P0[s]["iy"] >= j0 - 5) & (P0[s]["iy"] < j0 + 13))
+            p = oracle.Particles(*(P0[s][k][sel] for k in ("ix", "iy", "fx", "fy", "ux", "uy",
+                                                            "uz")), q, Q)
+            f = oracle.gather(NX, NY, ORDER, fields32, p)
+            oracle.boris(p, dt, f[0:3], f[3:6])
+            old = p.copy()
+            oracle.move(p, dt, DX, DX)
+            oracle.deposit(NX, NY, ORDER, DX, DX, dt, old, p, Jr)
+            one = old.copy()
+            one.q = 1.0
+            oracle.charge(NX, NY, ORDER, 1.0, 1.0, one, count)
+        nmax = count[j0:j0 + 8, i0:i0 + 8].max()
+        jscale = [Q / (DX * dt) * nmax, Q / (DX * dt) * nmax, Q * nmax / (DX * DX)]
+        for c in range(3):
+            err = np.abs(J1[c][j0:j0 + 8, i0:i0 + 8] - Jr[c][j0:j0 + 8, i0:i0 + 8]).max()
+            _say(f"  box {b} J{'xyz'[c]}: err/scale {err / jscale[c]:.2e}")
+            assert err <= 1e-6 * jscale[c]
+
+    # ---- field solve on the whole grid, from the GPU's current, in FP64
+    ref = oracle.Sim(NX, NY, DX, DX, 1.0, 0.6, ORDER, [], rtol=1e-8)
+    for k, name in enumerate(("Ex", "Ey", "Ez")):
+        ref.E[k][...] = F0[name]
+    for k, name in enumerate(("Bx", "By", "Bz")):
+        ref.B[k][...] = F0[name]
+    for c in range(3):
+        ref.J[c][...] = J1[c]
+    ref.field_solve()
+    for k, name in enumerate(("Ex", "Ey", "Ez")):
+        e = relerr(F1[name] - F0[name], ref.E[k] - F0[name])
+        _say(f"  {name} increment relerr {e:.2e}")
+        assert e <= 1e-6
+    for k, name in enumerate(("Bx", "By", "Bz")):
+        e = relerr(F1[name] - F0[name], ref.B[k] - F0[name])
+        _say(f"  {name} increment relerr {e:.2e}")
+        assert e <= 1e-6
