@@ -42,21 +42,22 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_sim(pic, cfg, load, precision, tile, cg_blocks=0):
+def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0):
     from synth import loads
     Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
     run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
                        [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8, cg_maxit=200)
     sim = pic.Sim([run], pic.make_options(precision, tile=tile, diag_every=0,
-                                          cg_blocks=cg_blocks, track_ids=False))
+                                          cg_blocks=cg_blocks, track_ids=False,
+                                          tile_split=tile_split))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
     return sim
 
 
-def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0):
-    sim = make_sim(pic, cfg, load, precision, tile, cg_blocks)
+def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0):
+    sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split)
     n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
     if warmup:
         sim.step(warmup)
@@ -117,6 +118,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--cg-blocks", type=int, default=0, help="field-solve work-groups (0 = auto)")
     ap.add_argument("--sweep-cg", default="", help="comma list of cg_blocks to time (FP32 form)")
+    ap.add_argument("--tile-split", type=int, default=0, help="work-groups per tile (0 = auto)")
+    ap.add_argument("--sweep-tiles", default="",
+                    help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first copy a 512 MiB buffer three times (a plain copy kernel of known "
+                         "size, for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: multi-GPU runs are not part of this build "
@@ -129,6 +136,14 @@ def main():
 
     cfg = CONFIGS[args.config]
     tile = tuple(int(v) for v in args.tile.split("x"))
+    if args.calib_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 2.0, out=dst)   # an elementwise kernel: reads and writes 512 MiB
+        torch.cuda.synchronize()
+        del src, dst
+        log("bench: calibration copies done (3 x 512 MiB)")
     log(f"bench: generating load {cfg['label']}")
     t0 = time.perf_counter()
     load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
@@ -139,14 +154,23 @@ def main():
             r = time_form(pic, torch, cfg, load, "fp32", tile, 10, 2, nb)
             log(f"bench: cg_blocks={nb}: field solve {r['field_solve_ms']:.3f} ms/step, "
                 f"iters {r['cg_iters']}")
+    if args.sweep_tiles:
+        for item in args.sweep_tiles.split(","):
+            shape, k = item.split(":")
+            tt = tuple(int(v) for v in shape.split("x"))
+            for prec in ("fp32", "fp64"):
+                r = time_form(pic, torch, cfg, load, prec, tt, 20, 20, args.cg_blocks, int(k))
+                log(f"bench: {prec} tile {shape} split {k}: push {r['push_ms']:.3f} ms, "
+                    f"step {r['ms_per_step']:.3f} ms")
     log("bench: FP32 form")
-    fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks)
+    fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
+                     args.tile_split)
     log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step")
     plain = None
     if not args.no_fp64:
         log("bench: FP64 form")
         plain = time_form(pic, torch, cfg, load, "fp64", tile, args.steps, args.warmup,
-                          args.cg_blocks)
+                          args.cg_blocks, args.tile_split)
         log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
     del load
 

@@ -97,6 +97,7 @@ typedef struct pic_options {
   int32_t track_ids;     /* 1: particles carry ids and reads return them ordered by id;
                             0: no ids (8 B less traffic per particle-step), reads return
                             storage order */
+  int32_t tile_split;    /* work-groups per tile in the particle kernel; 0 = 4 */
 } pic_options;
 
 typedef struct pic_plan_info {
@@ -104,7 +105,8 @@ typedef struct pic_plan_info {
   int32_t tile_x, tile_y;
   int32_t n_tiles;                         /* over all runs */
   int32_t tile_slots[PIC_MAX_SPECIES];     /* particle slots per tile per species */
-  int32_t exchange_slots;                  /* inbox/hole slots per tile per species */
+  int32_t exchange_slots;                  /* inbox slots per tile per species */
+  int32_t tile_split;                      /* work-groups per tile */
   int64_t particle_slots[PIC_MAX_SPECIES]; /* total slots per species */
   int64_t n_cells;                         /* over all runs */
 } pic_plan_info;

@@ -48,14 +48,15 @@ class Options(ctypes.Structure):
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
                 ("slack", ctypes.c_double), ("exchange_frac", ctypes.c_double),
                 ("diag_every", ctypes.c_int32), ("history_cap", ctypes.c_int32),
-                ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32)]
+                ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32),
+                ("tile_split", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [("workspace_bytes", ctypes.c_uint64), ("tile_x", ctypes.c_int32),
                 ("tile_y", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("tile_slots", ctypes.c_int32 * PIC_MAX_SPECIES),
-                ("exchange_slots", ctypes.c_int32),
+                ("exchange_slots", ctypes.c_int32), ("tile_split", ctypes.c_int32),
                 ("particle_slots", ctypes.c_int64 * PIC_MAX_SPECIES),
                 ("n_cells", ctypes.c_int64)]
 
@@ -149,7 +150,7 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 
 
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
-                 diag_every=0, history_cap=1, cg_blocks=0, track_ids=True):
+                 diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0):
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
     o.solver = PIC_SOLVER_CG
@@ -158,6 +159,7 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)
     o.cg_blocks = int(cg_blocks)
     o.track_ids = 1 if track_ids else 0
+    o.tile_split = int(tile_split)
     return o
 
 

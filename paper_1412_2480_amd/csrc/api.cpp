@@ -188,6 +188,7 @@ template <typename R>
 size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
              bool split, bool ids, int hist_cap, pic_ctx* c, DevState<R>* st) {
   Bump b(base);
+  const int K = pl.tile_split;
   const long long nc = tl.n_cells;
   const size_t plane = (size_t)(tl.TXA + 5) * (tl.TYA + 5);
   DevRun* d_runs = b.take<DevRun>(n_runs);
@@ -216,11 +217,11 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   double* stats = b.take<double>((size_t)n_runs * 9);
   double* history = b.take<double>((size_t)n_runs * hist_cap * PIC_REC_WORDS);
   int* err = b.take<int>(1);
-  double* wk_part = b.take<double>((size_t)tl.n_tiles * PIC_MAXS * 2);
+  double* wk_part = b.take<double>((size_t)tl.n_tiles * K * PIC_MAXS * 2);
   double* rho = b.take<double>(tl.max_cells);
   double* divpart = b.take<double>((size_t)kDivBlocks * 2);
   double* patch[3];
-  for (int k = 0; k < 3; ++k) patch[k] = b.take<double>((size_t)tl.n_tiles * plane);
+  for (int k = 0; k < 3; ++k) patch[k] = b.take<double>((size_t)tl.n_tiles * K * plane);
   DevState<R> s{};
   for (int sp = 0; sp < PIC_MAXS; ++sp) {
     const size_t slots = (size_t)tl.n_tiles * pl.tile_slots[sp];
@@ -271,6 +272,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   s.PH = tl.TYA + 5;
   for (int sp = 0; sp < PIC_MAXS; ++sp) s.tile_slots[sp] = pl.tile_slots[sp];
   s.ex_slots = pl.exchange_slots;
+  s.K = K;
   s.runs = d_runs;
   s.tile_run = tile_run;
   for (int k = 0; k < 3; ++k) {
@@ -307,6 +309,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   f.err = err;
   f.stats = stats;
   f.wk_part = wk_part;
+  f.K = K;
   f.history = history;
   f.hist_cap = hist_cap;
   c->d_runs = d_runs;
@@ -358,6 +361,7 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
     p.tile_slots[s] = (int)slots;
     p.particle_slots[s] = slots * tl->n_tiles;
   }
+  p.tile_split = o->tile_split > 0 ? std::min(o->tile_split, 64) : 4;
   int ts = std::max(p.tile_slots[0], p.tile_slots[1]);
   p.exchange_slots = std::max(64, (int)(std::ceil(ts * exf) + 63) / 64 * 64);
   const int hist_cap = o->history_cap > 0 ? o->history_cap : 1;

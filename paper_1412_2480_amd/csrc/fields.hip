@@ -333,7 +333,7 @@ k_field_solve(FieldArgs a) {
     if (a.diag) {
       double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
       const int nt = R.ntx * R.nty;
-      for (int t = R.tile0; t < R.tile0 + nt; ++t)
+      for (int t = R.tile0 * a.K; t < (R.tile0 + nt) * a.K; ++t)
         for (int s = 0; s < R.nspecies; ++s) {
           wk[s][0] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 0];
           wk[s][1] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 1];

@@ -105,22 +105,15 @@ __device__ __forceinline__ int advance(R& f, R disp) {
   return d;
 }
 
-// node shapes of the Esirkepov window (P + 3 nodes starting one node before
-// the old support): old weights sit at window index 1, new weights at
-// index a1 = dc + first1 - first0 + 1, which is 0, 1 or 2
+// Node shapes on the Esirkepov window. A particle moves less than one cell,
+// so the first support node of the new position differs from that of the old
+// one by at most one node and both supports fit in P + 2 nodes starting at the
+// smaller first node. off is 0 or 1: where the P + 1 weights start.
 template <int P, typename R>
-__device__ __forceinline__ void window_shapes(const R (&w0)[P + 1], const R (&w1)[P + 1], int a1,
-                                              R (&S0)[P + 3], R (&DS)[P + 3]) {
-#pragma unroll
-  for (int a = 0; a < P + 3; ++a) {
-    const R s0 = (a >= 1 && a - 1 <= P) ? w0[a - 1 < 0 ? 0 : (a - 1 > P ? P : a - 1)] : R(0);
-    const R v0 = (a <= P) ? w1[a > P ? P : a] : R(0);
-    const R v1 = (a >= 1 && a - 1 <= P) ? w1[a - 1 < 0 ? 0 : (a - 1 > P ? P : a - 1)] : R(0);
-    const R v2 = (a >= 2 && a - 2 <= P) ? w1[a - 2 < 0 ? 0 : (a - 2 > P ? P : a - 2)] : R(0);
-    const R s1 = a1 == 0 ? v0 : (a1 == 1 ? v1 : v2);
-    S0[a] = s0;
-    DS[a] = s1 - s0;
-  }
+__device__ __forceinline__ R place(const R (&w)[P + 1], int off, int a) {
+  const R v0 = (a <= P) ? w[a > P ? P : a] : R(0);
+  const R v1 = (a >= 1) ? w[a < 1 ? 0 : a - 1] : R(0);
+  return off == 0 ? v0 : v1;
 }
 
 // reserve slots in counters[key] for every lane with want set, one atomic per
@@ -150,9 +143,9 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
 
 template <typename R, typename F, int P, int MODE>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
-                          int x0, int y0, int tw, int th, const F* sF, double* sJ, int* s_stay,
+                          int x0, int y0, int tw, int th, const F* sF, double* sJ, int part,
                           int diag, double (&wk)[PIC_MAXS][2]) {
-  constexpr int W = P + 3;
+  constexpr int W = P + 2;   // Esirkepov window: union of old and new supports
   const int PW = st.PW, PH = st.PH;
   const int plane = PW * PH;
   const R dt = R(run.dt);
@@ -160,14 +153,17 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
   const R lim = max_disp<R>();
 
   for (int s = 0; s < run.nspecies; ++s) {
-    const int n = st.cnt[s][tile];
+    const int n_all = st.cnt[s][tile];
+    // this work-group's share of the tile's particles
+    const int lo = (int)(((long long)n_all * part) / st.K);
+    const int n = (int)(((long long)n_all * (part + 1)) / st.K);
     const long long base = (long long)tile * st.tile_slots[s];
     const R qdt_2m = R(run.q[s] * run.dt / (2.0 * run.m[s]));
     const R cjx = R(-run.q[s] / (run.dy * run.dt));
     const R cjy = R(-run.q[s] / (run.dx * run.dt));
     const R cjz = R(run.q[s] / (run.dx * run.dy));
     const double mass = run.m[s];
-    for (int k0 = 0; k0 < n; k0 += blockDim.x) {
+    for (int k0 = lo; k0 < n; k0 += blockDim.x) {
       const int k = k0 + threadIdx.x;
       const bool active = k < n;
       bool leave = false;
@@ -280,17 +276,24 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           R w1x[P + 1], w1y[P + 1];
           const int f1x = bspline_weights<P, R>(fx1, w1x);
           const int f1y = bspline_weights<P, R>(fy1, w1y);
-          int a1x = dcx + f1x - f0x + 1, a1y = dcy + f1y - f0y + 1;
-          a1x = a1x < 0 ? 0 : (a1x > 2 ? 2 : a1x);
-          a1y = a1y < 0 ? 0 : (a1y > 2 ? 2 : a1y);
+          // first support nodes (relative to the old cell) of old and new shapes
+          const int n1x = dcx + f1x, n1y = dcy + f1y;
+          const int Ax = f0x < n1x ? f0x : n1x, Ay = f0y < n1y ? f0y : n1y;
+          const int o0x = f0x - Ax, o1x = n1x - Ax, o0y = f0y - Ay, o1y = n1y - Ay;
           R S0x[W], DSx[W], S0y[W], DSy[W];
-          window_shapes<P, R>(w0x, w1x, a1x, S0x, DSx);
-          window_shapes<P, R>(w0y, w1y, a1y, S0y, DSy);
-          const int ax0 = lx + f0x - 1 + G, ay0 = ly + f0y - 1 + G;
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            S0x[a] = place<P, R>(w0x, o0x, a);
+            DSx[a] = place<P, R>(w1x, o1x, a) - S0x[a];
+            S0y[a] = place<P, R>(w0y, o0y, a);
+            DSy[a] = place<P, R>(w1y, o1y, a) - S0y[a];
+          }
+          const int ax0 = lx + Ax + G, ay0 = ly + Ay + G;
           const R vz = uz / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
           double* jx = sJ;
           double* jy = sJ + plane;
           double* jz = sJ + 2 * plane;
+          // Jx(i+1/2): running sum of Wx along x; the last node's sum is zero
 #pragma unroll
           for (int b = 0; b < W; ++b) {
             const R wy = S0y[b] + R(0.5) * DSy[b];
@@ -345,7 +348,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
         const bool stay = active && !leave;
         const unsigned long long m = __ballot(stay);
         int wbase = 0;
-        if (__lane_id() == 0 && m) wbase = atomicAdd(&s_stay[s], __popcll(m));
+        if (__lane_id() == 0 && m) wbase = atomicAdd(&st.stay_cnt[s][tile], __popcll(m));
         wbase = __shfl(wbase, 0);
         if (stay) {
           const int lane = __lane_id();
@@ -382,10 +385,11 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
 
 template <typename R, typename F, int MODE>
 __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
-  // XCD-aware order: consecutive tiles go to the same XCD
+  // XCD-aware order: consecutive (tile, part) items go to the same XCD
   const int per = gridDim.x / 8;
-  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (tile >= st.n_tiles) return;
+  const int item = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (item >= st.n_tiles * st.K) return;
+  const int tile = item / st.K, part = item % st.K;
   const int ri = st.tile_run[tile];
   const DevRun& run = st.runs[ri];
   const int lt = tile - run.tile0;
@@ -402,10 +406,8 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   // atomic add retires about 20x faster than an FP32 one
   double* sJ = reinterpret_cast<double*>(smem_raw + fbytes);
   const int nj = (MODE == MODE_PUSH) ? 0 : (MODE == MODE_CHARGE ? 1 : 3);
-  __shared__ int s_stay[PIC_MAXS];
   __shared__ double s_red[4][PIC_MAXS * 2];
 
-  if (threadIdx.x < PIC_MAXS) s_stay[threadIdx.x] = 0;
   if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
     for (int e = threadIdx.x; e < plane; e += blockDim.x) {
       const int ly = e / PW - G, lx = e % PW - G;
@@ -431,25 +433,22 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
   switch (run.order) {
     case 1:
-      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
+      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
       break;
     case 2:
-      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
+      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
       break;
     default:
-      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, s_stay, diag, wk);
+      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
       break;
   }
   __syncthreads();
 
   if constexpr (MODE != MODE_PUSH) {
     for (int c = 0; c < nj; ++c) {
-      double* out = st.patch[c] + (size_t)tile * plane;
+      double* out = st.patch[c] + (size_t)item * plane;
       for (int e = threadIdx.x; e < plane; e += blockDim.x) out[e] = sJ[c * plane + e];
     }
-  }
-  if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
-    if (threadIdx.x < run.nspecies) st.stay_cnt[threadIdx.x][tile] = s_stay[threadIdx.x];
   }
   if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
     if (diag) {
@@ -466,7 +465,7 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
       if (threadIdx.x < PIC_MAXS * 2) {
         double v = 0.0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) v += s_red[w][threadIdx.x];
-        st.wk_part[(size_t)tile * PIC_MAXS * 2 + threadIdx.x] = v;
+        st.wk_part[(size_t)item * PIC_MAXS * 2 + threadIdx.x] = v;
       }
     }
   }
@@ -504,6 +503,7 @@ __global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
   if (threadIdx.x == 0) {
     st.cnt[s][tile] = S + A;
     st.in_cnt[s][tile] = 0;
+    st.stay_cnt[s][tile] = 0;
   }
 }
 
@@ -536,9 +536,12 @@ __global__ void __launch_bounds__(256) k_current_sum(DevState<R> st, int ncomp, 
       const int hx = pic_tile_width(t_x, TX, run.ntx, run.nx);
       const int lx = i - ox;
       if (lx < -G || lx > hx + PIC_GUARD_HI - 1) continue;
-      const size_t off = (size_t)(run.tile0 + t_y * run.ntx + t_x) * plane +
-                         (size_t)(ly + G) * PW + (lx + G);
-      for (int c = 0; c < ncomp; ++c) acc[c] += (double)st.patch[c][off];
+      const size_t t = (size_t)(run.tile0 + t_y * run.ntx + t_x);
+      const size_t in_patch = (size_t)(ly + G) * PW + (lx + G);
+      for (int pk = 0; pk < st.K; ++pk) {
+        const size_t off = (t * st.K + pk) * plane + in_patch;
+        for (int c = 0; c < ncomp; ++c) acc[c] += st.patch[c][off];
+      }
     }
   }
   const long long g = run.cell0 + k;
@@ -608,7 +611,7 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
                                 hipStream_t s) {
   using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
   const size_t smem = pic_particle_smem(st, mode);
-  const dim3 grid(grid_tiles(st.n_tiles)), block(threads);
+  const dim3 grid(grid_tiles(st.n_tiles * st.K)), block(threads);
   switch (mode) {
     case MODE_FUSED:
       k_particles<R, F, MODE_FUSED><<<grid, block, smem, s>>>(st, diag);

@@ -36,7 +36,8 @@ struct DevState {
   int n_runs, n_tiles;
   int TX, TY, TXA, TYA, PW, PH;  // tile shape, widest tile, patch pitch/rows
   int tile_slots[PIC_MAXS];
-  int ex_slots;                   // inbox / hole slots per tile per species
+  int ex_slots;                   // inbox slots per tile per species
+  int K;                          // work-groups per tile (each takes 1/K of its particles)
   const DevRun* runs;
   const int* tile_run;            // run index of each global tile
 
@@ -82,8 +83,8 @@ struct DevState {
   R* old_ox[PIC_MAXS];
   R* old_oy[PIC_MAXS];
 
-  double* patch[3];               // per-tile current patches [tile][PH][PW] (FP64)
-  double* wk_part;                // [tile][species][2] kinetic energy partials
+  double* patch[3];               // current patches [tile][K][PH][PW] (FP64)
+  double* wk_part;                // [tile][K][species][2] kinetic energy partials
   int* err;                       // error bits
 };
 

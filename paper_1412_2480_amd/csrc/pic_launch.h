@@ -29,7 +29,8 @@ struct FieldArgs {
   unsigned* bar;           // grid barrier: counter at [0], generation at [32]
   int* err;                // error bits
   double* stats;           // [run][9]: iters, relres, ||b||
-  const double* wk_part;   // [tile][species][2] kinetic partials
+  const double* wk_part;   // [tile][K][species][2] kinetic partials
+  int K;                   // work-groups per tile in the particle kernel
   double* history;         // [run][hist_cap][PIC_REC_WORDS]
   int hist_cap, hist_slot;
   long long step;
