@@ -83,6 +83,52 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
                 cg_iters=st[0]["iters"], n_particles=n_part)
 
 
+def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
+    """The 48-run sweep table in one context (FP32 particles) against the same
+    runs launched one context at a time; aggregate particle-steps/s."""
+    from synth import configs, loads
+    table = configs.sweep_runs()
+    descs, lds = [], []
+    for t in table:
+        Q = loads.macro_charge(t["gamma0"], t["dx"], t["dx"], t["ppc"])
+        descs.append(pic.run_desc(t["nx"], t["ny"], t["dx"], t["cfl"], t["theta"], t["order"],
+                                  [(-Q, Q, t["ppc"]), (Q, Q, t["ppc"])], cg_rtol=1e-8))
+        lds.append(loads.pair_plasma_cells(t["nx"], t["ny"], t["ppc"], t["gamma0"], t["T"],
+                                           t["seed"]))
+    n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
+    opts = pic.make_options("fp32", tile=(16, 16), track_ids=False)
+    sim = pic.Sim(descs, opts)
+    for r, ld in enumerate(lds):
+        for s in range(2):
+            d = ld[s]
+            sim.load_particles(r, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc = sim.step_async(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if rc != 0:
+        raise RuntimeError(f"batched pic_step returned {pic.STATUS.get(rc, rc)}")
+    sim.close()
+    seq_ms = 0.0
+    for r, ld in enumerate(lds):
+        one = pic.Sim([descs[r]], opts)
+        for s in range(2):
+            d = ld[s]
+            one.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+        one.step(1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        one.step_async(seq_steps)
+        torch.cuda.synchronize()
+        seq_ms += (time.perf_counter() - t0) * 1e3 / seq_steps
+        one.close()
+    return dict(runs=len(table), particles=n_part, ms_per_step=ms,
+                particle_steps_per_s=n_part / (ms * 1e-3), sequential_ms_per_step=seq_ms,
+                batched_speedup=seq_ms / ms)
+
+
 def cpu_baseline(cfg, seconds=15.0):
     """The FP64 oracle on a 4-row strip of the same workload (same grid width,
     ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
@@ -121,6 +167,7 @@ def main():
     ap.add_argument("--tile-split", type=int, default=0, help="work-groups per tile (0 = auto)")
     ap.add_argument("--sweep-tiles", default="",
                     help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 48-run batched sweep")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 512 MiB buffer three times (a plain copy kernel of known "
                          "size, for scaling HBM traffic counters)")
@@ -174,6 +221,13 @@ def main():
         log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
     del load
 
+    batched = None
+    if not args.no_batched:
+        log("bench: batched 48-run sweep")
+        batched = batched_sweep(pic, torch, 20, 3)
+        log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs, "
+            f"sequential {batched['sequential_ms_per_step']:.3f} ms")
+
     cpu = None
     if not args.no_cpu:
         log("bench: oracle CPU baseline")
@@ -212,6 +266,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
                      "avg_launch_ms": fast["push_ms"]},
+        "batched_sweep": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
