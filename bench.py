@@ -184,13 +184,18 @@ def main():
     cfg = CONFIGS[args.config]
     tile = tuple(int(v) for v in args.tile.split("x"))
     if args.calib_copy:
-        src = torch.ones(128 << 20, dtype=torch.float32, device="cuda")
+        # A plain elementwise kernel of known size for scaling the HBM traffic
+        # counters: the source is written first, then a second 1 GiB buffer is
+        # written so the source is no longer resident in the 256 MB Infinity
+        # Cache; the multiply then reads 1 GiB and writes 1 GiB.
+        n = 256 << 20
+        src = torch.full((n,), 1.5, dtype=torch.float32, device="cuda")
+        flush = torch.full((n,), 2.5, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.mul(src, 2.0, out=dst)   # an elementwise kernel: reads and writes 512 MiB
+        torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
-        del src, dst
-        log("bench: calibration copies done (3 x 512 MiB)")
+        del src, dst, flush
+        log("bench: calibration multiply done (reads 1 GiB, writes 1 GiB)")
     log(f"bench: generating load {cfg['label']}")
     t0 = time.perf_counter()
     load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
