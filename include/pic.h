@@ -60,7 +60,14 @@ enum pic_status {
 
 enum pic_bc { PIC_BC_PERIODIC = 0 };
 enum pic_precision { PIC_FP64 = 0, PIC_FP32_FAST = 1 };
-enum pic_solver { PIC_SOLVER_CG = 0 };
+enum pic_solver {
+  PIC_SOLVER_CG = 0,          /* plain CG on Eq. (7) (the paper's solver) */
+  PIC_SOLVER_LEARNED_PCG = 1  /* learned x0 + flexible PCG, plain-CG fallback (an addition) */
+};
+enum pic_learned_form {
+  PIC_NET_COLLAPSED = 0,      /* the network's exact 7 x 7 composite filter, FP64 */
+  PIC_NET_MFMA = 1            /* the network itself, BF16 matrix cores, FP32 accumulation */
+};
 enum pic_field_id {
   PIC_EX = 0, PIC_EY, PIC_EZ, PIC_BX, PIC_BY, PIC_BZ, PIC_JX, PIC_JY, PIC_JZ, PIC_RHO
 };
@@ -87,7 +94,7 @@ typedef struct pic_run_desc {
 
 typedef struct pic_options {
   int32_t precision;     /* PIC_FP64 or PIC_FP32_FAST (particles in FP32, fields FP64) */
-  int32_t solver;        /* PIC_SOLVER_CG */
+  int32_t solver;        /* PIC_SOLVER_CG or PIC_SOLVER_LEARNED_PCG */
   int32_t tile_x, tile_y;/* tile shape in cells; 0 picks a default */
   double slack;          /* extra tile slots over ppc*cells (default 0.25 if <= 0) */
   double exchange_frac;  /* inbox/hole slots per tile as a fraction of tile slots (0.25) */
@@ -98,6 +105,10 @@ typedef struct pic_options {
                             0: no ids (8 B less traffic per particle-step), reads return
                             storage order */
   int32_t tile_split;    /* work-groups per tile in the particle kernel; 0 = 4 */
+  int32_t learned_form;  /* PIC_NET_COLLAPSED or PIC_NET_MFMA (learned solver only) */
+  int32_t learned_maxit; /* iteration budget of the learned PCG before the plain-CG
+                            fallback; 0 = 30 */
+  int32_t precond_slots; /* (b, dB) training pairs kept (ring); 0 = 16 */
 } pic_options;
 
 typedef struct pic_plan_info {
@@ -112,9 +123,11 @@ typedef struct pic_plan_info {
 } pic_plan_info;
 
 typedef struct pic_solve_stats {
-  int32_t iters[3];      /* CG iterations per B component */
+  int32_t iters[3];      /* CG iterations per B component (learned + plain) */
   double relres[3];      /* recursive relative residual ||r||/||b|| at exit */
   double bnorm[3];       /* ||b||_2 of Eq. (7)'s right-hand side */
+  int32_t learned_iters[3]; /* iterations of the learned PCG (0 with plain CG) */
+  int32_t fallback;      /* 1 if the learned PCG missed cg_rtol and plain CG finished */
 } pic_solve_stats;
 
 typedef struct pic_diag_out {
@@ -195,6 +208,56 @@ int32_t pic_history(pic_ctx* ctx, int32_t run, pic_diag_out* out, int32_t cap, i
 /* Event timing per kernel class (on the context stream). */
 int32_t pic_timing(pic_ctx* ctx, int32_t on);
 int32_t pic_get_timing(pic_ctx* ctx, pic_timing_out* out);
+
+/* ---- Learned CG aid (solver PIC_SOLVER_LEARNED_PCG; an addition to the
+ * paper, which solves Eq. (7) by plain CG). A linear network N of three 3 x 3
+ * periodic convolutions, 1 -> 32 -> 32 -> 1 channels (9792 FP32 weights,
+ * layout W1[32][3][3], W2[32][32][3][3], W3[32][3][3], taps [dy][dx] with
+ * offset (dx-1, dy-1)), approximates the inverse of Eq. (7)'s operator. Every
+ * run of the context must share dx, dy, cfl and theta (one operator). The
+ * field solve starts from x0 = N(b) and runs flexible PCG with z = N(r) to
+ * cg_rtol; plain CG from the current iterate finishes any component that
+ * misses it within learned_maxit, so the result always meets cg_rtol as plain
+ * CG would. The weights start at the identity map plus small fixed noise. */
+typedef struct pic_train_opts {
+  int32_t epochs;        /* passes over the recorded pairs (>= 1) */
+  double lr;             /* Adam step size; <= 0 picks 1e-3 */
+} pic_train_opts;
+
+typedef struct pic_train_stats {
+  double loss_first;     /* mean of sum (N(b) - dB)^2 / sum dB^2 over the first epoch */
+  double loss_last;      /* the same over the last epoch */
+  int32_t samples;       /* (pair, component) samples per epoch */
+  int32_t updates;       /* Adam updates made */
+} pic_train_stats;
+
+/* Record (b, dB) of run 0 from every following field solve (on != 0) into
+ * the ring of precond_slots pairs; n_pairs (nullable) receives the number held. */
+int32_t pic_precond_collect(pic_ctx* ctx, int32_t on, int32_t* n_pairs);
+
+/* Train N on the recorded pairs: per epoch one Adam update per (pair,
+ * component) sample, oldest pair first, all in FP32 on the device; then
+ * refresh the BF16 copy and the collapsed filter. Synchronises. */
+int32_t pic_precond_train(pic_ctx* ctx, const pic_train_opts* opts, pic_train_stats* out);
+
+/* Use the learned path in the following field solves (on != 0, the default
+ * for PIC_SOLVER_LEARNED_PCG) or plain CG (on == 0). */
+int32_t pic_precond_use(pic_ctx* ctx, int32_t on);
+
+/* Copy the FP32 weights out / in (n must be 9792). set_weights refreshes the
+ * derived BF16 copy and collapsed filter. */
+int32_t pic_precond_get_weights(pic_ctx* ctx, float* host, size_t n);
+int32_t pic_precond_set_weights(pic_ctx* ctx, const float* host, size_t n);
+
+/* For parity checks. apply: d_out = N(d_in) on one nx x ny periodic FP64
+ * device field ([ny][nx]) in the given form (PIC_NET_COLLAPSED or
+ * PIC_NET_MFMA). grad: FP32 loss and weight gradient of one sample (d_b, d_t
+ * device FP64 fields), host_grad receiving n = 9792 floats. Both need
+ * nx * ny <= run 0's cell count, nx, ny >= 3, and synchronise. */
+int32_t pic_precond_apply(pic_ctx* ctx, int32_t form, int32_t nx, int32_t ny, const double* d_in,
+                          double* d_out);
+int32_t pic_precond_grad(pic_ctx* ctx, int32_t nx, int32_t ny, const double* d_b,
+                         const double* d_t, float* host_grad, size_t n, double* loss);
 
 int32_t pic_sync(pic_ctx* ctx);
 int32_t pic_destroy(pic_ctx* ctx);

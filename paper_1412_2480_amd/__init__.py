@@ -17,7 +17,9 @@ LIB_PATH = os.path.join(HERE, "libpic.so")
 
 PIC_MAX_SPECIES = 2
 PIC_FP64, PIC_FP32_FAST = 0, 1
-PIC_SOLVER_CG = 0
+PIC_SOLVER_CG, PIC_SOLVER_LEARNED_PCG = 0, 1
+PIC_NET_COLLAPSED, PIC_NET_MFMA = 0, 1
+NET_NW = 9792
 PIC_BC_PERIODIC = 0
 FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
              "rho": 9}
@@ -25,8 +27,10 @@ STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
           -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
 EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_read_particles", "pic_set_field",
            "pic_get_field", "pic_gather_push", "pic_deposit", "pic_field_solve", "pic_step",
-           "pic_diag", "pic_history", "pic_timing", "pic_get_timing", "pic_sync", "pic_destroy",
-           "pic_last_error", "pic_status_str"]
+           "pic_diag", "pic_history", "pic_timing", "pic_get_timing", "pic_precond_collect",
+           "pic_precond_train", "pic_precond_use", "pic_precond_get_weights",
+           "pic_precond_set_weights", "pic_precond_apply", "pic_precond_grad", "pic_sync",
+           "pic_destroy", "pic_last_error", "pic_status_str"]
 
 
 class SpeciesDesc(ctypes.Structure):
@@ -49,7 +53,8 @@ class Options(ctypes.Structure):
                 ("slack", ctypes.c_double), ("exchange_frac", ctypes.c_double),
                 ("diag_every", ctypes.c_int32), ("history_cap", ctypes.c_int32),
                 ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32),
-                ("tile_split", ctypes.c_int32)]
+                ("tile_split", ctypes.c_int32), ("learned_form", ctypes.c_int32),
+                ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -63,7 +68,17 @@ class PlanInfo(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32 * 3), ("relres", ctypes.c_double * 3),
-                ("bnorm", ctypes.c_double * 3)]
+                ("bnorm", ctypes.c_double * 3), ("learned_iters", ctypes.c_int32 * 3),
+                ("fallback", ctypes.c_int32)]
+
+
+class TrainOpts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_double)]
+
+
+class TrainStats(ctypes.Structure):
+    _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
+                ("samples", ctypes.c_int32), ("updates", ctypes.c_int32)]
 
 
 class DiagOut(ctypes.Structure):
@@ -114,6 +129,16 @@ def lib():
                                   ctypes.c_int32, P(ctypes.c_int32)]
         L.pic_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
         L.pic_get_timing.argtypes = [ctypes.c_void_p, P(TimingOut)]
+        L.pic_precond_collect.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_int32)]
+        L.pic_precond_train.argtypes = [ctypes.c_void_p, P(TrainOpts), P(TrainStats)]
+        L.pic_precond_use.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+        L.pic_precond_get_weights.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+        L.pic_precond_set_weights.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t]
+        L.pic_precond_apply.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+        L.pic_precond_grad.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_size_t, P(ctypes.c_double)]
         L.pic_sync.argtypes = [ctypes.c_void_p]
         L.pic_destroy.argtypes = [ctypes.c_void_p]
         L.pic_last_error.argtypes = [ctypes.c_void_p]
@@ -150,10 +175,17 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 
 
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
-                 diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0):
+                 diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0,
+                 solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0):
+    """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma"."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
-    o.solver = PIC_SOLVER_CG
+    o.solver = PIC_SOLVER_LEARNED_PCG if solver in ("learned", PIC_SOLVER_LEARNED_PCG) \
+        else PIC_SOLVER_CG
+    o.learned_form = PIC_NET_MFMA if learned_form in ("mfma", PIC_NET_MFMA) \
+        else PIC_NET_COLLAPSED
+    o.learned_maxit = int(learned_maxit)
+    o.precond_slots = int(precond_slots)
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)
@@ -257,7 +289,8 @@ class Sim:
         self._check(self.L.pic_deposit(self.ctx), "deposit")
 
     def _stats(self, st):
-        return [dict(iters=list(s.iters), relres=list(s.relres), bnorm=list(s.bnorm)) for s in st]
+        return [dict(iters=list(s.iters), relres=list(s.relres), bnorm=list(s.bnorm),
+                     learned_iters=list(s.learned_iters), fallback=s.fallback) for s in st]
 
     def field_solve(self, allow_noconv=False):
         st = (SolveStats * len(self.runs))()
@@ -305,6 +338,61 @@ class Sim:
         self._check(self.L.pic_history(self.ctx, run, out, cap, ctypes.byref(n)), "history")
         return [self._rec(out[k]) for k in range(n.value)]
 
+    # ---- learned CG aid
+    def precond_collect(self, on=True):
+        n = ctypes.c_int32(0)
+        self._check(self.L.pic_precond_collect(self.ctx, 1 if on else 0, ctypes.byref(n)),
+                    "precond_collect")
+        return n.value
+
+    def precond_train(self, epochs=1, lr=0.0):
+        o = TrainOpts()
+        o.epochs, o.lr = int(epochs), float(lr)
+        st = TrainStats()
+        self._check(self.L.pic_precond_train(self.ctx, ctypes.byref(o), ctypes.byref(st)),
+                    "precond_train")
+        return dict(loss_first=st.loss_first, loss_last=st.loss_last, samples=st.samples,
+                    updates=st.updates)
+
+    def precond_use(self, on=True):
+        self._check(self.L.pic_precond_use(self.ctx, 1 if on else 0), "precond_use")
+
+    def get_weights(self):
+        w = np.empty(NET_NW, np.float32)
+        self._check(self.L.pic_precond_get_weights(self.ctx, _ptr(w), NET_NW), "get_weights")
+        return w
+
+    def set_weights(self, w):
+        a = np.ascontiguousarray(w, dtype=np.float32).ravel()
+        self._check(self.L.pic_precond_set_weights(self.ctx, _ptr(a), a.size), "set_weights")
+
+    def _device_field(self, a):
+        import torch
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=self.device)
+
+    def precond_apply(self, x, form="collapsed"):
+        """N(x) for one [ny][nx] periodic field (host array in, host array out)."""
+        xd = self._device_field(x)
+        yd = torch_empty_like(xd)
+        f = PIC_NET_MFMA if form in ("mfma", PIC_NET_MFMA) else PIC_NET_COLLAPSED
+        ny, nx = xd.shape
+        self.stream.synchronize()
+        self._check(self.L.pic_precond_apply(self.ctx, f, nx, ny, ctypes.c_void_p(xd.data_ptr()),
+                                             ctypes.c_void_p(yd.data_ptr())), "precond_apply")
+        return yd.cpu().numpy()
+
+    def precond_grad(self, b, t):
+        """(loss, dL/dW) of one sample, L = sum (N(b) - t)^2 / sum t^2."""
+        bd, td = self._device_field(b), self._device_field(t)
+        ny, nx = bd.shape
+        g = np.empty(NET_NW, np.float32)
+        loss = ctypes.c_double(0.0)
+        self.stream.synchronize()
+        self._check(self.L.pic_precond_grad(self.ctx, nx, ny, ctypes.c_void_p(bd.data_ptr()),
+                                            ctypes.c_void_p(td.data_ptr()), _ptr(g), NET_NW,
+                                            ctypes.byref(loss)), "precond_grad")
+        return loss.value, g
+
     def timing(self, on=True):
         self._check(self.L.pic_timing(self.ctx, 1 if on else 0), "timing")
 
@@ -313,6 +401,11 @@ class Sim:
         self._check(self.L.pic_get_timing(self.ctx, ctypes.byref(t)), "get_timing")
         return {name: dict(ms=t.ms[k], launches=t.launches[k])
                 for k, name in enumerate(TIMING_CLASSES)}
+
+
+def torch_empty_like(t):
+    import torch
+    return torch.empty_like(t)
 
 
 def exported_symbols():

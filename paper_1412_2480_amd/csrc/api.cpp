@@ -21,6 +21,9 @@ constexpr int kMaxCgBlocks = 4096;
 constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kTimingClasses = 8;
+constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
+constexpr int kDefaultLearnedMaxit = 30;
+constexpr int kDefaultPrecondSlots = 16;
 
 struct Bump {
   uint8_t* base;
@@ -81,6 +84,16 @@ struct pic_ctx {
   DevState<double> sd{};
   FieldArgs fa{};
   double* d_stats = nullptr;
+  // learned aid
+  bool learned = false;      // storage carved (solver PIC_SOLVER_LEARNED_PCG)
+  bool use_learned = false;  // field solves take the learned path
+  bool collect = false;
+  NetTrain net{};
+  double* d_pairs = nullptr;
+  int pair_slots = 0;
+  long long pairs_written = 0;
+  long long train_cells = 0;
+  int adam_step = 0;
   double* d_history = nullptr;
   double* d_rho = nullptr;
   double* d_divpart = nullptr;
@@ -127,9 +140,26 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     *msg = "precision must be PIC_FP64 or PIC_FP32_FAST";
     return PIC_E_INVAL;
   }
-  if (o->solver != PIC_SOLVER_CG) {
+  if (o->solver != PIC_SOLVER_CG && o->solver != PIC_SOLVER_LEARNED_PCG) {
     *msg = "unknown solver";
     return PIC_E_INVAL;
+  }
+  if (o->solver == PIC_SOLVER_LEARNED_PCG) {
+    if (o->learned_form != PIC_NET_COLLAPSED && o->learned_form != PIC_NET_MFMA) {
+      *msg = "learned_form must be PIC_NET_COLLAPSED or PIC_NET_MFMA";
+      return PIC_E_INVAL;
+    }
+    if (o->learned_maxit < 0 || o->precond_slots < 0) {
+      *msg = "learned_maxit and precond_slots must be >= 0";
+      return PIC_E_INVAL;
+    }
+    // one network approximates one operator of Eq. (7)
+    for (int r = 1; r < n_runs; ++r)
+      if (runs[r].dx != runs[0].dx || runs[r].dy != runs[0].dy || runs[r].cfl != runs[0].cfl ||
+          runs[r].theta != runs[0].theta) {
+        *msg = "the learned solver needs equal dx, dy, cfl and theta in every run";
+        return PIC_E_INVAL;
+      }
   }
   for (int r = 0; r < n_runs; ++r) {
     const pic_run_desc& d = runs[r];
@@ -186,7 +216,8 @@ void make_tiling(const pic_run_desc* runs, int n_runs, const pic_options* o, Til
 // Carve (or, with base == nullptr, size) the workspace.
 template <typename R>
 size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
-             bool split, bool ids, int hist_cap, pic_ctx* c, DevState<R>* st) {
+             bool split, bool ids, int hist_cap, int pair_slots, long long train_cells, pic_ctx* c,
+             DevState<R>* st) {
   Bump b(base);
   const int K = pl.tile_split;
   const long long nc = tl.n_cells;
@@ -211,10 +242,33 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     s0[k] = b.take<double>(nc);
     s1[k] = b.take<double>(nc);
   }
-  double* part = b.take<double>((size_t)kMaxCgBlocks * 16);
+  double* part = b.take<double>((size_t)kMaxCgBlocks * 24);
   int* g_active = b.take<int>(4);
   unsigned* bar = b.take<unsigned>(64);
-  double* stats = b.take<double>((size_t)n_runs * 9);
+  double* stats = b.take<double>((size_t)n_runs * PIC_STAT_WORDS);
+  NetTrain nt{};
+  double* pairs = nullptr;
+  if (pair_slots > 0) {
+    const size_t n1 = (size_t)train_cells, nC = n1 * NET_C;
+    nt.w = b.take<float>(NET_NW);
+    nt.w2b = b.take<__bf16>(NET_C * NET_C * 9);
+    nt.k49 = b.take<double>(64);
+    nt.grad = b.take<float>(NET_NW);
+    nt.m = b.take<float>(NET_NW);
+    nt.v = b.take<float>(NET_NW);
+    nt.part = b.take<float>((size_t)kWgradBlocks * NET_C * NET_C * 9);
+    nt.xin = b.take<float>(n1);
+    nt.y = b.take<float>(n1);
+    nt.gy = b.take<float>(n1);
+    nt.h1 = b.take<float>(nC);
+    nt.h2 = b.take<float>(nC);
+    nt.gh1 = b.take<float>(nC);
+    nt.gh2 = b.take<float>(nC);
+    nt.dpart = b.take<double>(512);
+    nt.scal = b.take<double>(4);
+    nt.wg_blocks = kWgradBlocks;
+    pairs = b.take<double>((size_t)pair_slots * 6 * n1);
+  }
   double* history = b.take<double>((size_t)n_runs * hist_cap * PIC_REC_WORDS);
   int* err = b.take<int>(1);
   double* wk_part = b.take<double>((size_t)tl.n_tiles * K * PIC_MAXS * 2);
@@ -312,6 +366,10 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   f.K = K;
   f.history = history;
   f.hist_cap = hist_cap;
+  f.net = NetWeights{nt.w, nt.w2b, nt.k49};
+  f.pairs = pairs;
+  c->net = nt;
+  c->d_pairs = pairs;
   c->d_runs = d_runs;
   c->d_tile_run = tile_run;
   c->d_stats = stats;
@@ -320,6 +378,11 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   c->d_divpart = divpart;
   c->d_err = err;
   return total;
+}
+
+int pair_slots_of(const pic_options* o) {
+  if (o->solver != PIC_SOLVER_LEARNED_PCG) return 0;
+  return o->precond_slots > 0 ? o->precond_slots : kDefaultPrecondSlots;
 }
 
 int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_plan_info* out,
@@ -367,10 +430,12 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   const int hist_cap = o->history_cap > 0 ? o->history_cap : 1;
   const bool split = true;
   const bool ids = o->track_ids != 0;
+  const int slots = pair_slots_of(o);
+  const long long tc = (long long)runs[0].nx * runs[0].ny;
   p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, ids, hist_cap,
-                                          nullptr, (DevState<float>*)nullptr)
+                                          slots, tc, nullptr, (DevState<float>*)nullptr)
                            : carve<double>(nullptr, *tl, p, n_runs, false, split, ids, hist_cap,
-                                           nullptr, (DevState<double>*)nullptr);
+                                           slots, tc, nullptr, (DevState<double>*)nullptr);
   *out = p;
   return PIC_OK;
 }
@@ -463,6 +528,9 @@ int launch_field(pic_ctx* c, int diag) {
   a.diag = diag;
   a.step = c->step;
   a.hist_slot = (int)(c->diag_count % std::max(1, c->opt.history_cap));
+  a.learned = c->use_learned ? 1 : 0;
+  a.collect = c->collect ? 1 : 0;
+  a.pair_slot = c->pair_slots > 0 ? (int)(c->pairs_written % c->pair_slots) : 0;
   t_begin(c, 5);
   hipError_t e = pic_launch_field_solve(a, c->stream);
   t_end(c);
@@ -471,24 +539,28 @@ int launch_field(pic_ctx* c, int diag) {
     c->hist_step.push_back(c->step);
     c->diag_count += 1;
   }
+  if (c->collect) c->pairs_written += 1;
   return PIC_OK;
 }
 
 int read_stats(pic_ctx* c, pic_solve_stats* out) {
   const int n = (int)c->runs.size();
-  std::vector<double> h((size_t)n * 9);
+  std::vector<double> h((size_t)n * PIC_STAT_WORDS);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_stats, h.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   int rc = PIC_OK;
   for (int r = 0; r < n; ++r) {
+    const double* st = h.data() + (size_t)r * PIC_STAT_WORDS;
+    if (out) out[r].fallback = (int)st[12];
     for (int k = 0; k < 3; ++k) {
-      const int it = (int)h[r * 9 + k];
-      const double rel = h[r * 9 + 3 + k];
+      const int it = (int)st[k];
+      const double rel = st[3 + k];
       if (out) {
         out[r].iters[k] = it;
         out[r].relres[k] = rel;
-        out[r].bnorm[k] = h[r * 9 + 6 + k];
+        out[r].bnorm[k] = st[6 + k];
+        out[r].learned_iters[k] = (int)st[9 + k];
       }
       if (!std::isfinite(rel)) rc = PIC_E_NAN;
       else if (it >= c->runs[r].cg_maxit && rel > c->runs[r].cg_rtol && rc == PIC_OK)
@@ -690,6 +762,30 @@ int rho_impl(pic_ctx* c, int run) {
   return PIC_OK;
 }
 
+// Identity map plus small fixed noise (a splitmix64 sequence mapped to
+// [-1, 1)), so that every channel receives gradient from the first update.
+std::vector<float> initial_weights() {
+  std::vector<float> w(NET_NW);
+  uint64_t z = 0x2545F4914F6CDD1DULL;
+  auto next = [&]() {
+    z += 0x9E3779B97F4A7C15ULL;
+    uint64_t x = z;
+    x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+    x ^= x >> 31;
+    return (double)(x >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+  };
+  const double amp = 0.01 * std::sqrt(3.0);   // standard deviation 0.01
+  for (int k = 0; k < NET_C * 9; ++k) w[NET_W1 + k] = (float)(amp * next());
+  for (int k = 0; k < NET_C * NET_C * 9; ++k)
+    w[NET_W2 + k] = (float)(amp * next() / std::sqrt((double)NET_C));
+  for (int k = 0; k < NET_C * 9; ++k) w[NET_W3 + k] = (float)(amp * next() / std::sqrt((double)NET_C));
+  w[NET_W1 + 4] += 1.f;   // W1[0][1][1]
+  w[NET_W2 + 4] += 1.f;   // W2[0][0][1][1]
+  w[NET_W3 + 4] += 1.f;   // W3[0][1][1]
+  return w;
+}
+
 }  // namespace
 
 extern "C" {
@@ -725,12 +821,18 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   c->ws_bytes = ws_bytes;
   c->fast = opt->precision == PIC_FP32_FAST;
   c->ids = opt->track_ids != 0;
+  c->pair_slots = pair_slots_of(opt);
+  c->train_cells = (long long)runs[0].nx * runs[0].ny;
+  c->learned = c->pair_slots > 0;
+  c->use_learned = c->learned;
   if (c->fast)
-    carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->ids, c->opt.history_cap, c,
-                 &c->sf);
+    carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->ids, c->opt.history_cap,
+                 c->pair_slots, c->train_cells, c, &c->sf);
   else
-    carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap, c,
-                  &c->sd);
+    carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap,
+                  c->pair_slots, c->train_cells, c, &c->sd);
+  c->fa.learned_form = opt->learned_form;
+  c->fa.learned_maxit = opt->learned_maxit > 0 ? opt->learned_maxit : kDefaultLearnedMaxit;
 
   // CG work-groups: as many as can be co-resident, split over runs by cells
   int dev = 0, n_cu = 0;
@@ -739,7 +841,10 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     delete c;
     return PIC_E_HIP;
   }
-  int maxb = pic_field_solve_max_blocks(n_cu);
+  // the plain and the learned variant must both fit the same grid
+  int maxb = pic_field_solve_max_blocks(n_cu, 0, 0);
+  if (c->learned)
+    maxb = std::min(maxb, pic_field_solve_max_blocks(n_cu, 1, opt->learned_form));
   if (maxb < n_runs) {
     delete c;
     return PIC_E_HIP;
@@ -800,6 +905,11 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_tile_run, tile_run.data(), sizeof(int) * tile_run.size(),
                        hipMemcpyHostToDevice, S);
+  if (e == hipSuccess && c->learned) {
+    const std::vector<float> w0 = initial_weights();
+    e = hipMemcpyAsync(c->net.w, w0.data(), w0.size() * sizeof(float), hipMemcpyHostToDevice, S);
+    if (e == hipSuccess) e = pic_net_refresh(c->net, S);
+  }
   if (e == hipSuccess) e = hipStreamSynchronize(S);
   if (e != hipSuccess) {
     delete c;
@@ -1010,6 +1120,116 @@ int32_t pic_get_timing(pic_ctx* c, pic_timing_out* out) {
     out->ms[k] = c->t_ms[k];
     out->launches[k] = c->t_n[k];
   }
+  return PIC_OK;
+}
+
+int32_t pic_precond_collect(pic_ctx* c, int32_t on, int32_t* n_pairs) {
+  if (!c) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "collection needs solver PIC_SOLVER_LEARNED_PCG");
+  c->collect = on != 0;
+  if (n_pairs) *n_pairs = (int32_t)std::min<long long>(c->pairs_written, c->pair_slots);
+  return PIC_OK;
+}
+
+int32_t pic_precond_use(pic_ctx* c, int32_t on) {
+  if (!c) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "the learned path needs solver PIC_SOLVER_LEARNED_PCG");
+  c->use_learned = on != 0;
+  return PIC_OK;
+}
+
+int32_t pic_precond_train(pic_ctx* c, const pic_train_opts* o, pic_train_stats* out) {
+  if (!c || !o) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "training needs solver PIC_SOLVER_LEARNED_PCG");
+  if (o->epochs < 1) return fail(c, PIC_E_INVAL, "epochs must be >= 1");
+  const long long have = std::min<long long>(c->pairs_written, c->pair_slots);
+  if (have < 1) return fail(c, PIC_E_STATE, "no training pairs recorded");
+  const float lr = (float)(o->lr > 0 ? o->lr : 1e-3);
+  const long long n1 = c->train_cells;
+  const pic_run_desc& d = c->runs[0];
+  hipStream_t S = c->stream;
+  const long long oldest = c->pairs_written - have;
+  double first = 0, last = 0;
+  int updates = 0;
+  for (int ep = 0; ep < o->epochs; ++ep) {
+    HIPCHK(c, hipMemsetAsync(c->net.scal, 0, 4 * sizeof(double), S));
+    for (long long k = oldest; k < c->pairs_written; ++k) {
+      const double* pb = c->d_pairs + (size_t)(k % c->pair_slots) * 6 * n1;
+      for (int comp = 0; comp < 3; ++comp) {
+        HIPCHK(c, pic_net_grad(c->net, pb + (size_t)(2 * comp) * n1, pb + (size_t)(2 * comp + 1) * n1,
+                               d.nx, d.ny, S));
+        HIPCHK(c, pic_net_adam(c->net, lr, ++c->adam_step, S));
+        ++updates;
+      }
+    }
+    double scal[4];
+    HIPCHK(c, hipMemcpyAsync(scal, c->net.scal, sizeof scal, hipMemcpyDeviceToHost, S));
+    HIPCHK(c, hipStreamSynchronize(S));
+    const double mean = scal[2] / (double)(have * 3);
+    if (ep == 0) first = mean;
+    last = mean;
+  }
+  HIPCHK(c, pic_net_refresh(c->net, S));
+  HIPCHK(c, hipStreamSynchronize(S));
+  if (out) {
+    out->loss_first = first;
+    out->loss_last = last;
+    out->samples = (int32_t)(have * 3);
+    out->updates = updates;
+  }
+  if (!std::isfinite(last)) return fail(c, PIC_E_NAN, "non-finite training loss");
+  return PIC_OK;
+}
+
+int32_t pic_precond_get_weights(pic_ctx* c, float* host, size_t n) {
+  if (!c || !host) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
+  if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "weight count must be 9792");
+  HIPCHK(c, hipMemcpyAsync(host, c->net.w, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_precond_set_weights(pic_ctx* c, const float* host, size_t n) {
+  if (!c || !host) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
+  if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "weight count must be 9792");
+  for (size_t k = 0; k < n; ++k)
+    if (!std::isfinite(host[k])) return fail(c, PIC_E_INVAL, "non-finite weight");
+  HIPCHK(c, hipMemcpyAsync(c->net.w, host, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, pic_net_refresh(c->net, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_precond_apply(pic_ctx* c, int32_t form, int32_t nx, int32_t ny, const double* d_in,
+                          double* d_out) {
+  if (!c || !d_in || !d_out) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
+  if (form != PIC_NET_COLLAPSED && form != PIC_NET_MFMA)
+    return fail(c, PIC_E_INVAL, "form must be PIC_NET_COLLAPSED or PIC_NET_MFMA");
+  if (nx < 3 || ny < 3 || (long long)nx * ny > c->train_cells)
+    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= run 0's cells");
+  HIPCHK(c, pic_net_apply(c->net, form, d_in, d_out, nx, ny, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_precond_grad(pic_ctx* c, int32_t nx, int32_t ny, const double* d_b, const double* d_t,
+                         float* host_grad, size_t n, double* loss) {
+  if (!c || !d_b || !d_t || !host_grad) return PIC_E_INVAL;
+  if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
+  if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "gradient count must be 9792");
+  if (nx < 3 || ny < 3 || (long long)nx * ny > c->train_cells)
+    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= run 0's cells");
+  HIPCHK(c, hipMemsetAsync(c->net.scal, 0, 4 * sizeof(double), c->stream));
+  HIPCHK(c, pic_net_grad(c->net, d_b, d_t, nx, ny, c->stream));
+  double scal[4];
+  HIPCHK(c, hipMemcpyAsync(scal, c->net.scal, sizeof scal, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host_grad, c->net.grad, n * sizeof(float), hipMemcpyDeviceToHost,
+                           c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = scal[1];
   return PIC_OK;
 }
 

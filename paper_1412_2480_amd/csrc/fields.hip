@@ -7,28 +7,32 @@
 //
 // One persistent kernel per step does all of it for every run of the
 // context: each run owns a contiguous range of work-groups, the three B
-// components are solved together (three independent CG recurrences sharing
-// one stencil sweep), and grid-wide barriers separate the phases. All
-// arithmetic is FP64; block reductions are deterministic and are summed
-// across a run's blocks in a fixed order, so every block of a run holds
-// bit-identical CG scalars.
+// components are solved together (three recurrences sharing one sweep), and
+// grid-wide barriers separate the phases. All arithmetic of the solve is FP64;
+// block reductions are deterministic and are summed across a run's blocks in
+// a fixed order, so every block of a run holds bit-identical scalars.
 //
-// The CG recurrence is the Chronopoulos-Gear form (Chronopoulos & Gear 1989):
-// it produces the iterates of CG in exact arithmetic but needs a single global
+// Plain solver: the Chronopoulos-Gear form of CG (Chronopoulos & Gear 1989),
+// which produces the iterates of CG in exact arithmetic with a single global
 // reduction, <r,r> and <Ar,r> together, per iteration. The residual at a
 // neighbour, r_{k+1} = r_k - alpha_k (w_k + beta_k s_{k-1}), is recomputed
-// from the previous iteration's buffers, so each iteration is one sweep and
-// one barrier:
+// from the previous iteration's buffers, so each iteration is one sweep and one
+// barrier:
 //   p_k = r_k + beta_k p_{k-1},  s_k = w_k + beta_k s_{k-1}   (s = A p)
 //   x_{k+1} = x_k + alpha_k p_k, r_{k+1} = r_k - alpha_k s_k, w_{k+1} = A r_{k+1}
 //   gamma = <r,r>, delta = <w,r>, beta = gamma_{k+1}/gamma_k,
 //   alpha_{k+1} = gamma_{k+1} / (delta_{k+1} - beta_{k+1} gamma_{k+1}/alpha_k).
 //
-// Phases ("|" = grid barrier): P0 right-hand side and field-energy partials |
-// P1 w_0 = A r_0, <r,r>, <w,r> | iterations | E update | B update and FP32
-// field copy.
+// Learned solver (an addition to the method): x_0 = N(b) and flexible CG
+// with z = N(r) as preconditioner and the Polak-Ribiere beta,
+// beta = <z_{k+1}, r_{k+1} - r_k>/<z_k, r_k> = -alpha_k <z_{k+1}, q_k>/<z_k, r_k>,
+// to the same relative residual; if it has not converged within its
+// iteration budget the plain solver restarts from the current iterate. N is
+// applied either as the BF16 network on the matrix cores or as its exact
+// collapsed 7 x 7 filter in FP64.
 #include <math.h>
 
+#include "net_dev.h"
 #include "pic_dev.h"
 #include "pic_launch.h"
 
@@ -113,6 +117,12 @@ __device__ __forceinline__ void run_sum(const double* part, int blo, int bhi, do
   block_sum<N>(s, sm);
 }
 
+template <int N>
+__device__ __forceinline__ void put_part(double* part, const double (&v)[N]) {
+  if (threadIdx.x == 0)
+    for (int k = 0; k < N; ++k) part[(size_t)blockIdx.x * 8 + k] = v[k];
+}
+
 // curl with forward differences at the B points (Eq. (5)), F co-located with E
 __device__ __forceinline__ void curl_fwd(const Loc& L, double* const* F, int i, int j,
                                          double idx_, double idy_, double out[3]) {
@@ -130,10 +140,14 @@ __device__ __forceinline__ double lap5(const Loc& L, const double* f, int i, int
          (f[lidx(L, i, j + 1)] - 2.0 * c + f[lidx(L, i, j - 1)]) * idy2;
 }
 
+// kMode: 0 plain CG, 1 learned with the collapsed filter, 2 learned with the
+// BF16 network
+template <int kMode>
 __global__ void __launch_bounds__(kThreads)
 k_field_solve(FieldArgs a) {
   __shared__ double sm[kWaves * 8];
   __shared__ int s_run;
+  extern __shared__ __align__(16) unsigned char net_lds[];
 
   if (threadIdx.x == 0) {
     int r = 0;
@@ -158,17 +172,52 @@ k_field_solve(FieldArgs a) {
   // the generation word persists across launches; it cannot move before every
   // block has arrived at the first barrier, so all blocks read the same value
   unsigned my_gen = __hip_atomic_load(a.bar + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  // per-block partial sums, two halves of [block][8] used alternately
+  auto barrier = [&]() { grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err); };
+  // per-block partial sums, three sets of [block][8]
   double* const part0 = a.part;
   double* const part1 = a.part + (size_t)a.n_blocks * 8;
+  double* const part2 = a.part + (size_t)a.n_blocks * 16;
   // A v at (i, j) for a vector given by a functor of the linear index
   auto applyA = [&](auto&& v, long long g, long long gxp, long long gxm, long long gyp,
                     long long gym) {
     const double c = v(g);
     return c - ax * (v(gxp) - 2.0 * c + v(gxm)) - ay * (v(gyp) - 2.0 * c + v(gym));
   };
+  // Global "does any run still iterate" decisions: round k adds into
+  // g_active[k % 3] before a barrier and reads it after; block 0 clears the
+  // next round's slot (its previous readers finished two barriers earlier).
+  int round = 0;
+  auto count_active = [&](bool any) {
+    if (leader && threadIdx.x == 0) atomicAdd(&a.g_active[round % 3], any ? 1 : 0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.g_active[(round + 1) % 3] = 0;
+  };
+  auto read_active = [&]() {
+    const int t = __hip_atomic_load(&a.g_active[round % 3], __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    ++round;
+    return t;
+  };
+  // z = N(v) over every tile of every active component, items spread over the
+  // run's blocks: rd(c, i, j) gives the input at any cell, wr(c, i, j, z) sees
+  // each output of the run's own cells
+  constexpr bool collapsed = kMode == 1;
+  constexpr int TE = collapsed ? NET_KT : NET_T;
+  const int ntx = (R.nx + TE - 1) / TE, nty = (R.ny + TE - 1) / TE;
+  auto net_sweep = [&](const bool (&act)[3], auto&& rd, auto&& wr) {
+    for (int item = lb; item < ntx * nty * 3; item += nb) {
+      const int c = item % 3, t = item / 3;
+      if (!act[c]) continue;
+      auto rd_c = [&](int i, int j) { return rd(c, i, j); };
+      auto wr_c = [&](int i, int j, double v) { wr(c, i, j, v); };
+      if constexpr (collapsed)
+        net_apply_tile_collapsed(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c,
+                                 net_lds);
+      else
+        net_apply_tile(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c, net_lds);
+    }
+  };
 
-  // ---- P0: right-hand side of Eq. (7) into r (x = 0, so r = b); energies
+  // ---- P0: right-hand side of Eq. (7): b into r0 and r1 (kept), x = 0; energies
   {
     double en[2] = {0.0, 0.0};
     for (int k = first; k < ncell; k += stride) {
@@ -180,7 +229,9 @@ k_field_solve(FieldArgs a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
-        a.r0[c][g] = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        const double b = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        a.r0[c][g] = b;
+        a.r1[c][g] = b;
         a.x[c][g] = 0.0;
       }
       if (a.diag) {
@@ -199,80 +250,178 @@ k_field_solve(FieldArgs a) {
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) a.g_active[0] = 0;
   }
-  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
-
-  // ---- P1: w0 = A r0; gamma0 = <r0,r0>, delta0 = <w0,r0>; s_{-1} = 0, p_{-1} = 0
-  {
-    double d[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = first; k < ncell; k += stride) {
-      const int j = k / R.nx, i = k - j * R.nx;
-      const long long g = L.base + k;
-      const long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
-      const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const double* rc = a.r0[c];
-        const double w = applyA([&](long long q) { return rc[q]; }, g, gxp, gxm, gyp, gym);
-        const double r = rc[g];
-        a.w0[c][g] = w;
-        a.s0[c][g] = 0.0;
-        a.p[c][g] = 0.0;
-        d[c] += r * r;
-        d[3 + c] += w * r;
-      }
-    }
-    block_sum<6>(d, sm);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 6; ++k) part1[(size_t)blockIdx.x * 8 + k] = d[k];
-  }
-  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
+  barrier();
   double we_tot = 0.0, wb_tot = 0.0;
   if (leader && a.diag) {
-    // energies of step n (partials written before the first barrier; the
-    // iterations below never write words 6 and 7)
+    // energies of step n; later phases never write words 6 and 7 of part0
     double e2[2];
     run_sum<2>(part0 + 6, blo, bhi, e2, sm);
     we_tot = e2[0];
     wb_tot = e2[1];
   }
 
-  double gam[3], alpha[3], beta[3], bn2[3];
-  bool act[3];
-  int iters[3] = {0, 0, 0};
-  {
-    double s[6];
-    run_sum<6>(part1, blo, bhi, s, sm);
+  double bn2[3] = {0, 0, 0}, gam[3] = {0, 0, 0};
+  int iters[3] = {0, 0, 0}, learned_iters[3] = {0, 0, 0};
+  bool need_plain[3] = {true, true, true};
+  bool x_nonzero = false;
+  int fallback = 0;
+
+  if constexpr (kMode != 0) {
+    // ---- L1: x0 = N(b); ||b||^2
+    {
+      const bool all3[3] = {true, true, true};
+      double d[3] = {0, 0, 0};
+      net_sweep(all3, [&](int c, int i, int j) { return a.r1[c][L.base + (long long)j * R.nx + i]; },
+                [&](int c, int i, int j, double v) {
+                  const long long g = L.base + (long long)j * R.nx + i;
+                  a.x[c][g] = v;
+                  const double b = a.r1[c][g];
+                  d[c] += b * b;
+                });
+      block_sum<3>(d, sm);
+      put_part<3>(part2, d);
+    }
+    barrier();
+    bool act[3];
+    {
+      double s[3];
+      run_sum<3>(part2, blo, bhi, s, sm);
+      for (int c = 0; c < 3; ++c) {
+        bn2[c] = s[c];
+        act[c] = bn2[c] > 0.0;
+      }
+    }
+    x_nonzero = true;
+    // ---- L2: r0 = b - A x0 (recomputed at the halo), z0 = N(r0); p_old = 0;
+    // <r0, r0>, <z0, r0>
+    auto resid0 = [&](int c, int i, int j) {
+      const long long g = lidx(L, i, j);
+      const double* xc = a.x[c];
+      return a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, g, lidx(L, i + 1, j),
+                                 lidx(L, i - 1, j), lidx(L, i, j + 1), lidx(L, i, j - 1));
+    };
+    {
+      double d[6] = {0, 0, 0, 0, 0, 0};
+      net_sweep(act, resid0, [&](int c, int i, int j, double v) {
+        const long long g = L.base + (long long)j * R.nx + i;
+        const double r = resid0(c, i, j);
+        a.r0[c][g] = r;
+        a.w0[c][g] = v;
+        a.s0[c][g] = 0.0;
+        d[c] += r * r;
+        d[3 + c] += v * r;
+      });
+      block_sum<6>(d, sm);
+      put_part<6>(part1, d);
+    }
+    barrier();
+    double rr[3] = {0, 0, 0}, rho[3] = {0, 0, 0}, beta[3] = {0, 0, 0}, alpha[3] = {0, 0, 0};
+    const int budget = R.cg_maxit < a.learned_maxit ? R.cg_maxit : a.learned_maxit;
+    {
+      double s[6];
+      run_sum<6>(part1, blo, bhi, s, sm);
+      for (int c = 0; c < 3; ++c) {
+        rr[c] = s[c];
+        rho[c] = s[3 + c];
+        act[c] = act[c] && budget > 0 && sqrt(rr[c]) > R.cg_rtol * sqrt(bn2[c]);
+      }
+    }
+    // Flexible PCG, two grid barriers per iteration:
+    //   A:  p = z + beta p_old, q = A p (p recomputed at the halo); <p, q>
+    //   BC: alpha; x += alpha p; r' = r - alpha q (recomputed at the halo);
+    //       z = N(r'); <r', r'>, <z, r'>, <z, q>
+    for (int it = 0;; ++it) {
+      bool any = act[0] || act[1] || act[2];
+      count_active(any);
+      double* const* rc = (it & 1) ? a.p : a.r0;    // r_k
+      double* const* rn = (it & 1) ? a.r0 : a.p;    // r_{k+1}
+      double* const* po = (it & 1) ? a.s1 : a.s0;   // p_{k-1}
+      double* const* pn = (it & 1) ? a.s0 : a.s1;   // p_k
+      {
+        double d[3] = {0, 0, 0};
+        if (any) {
+          for (int k = first; k < ncell; k += stride) {
+            const int j = k / R.nx, i = k - j * R.nx;
+            const long long g = L.base + k;
+            const long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+            const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+              if (!act[c]) continue;
+              const double* z_ = a.w0[c];
+              const double* p_ = po[c];
+              const double be = beta[c];
+              auto pv = [&](long long q) { return z_[q] + be * p_[q]; };
+              const double p = pv(g);
+              const double qv = applyA(pv, g, gxp, gxm, gyp, gym);
+              pn[c][g] = p;
+              a.w1[c][g] = qv;
+              d[c] += p * qv;
+            }
+          }
+        }
+        block_sum<3>(d, sm);
+        put_part<3>(part0, d);
+      }
+      barrier();
+      if (read_active() == 0) break;
+      {
+        double s[3];
+        run_sum<3>(part0, blo, bhi, s, sm);
+        for (int c = 0; c < 3; ++c) alpha[c] = (act[c] && s[c] != 0.0) ? rho[c] / s[c] : 0.0;
+        double d[6] = {0, 0, 0, 0, 0, 0}, e[3] = {0, 0, 0};
+        auto rnext = [&](int c, int i, int j) {
+          const long long g = L.base + (long long)j * R.nx + i;
+          return rc[c][g] - alpha[c] * a.w1[c][g];
+        };
+        net_sweep(act, rnext, [&](int c, int i, int j, double v) {
+          const long long g = L.base + (long long)j * R.nx + i;
+          const double r = rnext(c, i, j);
+          rn[c][g] = r;
+          a.x[c][g] += alpha[c] * pn[c][g];
+          a.w0[c][g] = v;
+          d[c] += r * r;
+          d[3 + c] += v * r;
+          e[c] += v * a.w1[c][g];
+        });
+        block_sum<6>(d, sm);
+        block_sum<3>(e, sm);
+        put_part<6>(part1, d);
+        put_part<3>(part2, e);
+      }
+      barrier();
+      {
+        double s[6], s2[3];
+        run_sum<6>(part1, blo, bhi, s, sm);
+        run_sum<3>(part2, blo, bhi, s2, sm);
+        for (int c = 0; c < 3; ++c) {
+          if (!act[c]) continue;
+          rr[c] = s[c];
+          learned_iters[c] = it + 1;
+          beta[c] = rho[c] != 0.0 ? -alpha[c] * s2[c] / rho[c] : 0.0;
+          rho[c] = s[3 + c];
+          act[c] = sqrt(rr[c]) > R.cg_rtol * sqrt(bn2[c]) && it + 1 < budget;
+        }
+      }
+    }
     for (int c = 0; c < 3; ++c) {
-      bn2[c] = s[c];
-      gam[c] = s[c];
-      beta[c] = 0.0;
-      alpha[c] = s[3 + c] > 0.0 ? s[c] / s[3 + c] : 0.0;
-      act[c] = R.cg_maxit > 0 && bn2[c] > 0.0;
+      gam[c] = rr[c];
+      iters[c] = learned_iters[c];
+      need_plain[c] = bn2[c] > 0.0 && sqrt(rr[c]) > R.cg_rtol * sqrt(bn2[c]);
+      fallback |= need_plain[c] ? 1 : 0;
     }
   }
 
-  // Pass `it` writes partials into half it&1 and counts active runs in
-  // g_active[it % 3]; block 0 clears the counter of the next pass before the
-  // barrier (its previous readers finished two barriers earlier).
-  for (int it = 0;; ++it) {
-    // all blocks of all runs take the same number of passes; a run whose
-    // components have all converged sweeps nothing
-    bool any = false;
-    for (int c = 0; c < 3; ++c) {
-      act[c] = act[c] && it < R.cg_maxit && sqrt(gam[c]) > R.cg_rtol * sqrt(bn2[c]);
-      if (act[c]) iters[c] = it + 1;
-      any |= act[c];
-    }
-    if (leader && threadIdx.x == 0) atomicAdd(&a.g_active[it % 3], any ? 1 : 0);
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.g_active[(it + 1) % 3] = 0;
-    double* const* rc = (it & 1) ? a.r1 : a.r0;
-    double* const* rn = (it & 1) ? a.r0 : a.r1;
-    double* const* wc = (it & 1) ? a.w1 : a.w0;
-    double* const* wn = (it & 1) ? a.w0 : a.w1;
-    double* const* sc = (it & 1) ? a.s1 : a.s0;   // s_{k-1}
-    double* const* sn = (it & 1) ? a.s0 : a.s1;   // s_k
-    double d[6] = {0, 0, 0, 0, 0, 0};
-    if (any) {
+  // every block must agree whether the plain solver runs (it has barriers)
+  bool run_plain = true;
+  if constexpr (kMode != 0) {
+    count_active(need_plain[0] || need_plain[1] || need_plain[2]);
+    barrier();
+    run_plain = read_active() > 0;
+  }
+  if (run_plain) {
+    if (x_nonzero) {
+      // restart from the current iterate: r0 = b - A x
       for (int k = first; k < ncell; k += stride) {
         const int j = k / R.nx, i = k - j * R.nx;
         const long long g = L.base + k;
@@ -280,56 +429,135 @@ k_field_solve(FieldArgs a) {
         const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          if (!act[c]) continue;
-          const double* r_ = rc[c];
-          const double* w_ = wc[c];
-          const double* s_ = sc[c];
-          const double al = alpha[c], be = beta[c];
-          // r_{k+1} at any point from the previous buffers
-          auto rnext = [&](long long q) { return r_[q] - al * (w_[q] + be * s_[q]); };
-          const double sk = w_[g] + be * s_[g];
-          const double pk = r_[g] + be * a.p[c][g];
-          const double r1 = r_[g] - al * sk;
-          const double w1 = applyA(rnext, g, gxp, gxm, gyp, gym);
-          a.p[c][g] = pk;
-          sn[c][g] = sk;
-          a.x[c][g] += al * pk;
-          rn[c][g] = r1;
-          wn[c][g] = w1;
-          d[c] += r1 * r1;
-          d[3 + c] += w1 * r1;
+          if (!need_plain[c]) continue;
+          const double* xc = a.x[c];
+          a.r0[c][g] = a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, g, gxp, gxm, gyp, gym);
         }
       }
+      barrier();
     }
-    double* const pw = (it & 1) ? part1 : part0;
-    block_sum<6>(d, sm);
-    if (threadIdx.x == 0)
-      for (int k = 0; k < 6; ++k) pw[(size_t)blockIdx.x * 8 + k] = d[k];
-    grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
-    const int total = __hip_atomic_load(&a.g_active[it % 3], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    if (total == 0) break;
-    double s[6];
-    run_sum<6>(pw, blo, bhi, s, sm);
-    for (int c = 0; c < 3; ++c) {
-      if (!act[c]) continue;
-      const double gnew = s[c], dnew = s[3 + c];
-      const double bnew = gnew / gam[c];
-      const double den = dnew - bnew * gnew / alpha[c];
-      beta[c] = bnew;
-      alpha[c] = den != 0.0 ? gnew / den : 0.0;
-      gam[c] = gnew;
+    // ---- P1: w0 = A r0; gamma0 = <r0,r0>, delta0 = <w0,r0>, <b,b>; s_{-1} = p_{-1} = 0
+    {
+      double d[6] = {0, 0, 0, 0, 0, 0};
+      double bb[3] = {0, 0, 0};
+      for (int k = first; k < ncell; k += stride) {
+        const int j = k / R.nx, i = k - j * R.nx;
+        const long long g = L.base + k;
+        const long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+        const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (!need_plain[c]) continue;
+          const double* rc = a.r0[c];
+          const double w = applyA([&](long long q) { return rc[q]; }, g, gxp, gxm, gyp, gym);
+          const double r = rc[g];
+          const double b = a.r1[c][g];
+          a.w0[c][g] = w;
+          a.s0[c][g] = 0.0;
+          a.p[c][g] = 0.0;
+          d[c] += r * r;
+          d[3 + c] += w * r;
+          bb[c] += b * b;
+        }
+      }
+      block_sum<6>(d, sm);
+      block_sum<3>(bb, sm);
+      put_part<6>(part1, d);
+      put_part<3>(part2, bb);
+    }
+    barrier();
+    double alpha[3], beta[3];
+    bool act[3];
+    {
+      double s[6], sb[3];
+      run_sum<6>(part1, blo, bhi, s, sm);
+      run_sum<3>(part2, blo, bhi, sb, sm);
+      for (int c = 0; c < 3; ++c) {
+        alpha[c] = beta[c] = 0.0;
+        act[c] = false;
+        if (!need_plain[c]) continue;
+        bn2[c] = sb[c];
+        gam[c] = s[c];
+        alpha[c] = s[3 + c] > 0.0 ? s[c] / s[3 + c] : 0.0;
+        act[c] = R.cg_maxit > iters[c] && bn2[c] > 0.0;
+      }
+    }
+    const int done0[3] = {iters[0], iters[1], iters[2]};
+    for (int it = 0;; ++it) {
+      // all blocks of all runs take the same number of passes; a run whose
+      // components have all converged sweeps nothing
+      bool any = false;
+      for (int c = 0; c < 3; ++c) {
+        act[c] = act[c] && done0[c] + it < R.cg_maxit && sqrt(gam[c]) > R.cg_rtol * sqrt(bn2[c]);
+        if (act[c]) iters[c] = done0[c] + it + 1;
+        any |= act[c];
+      }
+      count_active(any);
+      double* const* rc = (it & 1) ? a.r1 : a.r0;
+      double* const* rn = (it & 1) ? a.r0 : a.r1;
+      double* const* wc = (it & 1) ? a.w1 : a.w0;
+      double* const* wn = (it & 1) ? a.w0 : a.w1;
+      double* const* sc = (it & 1) ? a.s1 : a.s0;   // s_{k-1}
+      double* const* sn = (it & 1) ? a.s0 : a.s1;   // s_k
+      double d[6] = {0, 0, 0, 0, 0, 0};
+      if (any) {
+        for (int k = first; k < ncell; k += stride) {
+          const int j = k / R.nx, i = k - j * R.nx;
+          const long long g = L.base + k;
+          const long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+          const long long gyp = lidx(L, i, j + 1), gym = lidx(L, i, j - 1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            if (!act[c]) continue;
+            const double* r_ = rc[c];
+            const double* w_ = wc[c];
+            const double* s_ = sc[c];
+            const double al = alpha[c], be = beta[c];
+            // r_{k+1} at any point from the previous buffers
+            auto rnext = [&](long long q) { return r_[q] - al * (w_[q] + be * s_[q]); };
+            const double sk = w_[g] + be * s_[g];
+            const double pk = r_[g] + be * a.p[c][g];
+            const double r1 = r_[g] - al * sk;
+            const double w1 = applyA(rnext, g, gxp, gxm, gyp, gym);
+            a.p[c][g] = pk;
+            sn[c][g] = sk;
+            a.x[c][g] += al * pk;
+            rn[c][g] = r1;
+            wn[c][g] = w1;
+            d[c] += r1 * r1;
+            d[3 + c] += w1 * r1;
+          }
+        }
+      }
+      double* const pw = (it & 1) ? part1 : part0;
+      block_sum<6>(d, sm);
+      put_part<6>(pw, d);
+      barrier();
+      if (read_active() == 0) break;
+      double s[6];
+      run_sum<6>(pw, blo, bhi, s, sm);
+      for (int c = 0; c < 3; ++c) {
+        if (!act[c]) continue;
+        const double gnew = s[c], dnew = s[3 + c];
+        const double bnew = gnew / gam[c];
+        const double den = dnew - bnew * gnew / alpha[c];
+        beta[c] = bnew;
+        alpha[c] = den != 0.0 ? gnew / den : 0.0;
+        gam[c] = gnew;
+      }
     }
   }
 
-  // ---- per-run record: CG statistics and energies of step n
+  // ---- per-run record: solve statistics and energies of step n
   if (leader && threadIdx.x == 0) {
-    double* st = a.stats + (size_t)run * 9;
+    double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
     for (int c = 0; c < 3; ++c) {
       st[c] = (double)iters[c];
       st[3 + c] = bn2[c] > 0.0 ? sqrt(gam[c] / bn2[c]) : 0.0;
       st[6 + c] = sqrt(bn2[c]);
+      st[9 + c] = (double)learned_iters[c];
     }
+    st[12] = (double)fallback;
     if (a.diag) {
       double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
       const int nt = R.ntx * R.nty;
@@ -353,6 +581,26 @@ k_field_solve(FieldArgs a) {
     }
   }
 
+  // ---- training pairs (b, dB) of run 0, recorded after the solve; the
+  // right-hand side is recomputed from E^n, B^n, J (r1 may be overwritten)
+  if (a.collect && run == 0) {
+    double* const pb = a.pairs + (size_t)a.pair_slot * 6 * ncell;
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      double cj[3], ce[3];
+      curl_fwd(L, a.J, i, j, idx_, idy_, cj);
+      curl_fwd(L, a.E, i, j, idx_, idy_, ce);
+      const long long g = L.base + k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
+        pb[(size_t)(2 * c) * ncell + k] = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        pb[(size_t)(2 * c + 1) * ncell + k] = a.x[c][g];
+      }
+    }
+  }
+  barrier();
+
   // ---- E update, Eq. (6): E += dt curl_B(B^n + theta dB) - 4 pi dt J
   for (int k = first; k < ncell; k += stride) {
     const int j = k / R.nx, i = k - j * R.nx;
@@ -372,7 +620,7 @@ k_field_solve(FieldArgs a) {
     a.E[1][g] += dt * cy - kFourPi * dt * a.J[1][g];
     a.E[2][g] += dt * cz - kFourPi * dt * a.J[2][g];
   }
-  grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err);
+  barrier();
   // ---- B update, Eq. (5) through dB; FP32 copies for the fast particle path
   for (int k = first; k < ncell; k += stride) {
     const long long g = L.base + k;
@@ -390,9 +638,22 @@ k_field_solve(FieldArgs a) {
 
 }  // namespace
 
-int pic_field_solve_max_blocks(int n_cu) {
+size_t pic_field_solve_smem(int learned, int form) {
+  return learned ? (form == 0 ? NET_K_LDS_BYTES : NET_LDS_BYTES) : 0;
+}
+
+namespace {
+const void* solve_kernel(int learned, int form) {
+  if (!learned) return (const void*)k_field_solve<0>;
+  return form == 0 ? (const void*)k_field_solve<1> : (const void*)k_field_solve<2>;
+}
+}  // namespace
+
+int pic_field_solve_max_blocks(int n_cu, int learned, int form) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_field_solve, kThreads, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel(learned, form), kThreads,
+                                                   pic_field_solve_smem(learned, form)) !=
+      hipSuccess)
     return -1;
   return nb * n_cu;
 }
@@ -400,6 +661,7 @@ int pic_field_solve_max_blocks(int n_cu) {
 hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s) {
   FieldArgs copy = a;
   void* args[] = {(void*)&copy};
-  return hipLaunchCooperativeKernel((const void*)k_field_solve, dim3(a.n_blocks),
-                                    dim3(kThreads), args, 0, s);
+  return hipLaunchCooperativeKernel(solve_kernel(a.learned, a.learned_form), dim3(a.n_blocks),
+                                    dim3(kThreads), args,
+                                    pic_field_solve_smem(a.learned, a.learned_form), s);
 }

@@ -3,11 +3,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include "net_dev.h"
 #include "pic_dev.h"
 
 #define PIC_REC_WORDS 16   // doubles per history record
 
 #define PIC_CG_THREADS 512    // work-group size of the persistent field solve
+#define PIC_STAT_WORDS 16     // doubles per run of solve statistics
 
 struct FieldArgs {
   int n_runs, n_blocks, diag;
@@ -24,19 +26,29 @@ struct FieldArgs {
   double* w1[3];
   double* s0[3];
   double* s1[3];
-  double* part;            // per-block partial sums, 2 x [block][8]
+  double* part;            // per-block partial sums, 3 x [block][8]
   int* g_active;           // active-run counters (3)
   unsigned* bar;           // grid barrier: counter at [0], generation at [32]
   int* err;                // error bits
-  double* stats;           // [run][9]: iters, relres, ||b||
+  double* stats;           // [run][PIC_STAT_WORDS]: iters, relres, ||b||, learned iters, fallback
   const double* wk_part;   // [tile][K][species][2] kinetic partials
   int K;                   // work-groups per tile in the particle kernel
   double* history;         // [run][hist_cap][PIC_REC_WORDS]
   int hist_cap, hist_slot;
   long long step;
+  int learned;             // x0 = N(b) and flexible CG preconditioned by N
+  int learned_form;        // 0: collapsed 7 x 7 filter (FP64), 1: BF16 network
+  int learned_maxit;       // iteration budget of the learned solver
+  NetWeights net;
+  int collect;             // record (b, dB) of run 0 into pairs[pair_slot]
+  double* pairs;           // [slot][component][b | dB][ncell of run 0]
+  int pair_slot;
 };
 
-int pic_field_solve_max_blocks(int n_cu);
+size_t pic_field_solve_smem(int learned, int form);
+// co-resident work-groups of the solve kernel variant (plain, or learned in
+// the given form) over n_cu compute units
+int pic_field_solve_max_blocks(int n_cu, int learned, int form);
 hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s);
 
 enum PicParticleMode { PIC_MODE_FUSED = 0, PIC_MODE_PUSH = 1, PIC_MODE_DEPOSIT = 2 };
@@ -58,3 +70,28 @@ hipError_t pic_launch_divergences(const DevRun* runs, int run, long long ncell,
                                   const double* const* E, const double* const* B,
                                   const double* rho, double* partial_max, int n_blocks,
                                   hipStream_t s);
+
+// Training state of the learned aid: FP32 weights and Adam moments, the BF16
+// copy used by the matrix cores, and whole-field activation buffers of the
+// largest training grid.
+struct NetTrain {
+  float* w;              // [NET_NW]
+  __bf16* w2b;           // [9][NET_C][NET_C]
+  double* k49;           // collapsed filter [7][7]
+  float *grad, *m, *v;   // [NET_NW]
+  float* part;           // [wg_blocks][NET_C * NET_C * 9]
+  float *xin, *y, *gy;   // [ncell]
+  float *h1, *h2, *gh1, *gh2;   // [NET_C][ncell]
+  double* dpart;         // [256][2]
+  double* scal;          // [4]: sum t^2, loss, loss accumulator
+  int wg_blocks;
+};
+
+// BF16 copy of W2 and the collapsed filter, after any change of the weights
+hipError_t pic_net_refresh(const NetTrain& T, hipStream_t s);
+// out = N(in) on an nx x ny periodic field (form 0 collapsed, 1 network)
+hipError_t pic_net_apply(const NetTrain& T, int form, const double* in, double* out, int nx,
+                         int ny, hipStream_t s);
+hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int nx, int ny,
+                        hipStream_t s);
+hipError_t pic_net_adam(const NetTrain& T, float lr, int step, hipStream_t s);

@@ -66,3 +66,19 @@ def test_plan_batched_runs():
     info = pic.plan(runs, pic.make_options("fp32"))
     assert info.n_tiles == 8 * 4 + 32 * 8
     assert info.n_cells == 128 * 64 + 512 * 128
+
+
+def test_plan_learned_solver():
+    base = pic.plan([_run()], pic.make_options("fp32"))
+    lrn = pic.plan([_run()], pic.make_options("fp32", solver="learned", precond_slots=4))
+    # network, training activations (4 x 32 channels) and 4 pairs of 6 fields
+    assert lrn.workspace_bytes >= base.workspace_bytes + 64 * 64 * (4 * 32 * 4 + 4 * 6 * 8)
+    # one network approximates one operator: runs must share dx, dy, cfl, theta
+    with pytest.raises(pic.PicError) as ei:
+        pic.plan([_run(), _run(theta=0.5)], pic.make_options("fp32", solver="learned"))
+    assert ei.value.code == -1
+    pic.plan([_run(), _run(order=3, nx=32)], pic.make_options("fp32", solver="learned"))
+    o = pic.make_options("fp32", solver="learned")
+    o.learned_form = 7
+    with pytest.raises(pic.PicError):
+        pic.plan([_run()], o)
