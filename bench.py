@@ -8,9 +8,14 @@ One step = gather + Boris push + move + Esirkepov deposit of every particle,
 tile re-binning, the current reduction and the implicit field solve (RHS of
 Eq. (7), CG, update of Eqs. (5)-(6)).
 
-The timed form is the FP32 particle path (FP64 fields and CG); the plain FP64
-form is timed on the same GPU beside it. Inputs are synthetic (seeded
-Maxwell-Juettner load) and resident in HBM before the timed region.
+The timed form is the FP32 particle path (FP64 fields and CG) with the learned
+CG aid: the network is trained on the (b, dB) pairs of the first steps (solved
+by plain CG), then every timed step starts the field solve from x0 = N(b) and
+runs flexible PCG to the same 1e-8 relative residual. Training is a one-time
+set-up, timed and reported on its own. The same workload with plain CG in the
+FP32 form and the plain FP64 form are timed on the same GPU beside it. Inputs
+are synthetic (seeded Maxwell-Juettner load) and resident in HBM before the
+timed region.
 
 Prints one JSON line.
 """
@@ -42,23 +47,43 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0):
+def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
+             form="collapsed", slots=0):
     from synth import loads
     Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
     run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
                        [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8, cg_maxit=200)
     sim = pic.Sim([run], pic.make_options(precision, tile=tile, diag_every=0,
                                           cg_blocks=cg_blocks, track_ids=False,
-                                          tile_split=tile_split))
+                                          tile_split=tile_split, solver=solver,
+                                          learned_form=form, precond_slots=slots))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
     return sim
 
 
-def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0):
-    sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split)
+def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0,
+              learned=None):
+    """learned: None (plain CG) or dict(form, pairs, epochs, lr): collect that
+    many pairs with plain CG, train, then take the learned path."""
+    solver = "learned" if learned else "cg"
+    sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split, solver,
+                   learned["form"] if learned else "collapsed",
+                   learned["pairs"] if learned else 0)
     n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
+    train = None
+    if learned:
+        sim.precond_use(False)
+        sim.precond_collect(True)
+        sim.step(learned["pairs"])
+        sim.precond_collect(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = sim.precond_train(learned["epochs"], learned["lr"])
+        train = dict(tr, seconds=time.perf_counter() - t0, pairs=learned["pairs"],
+                     epochs=learned["epochs"], form=learned["form"])
+        sim.precond_use(True)
     if warmup:
         sim.step(warmup)
     torch.cuda.synchronize()
@@ -80,7 +105,9 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
                 push_ms=push_ms, field_solve_ms=tim["field_solve"]["ms"] / max(1, steps),
                 rebin_ms=tim["rebin"]["ms"] / max(1, steps),
                 current_sum_ms=tim["current_sum"]["ms"] / max(1, steps),
-                cg_iters=st[0]["iters"], n_particles=n_part)
+                cg_iters=st[0]["iters"], learned_iters=st[0]["learned_iters"],
+                fallback=st[0]["fallback"], relres=st[0]["relres"], n_particles=n_part,
+                train=train)
 
 
 def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
@@ -168,6 +195,14 @@ def main():
     ap.add_argument("--sweep-tiles", default="",
                     help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-run batched sweep")
+    ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"],
+                    help="inference form of the network in the timed form")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="time the FP32 form with plain CG only")
+    ap.add_argument("--train-pairs", type=int, default=8)
+    ap.add_argument("--train-epochs", type=int, default=10)
+    ap.add_argument("--also-mfma", action="store_true",
+                    help="also time the FP32 form with the BF16 matrix-core network")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first copy a 512 MiB buffer three times (a plain copy kernel of known "
                          "size, for scaling HBM traffic counters)")
@@ -201,11 +236,15 @@ def main():
     load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
     log(f"bench: load ready in {time.perf_counter() - t0:.1f} s")
 
+    learned = None if args.no_learned else dict(form=args.learned_form, pairs=args.train_pairs,
+                                                 epochs=args.train_epochs, lr=1e-3)
     if args.sweep_cg:
         for nb in [int(v) for v in args.sweep_cg.split(",")]:
-            r = time_form(pic, torch, cfg, load, "fp32", tile, 10, 2, nb)
-            log(f"bench: cg_blocks={nb}: field solve {r['field_solve_ms']:.3f} ms/step, "
-                f"iters {r['cg_iters']}")
+            for lrn in ([None] if learned is None else [None, learned]):
+                r = time_form(pic, torch, cfg, load, "fp32", tile, 10, 2, nb, args.tile_split,
+                              lrn)
+                log(f"bench: cg_blocks={nb} {'learned' if lrn else 'plain'}: field solve "
+                    f"{r['field_solve_ms']:.3f} ms/step, iters {r['cg_iters']}")
     if args.sweep_tiles:
         for item in args.sweep_tiles.split(","):
             shape, k = item.split(":")
@@ -214,10 +253,25 @@ def main():
                 r = time_form(pic, torch, cfg, load, prec, tt, 20, 20, args.cg_blocks, int(k))
                 log(f"bench: {prec} tile {shape} split {k}: push {r['push_ms']:.3f} ms, "
                     f"step {r['ms_per_step']:.3f} ms")
-    log("bench: FP32 form")
+    log("bench: FP32 form" + ("" if learned is None else f" + learned ({args.learned_form})"))
     fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
-                     args.tile_split)
-    log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step")
+                     args.tile_split, learned)
+    log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step, field solve "
+        f"{fast['field_solve_ms']:.3f} ms, iters {fast['cg_iters']}")
+    fast_cg = None
+    if learned is not None:
+        log("bench: FP32 form, plain CG")
+        fast_cg = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup,
+                            args.cg_blocks, args.tile_split)
+        log(f"bench: FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
+            f"{fast_cg['field_solve_ms']:.3f} ms, iters {fast_cg['cg_iters']}")
+    mfma = None
+    if args.also_mfma and learned is not None and args.learned_form != "mfma":
+        log("bench: FP32 form + learned (mfma)")
+        mfma = time_form(pic, torch, cfg, load, "fp32", tile, max(10, args.steps // 4),
+                         args.warmup, args.cg_blocks, args.tile_split, dict(learned, form="mfma"))
+        log(f"bench: FP32 mfma {mfma['ms_per_step']:.3f} ms/step, field solve "
+            f"{mfma['field_solve_ms']:.3f} ms, iters {mfma['cg_iters']}")
     plain = None
     if not args.no_fp64:
         log("bench: FP64 form")
@@ -240,8 +294,15 @@ def main():
 
     n_part = fast["n_particles"]
     achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
+    def solve_info(r):
+        return None if r is None else dict(
+            ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],
+            field_solve_ms_per_step=r["field_solve_ms"], cg_iters_last_step=r["cg_iters"],
+            learned_iters_last_step=r["learned_iters"], fallback=r["fallback"],
+            relres_last_step=r["relres"], training=r["train"])
+
     line = {
-        "metric": "particle-steps/s (whole step, FP32 particle path) + field-solve ms/step",
+        "metric": "particle-steps/s + field-solve ms/step; FP32+learned vs plain FP64, same GPU",
         "value": fast["particle_steps_per_s"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
@@ -251,12 +312,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 particles, f64 fields/CG",
+        "dtype": "f32 particles, f64 fields/CG" + ("" if learned is None else
+                                                    f", learned aid ({args.learned_form})"),
         "data": "synthetic (seeded Maxwell-Juettner pair plasma)",
         "config": {"workload": cfg["label"], "particles": n_part, "cells": cfg["nx"] * cfg["ny"],
                    "tile": list(tile), "cg_rtol": 1e-8},
         "field_solve_ms_per_step": fast["field_solve_ms"],
         "cg_iters_last_step": fast["cg_iters"],
+        "learned": solve_info(fast) if learned is not None else None,
+        "fp32_plain_cg": solve_info(fast_cg),
+        "fp32_learned_mfma": solve_info(mfma),
         "breakdown_ms": {k: fast[k] for k in ("push_ms", "rebin_ms", "current_sum_ms",
                                               "field_solve_ms")},
         "plain_fp64": None if plain is None else {
@@ -264,7 +329,9 @@ def main():
             "ms_per_step": plain["ms_per_step"],
             "field_solve_ms_per_step": plain["field_solve_ms"],
             "push_ms": plain["push_ms"],
-            "fp32_speedup": plain["ms_per_step"] / fast["ms_per_step"],
+            "cg_iters_last_step": plain["cg_iters"],
+            "speedup_of_timed_form": plain["ms_per_step"] / fast["ms_per_step"],
+            "field_solve_speedup_of_timed_form": plain["field_solve_ms"] / fast["field_solve_ms"],
         },
         "roofline": {"bound": "hbm", "kernel": "fused particle push (gather+Boris+move+deposit)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -204,16 +204,19 @@ k_field_solve(FieldArgs a) {
   constexpr int TE = collapsed ? NET_KT : NET_T;
   const int ntx = (R.nx + TE - 1) / TE, nty = (R.ny + TE - 1) / TE;
   auto net_sweep = [&](const bool (&act)[3], auto&& rd, auto&& wr) {
-    for (int item = lb; item < ntx * nty * 3; item += nb) {
-      const int c = item % 3, t = item / 3;
-      if (!act[c]) continue;
-      auto rd_c = [&](int i, int j) { return rd(c, i, j); };
-      auto wr_c = [&](int i, int j, double v) { wr(c, i, j, v); };
-      if constexpr (collapsed)
-        net_apply_tile_collapsed(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c,
-                                 net_lds);
-      else
+    if constexpr (collapsed) {
+      // one item = one tile, all three components
+      for (int t = lb; t < ntx * nty; t += nb)
+        net_apply_tile_collapsed<3>(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, act, rd,
+                                    wr, net_lds);
+    } else {
+      for (int item = lb; item < ntx * nty * 3; item += nb) {
+        const int c = item % 3, t = item / 3;
+        if (!act[c]) continue;
+        auto rd_c = [&](int i, int j) { return rd(c, i, j); };
+        auto wr_c = [&](int i, int j, double v) { wr(c, i, j, v); };
         net_apply_tile(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c, net_lds);
+      }
     }
   };
 

@@ -213,9 +213,12 @@ __global__ void __launch_bounds__(PIC_CG_THREADS) k_net_apply(NetWeights W, cons
   const int ntx = (nx + TE - 1) / TE, nty = (ny + TE - 1) / TE;
   auto rd = [&](int i, int j) { return in[(long long)j * nx + i]; };
   auto wr = [&](int i, int j, double v) { out[(long long)j * nx + i] = v; };
+  const bool one[1] = {true};
   for (int t = blockIdx.x; t < ntx * nty; t += gridDim.x) {
-    if (kCollapsed)
-      net_apply_tile_collapsed(W, (t % ntx) * TE, (t / ntx) * TE, nx, ny, rd, wr, lds);
+    if constexpr (kCollapsed)
+      net_apply_tile_collapsed<1>(W, (t % ntx) * TE, (t / ntx) * TE, nx, ny, one,
+                                  [&](int, int i, int j) { return rd(i, j); },
+                                  [&](int, int i, int j, double v) { wr(i, j, v); }, lds);
     else
       net_apply_tile(W, (t % ntx) * TE, (t / ntx) * TE, nx, ny, rd, wr, lds);
   }

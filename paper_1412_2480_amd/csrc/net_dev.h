@@ -34,7 +34,8 @@ typedef float net_f32x16 __attribute__((ext_vector_type(16)));
 #define NET_LDS_BYTES (NET_X_E * 4 + NET_H1_E * NET_C * 2 + NET_H2_E * NET_C * 2 + 2 * NET_C * 9 * 4)
 
 #define NET_KT 32                                     // output tile edge, collapsed form
-#define NET_K_LDS_BYTES ((64 + (NET_KT + 6) * (NET_KT + 6)) * 8)
+#define NET_KE (NET_KT + 6)                           // staged edge (3-cell halo)
+#define NET_K_LDS_BYTES ((64 + 3 * NET_KE * NET_KE) * 8)   // filter + 3 staged components
 
 struct NetWeights {
   const float* w;        // FP32 weights: W1[co][tap], W2[co][ci][tap], W3[ci][tap]
@@ -42,9 +43,12 @@ struct NetWeights {
   const double* k49;     // collapsed filter: N(x)(p) = sum_o K[(oy+3)*7 + ox+3] x(p + o)
 };
 
+// i mod n for i within a few periods of [0, n) (the staged halo is at most
+// 3 cells; a loop keeps grids narrower than the halo correct)
 __device__ __forceinline__ int net_mod(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+  while (i < 0) i += n;
+  while (i >= n) i -= n;
+  return i;
 }
 
 // z(tile) = N(r) for the 16 x 16 output tile at (X0, Y0) of a periodic nx x ny
@@ -135,29 +139,42 @@ __device__ void net_apply_tile(const NetWeights& W, int X0, int Y0, int nx, int 
   __syncthreads();
 }
 
-// Collapsed form: z = K * x on the NET_KT x NET_KT output tile at (X0, Y0), in
-// FP64; same calling convention as net_apply_tile.
-template <typename Rd, typename Wr>
+// Collapsed form: z_c = K * x_c on the NET_KT x NET_KT output tile at
+// (X0, Y0) for every component c < NC with act[c], in FP64. The components
+// share one staging pass, so their loads are in flight together.
+// rd(c, i, j) reads component c at an in-grid cell; wr(c, i, j, z) receives
+// each output of an in-grid cell. All threads of the block call it.
+template <int NC, typename Rd, typename Wr>
 __device__ void net_apply_tile_collapsed(const NetWeights& W, int X0, int Y0, int nx, int ny,
-                                         Rd&& rd, Wr&& wr, unsigned char* lds) {
-  constexpr int E = NET_KT + 6;
+                                         const bool (&act)[NC], Rd&& rd, Wr&& wr,
+                                         unsigned char* lds) {
+  constexpr int E = NET_KE;
   double* sk = reinterpret_cast<double*>(lds);
   double* sx = sk + 64;
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int e = tid; e < 49; e += nthr) sk[e] = W.k49[e];
-  for (int e = tid; e < E * E; e += nthr)
-    sx[e] = rd(net_mod(X0 + e % E - 3, nx), net_mod(Y0 + e / E - 3, ny));
+  for (int e = tid; e < E * E; e += nthr) {
+    const int i = net_mod(X0 + e % E - 3, nx), j = net_mod(Y0 + e / E - 3, ny);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (act[c]) sx[c * E * E + e] = rd(c, i, j);
+  }
   __syncthreads();
   for (int cell = tid; cell < NET_KT * NET_KT; cell += nthr) {
     const int u = cell % NET_KT, v = cell / NET_KT;
     const int i = X0 + u, j = Y0 + v;
     if (i >= nx || j >= ny) continue;
-    double acc = 0.0;
-#pragma unroll 1
-    for (int dy = 0; dy < 7; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 7; ++dx) acc += sk[dy * 7 + dx] * sx[(v + dy) * E + (u + dx)];
-    wr(i, j, acc);
+    for (int c = 0; c < NC; ++c) {
+      if (!act[c]) continue;
+      const double* x = sx + c * E * E;
+      double acc = 0.0;
+#pragma unroll 1
+      for (int dy = 0; dy < 7; ++dy)
+#pragma unroll
+        for (int dx = 0; dx < 7; ++dx) acc += sk[dy * 7 + dx] * x[(v + dy) * E + (u + dx)];
+      wr(c, i, j, acc);
+    }
   }
   __syncthreads();
 }

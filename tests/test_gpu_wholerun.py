@@ -1,0 +1,110 @@
+"""Whole-run parity of the FP32 fast form (FP32 particles, FP64 fields and CG)
+against the FP64 oracle: a drifting pair plasma at gamma0 = 40 in which the
+numerical Cherenkov instability grows from noise and saturates (Sec. 3).
+
+The stored history was written by tests/golden/make_nci_history.py from the
+oracle alone. Bars: the field-energy history within 1e-3, measured against
+the largest oracle field energy so far, e(n) = |W_F(n) - W_F^ora(n)| /
+max_{m <= n} W_F^ora(m), because FP32 and FP64 trajectories cannot agree
+pointwise at the noise floor; the total energy within 1e-3 relative; the
+growth rate, half the slope of ln W_B over the exponential phase, within 5%.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.growth import growth_rate
+from synth import loads
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = os.path.join(HERE, "golden", "nci_history_128x64.json")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _run(golden, solver, train_after=0):
+    import paper_1412_2480_amd as pic
+    c = golden["case"]
+    Q = golden["macro_charge"]
+    run = pic.run_desc(c["nx"], c["ny"], c["dx"], c["cfl"], c["theta"], c["order"],
+                       [(-Q, Q, c["ppc"]), (Q, Q, c["ppc"])], cg_rtol=c["rtol"])
+    opts = pic.make_options("fp32", diag_every=1, history_cap=c["steps"] + 1, slack=1.0,
+                            exchange_frac=0.5, solver=solver, precond_slots=8)
+    sim = pic.Sim([run], opts)
+    ld = loads.pair_plasma_cells(c["nx"], c["ny"], c["ppc"], c["gamma0"], c["T"], c["seed"])
+    for s in range(2):
+        d = ld[s]
+        sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    learned_iters = 0
+    if solver == "learned":
+        # plain CG while pairs are recorded, then train and switch
+        sim.precond_use(False)
+        sim.precond_collect(True)
+        sim.step(train_after)
+        sim.precond_collect(False)
+        tr = sim.precond_train(epochs=20)
+        _say(f"trained: {tr}")
+        sim.precond_use(True)
+        left = c["steps"] - train_after
+        while left > 0:
+            n = min(25, left)
+            st = sim.step(n)[0]
+            assert st["fallback"] == 0 and max(st["relres"]) <= c["rtol"]
+            learned_iters = max(learned_iters, max(st["learned_iters"]))
+            left -= n
+    else:
+        sim.step(c["steps"])
+    h = sim.history(0)
+    sim.close()
+    a = np.array([[r["W_E"], r["W_B"], r["W_K_minus"], r["W_K_plus"]] for r in h])
+    return a, learned_iters
+
+
+def _check(golden, a):
+    ref = np.array(golden["records"])[:, :4]
+    c = golden["case"]
+    assert a.shape == ref.shape
+    wf, wf_ref = a[:, 0] + a[:, 1], ref[:, 0] + ref[:, 1]
+    runmax = np.maximum.accumulate(wf_ref)
+    ok = runmax > 0
+    e = np.abs(wf - wf_ref)[ok] / runmax[ok]
+    _say(f"field-energy history: max e = {e.max():.3e}")
+    assert e.max() <= 1e-3
+    tot = a[:, 0] + a[:, 1] + 0.5 * (a[:, 2] + a[:, 3])
+    tot_ref = ref[:, 0] + ref[:, 1] + 0.5 * (ref[:, 2] + ref[:, 3])
+    et = np.abs(tot - tot_ref).max() / np.abs(tot_ref).max()
+    _say(f"total energy: max rel = {et:.3e}")
+    assert et <= 1e-3
+    t = np.arange(c["steps"]) * c["cfl"] * c["dx"]
+    g = growth_rate(t, a[:, 1])
+    g_ref = golden["growth"]
+    assert g is not None and g_ref is not None
+    _say(f"growth rate {g['rate']:.5f} vs oracle {g_ref['rate']:.5f}")
+    assert abs(g["rate"] - g_ref["rate"]) <= 0.05 * g_ref["rate"]
+
+
+def test_fp32_whole_run_matches_oracle(golden):
+    _say("whole run, FP32 form, plain CG")
+    a, _ = _run(golden, "cg")
+    _check(golden, a)
+
+
+def test_fp32_learned_whole_run_matches_oracle(golden):
+    _say("whole run, FP32 form, learned CG aid")
+    a, it = _run(golden, "learned", train_after=20)
+    _check(golden, a)
+    assert it >= 1
