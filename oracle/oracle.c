@@ -251,11 +251,13 @@ static double dot(int64_t n, const double* a, const double* b) {
   return s;
 }
 
-/* Conjugate gradient (Hestenes-Stiefel) on the symmetric positive definite
- * A of Eq. (7); the paper solves Eq. (7) by CG (Sec. 2, citing Hoshino 2013). */
-int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
-           const double* b, double* x, double rtol, int maxit, double* relres) {
-  int64_t n = (int64_t)nx * ny;
+/* Conjugate gradient (Hestenes-Stiefel) for a symmetric positive definite
+ * operator given as a callback; the paper solves Eq. (7) by CG (Sec. 2,
+ * citing Hoshino 2013). Starts from the x passed in; stops when
+ * ||r||_2 <= rtol ||b||_2 (recursive residual) or after maxit iterations. */
+static int cg_generic(int64_t n, void (*apply)(const void*, const double*, double*),
+                      const void* ctx, const double* b, double* x, double rtol, int maxit,
+                      double* relres) {
   double bnorm = sqrt(dot(n, b, b));
   if (bnorm == 0.0) {
     memset(x, 0, sizeof(double) * n);
@@ -265,7 +267,7 @@ int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
   double* r = malloc(sizeof(double) * n);
   double* p = malloc(sizeof(double) * n);
   double* q = malloc(sizeof(double) * n);
-  ora_apply_A(nx, ny, dx, dy, dt, theta, x, q);
+  apply(ctx, x, q);
   for (int64_t k = 0; k < n; ++k) {
     r[k] = b[k] - q[k];
     p[k] = r[k];
@@ -273,7 +275,7 @@ int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
   double rr = dot(n, r, r);
   int it = 0;
   while (it < maxit && sqrt(rr) > rtol * bnorm) {
-    ora_apply_A(nx, ny, dx, dy, dt, theta, p, q);
+    apply(ctx, p, q);
     double alpha = rr / dot(n, p, q);
     for (int64_t k = 0; k < n; ++k) {
       x[k] += alpha * p[k];
@@ -286,7 +288,7 @@ int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
     ++it;
   }
   if (relres) {
-    ora_apply_A(nx, ny, dx, dy, dt, theta, x, q);
+    apply(ctx, x, q);
     for (int64_t k = 0; k < n; ++k) r[k] = b[k] - q[k];
     *relres = sqrt(dot(n, r, r)) / bnorm;
   }
@@ -294,6 +296,21 @@ int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
   free(p);
   free(q);
   return it;
+}
+
+struct periodic_op {
+  int nx, ny;
+  double dx, dy, dt, theta;
+};
+static void periodic_apply(const void* ctx, const double* x, double* y) {
+  const struct periodic_op* o = (const struct periodic_op*)ctx;
+  ora_apply_A(o->nx, o->ny, o->dx, o->dy, o->dt, o->theta, x, y);
+}
+
+int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
+           const double* b, double* x, double rtol, int maxit, double* relres) {
+  struct periodic_op o = {nx, ny, dx, dy, dt, theta};
+  return cg_generic((int64_t)nx * ny, periodic_apply, &o, b, x, rtol, maxit, relres);
 }
 
 /* Eqs. (5)-(6) with dB known:
@@ -357,4 +374,248 @@ double ora_kinetic(int64_t np, double m, const double* ux, const double* uy, con
   for (int64_t k = 0; k < np; ++k)
     s += m * (sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]) - 1.0);
   return s;
+}
+
+/* ------------------------------------------------------------------------
+ * Shock set-up (a reading: the paper only says that the shock runs inject
+ * the flow at one side and reflect it at the other, Sec. 4). x = 0 and
+ * x = (nx-1) dx are conducting walls: Ey, Ez and Bx are zero on those node
+ * lines, and the half-integer components (Ex, By, Bz, Jx) of the last column
+ * lie outside and are zero. Particles reflect specularly at x = 0 and leave
+ * the run when they reach x_out = (nx - ORA_WALL_GAP) dx, where new flow is
+ * injected. y stays periodic.
+ * ---------------------------------------------------------------------- */
+
+/* field value at column i (any integer) of component c with the conductor
+ * images behind x = 0: integer-x components (Ey, Ez, Bx) are odd about the
+ * wall node line, half-integer ones (Ex, By, Bz) even */
+static double wall_field(int nx, int ny, const double* f, int c, int i, int j) {
+  if (i < 0) {
+    if (STAG_X[c] > 0.0) return f[at(nx, ny, -i - 1, j)];
+    return -f[at(nx, ny, -i, j)];
+  }
+  if (i >= nx) abort();   /* particles stay ORA_WALL_GAP cells from the right wall */
+  return f[at(nx, ny, i, j)];
+}
+
+void ora_gather_wall(int nx, int ny, int order, const double* const* f6,
+                     int64_t np, const int32_t* ix, const int32_t* iy,
+                     const double* fx, const double* fy, double* out6) {
+  for (int64_t k = 0; k < np; ++k) {
+    for (int c = 0; c < 6; ++c) {
+      double sum = 0.0;
+      for (int j = iy[k] - 2; j <= iy[k] + 2; ++j) {
+        double wy = ora_shape(order, (double)(iy[k] - j) + fy[k] - STAG_Y[c]);
+        for (int i = ix[k] - 2; i <= ix[k] + 2; ++i) {
+          double wx = ora_shape(order, (double)(ix[k] - i) + fx[k] - STAG_X[c]);
+          if (wx == 0.0 || wy == 0.0) continue;
+          sum += wall_field(nx, ny, f6[c], c, i, j) * wx * wy;
+        }
+      }
+      out6[(int64_t)c * np + k] = sum;
+    }
+  }
+}
+
+/* add v to component c (0 Jx, 1 Jy, 2 Jz, 3 rho) at column i, folding a
+ * column behind the wall onto its mirror: rho, Jy and Jz keep their sign,
+ * Jx (half-integer x, the normal current) changes sign. The fold keeps the
+ * discrete continuity equation exact at every node off the wall line. */
+static void wall_add(int nx, int ny, double* f, int c, int i, int j, double v) {
+  if (i < 0) {
+    if (c == 0) {
+      i = -i - 1;
+      v = -v;
+    } else {
+      i = -i;
+    }
+  }
+  if (i >= nx) abort();
+  f[at(nx, ny, i, j)] += v;
+}
+
+/* Esirkepov deposit (same arithmetic as ora_deposit) of the unreflected
+ * displacement, with the wall fold */
+void ora_deposit_wall(int nx, int ny, int order, double dx, double dy, double dt,
+                      double q, int64_t np,
+                      const int32_t* ix0, const int32_t* iy0, const double* fx0,
+                      const double* fy0, const int32_t* ix1, const int32_t* iy1,
+                      const double* fx1, const double* fy1, const double* ux,
+                      const double* uy, const double* uz, double* jx, double* jy, double* jz) {
+  enum { W = 6 };
+  for (int64_t k = 0; k < np; ++k) {
+    double s0x[W], s1x[W], dsx[W], s0y[W], s1y[W], dsy[W];
+    int bi = ix0[k] - 2, bj = iy0[k] - 2;
+    for (int a = 0; a < W; ++a) {
+      int i = bi + a, j = bj + a;
+      s0x[a] = ora_shape(order, (double)(ix0[k] - i) + fx0[k]);
+      s1x[a] = ora_shape(order, (double)(ix1[k] - i) + fx1[k]);
+      s0y[a] = ora_shape(order, (double)(iy0[k] - j) + fy0[k]);
+      s1y[a] = ora_shape(order, (double)(iy1[k] - j) + fy1[k]);
+      dsx[a] = s1x[a] - s0x[a];
+      dsy[a] = s1y[a] - s0y[a];
+    }
+    double g = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
+    double vz = uz[k] / g;
+    double cx = -q / (dy * dt), cy = -q / (dx * dt), cz = q * vz / (dx * dy);
+    for (int b = 0; b < W; ++b) {
+      double acc = 0.0;
+      for (int a = 0; a < W; ++a) {
+        acc += dsx[a] * (s0y[b] + 0.5 * dsy[b]);
+        if (acc != 0.0) wall_add(nx, ny, jx, 0, bi + a, bj + b, cx * acc);
+      }
+    }
+    for (int a = 0; a < W; ++a) {
+      double acc = 0.0;
+      for (int b = 0; b < W; ++b) {
+        acc += dsy[b] * (s0x[a] + 0.5 * dsx[a]);
+        if (acc != 0.0) wall_add(nx, ny, jy, 1, bi + a, bj + b, cy * acc);
+      }
+    }
+    for (int b = 0; b < W; ++b)
+      for (int a = 0; a < W; ++a) {
+        double wz = s0x[a] * s0y[b] + 0.5 * dsx[a] * s0y[b] + 0.5 * s0x[a] * dsy[b] +
+                    dsx[a] * dsy[b] / 3.0;
+        if (wz != 0.0) wall_add(nx, ny, jz, 2, bi + a, bj + b, cz * wz);
+      }
+  }
+}
+
+/* currents on the conductors drive no field: Jy, Jz on both wall node lines
+ * and Jx of the last (outside) column are set to zero */
+void ora_mask_wall_currents(int nx, int ny, double* jx, double* jy, double* jz) {
+  for (int j = 0; j < ny; ++j) {
+    jy[at(nx, ny, 0, j)] = 0.0;
+    jz[at(nx, ny, 0, j)] = 0.0;
+    jy[at(nx, ny, nx - 1, j)] = 0.0;
+    jz[at(nx, ny, nx - 1, j)] = 0.0;
+    jx[at(nx, ny, nx - 1, j)] = 0.0;
+  }
+}
+
+/* after the deposit: specular reflection of particles behind x = 0
+ * (x -> -x, ux -> -ux) and removal of those at or beyond x_out; keep[k] = 0
+ * marks a removed particle. y is wrapped periodically. */
+void ora_boundary_wall(int nx, int ny, int64_t np, int32_t* ix, int32_t* iy, double* fx,
+                       double* ux, uint8_t* keep) {
+  for (int64_t k = 0; k < np; ++k) {
+    if (ix[k] < 0) {
+      /* x = ix + fx with ix = -1: -x = (-ix - 1) + (1 - fx) */
+      double f = 1.0 - fx[k];
+      int32_t c = -ix[k] - 1;
+      if (f >= 1.0) {
+        f -= 1.0;
+        c += 1;
+      }
+      ix[k] = c;
+      fx[k] = f;
+      ux[k] = -ux[k];
+    }
+    keep[k] = ix[k] < nx - ORA_WALL_GAP ? 1 : 0;
+    iy[k] = wrapi(iy[k], ny);
+  }
+}
+
+/* row class of component c at column i: 0 free, 1 fixed (zero). Bx lives on
+ * integer x and is zero on both wall lines; By, Bz live on half-integer x and
+ * the last column is outside. */
+static int wall_fixed(int nx, int c, int i) {
+  if (c == 0) return i == 0 || i == nx - 1;
+  return i == nx - 1;
+}
+
+/* x-neighbour value for the Laplacian of component c at free row i: a fixed
+ * neighbour is zero (Dirichlet); behind a conductor the tangential By, Bz take
+ * the row's own value (their normal derivative vanishes at the wall) */
+static double wall_xnb(int nx, int ny, const double* f, int c, int i, int j, int di) {
+  int n = i + di;
+  if (c == 0) {
+    if (n <= 0 || n >= nx - 1) return 0.0;
+    return f[at(nx, ny, n, j)];
+  }
+  if (n < 0 || n >= nx - 1) return f[at(nx, ny, i, j)];
+  return f[at(nx, ny, n, j)];
+}
+
+static double lap_wall(int nx, int ny, double dx, double dy, const double* f, int c, int i,
+                       int j) {
+  double v = f[at(nx, ny, i, j)];
+  return (wall_xnb(nx, ny, f, c, i, j, 1) - 2.0 * v + wall_xnb(nx, ny, f, c, i, j, -1)) /
+             (dx * dx) +
+         (f[at(nx, ny, i, j + 1)] - 2.0 * v + f[at(nx, ny, i, j - 1)]) / (dy * dy);
+}
+
+void ora_rhs_wall(int nx, int ny, double dx, double dy, double dt, double theta,
+                  const double* const* e3, const double* const* b3, const double* const* j3,
+                  double* const* b_out) {
+  const double four_pi = 4.0 * M_PI;
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double cj[3], ce[3];
+      curl_e(nx, ny, dx, dy, j3, i, j, cj);
+      curl_e(nx, ny, dx, dy, e3, i, j, ce);
+      for (int c = 0; c < 3; ++c) {
+        double v = 0.0;
+        if (!wall_fixed(nx, c, i)) {
+          double lb = lap_wall(nx, ny, dx, dy, b3[c], c, i, j);
+          v = theta * dt * dt * (lb + four_pi * cj[c]) - dt * ce[c];
+        }
+        b_out[c][at(nx, ny, i, j)] = v;
+      }
+    }
+}
+
+void ora_apply_A_wall(int nx, int ny, double dx, double dy, double dt, double theta, int c,
+                      const double* x, double* y) {
+  double a = (theta * dt) * (theta * dt);
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      int64_t k = at(nx, ny, i, j);
+      y[k] = wall_fixed(nx, c, i) ? x[k] : x[k] - a * lap_wall(nx, ny, dx, dy, x, c, i, j);
+    }
+}
+
+struct wall_op {
+  int nx, ny, c;
+  double dx, dy, dt, theta;
+};
+static void wall_apply(const void* ctx, const double* x, double* y) {
+  const struct wall_op* o = (const struct wall_op*)ctx;
+  ora_apply_A_wall(o->nx, o->ny, o->dx, o->dy, o->dt, o->theta, o->c, x, y);
+}
+
+int ora_cg_wall(int nx, int ny, double dx, double dy, double dt, double theta, int c,
+                const double* b, double* x, double rtol, int maxit, double* relres) {
+  struct wall_op o = {nx, ny, c, dx, dy, dt, theta};
+  return cg_generic((int64_t)nx * ny, wall_apply, &o, b, x, rtol, maxit, relres);
+}
+
+/* Eqs. (5)-(6) with the walls: E nodes on a conductor (Ey, Ez on both wall
+ * lines, Ex of the outside column) stay zero; B += dB (dB is zero on fixed rows) */
+void ora_update_wall(int nx, int ny, double dx, double dy, double dt, double theta,
+                     double* const* e3, double* const* b3, const double* const* db3,
+                     const double* const* j3) {
+  ora_update(nx, ny, dx, dy, dt, theta, e3, b3, db3, j3);
+  for (int j = 0; j < ny; ++j) {
+    e3[1][at(nx, ny, 0, j)] = 0.0;
+    e3[2][at(nx, ny, 0, j)] = 0.0;
+    e3[0][at(nx, ny, nx - 1, j)] = 0.0;
+    e3[1][at(nx, ny, nx - 1, j)] = 0.0;
+    e3[2][at(nx, ny, nx - 1, j)] = 0.0;
+  }
+}
+
+/* charge density with the wall fold (rho keeps its sign behind x = 0) */
+void ora_charge_wall(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
+                     const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
+                     double* rho) {
+  for (int64_t k = 0; k < np; ++k)
+    for (int j = iy[k] - 2; j <= iy[k] + 3; ++j) {
+      double wy = ora_shape(order, (double)(iy[k] - j) + fy[k]);
+      for (int i = ix[k] - 2; i <= ix[k] + 3; ++i) {
+        double wx = ora_shape(order, (double)(ix[k] - i) + fx[k]);
+        if (wx == 0.0 || wy == 0.0) continue;
+        wall_add(nx, ny, rho, 3, i, j, q * wx * wy / (dx * dy));
+      }
+    }
 }

@@ -102,6 +102,59 @@ void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64
 void ora_div_e(int nx, int ny, double dx, double dy, const double* ex, const double* ey, double* out);
 void ora_div_b(int nx, int ny, double dx, double dy, const double* bx, const double* by, double* out);
 
+/* ---- Shock set-up (a reading; the paper only says the shock runs inject the
+ * flow at one side and reflect it at the other, Sec. 4): conducting walls at
+ * x = 0 and x = (nx-1) dx, specular particle reflection at x = 0, particles
+ * removed at x >= (nx - ORA_WALL_GAP) dx where the flow is injected, y
+ * periodic. Tangential E (Ey, Ez) and normal B (Bx) vanish on the wall node
+ * lines; the half-integer components of the last column lie outside. */
+#define ORA_WALL_GAP 4
+
+/* gather with the conductor images behind x = 0 (Ey, Ez, Bx odd; Ex, By, Bz
+ * even about the wall line) */
+void ora_gather_wall(int nx, int ny, int order, const double* const* f6,
+                     int64_t np, const int32_t* ix, const int32_t* iy,
+                     const double* fx, const double* fy, double* out6);
+
+/* Esirkepov deposit of the unreflected displacement; columns behind the wall
+ * fold onto their mirrors (rho, Jy, Jz with their sign, Jx negated) */
+void ora_deposit_wall(int nx, int ny, int order, double dx, double dy, double dt,
+                      double q, int64_t np,
+                      const int32_t* ix0, const int32_t* iy0, const double* fx0,
+                      const double* fy0, const int32_t* ix1, const int32_t* iy1,
+                      const double* fx1, const double* fy1, const double* ux,
+                      const double* uy, const double* uz, double* jx, double* jy, double* jz);
+
+/* zero Jy, Jz on both wall lines and Jx of the outside column */
+void ora_mask_wall_currents(int nx, int ny, double* jx, double* jy, double* jz);
+
+/* reflect particles behind x = 0 (x -> -x, ux -> -ux); keep[k] = 0 for those
+ * at or beyond x_out; wrap y */
+void ora_boundary_wall(int nx, int ny, int64_t np, int32_t* ix, int32_t* iy, double* fx,
+                       double* ux, uint8_t* keep);
+
+/* Eq. (7) with the walls, component by component (c = 0 Bx, 1 By, 2 Bz):
+ * fixed rows (Bx on both wall lines, the outside column of By and Bz) have
+ * b = 0 and an identity row; a fixed x-neighbour reads zero; behind a wall By
+ * and Bz take the row's own value. */
+void ora_rhs_wall(int nx, int ny, double dx, double dy, double dt, double theta,
+                  const double* const* e3, const double* const* b3, const double* const* j3,
+                  double* const* b_out);
+void ora_apply_A_wall(int nx, int ny, double dx, double dy, double dt, double theta, int c,
+                      const double* x, double* y);
+int ora_cg_wall(int nx, int ny, double dx, double dy, double dt, double theta, int c,
+                const double* b, double* x, double rtol, int maxit, double* relres);
+
+/* charge density at nodes with the same fold as the deposit */
+void ora_charge_wall(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
+                     const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
+                     double* rho);
+
+/* Eqs. (5)-(6) with the conductor E nodes held at zero */
+void ora_update_wall(int nx, int ny, double dx, double dy, double dt, double theta,
+                     double* const* e3, double* const* b3, const double* const* db3,
+                     const double* const* j3);
+
 /* sum m (gamma - 1) over particles */
 double ora_kinetic(int64_t np, double m, const double* ux, const double* uy, const double* uz);
 
