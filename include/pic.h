@@ -58,7 +58,16 @@ enum pic_status {
   PIC_E_STATE = -7     /* calls out of order (e.g. deposit before gather_push) */
 };
 
-enum pic_bc { PIC_BC_PERIODIC = 0 };
+/* Boundaries. PIC_BC_SHOCK is the shock set-up (a reading: the paper only says
+ * the flow is injected at one side and reflected at the other, Sec. 4):
+ * conducting walls at x = 0 and x = (nx-1) dx (Ey, Ez, Bx zero on those node
+ * lines; Ex, By, Bz of the last column lie outside and are zero), specular
+ * reflection of particles at x = 0 (x -> -x, ux -> -ux; the deposit folds the
+ * part of a shape behind the wall back, rho/Jy/Jz with their sign and Jx
+ * negated), removal of particles reaching x_out = (nx - PIC_WALL_GAP) dx,
+ * where new flow enters through pic_inject_particles; y periodic. */
+enum pic_bc { PIC_BC_PERIODIC = 0, PIC_BC_SHOCK = 1 };
+#define PIC_WALL_GAP 4
 enum pic_precision { PIC_FP64 = 0, PIC_FP32_FAST = 1 };
 enum pic_solver {
   PIC_SOLVER_CG = 0,          /* plain CG on Eq. (7) (the paper's solver) */
@@ -85,7 +94,7 @@ typedef struct pic_run_desc {
   double cfl;            /* sigma = c dt/dx, 0 < sigma <= 1 (Esirkepov needs < 1 cell/step) */
   double theta;          /* implicitness factor of Eqs. (5)-(6), 0.5 <= theta <= 1 */
   int32_t shape_order;   /* B-spline degree 1, 2 or 3 */
-  int32_t bc;            /* PIC_BC_PERIODIC (both directions) */
+  int32_t bc;            /* PIC_BC_PERIODIC (both directions) or PIC_BC_SHOCK (nx >= 16) */
   int32_t n_species;     /* 1 .. PIC_MAX_SPECIES */
   pic_species_desc species[PIC_MAX_SPECIES];
   double cg_rtol;        /* relative residual target of the field CG (e.g. 1e-8) */
@@ -170,9 +179,20 @@ int32_t pic_load_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t n
                            const double* fy, const double* ux, const double* uy,
                            const double* uz);
 
+/* Append n host particles to (run, species) of a PIC_BC_SHOCK run between
+ * steps (same arrays as pic_load_particles; ix < nx - PIC_WALL_GAP). They get
+ * the next ids of the species. At most four cell columns' worth of the run
+ * (4 ny ppc) per call; PIC_E_CAPACITY if a tile's slots would overflow (state
+ * unchanged). Synchronises. */
+int32_t pic_inject_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t n,
+                             const int32_t* ix, const int32_t* iy, const double* fx,
+                             const double* fy, const double* ux, const double* uy,
+                             const double* uz);
+
 /* Copy the particles of (run, species) to the host, with n_out = count (at
- * most cap), ordered by id when ids are tracked (storage order otherwise).
- * Any output pointer may be NULL. */
+ * most cap), in ascending id order when ids are tracked (ids are load order,
+ * then injection order; removed particles leave gaps), storage order
+ * otherwise. Any output pointer may be NULL. */
 int32_t pic_read_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t cap,
                            int32_t* ix, int32_t* iy, double* fx, double* fy, double* ux,
                            double* uy, double* uz, int64_t* n_out);
@@ -199,7 +219,9 @@ int32_t pic_step(pic_ctx* ctx, int32_t nsteps, pic_solve_stats* last);
 
 /* Diagnostics of the current state of one run (synchronises): energies of
  * the last recorded step plus particle counts. gauss/divb (nullable) receive
- * max |div E - 4 pi rho| and max |div B| over the grid. */
+ * max |div E - 4 pi rho| and max |div B| over the grid (for a shock run the
+ * Gauss residual covers the node columns 1 .. x_out - 4: the wall line holds
+ * the conductor's surface charge and particles leave at x_out). */
 int32_t pic_diag(pic_ctx* ctx, int32_t run, pic_diag_out* out, double* gauss, double* divb);
 
 /* History records collected every diag_every steps (oldest first). */

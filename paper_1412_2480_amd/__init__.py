@@ -20,17 +20,19 @@ PIC_FP64, PIC_FP32_FAST = 0, 1
 PIC_SOLVER_CG, PIC_SOLVER_LEARNED_PCG = 0, 1
 PIC_NET_COLLAPSED, PIC_NET_MFMA = 0, 1
 NET_NW = 9792
-PIC_BC_PERIODIC = 0
+PIC_BC_PERIODIC, PIC_BC_SHOCK = 0, 1
+PIC_WALL_GAP = 4
 FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
              "rho": 9}
 STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
           -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
-EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_read_particles", "pic_set_field",
-           "pic_get_field", "pic_gather_push", "pic_deposit", "pic_field_solve", "pic_step",
-           "pic_diag", "pic_history", "pic_timing", "pic_get_timing", "pic_precond_collect",
-           "pic_precond_train", "pic_precond_use", "pic_precond_get_weights",
-           "pic_precond_set_weights", "pic_precond_apply", "pic_precond_grad", "pic_sync",
-           "pic_destroy", "pic_last_error", "pic_status_str"]
+EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_inject_particles",
+           "pic_read_particles", "pic_set_field", "pic_get_field", "pic_gather_push",
+           "pic_deposit", "pic_field_solve", "pic_step", "pic_diag", "pic_history",
+           "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
+           "pic_precond_use", "pic_precond_get_weights", "pic_precond_set_weights",
+           "pic_precond_apply", "pic_precond_grad", "pic_sync", "pic_destroy",
+           "pic_last_error", "pic_status_str"]
 
 
 class SpeciesDesc(ctypes.Structure):
@@ -112,6 +114,8 @@ def lib():
                                ctypes.c_size_t, ctypes.c_void_p, P(ctypes.c_void_p)]
         L.pic_load_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64] + [ctypes.c_void_p] * 7
+        L.pic_inject_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                           ctypes.c_int64] + [ctypes.c_void_p] * 7
         L.pic_read_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64] + [ctypes.c_void_p] * 7 + \
                                         [P(ctypes.c_int64)]
@@ -158,15 +162,16 @@ class PicError(RuntimeError):
         self.code = code
 
 
-def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_maxit=200):
-    """species: list of (q, m, ppc)."""
+def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_maxit=200,
+             bc="periodic"):
+    """species: list of (q, m, ppc); bc: "periodic" or "shock"."""
     d = RunDesc()
     d.nx, d.ny = int(nx), int(ny)
     d.dx = float(dx)
     d.dy = float(dx if dy is None else dy)
     d.cfl, d.theta = float(cfl), float(theta)
     d.shape_order = int(order)
-    d.bc = PIC_BC_PERIODIC
+    d.bc = PIC_BC_SHOCK if bc in ("shock", PIC_BC_SHOCK) else PIC_BC_PERIODIC
     d.n_species = len(species)
     for k, (q, m, ppc) in enumerate(species):
         d.species[k].q, d.species[k].m, d.species[k].ppc = float(q), float(m), float(ppc)
@@ -257,6 +262,13 @@ class Sim:
         n = a[0].size
         self._check(self.L.pic_load_particles(self.ctx, run, species, n, *[_ptr(v) for v in a]),
                     "load_particles")
+
+    def inject_particles(self, run, species, ix, iy, fx, fy, ux, uy, uz):
+        a = [np.ascontiguousarray(v, dtype=t) for v, t in
+             ((ix, np.int32), (iy, np.int32), (fx, np.float64), (fy, np.float64),
+              (ux, np.float64), (uy, np.float64), (uz, np.float64))]
+        self._check(self.L.pic_inject_particles(self.ctx, run, species, a[0].size,
+                                                *[_ptr(v) for v in a]), "inject_particles")
 
     def read_particles(self, run, species, cap):
         out = dict(ix=np.empty(cap, np.int32), iy=np.empty(cap, np.int32),

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -95,6 +96,17 @@ struct pic_ctx {
   long long train_cells = 0;
   int adam_step = 0;
   double* d_history = nullptr;
+  // injection staging (shock runs): particles sorted by tile + (tile, first, count) list
+  long long inj_cap = 0;
+  int* d_inj_cell = nullptr;
+  void* d_inj_ox = nullptr;
+  void* d_inj_oy = nullptr;
+  void* d_inj_ux = nullptr;
+  void* d_inj_uy = nullptr;
+  void* d_inj_uz = nullptr;
+  int* d_inj_id = nullptr;
+  int* d_inj_list = nullptr;
+  std::vector<std::array<long long, PIC_MAXS>> next_id;   // per run and species
   double* d_rho = nullptr;
   double* d_divpart = nullptr;
   int* d_err = nullptr;
@@ -175,7 +187,9 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     if (d.cfl * d.dx > d.dy * (1.0 + 1e-12)) return bad("dt must not exceed dy (one cell per step)");
     if (!(d.theta >= 0.5) || d.theta > 1.0) return bad("theta must be in [0.5, 1]");
     if (d.shape_order < 1 || d.shape_order > 3) return bad("shape_order must be 1, 2 or 3");
-    if (d.bc != PIC_BC_PERIODIC) return bad("only periodic boundaries are supported");
+    if (d.bc != PIC_BC_PERIODIC && d.bc != PIC_BC_SHOCK)
+      return bad("bc must be PIC_BC_PERIODIC or PIC_BC_SHOCK");
+    if (d.bc == PIC_BC_SHOCK && d.nx < 16) return bad("a shock run needs nx >= 16");
     if (d.n_species < 1 || d.n_species > PIC_MAX_SPECIES) return bad("n_species out of range");
     for (int s = 0; s < d.n_species; ++s)
       if (!(d.species[s].m > 0) || !std::isfinite(d.species[s].q) || !(d.species[s].ppc >= 0))
@@ -216,8 +230,8 @@ void make_tiling(const pic_run_desc* runs, int n_runs, const pic_options* o, Til
 // Carve (or, with base == nullptr, size) the workspace.
 template <typename R>
 size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
-             bool split, bool ids, int hist_cap, int pair_slots, long long train_cells, pic_ctx* c,
-             DevState<R>* st) {
+             bool split, bool ids, int hist_cap, int pair_slots, long long train_cells,
+             long long inj_cap, pic_ctx* c, DevState<R>* st) {
   Bump b(base);
   const int K = pl.tile_split;
   const long long nc = tl.n_cells;
@@ -273,6 +287,18 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   int* err = b.take<int>(1);
   double* wk_part = b.take<double>((size_t)tl.n_tiles * K * PIC_MAXS * 2);
   double* rho = b.take<double>(tl.max_cells);
+  int *inj_cell = nullptr, *inj_id = nullptr, *inj_list = nullptr;
+  R *inj_ox = nullptr, *inj_oy = nullptr, *inj_ux = nullptr, *inj_uy = nullptr, *inj_uz = nullptr;
+  if (inj_cap > 0) {
+    inj_cell = b.take<int>(inj_cap);
+    inj_ox = b.take<R>(inj_cap);
+    inj_oy = b.take<R>(inj_cap);
+    inj_ux = b.take<R>(inj_cap);
+    inj_uy = b.take<R>(inj_cap);
+    inj_uz = b.take<R>(inj_cap);
+    inj_id = b.take<int>(inj_cap);
+    inj_list = b.take<int>((size_t)3 * tl.n_tiles);
+  }
   double* divpart = b.take<double>((size_t)kDivBlocks * 2);
   double* patch[3];
   for (int k = 0; k < 3; ++k) patch[k] = b.take<double>((size_t)tl.n_tiles * K * plane);
@@ -375,9 +401,31 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   c->d_stats = stats;
   c->d_history = history;
   c->d_rho = rho;
+  c->inj_cap = inj_cap;
+  c->d_inj_cell = inj_cell;
+  c->d_inj_ox = inj_ox;
+  c->d_inj_oy = inj_oy;
+  c->d_inj_ux = inj_ux;
+  c->d_inj_uy = inj_uy;
+  c->d_inj_uz = inj_uz;
+  c->d_inj_id = inj_id;
+  c->d_inj_list = inj_list;
   c->d_divpart = divpart;
   c->d_err = err;
   return total;
+}
+
+// staged particles per injection call: four cell columns of every shock run
+// at the largest ppc of its species
+long long inject_cap_of(const pic_run_desc* runs, int n_runs) {
+  long long cap = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    if (runs[r].bc != PIC_BC_SHOCK) continue;
+    double ppc = 0;
+    for (int s = 0; s < runs[r].n_species; ++s) ppc = std::max(ppc, runs[r].species[s].ppc);
+    cap += 4LL * runs[r].ny * (long long)std::ceil(ppc) + 64;
+  }
+  return cap;
 }
 
 int pair_slots_of(const pic_options* o) {
@@ -432,10 +480,11 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   const bool ids = o->track_ids != 0;
   const int slots = pair_slots_of(o);
   const long long tc = (long long)runs[0].nx * runs[0].ny;
+  const long long ic = inject_cap_of(runs, n_runs);
   p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, ids, hist_cap,
-                                          slots, tc, nullptr, (DevState<float>*)nullptr)
+                                          slots, tc, ic, nullptr, (DevState<float>*)nullptr)
                            : carve<double>(nullptr, *tl, p, n_runs, false, split, ids, hist_cap,
-                                           slots, tc, nullptr, (DevState<double>*)nullptr);
+                                           slots, tc, ic, nullptr, (DevState<double>*)nullptr);
   *out = p;
   return PIC_OK;
 }
@@ -622,8 +671,9 @@ int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const in
   if (n > (int64_t)INT32_MAX) return fail(c, PIC_E_INVAL, "too many particles for int32 ids");
   std::vector<int> tile_of(n);
   std::vector<int> count(nt, 0);
+  const int xmax = d.bc == PIC_BC_SHOCK ? d.nx - PIC_WALL_GAP : d.nx;
   for (int64_t k = 0; k < n; ++k) {
-    if (ix[k] < 0 || ix[k] >= d.nx || iy[k] < 0 || iy[k] >= d.ny || !(fx[k] >= 0.0) ||
+    if (ix[k] < 0 || ix[k] >= xmax || iy[k] < 0 || iy[k] >= d.ny || !(fx[k] >= 0.0) ||
         !(fx[k] < 1.0) || !(fy[k] >= 0.0) || !(fy[k] < 1.0) || !std::isfinite(ux[k]) ||
         !std::isfinite(uy[k]) || !std::isfinite(uz[k]))
       return fail(c, PIC_E_INVAL, "particle outside the grid, offset outside [0,1) or non-finite u");
@@ -691,6 +741,87 @@ int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const in
   HIPCHK(c, hipMemcpyAsync(st.cnt[s] + tl.tile0[run], count.data(), nt * sizeof(int),
                            hipMemcpyHostToDevice, S));
   HIPCHK(c, hipStreamSynchronize(S));
+  c->next_id[run][s] = n;
+  return PIC_OK;
+}
+
+// Append n particles to (run, species): staged sorted by tile, then one
+// work-group per receiving tile copies them after the tile's particles.
+template <typename R>
+int inject_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const int32_t* iy,
+                const double* fx, const double* fy, const double* ux, const double* uy,
+                const double* uz) {
+  const pic_run_desc& d = c->runs[run];
+  const Tiling& tl = c->tl;
+  const int ntx = tl.ntx[run], nty = tl.nty[run], nt = ntx * nty;
+  const int slots = c->plan.tile_slots[s];
+  if (n == 0) return PIC_OK;
+  if (n > c->inj_cap)
+    return fail(c, PIC_E_CAPACITY, "more particles than the injection staging holds "
+                                   "(four cell columns of the run per call)");
+  if (c->next_id[run][s] + n > (long long)INT32_MAX)
+    return fail(c, PIC_E_INVAL, "particle ids exceed int32");
+  const int xmax = d.bc == PIC_BC_SHOCK ? d.nx - PIC_WALL_GAP : d.nx;
+  std::vector<int> tile_of(n), add(nt, 0);
+  for (int64_t k = 0; k < n; ++k) {
+    if (ix[k] < 0 || ix[k] >= xmax || iy[k] < 0 || iy[k] >= d.ny || !(fx[k] >= 0.0) ||
+        !(fx[k] < 1.0) || !(fy[k] >= 0.0) || !(fy[k] < 1.0) || !std::isfinite(ux[k]) ||
+        !std::isfinite(uy[k]) || !std::isfinite(uz[k]))
+      return fail(c, PIC_E_INVAL, "injected particle outside the run, offset outside [0,1) "
+                                  "or non-finite u");
+    const int tx = std::min(ix[k] / tl.TX, ntx - 1);
+    const int ty = std::min(iy[k] / tl.TY, nty - 1);
+    tile_of[k] = ty * ntx + tx;
+    add[tile_of[k]] += 1;
+  }
+  DevState<R>& st = state<R>(c);
+  hipStream_t S = c->stream;
+  std::vector<int> count(nt);
+  HIPCHK(c, hipMemcpyAsync(count.data(), st.cnt[s] + tl.tile0[run], nt * sizeof(int),
+                           hipMemcpyDeviceToHost, S));
+  HIPCHK(c, hipStreamSynchronize(S));
+  for (int t = 0; t < nt; ++t)
+    if (count[t] + add[t] > slots)
+      return fail(c, PIC_E_CAPACITY, "tile slots exceeded by injection; raise slack");
+  std::vector<int> first(nt + 1, 0), list;
+  for (int t = 0; t < nt; ++t) {
+    first[t + 1] = first[t] + add[t];
+    if (add[t]) {
+      list.push_back(tl.tile0[run] + t);
+      list.push_back(first[t]);
+      list.push_back(add[t]);
+    }
+  }
+  std::vector<int> hcell(n), hid(n), pos(first.begin(), first.end() - 1);
+  std::vector<R> hox(n), hoy(n), hux(n), huy(n), huz(n);
+  for (int64_t k = 0; k < n; ++k) {
+    const int o = pos[tile_of[k]]++;
+    hcell[o] = (iy[k] << 16) | ix[k];
+    hox[o] = (R)fx[k];
+    hoy[o] = (R)fy[k];
+    if (hox[o] >= R(1)) { hox[o] = R(0); hcell[o] = (iy[k] << 16) | (ix[k] + 1); }
+    if (hoy[o] >= R(1)) { hoy[o] = R(0); hcell[o] = ((((hcell[o] >> 16) + 1) % d.ny) << 16) | (hcell[o] & 0xffff); }
+    hux[o] = (R)ux[k];
+    huy[o] = (R)uy[k];
+    huz[o] = (R)uz[k];
+    hid[o] = (int)(c->next_id[run][s] + k);
+  }
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_cell, hcell.data(), n * sizeof(int), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_ox, hox.data(), n * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_oy, hoy.data(), n * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_ux, hux.data(), n * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_uy, huy.data(), n * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_uz, huz.data(), n * sizeof(R), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_id, hid.data(), n * sizeof(int), hipMemcpyHostToDevice, S));
+  HIPCHK(c, hipMemcpyAsync(c->d_inj_list, list.data(), list.size() * sizeof(int),
+                           hipMemcpyHostToDevice, S));
+  hipError_t e = pic_launch_inject<R>(st, s, (int)(list.size() / 3), c->d_inj_list, c->d_inj_cell,
+                                      (const R*)c->d_inj_ox, (const R*)c->d_inj_oy,
+                                      (const R*)c->d_inj_ux, (const R*)c->d_inj_uy,
+                                      (const R*)c->d_inj_uz, c->d_inj_id, S);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("inject: ") + hipGetErrorString(e));
+  HIPCHK(c, hipStreamSynchronize(S));
+  c->next_id[run][s] += n;
   return PIC_OK;
 }
 
@@ -720,23 +851,31 @@ int read_impl(pic_ctx* c, int run, int s, int64_t cap, int32_t* ix, int32_t* iy,
   for (int t = 0; t < nt; ++t) n += count[t];
   *n_out = n;
   if (n > cap) return fail(c, PIC_E_INVAL, "output capacity smaller than the particle count");
-  std::vector<char> seen(n, 0);
+  // storage positions in output order: ascending id (ids may have gaps once
+  // a shock run has removed particles), or storage order without ids
+  std::vector<std::pair<int, size_t>> order;
+  order.reserve(n);
   int64_t seq = 0;
   for (int t = 0; t < nt; ++t)
     for (int k = 0; k < count[t]; ++k) {
       const size_t o = (size_t)t * slots + k;
-      const int id = st.id[s] ? hid[o] : (int)seq++;   // storage order without ids
-      if (id < 0 || id >= n || seen[id] || hcell[o] < 0)
-        return fail(c, PIC_E_STATE, "particle store inconsistent (duplicate/missing id or hole)");
-      seen[id] = 1;
-      if (ix) ix[id] = hcell[o] & 0xffff;
-      if (iy) iy[id] = hcell[o] >> 16;
-      if (fx) fx[id] = (double)hox[o];
-      if (fy) fy[id] = (double)hoy[o];
-      if (ux) ux[id] = (double)hux[o];
-      if (uy) uy[id] = (double)huy[o];
-      if (uz) uz[id] = (double)huz[o];
+      if (hcell[o] < 0) return fail(c, PIC_E_STATE, "particle store inconsistent (hole)");
+      order.push_back({st.id[s] ? hid[o] : (int)seq++, o});
     }
+  std::sort(order.begin(), order.end());
+  for (size_t q = 1; q < order.size(); ++q)
+    if (order[q].first == order[q - 1].first)
+      return fail(c, PIC_E_STATE, "particle store inconsistent (duplicate id)");
+  for (int64_t q = 0; q < n; ++q) {
+    const size_t o = order[q].second;
+    if (ix) ix[q] = hcell[o] & 0xffff;
+    if (iy) iy[q] = hcell[o] >> 16;
+    if (fx) fx[q] = (double)hox[o];
+    if (fy) fy[q] = (double)hoy[o];
+    if (ux) ux[q] = (double)hux[o];
+    if (uy) uy[q] = (double)huy[o];
+    if (uz) uz[q] = (double)huz[o];
+  }
   return PIC_OK;
 }
 
@@ -825,12 +964,14 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   c->train_cells = (long long)runs[0].nx * runs[0].ny;
   c->learned = c->pair_slots > 0;
   c->use_learned = c->learned;
+  const long long ic = inject_cap_of(runs, n_runs);
   if (c->fast)
     carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->ids, c->opt.history_cap,
-                 c->pair_slots, c->train_cells, c, &c->sf);
+                 c->pair_slots, c->train_cells, ic, c, &c->sf);
   else
     carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap,
-                  c->pair_slots, c->train_cells, c, &c->sd);
+                  c->pair_slots, c->train_cells, ic, c, &c->sd);
+  c->next_id.assign(n_runs, std::array<long long, PIC_MAXS>{0, 0});
   c->fa.learned_form = opt->learned_form;
   c->fa.learned_maxit = opt->learned_maxit > 0 ? opt->learned_maxit : kDefaultLearnedMaxit;
 
@@ -868,6 +1009,8 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     h.ny = d.ny;
     h.order = d.shape_order;
     h.nspecies = d.n_species;
+    h.bc = d.bc;
+    h.x_out = d.bc == PIC_BC_SHOCK ? d.nx - PIC_WALL_GAP : d.nx;
     h.ntx = c->tl.ntx[r];
     h.nty = c->tl.nty[r];
     h.tile0 = c->tl.tile0[r];
@@ -929,6 +1072,22 @@ int32_t pic_load_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n, 
   if (c->phase != 0) return fail(c, PIC_E_STATE, "load during a split step");
   return c->fast ? load_impl<float>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz)
                  : load_impl<double>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz);
+}
+
+int32_t pic_inject_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n,
+                             const int32_t* ix, const int32_t* iy, const double* fx,
+                             const double* fy, const double* ux, const double* uy,
+                             const double* uz) {
+  if (!c) return PIC_E_INVAL;
+  if (run < 0 || run >= (int)c->runs.size() || species < 0 ||
+      species >= c->runs[run].n_species || n < 0 ||
+      (n > 0 && (!ix || !iy || !fx || !fy || !ux || !uy || !uz)))
+    return fail(c, PIC_E_INVAL, "bad run/species/arguments");
+  if (c->runs[run].bc != PIC_BC_SHOCK)
+    return fail(c, PIC_E_INVAL, "injection is for shock runs (PIC_BC_SHOCK)");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "inject during a split step");
+  return c->fast ? inject_impl<float>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz)
+                 : inject_impl<double>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz);
 }
 
 int32_t pic_read_particles(pic_ctx* c, int32_t run, int32_t species, int64_t cap, int32_t* ix,

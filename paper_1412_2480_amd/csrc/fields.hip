@@ -133,13 +133,6 @@ __device__ __forceinline__ void curl_fwd(const Loc& L, double* const* F, int i, 
            (F[0][lidx(L, i, j + 1)] - F[0][lidx(L, i, j)]) * idy_;
 }
 
-__device__ __forceinline__ double lap5(const Loc& L, const double* f, int i, int j,
-                                       double idx2, double idy2) {
-  const double c = f[lidx(L, i, j)];
-  return (f[lidx(L, i + 1, j)] - 2.0 * c + f[lidx(L, i - 1, j)]) * idx2 +
-         (f[lidx(L, i, j + 1)] - 2.0 * c + f[lidx(L, i, j - 1)]) * idy2;
-}
-
 // kMode: 0 plain CG, 1 learned with the collapsed filter, 2 learned with the
 // BF16 network
 template <int kMode>
@@ -177,11 +170,41 @@ k_field_solve(FieldArgs a) {
   double* const part0 = a.part;
   double* const part1 = a.part + (size_t)a.n_blocks * 8;
   double* const part2 = a.part + (size_t)a.n_blocks * 16;
-  // A v at (i, j) for a vector given by a functor of the linear index
-  auto applyA = [&](auto&& v, long long g, long long gxp, long long gxm, long long gyp,
-                    long long gym) {
-    const double c = v(g);
-    return c - ax * (v(gxp) - 2.0 * c + v(gxm)) - ay * (v(gyp) - 2.0 * c + v(gym));
+  // Shock runs (conducting walls at x = 0 and x = (nx-1) dx): fixed rows
+  // (Bx on both wall lines, the outside column of By and Bz) are identity rows
+  // holding zero, so a fixed neighbour of Bx reads zero; behind a wall the
+  // tangential By, Bz take the row's own value.
+  const bool shock = R.bc == 1;
+  auto fixed_row = [&](int c, int i) {
+    return shock && (c == 0 ? (i == 0 || i == R.nx - 1) : i == R.nx - 1);
+  };
+  // A v of component c at (i, j) for a vector given by a functor of the index
+  auto applyA = [&](auto&& v, int c, int i, long long g, long long gxp, long long gxm,
+                    long long gyp, long long gym) {
+    if (shock) {
+      if (fixed_row(c, i)) return v(g);
+      if (c > 0) {
+        if (i == 0) gxm = g;
+        if (i == R.nx - 2) gxp = g;
+      }
+    }
+    const double cc = v(g);
+    return cc - ax * (v(gxp) - 2.0 * cc + v(gxm)) - ay * (v(gyp) - 2.0 * cc + v(gym));
+  };
+  // right-hand side of Eq. (7) for component c at (i, j)
+  auto rhs_b = [&](int c, int i, int j, const double (&cj)[3], const double (&ce)[3]) {
+    if (fixed_row(c, i)) return 0.0;
+    const double* f = a.B[c];
+    const long long g = lidx(L, i, j);
+    long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+    if (shock && c > 0) {
+      if (i == 0) gxm = g;
+      if (i == R.nx - 2) gxp = g;
+    }
+    const double v = f[g];
+    const double lb = (f[gxp] - 2.0 * v + f[gxm]) * idx2 +
+                      (f[lidx(L, i, j + 1)] - 2.0 * v + f[lidx(L, i, j - 1)]) * idy2;
+    return th * dt * dt * (lb + kFourPi * cj[c]) - dt * ce[c];
   };
   // Global "does any run still iterate" decisions: round k adds into
   // g_active[k % 3] before a barrier and reads it after; block 0 clears the
@@ -231,8 +254,7 @@ k_field_solve(FieldArgs a) {
       const long long g = L.base + k;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
-        const double b = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        const double b = rhs_b(c, i, j, cj, ce);
         a.r0[c][g] = b;
         a.r1[c][g] = b;
         a.x[c][g] = 0.0;
@@ -277,7 +299,7 @@ k_field_solve(FieldArgs a) {
       net_sweep(all3, [&](int c, int i, int j) { return a.r1[c][L.base + (long long)j * R.nx + i]; },
                 [&](int c, int i, int j, double v) {
                   const long long g = L.base + (long long)j * R.nx + i;
-                  a.x[c][g] = v;
+                  a.x[c][g] = fixed_row(c, i) ? 0.0 : v;
                   const double b = a.r1[c][g];
                   d[c] += b * b;
                 });
@@ -300,7 +322,7 @@ k_field_solve(FieldArgs a) {
     auto resid0 = [&](int c, int i, int j) {
       const long long g = lidx(L, i, j);
       const double* xc = a.x[c];
-      return a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, g, lidx(L, i + 1, j),
+      return a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, c, i, g, lidx(L, i + 1, j),
                                  lidx(L, i - 1, j), lidx(L, i, j + 1), lidx(L, i, j - 1));
     };
     {
@@ -308,6 +330,7 @@ k_field_solve(FieldArgs a) {
       net_sweep(act, resid0, [&](int c, int i, int j, double v) {
         const long long g = L.base + (long long)j * R.nx + i;
         const double r = resid0(c, i, j);
+        if (fixed_row(c, i)) v = 0.0;
         a.r0[c][g] = r;
         a.w0[c][g] = v;
         a.s0[c][g] = 0.0;
@@ -356,7 +379,7 @@ k_field_solve(FieldArgs a) {
               const double be = beta[c];
               auto pv = [&](long long q) { return z_[q] + be * p_[q]; };
               const double p = pv(g);
-              const double qv = applyA(pv, g, gxp, gxm, gyp, gym);
+              const double qv = applyA(pv, c, i, g, gxp, gxm, gyp, gym);
               pn[c][g] = p;
               a.w1[c][g] = qv;
               d[c] += p * qv;
@@ -380,6 +403,7 @@ k_field_solve(FieldArgs a) {
         net_sweep(act, rnext, [&](int c, int i, int j, double v) {
           const long long g = L.base + (long long)j * R.nx + i;
           const double r = rnext(c, i, j);
+          if (fixed_row(c, i)) v = 0.0;
           rn[c][g] = r;
           a.x[c][g] += alpha[c] * pn[c][g];
           a.w0[c][g] = v;
@@ -434,7 +458,8 @@ k_field_solve(FieldArgs a) {
         for (int c = 0; c < 3; ++c) {
           if (!need_plain[c]) continue;
           const double* xc = a.x[c];
-          a.r0[c][g] = a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, g, gxp, gxm, gyp, gym);
+          a.r0[c][g] = a.r1[c][g] - applyA([&](long long q) { return xc[q]; }, c, i, g, gxp, gxm,
+                                           gyp, gym);
         }
       }
       barrier();
@@ -452,7 +477,7 @@ k_field_solve(FieldArgs a) {
         for (int c = 0; c < 3; ++c) {
           if (!need_plain[c]) continue;
           const double* rc = a.r0[c];
-          const double w = applyA([&](long long q) { return rc[q]; }, g, gxp, gxm, gyp, gym);
+          const double w = applyA([&](long long q) { return rc[q]; }, c, i, g, gxp, gxm, gyp, gym);
           const double r = rc[g];
           const double b = a.r1[c][g];
           a.w0[c][g] = w;
@@ -521,7 +546,7 @@ k_field_solve(FieldArgs a) {
             const double sk = w_[g] + be * s_[g];
             const double pk = r_[g] + be * a.p[c][g];
             const double r1 = r_[g] - al * sk;
-            const double w1 = applyA(rnext, g, gxp, gxm, gyp, gym);
+            const double w1 = applyA(rnext, c, i, g, gxp, gxm, gyp, gym);
             a.p[c][g] = pk;
             sn[c][g] = sk;
             a.x[c][g] += al * pk;
@@ -596,8 +621,7 @@ k_field_solve(FieldArgs a) {
       const long long g = L.base + k;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double lb_ = lap5(L, a.B[c], i, j, idx2, idy2);
-        pb[(size_t)(2 * c) * ncell + k] = th * dt * dt * (lb_ + kFourPi * cj[c]) - dt * ce[c];
+        pb[(size_t)(2 * c) * ncell + k] = rhs_b(c, i, j, cj, ce);
         pb[(size_t)(2 * c + 1) * ncell + k] = a.x[c][g];
       }
     }
@@ -622,6 +646,12 @@ k_field_solve(FieldArgs a) {
     a.E[0][g] += dt * cx - kFourPi * dt * a.J[0][g];
     a.E[1][g] += dt * cy - kFourPi * dt * a.J[1][g];
     a.E[2][g] += dt * cz - kFourPi * dt * a.J[2][g];
+    if (shock) {
+      // E nodes on the conductors (Ey, Ez on both wall lines, the outside
+      // column's Ex) stay zero
+      if (i == 0 || i == R.nx - 1) a.E[1][g] = a.E[2][g] = 0.0;
+      if (i == R.nx - 1) a.E[0][g] = 0.0;
+    }
   }
   barrier();
   // ---- B update, Eq. (5) through dB; FP32 copies for the fast particle path

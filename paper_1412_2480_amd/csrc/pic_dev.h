@@ -19,8 +19,12 @@
 #define PIC_ERRBIT_TILE 4       // tile slots full after re-binning
 #define PIC_ERRBIT_BARRIER 8    // a grid barrier timed out
 
+#define PIC_WALL_GAP 4   // shock runs: particles leave at x >= (nx - PIC_WALL_GAP) dx
+
 struct DevRun {
   int nx, ny, order, nspecies;
+  int bc;             // 0 periodic, 1 shock (conducting walls in x, reflection at x = 0)
+  int x_out;          // shock runs: first cell column where particles leave
   int ntx, nty;       // tiles per row / column of this run
   int tile0;          // first global tile index
   long long cell0;    // first cell in the concatenated field arrays

@@ -58,6 +58,11 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
                                 hipStream_t s);
 template <typename R>
 hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s);
+// append staged particles (list of (tile, first, count)) to the current store
+template <typename R>
+hipError_t pic_launch_inject(const DevState<R>& st, int s, int n_entries, const int* list,
+                             const int* cell, const R* ox, const R* oy, const R* ux, const R* uy,
+                             const R* uz, const int* id, hipStream_t stream);
 template <typename R>
 hipError_t pic_launch_current_sum(const DevState<R>& st, long long max_cells, hipStream_t s);
 template <typename R>

@@ -207,3 +207,40 @@ def pair_plasma_cells(nx, ny, ppc, gamma0, T, seed, direction=+1, chunk=1 << 20,
     with ThreadPoolExecutor(max_workers=workers) as ex:
         list(ex.map(work, range(0, n, chunk)))
     return out
+
+
+def shock_load(x_out, ny, ppc, gamma0, T, seed):
+    """Initial plasma of a shock run: the flow fills the cells with i < x_out,
+    moving towards -x (the reflecting wall is at x = 0). Same recipe as
+    pair_plasma_cells on an x_out x ny grid."""
+    return pair_plasma_cells(x_out, ny, ppc, gamma0, T, seed, direction=-1)
+
+
+def shock_injection(x_out, ny, ppc, gamma0, T, seed, step, cfl):
+    """Flow entering a shock run through x_out = x_out cells before step `step`.
+
+    The stream moves w = beta0 * cfl cells per step (beta0 = sqrt(1 - 1/gamma0^2)),
+    so a slab of width w behind x_out is refilled each step at ppc per cell:
+    per row, floor(ppc w (step+1)) - floor(ppc w step) particles, at x uniform
+    in (x_out - w, x_out) and y uniform in the row; electrons and positrons
+    co-located; momenta drifting Maxwell-Juettner towards -x. Items continue
+    after those of shock_load, so every injected particle has its own counter.
+    Returns a list of two dicts (ix, iy, fx, fy, ux, uy, uz).
+    """
+    beta0 = math.sqrt(1.0 - 1.0 / (gamma0 * gamma0)) if gamma0 > 1.0 else 0.0
+    w = beta0 * cfl
+    done = math.floor(ppc * w * step)
+    per_row = math.floor(ppc * w * (step + 1)) - done
+    n = per_row * ny
+    base = x_out * ny * ppc + done * ny
+    items = np.arange(base, base + n, dtype=np.int64)
+    r0, r1 = Stream(seed, TAG_POS).uniforms(items, 0)
+    X = x_out - w * r0
+    ix = np.floor(X).astype(np.int32)
+    row = (np.arange(n) // max(per_row, 1)).astype(np.int32)
+    out = []
+    for s in range(2):
+        ux, uy, uz = drifting_mj(seed, s, n, T, gamma0, -1, first_item=base)
+        out.append(dict(ix=ix.copy(), iy=row.copy(), fx=X - ix, fy=r1.copy(), ux=ux, uy=uy,
+                        uz=uz))
+    return out
