@@ -47,6 +47,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
+
+
 def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
              form="collapsed", slots=0):
     from synth import loads
@@ -56,7 +59,8 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
     sim = pic.Sim([run], pic.make_options(precision, tile=tile, diag_every=0,
                                           cg_blocks=cg_blocks, track_ids=False,
                                           tile_split=tile_split, solver=solver,
-                                          learned_form=form, precond_slots=slots))
+                                          learned_form=form, precond_slots=slots,
+                                          graph=GRAPH))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -87,13 +91,22 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
     if warmup:
         sim.step(warmup)
     torch.cuda.synchronize()
-    sim.timing(True)
+    # event timing switches graph replay off, so with graphs the timed region
+    # runs without events and a few plain steps afterwards give the breakdown
+    sim.timing(not GRAPH)
     t0 = time.perf_counter()
     rc = sim.step_async(steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     if rc not in (0,):
         raise RuntimeError(f"pic_step returned {pic.STATUS.get(rc, rc)}")
+    replays = sim.get_timing()["graph_replays"]
+    if GRAPH:
+        sim.timing(True)
+        sim.step(min(steps, 10))
+        steps_t = min(steps, 10)
+    else:
+        steps_t = steps
     tim = sim.get_timing()
     st = sim.step(0)
     sim.timing(False)
@@ -102,9 +115,10 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
     push = tim["push"]
     push_ms = push["ms"] / max(1, push["launches"])
     return dict(ms_per_step=ms, particle_steps_per_s=n_part / (ms * 1e-3),
-                push_ms=push_ms, field_solve_ms=tim["field_solve"]["ms"] / max(1, steps),
-                rebin_ms=tim["rebin"]["ms"] / max(1, steps),
-                current_sum_ms=tim["current_sum"]["ms"] / max(1, steps),
+                push_ms=push_ms, field_solve_ms=tim["field_solve"]["ms"] / max(1, steps_t),
+                rebin_ms=tim["rebin"]["ms"] / max(1, steps_t),
+                current_sum_ms=tim["current_sum"]["ms"] / max(1, steps_t),
+                graph_replays=replays,
                 cg_iters=st[0]["iters"], learned_iters=st[0]["learned_iters"],
                 fallback=st[0]["fallback"], relres=st[0]["relres"], n_particles=n_part,
                 train=train)
@@ -123,7 +137,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
         lds.append(loads.pair_plasma_cells(t["nx"], t["ny"], t["ppc"], t["gamma0"], t["T"],
                                            t["seed"]))
     n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
-    opts = pic.make_options("fp32", tile=(16, 16), track_ids=False)
+    opts = pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH)
     sim = pic.Sim(descs, opts)
     for r, ld in enumerate(lds):
         for s in range(2):
@@ -199,6 +213,8 @@ def main():
                     help="inference form of the network in the timed form")
     ap.add_argument("--no-learned", action="store_true",
                     help="time the FP32 form with plain CG only")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured two-step HIP graphs in every timed form")
     ap.add_argument("--train-pairs", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=10)
     ap.add_argument("--also-mfma", action="store_true",
@@ -215,6 +231,8 @@ def main():
     import torch
     import paper_1412_2480_amd as pic
     from synth import loads
+    global GRAPH
+    GRAPH = args.graph
 
     cfg = CONFIGS[args.config]
     tile = tuple(int(v) for v in args.tile.split("x"))

@@ -118,6 +118,10 @@ typedef struct pic_options {
   int32_t learned_maxit; /* iteration budget of the learned PCG before the plain-CG
                             fallback; 0 = 30 */
   int32_t precond_slots; /* (b, dB) training pairs kept (ring); 0 = 16 */
+  int32_t graph;         /* 1: pic_step replays HIP graphs of two captured steps (the
+                            particle double buffer returns to its arrangement after two)
+                            whenever no diagnostics record, timing or pair collection
+                            falls in them; 0: plain launches */
 } pic_options;
 
 typedef struct pic_plan_info {
@@ -157,6 +161,7 @@ typedef struct pic_timing_out {
      6 field update, 7 diagnostics */
   double ms[8];
   int64_t launches[8];
+  int64_t graph_replays; /* two-step graph replays since pic_init (graph mode) */
 } pic_timing_out;
 
 typedef struct pic_ctx pic_ctx;

@@ -56,7 +56,8 @@ class Options(ctypes.Structure):
                 ("diag_every", ctypes.c_int32), ("history_cap", ctypes.c_int32),
                 ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32),
                 ("tile_split", ctypes.c_int32), ("learned_form", ctypes.c_int32),
-                ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32)]
+                ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -92,7 +93,8 @@ class DiagOut(ctypes.Structure):
 
 
 class TimingOut(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8)]
+    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+                ("graph_replays", ctypes.c_int64)]
 
 
 TIMING_CLASSES = ["push", "deposit", "rebin", "current_sum", "rhs", "field_solve", "update", "diag"]
@@ -181,7 +183,8 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
                  diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0,
-                 solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0):
+                 solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0,
+                 graph=False):
     """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma"."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
@@ -191,6 +194,7 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
         else PIC_NET_COLLAPSED
     o.learned_maxit = int(learned_maxit)
     o.precond_slots = int(precond_slots)
+    o.graph = 1 if graph else 0
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)
@@ -411,8 +415,10 @@ class Sim:
     def get_timing(self):
         t = TimingOut()
         self._check(self.L.pic_get_timing(self.ctx, ctypes.byref(t)), "get_timing")
-        return {name: dict(ms=t.ms[k], launches=t.launches[k])
-                for k, name in enumerate(TIMING_CLASSES)}
+        out = {name: dict(ms=t.ms[k], launches=t.launches[k])
+               for k, name in enumerate(TIMING_CLASSES)}
+        out["graph_replays"] = t.graph_replays
+        return out
 
 
 def torch_empty_like(t):

@@ -112,6 +112,13 @@ struct pic_ctx {
   int* d_err = nullptr;
   int phase = 0;
   long long step = 0;
+  int parity = 0;                 // particle buffer swaps since init, mod 2
+  // graph mode: executable graphs of two steps per starting parity
+  bool graph_ok = true;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int gkey[2] = {-1, -1};
+  long long graph_replays = 0;
   long long diag_count = 0;
   std::vector<long long> hist_step;  // steps recorded (host mirror)
   int threads = 256;
@@ -565,6 +572,7 @@ int launch_exchange(pic_ctx* c) {
   t_end(c);
   if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("rebin: ") + hipGetErrorString(e));
   swap_buffers(state<R>(c));
+  c->parity ^= 1;
   t_begin(c, 3);
   e = pic_launch_current_sum<R>(state<R>(c), c->tl.max_cells, c->stream);
   t_end(c);
@@ -657,6 +665,68 @@ int do_step(pic_ctx* c) {
   rc = launch_field(c, diag);
   if (rc) return rc;
   c->step += 1;
+  return PIC_OK;
+}
+
+// Graph mode: two steps are captured once per starting buffer parity (and
+// solver variant) on an internal stream and replayed on the caller's stream.
+// Everything a step reads that changes between steps lives in device memory
+// (counts, fields, weights); what is baked into the graph (buffer pointers,
+// the solver variant, the diagnostics/collection switches) is the key.
+bool graph_usable(pic_ctx* c) {
+  if (!c->opt.graph || !c->graph_ok || c->timing || c->collect) return false;
+  const int de = c->opt.diag_every;
+  if (de > 0 && ((c->step % de) == 0 || ((c->step + 1) % de) == 0)) return false;
+  return true;
+}
+
+template <typename R>
+int graph_two_steps(pic_ctx* c) {
+  const int par = c->parity;
+  const int key = c->use_learned ? 1 : 0;
+  if (!c->gexec[par] || c->gkey[par] != key) {
+    if (c->gexec[par]) {
+      (void)hipGraphExecDestroy(c->gexec[par]);
+      c->gexec[par] = nullptr;
+    }
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+      c->graph_ok = false;
+      return PIC_E_HIP;
+    }
+    hipStream_t user = c->stream;
+    const long long step0 = c->step, pairs0 = c->pairs_written, diag0 = c->diag_count;
+    c->stream = c->cap_stream;
+    c->fa.coop = 0;
+    hipGraph_t g = nullptr;
+    int rc = PIC_OK;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      rc = PIC_E_HIP;
+    } else {
+      rc = do_step<R>(c);
+      if (rc == PIC_OK) rc = do_step<R>(c);
+      if (hipStreamEndCapture(c->stream, &g) != hipSuccess) rc = PIC_E_HIP;
+    }
+    c->stream = user;
+    c->fa.coop = 1;
+    c->step = step0;
+    c->pairs_written = pairs0;
+    c->diag_count = diag0;
+    hipGraphExec_t ex = nullptr;
+    if (rc == PIC_OK && (!g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess))
+      rc = PIC_E_HIP;
+    if (g) (void)hipGraphDestroy(g);
+    if (rc != PIC_OK) {
+      // capture is not available: stay with plain launches from now on
+      c->graph_ok = false;
+      (void)hipGetLastError();
+      return rc;
+    }
+    c->gexec[par] = ex;
+    c->gkey[par] = key;
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec[par], c->stream));
+  c->step += 2;
+  c->graph_replays += 1;
   return PIC_OK;
 }
 
@@ -973,6 +1043,10 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
                   c->pair_slots, c->train_cells, ic, c, &c->sd);
   c->next_id.assign(n_runs, std::array<long long, PIC_MAXS>{0, 0});
   c->fa.learned_form = opt->learned_form;
+  c->fa.coop = 1;
+  c->fa.any_shock = 0;
+  for (int r = 0; r < n_runs; ++r)
+    if (runs[r].bc == PIC_BC_SHOCK) c->fa.any_shock = 1;
   c->fa.learned_maxit = opt->learned_maxit > 0 ? opt->learned_maxit : kDefaultLearnedMaxit;
 
   // CG work-groups: as many as can be co-resident, split over runs by cells
@@ -1167,9 +1241,18 @@ int32_t pic_field_solve(pic_ctx* c, pic_solve_stats* stats) {
 int32_t pic_step(pic_ctx* c, int32_t nsteps, pic_solve_stats* last) {
   if (!c || nsteps < 0) return PIC_E_INVAL;
   if (c->phase != 0) return fail(c, PIC_E_STATE, "pic_step during a split step");
-  for (int k = 0; k < nsteps; ++k) {
+  for (int k = 0; k < nsteps;) {
+    if (nsteps - k >= 2 && graph_usable(c)) {
+      int rc = c->fast ? graph_two_steps<float>(c) : graph_two_steps<double>(c);
+      if (rc == PIC_OK) {
+        k += 2;
+        continue;
+      }
+      if (c->graph_ok) return rc;   // a launch error; otherwise fall through to eager
+    }
     int rc = c->fast ? do_step<float>(c) : do_step<double>(c);
     if (rc) return rc;
+    k += 1;
   }
   int rc = check_err(c);
   if (rc) return rc;
@@ -1279,6 +1362,7 @@ int32_t pic_get_timing(pic_ctx* c, pic_timing_out* out) {
     out->ms[k] = c->t_ms[k];
     out->launches[k] = c->t_n[k];
   }
+  out->graph_replays = c->graph_replays;
   return PIC_OK;
 }
 
@@ -1401,6 +1485,9 @@ int32_t pic_sync(pic_ctx* c) {
 int32_t pic_destroy(pic_ctx* c) {
   if (!c) return PIC_OK;
   (void)hipStreamSynchronize(c->stream);
+  for (auto& g : c->gexec)
+    if (g) (void)hipGraphExecDestroy(g);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (auto e : c->ev_pool) (void)hipEventDestroy(e);
   delete c;
   return PIC_OK;

@@ -134,8 +134,9 @@ __device__ __forceinline__ void curl_fwd(const Loc& L, double* const* F, int i, 
 }
 
 // kMode: 0 plain CG, 1 learned with the collapsed filter, 2 learned with the
-// BF16 network
-template <int kMode>
+// BF16 network. kShock: some run of the context has shock walls (the wall
+// rows are then tested per run; without it they compile away).
+template <int kMode, bool kShock>
 __global__ void __launch_bounds__(kThreads)
 k_field_solve(FieldArgs a) {
   __shared__ double sm[kWaves * 8];
@@ -174,7 +175,7 @@ k_field_solve(FieldArgs a) {
   // (Bx on both wall lines, the outside column of By and Bz) are identity rows
   // holding zero, so a fixed neighbour of Bx reads zero; behind a wall the
   // tangential By, Bz take the row's own value.
-  const bool shock = R.bc == 1;
+  const bool shock = kShock && R.bc == 1;
   auto fixed_row = [&](int c, int i) {
     return shock && (c == 0 ? (i == 0 || i == R.nx - 1) : i == R.nx - 1);
   };
@@ -676,25 +677,39 @@ size_t pic_field_solve_smem(int learned, int form) {
 }
 
 namespace {
-const void* solve_kernel(int learned, int form) {
-  if (!learned) return (const void*)k_field_solve<0>;
-  return form == 0 ? (const void*)k_field_solve<1> : (const void*)k_field_solve<2>;
+const void* solve_kernel(int learned, int form, int shock) {
+  if (shock) {
+    if (!learned) return (const void*)k_field_solve<0, true>;
+    return form == 0 ? (const void*)k_field_solve<1, true> : (const void*)k_field_solve<2, true>;
+  }
+  if (!learned) return (const void*)k_field_solve<0, false>;
+  return form == 0 ? (const void*)k_field_solve<1, false> : (const void*)k_field_solve<2, false>;
 }
 }  // namespace
 
 int pic_field_solve_max_blocks(int n_cu, int learned, int form) {
   int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, solve_kernel(learned, form), kThreads,
-                                                   pic_field_solve_smem(learned, form)) !=
-      hipSuccess)
-    return -1;
+  for (int shock = 0; shock < 2; ++shock) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_kernel(learned, form, shock),
+                                                     kThreads, pic_field_solve_smem(learned, form)) !=
+        hipSuccess)
+      return -1;
+    nb = shock == 0 ? v : (v < nb ? v : nb);
+  }
   return nb * n_cu;
 }
 
 hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s) {
   FieldArgs copy = a;
   void* args[] = {(void*)&copy};
-  return hipLaunchCooperativeKernel(solve_kernel(a.learned, a.learned_form), dim3(a.n_blocks),
-                                    dim3(kThreads), args,
-                                    pic_field_solve_smem(a.learned, a.learned_form), s);
+  const void* k = solve_kernel(a.learned, a.learned_form, a.any_shock);
+  const size_t smem = pic_field_solve_smem(a.learned, a.learned_form);
+  if (a.coop)
+    return hipLaunchCooperativeKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
+  // ordinary launch (inside a captured graph): the grid is no larger than the
+  // co-resident maximum and the kernel runs alone in its stream, so all
+  // work-groups are resident; a grid that is not still ends through the
+  // barrier's bounded spin with an error bit
+  return hipLaunchKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
 }

@@ -43,6 +43,8 @@ struct FieldArgs {
   int collect;             // record (b, dB) of run 0 into pairs[pair_slot]
   double* pairs;           // [slot][component][b | dB][ncell of run 0]
   int pair_slot;
+  int coop;                // 1: cooperative launch; 0: ordinary launch (graph capture)
+  int any_shock;           // some run has shock walls (selects the kernel variant)
 };
 
 size_t pic_field_solve_smem(int learned, int form);
