@@ -138,12 +138,14 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
                                            t["seed"]))
     n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
     opts = pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH)
-    sim = pic.Sim(descs, opts)
+    sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH,
+                                          tile_split=8))
     for r, ld in enumerate(lds):
         for s in range(2):
             d = ld[s]
             sim.load_particles(r, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
     sim.step(warmup)
+    tuned = sim.tune(2)     # work-groups per tile and field-solve work-groups of this mix
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rc = sim.step_async(steps)
@@ -166,6 +168,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
         seq_ms += (time.perf_counter() - t0) * 1e3 / seq_steps
         one.close()
     return dict(runs=len(table), particles=n_part, ms_per_step=ms,
+                tile_split=tuned["tile_split"], cg_blocks=tuned["cg_blocks"],
                 particle_steps_per_s=n_part / (ms * 1e-3), sequential_ms_per_step=seq_ms,
                 batched_speedup=seq_ms / ms)
 
@@ -213,6 +216,9 @@ def main():
                     help="inference form of the network in the timed form")
     ap.add_argument("--no-learned", action="store_true",
                     help="time the FP32 form with plain CG only")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the library's autotuner (tile shape, work-groups per tile, "
+                         "field-solve work-groups) and use --tile/--tile-split/--cg-blocks")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured two-step HIP graphs in every timed form")
     ap.add_argument("--train-pairs", type=int, default=8)
@@ -271,6 +277,32 @@ def main():
                 r = time_form(pic, torch, cfg, load, prec, tt, 20, 20, args.cg_blocks, int(k))
                 log(f"bench: {prec} tile {shape} split {k}: push {r['push_ms']:.3f} ms, "
                     f"step {r['ms_per_step']:.3f} ms")
+    tune = None
+    if not args.no_autotune:
+        from paper_1412_2480_amd.tune import autotune
+        from synth import loads as _l
+        Q = _l.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
+        run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
+                           [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8)
+
+        def _load(sim):
+            for s_ in range(2):
+                d = load[s_]
+                sim.load_particles(0, s_, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
+                                   d["uz"])
+        t0 = time.perf_counter()
+        best, table = autotune([run], _load, dict(precision="fp32", track_ids=False,
+                                                  tile_split=8))
+        tune = dict(best={k: best[k] for k in ("tile", "tile_split", "cg_blocks",
+                                               "ms_per_step")},
+                    table=[{k: r[k] for k in ("tile", "tile_split", "cg_blocks",
+                                              "ms_per_step")} for r in table],
+                    seconds=time.perf_counter() - t0)
+        tile = tuple(best["tile"])
+        args.tile_split = best["tile_split"]
+        args.cg_blocks = best["cg_blocks"]
+        log(f"bench: autotune picked tile {tile} split {args.tile_split} cg_blocks "
+            f"{args.cg_blocks} ({tune['seconds']:.1f} s)")
     log("bench: FP32 form" + ("" if learned is None else f" + learned ({args.learned_form})"))
     fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
                      args.tile_split, learned)
@@ -356,6 +388,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
                      "avg_launch_ms": fast["push_ms"]},
+        "autotune": tune,
         "batched_sweep": batched,
         "cpu_baseline": cpu,
     }

@@ -286,6 +286,31 @@ int32_t pic_precond_apply(pic_ctx* ctx, int32_t form, int32_t nx, int32_t ny, co
 int32_t pic_precond_grad(pic_ctx* ctx, int32_t nx, int32_t ny, const double* d_b,
                          const double* d_t, float* host_grad, size_t n, double* loss);
 
+/* ---- Autotuning of the launch schedule on a live context (the runs advance
+ * by the timed steps). Work-groups per tile of the particle kernel and
+ * work-groups of the persistent field solve are tried one after the other,
+ * each for `steps` steps timed with events, and the fastest is kept (the two
+ * kernels are independent). Tile shapes change the layout and are chosen by
+ * building one context per shape (paper_1412_2480_amd.tune). */
+typedef struct pic_tune_opts {
+  int32_t steps;         /* timed steps per candidate, >= 1 */
+  int32_t n_split;       /* 0: 1, 2, 4, 8 up to the planned tile_split */
+  int32_t split[8];
+  int32_t n_cg;          /* 0: 64, 128, 256, 512 up to the co-resident limit */
+  int32_t cg_blocks[8];
+} pic_tune_opts;
+
+typedef struct pic_tune_out {
+  int32_t tile_split;    /* chosen work-groups per tile */
+  int32_t cg_blocks;     /* chosen field-solve work-groups (as launched) */
+  int32_t n_split, n_cg; /* candidates tried */
+  int32_t split[8], cg_blocks_tried[8];
+  double particle_ms[8]; /* mean particle-kernel ms per step of each split candidate */
+  double field_ms[8];    /* mean field-solve ms per step of each cg candidate */
+} pic_tune_out;
+
+int32_t pic_tune(pic_ctx* ctx, const pic_tune_opts* opts, pic_tune_out* out);
+
 int32_t pic_sync(pic_ctx* ctx);
 int32_t pic_destroy(pic_ctx* ctx);
 const char* pic_last_error(const pic_ctx* ctx);

@@ -31,7 +31,7 @@ EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_inject_particles",
            "pic_deposit", "pic_field_solve", "pic_step", "pic_diag", "pic_history",
            "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
            "pic_precond_use", "pic_precond_get_weights", "pic_precond_set_weights",
-           "pic_precond_apply", "pic_precond_grad", "pic_sync", "pic_destroy",
+           "pic_precond_apply", "pic_precond_grad", "pic_tune", "pic_sync", "pic_destroy",
            "pic_last_error", "pic_status_str"]
 
 
@@ -82,6 +82,19 @@ class TrainOpts(ctypes.Structure):
 class TrainStats(ctypes.Structure):
     _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
                 ("samples", ctypes.c_int32), ("updates", ctypes.c_int32)]
+
+
+class TuneOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("n_split", ctypes.c_int32),
+                ("split", ctypes.c_int32 * 8), ("n_cg", ctypes.c_int32),
+                ("cg_blocks", ctypes.c_int32 * 8)]
+
+
+class TuneOut(ctypes.Structure):
+    _fields_ = [("tile_split", ctypes.c_int32), ("cg_blocks", ctypes.c_int32),
+                ("n_split", ctypes.c_int32), ("n_cg", ctypes.c_int32),
+                ("split", ctypes.c_int32 * 8), ("cg_blocks_tried", ctypes.c_int32 * 8),
+                ("particle_ms", ctypes.c_double * 8), ("field_ms", ctypes.c_double * 8)]
 
 
 class DiagOut(ctypes.Structure):
@@ -145,6 +158,7 @@ def lib():
         L.pic_precond_grad.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_size_t, P(ctypes.c_double)]
+        L.pic_tune.argtypes = [ctypes.c_void_p, P(TuneOpts), P(TuneOut)]
         L.pic_sync.argtypes = [ctypes.c_void_p]
         L.pic_destroy.argtypes = [ctypes.c_void_p]
         L.pic_last_error.argtypes = [ctypes.c_void_p]
@@ -408,6 +422,23 @@ class Sim:
                                             ctypes.c_void_p(td.data_ptr()), _ptr(g), NET_NW,
                                             ctypes.byref(loss)), "precond_grad")
         return loss.value, g
+
+    def tune(self, steps=3, splits=(), cg_blocks=()):
+        """Pick work-groups per tile and field-solve work-groups by timing
+        `steps` real steps per candidate (pic_tune); returns the table."""
+        o = TuneOpts()
+        o.steps = int(steps)
+        o.n_split = len(splits)
+        for k, v in enumerate(splits):
+            o.split[k] = int(v)
+        o.n_cg = len(cg_blocks)
+        for k, v in enumerate(cg_blocks):
+            o.cg_blocks[k] = int(v)
+        r = TuneOut()
+        self._check(self.L.pic_tune(self.ctx, ctypes.byref(o), ctypes.byref(r)), "tune")
+        return dict(tile_split=r.tile_split, cg_blocks=r.cg_blocks,
+                    split_ms={r.split[k]: r.particle_ms[k] for k in range(r.n_split)},
+                    cg_ms={r.cg_blocks_tried[k]: r.field_ms[k] for k in range(r.n_cg)})
 
     def timing(self, on=True):
         self._check(self.L.pic_timing(self.ctx, 1 if on else 0), "timing")

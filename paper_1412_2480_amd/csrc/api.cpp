@@ -19,6 +19,8 @@
 namespace {
 
 constexpr int kMaxCgBlocks = 4096;
+// grid-barrier latency grows with the number of work-groups (about 30 ns
+// each), so the default keeps the persistent grid small; pic_tune measures
 constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kTimingClasses = 8;
@@ -113,6 +115,8 @@ struct pic_ctx {
   int phase = 0;
   long long step = 0;
   int parity = 0;                 // particle buffer swaps since init, mod 2
+  int max_cg_blocks = 0;          // co-resident limit of the field-solve grid
+  int cg_cap = 0;                 // requested work-groups of the field solve
   // graph mode: executable graphs of two steps per starting parity
   bool graph_ok = true;
   hipStream_t cap_stream = nullptr;
@@ -971,6 +975,33 @@ int rho_impl(pic_ctx* c, int run) {
   return PIC_OK;
 }
 
+// Work-groups of the persistent field solve: at most `cap` (and never more
+// than can be co-resident), split over the runs in proportion to their cells,
+// at least one each and no more than one per PIC_CG_THREADS cells.
+void assign_cg_blocks(pic_ctx* c, int cap) {
+  const int n_runs = (int)c->runs.size();
+  int maxb = std::max(n_runs, std::min(c->max_cg_blocks, cap));
+  long long want = 0;
+  for (int r = 0; r < n_runs; ++r)
+    want += ((long long)c->runs[r].nx * c->runs[r].ny + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
+  const int total = (int)std::min<long long>(maxb, std::max<long long>(want, n_runs));
+  int blk = 0;
+  for (int r = 0; r < n_runs; ++r) {
+    const long long cells = (long long)c->runs[r].nx * c->runs[r].ny;
+    long long nb = (long long)((double)total * cells / (double)c->tl.n_cells);
+    const long long need = (cells + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
+    nb = std::max<long long>(1, std::min<long long>(nb, need));
+    const int left = total - blk - (n_runs - 1 - r);
+    nb = std::min<long long>(nb, left);
+    if (r == n_runs - 1) nb = std::max<long long>(1, std::min<long long>(need, left));
+    c->hruns[r].cg_blk_lo = blk;
+    c->hruns[r].cg_blk_hi = blk + (int)nb;
+    blk += (int)nb;
+  }
+  c->fa.n_blocks = blk;
+  c->cg_cap = cap;
+}
+
 // Identity map plus small fixed noise (a splitmix64 sequence mapped to
 // [-1, 1)), so that every channel receives gradient from the first update.
 std::vector<float> initial_weights() {
@@ -1064,17 +1095,8 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     delete c;
     return PIC_E_HIP;
   }
-  maxb = std::min(maxb, kMaxCgBlocks);
-  // grid-barrier latency grows with the number of work-groups (about 30 ns
-  // each), so the default keeps the persistent grid small
-  const int cap = opt->cg_blocks > 0 ? opt->cg_blocks : kDefaultCgBlocks;
-  maxb = std::max(n_runs, std::min(maxb, cap));
-  long long want = 0;
-  for (int r = 0; r < n_runs; ++r)
-    want += ((long long)runs[r].nx * runs[r].ny + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
-  const int total = (int)std::min<long long>(maxb, std::max<long long>(want, n_runs));
+  c->max_cg_blocks = std::min(maxb, kMaxCgBlocks);
   c->hruns.resize(n_runs);
-  int blk = 0;
   for (int r = 0; r < n_runs; ++r) {
     const pic_run_desc& d = runs[r];
     DevRun& h = c->hruns[r];
@@ -1099,18 +1121,8 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
       h.q[s] = d.species[s].q;
       h.m[s] = d.species[s].m;
     }
-    const long long cells = (long long)d.nx * d.ny;
-    long long nb = (long long)((double)total * cells / (double)c->tl.n_cells);
-    const long long need = (cells + PIC_CG_THREADS - 1) / PIC_CG_THREADS;
-    nb = std::max<long long>(1, std::min<long long>(nb, need));
-    const int left = total - blk - (n_runs - 1 - r);
-    nb = std::min<long long>(nb, left);
-    if (r == n_runs - 1) nb = std::max<long long>(1, std::min<long long>(need, left));
-    h.cg_blk_lo = blk;
-    h.cg_blk_hi = blk + (int)nb;
-    blk += (int)nb;
   }
-  c->fa.n_blocks = blk;
+  assign_cg_blocks(c, opt->cg_blocks > 0 ? opt->cg_blocks : kDefaultCgBlocks);
   std::vector<int> tile_run(c->tl.n_tiles);
   for (int r = 0; r < n_runs; ++r)
     for (int t = 0; t < c->tl.ntx[r] * c->tl.nty[r]; ++t) tile_run[c->tl.tile0[r] + t] = r;
@@ -1473,6 +1485,103 @@ int32_t pic_precond_grad(pic_ctx* c, int32_t nx, int32_t ny, const double* d_b, 
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (loss) *loss = scal[1];
+  return PIC_OK;
+}
+
+int32_t pic_tune(pic_ctx* c, const pic_tune_opts* o, pic_tune_out* out) {
+  if (!c || !o) return PIC_E_INVAL;
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "pic_tune during a split step");
+  if (o->steps < 1 || o->n_split < 0 || o->n_split > 8 || o->n_cg < 0 || o->n_cg > 8)
+    return fail(c, PIC_E_INVAL, "steps >= 1 and at most 8 candidates per parameter");
+  std::vector<int> ks, cgs;
+  if (o->n_split == 0) {
+    for (int k = 1; k <= 8; k *= 2)
+      if (k <= c->plan.tile_split) ks.push_back(k);
+  } else {
+    for (int q = 0; q < o->n_split; ++q) {
+      if (o->split[q] < 1 || o->split[q] > c->plan.tile_split)
+        return fail(c, PIC_E_INVAL, "split candidate outside [1, planned tile_split]");
+      ks.push_back(o->split[q]);
+    }
+  }
+  if (o->n_cg == 0) {
+    for (int b = 64; b <= 512; b *= 2)
+      if (b <= c->max_cg_blocks) cgs.push_back(b);
+    if (cgs.empty()) cgs.push_back(c->max_cg_blocks);
+  } else {
+    for (int q = 0; q < o->n_cg; ++q) {
+      if (o->cg_blocks[q] < 1) return fail(c, PIC_E_INVAL, "cg_blocks candidate must be >= 1");
+      cgs.push_back(o->cg_blocks[q]);
+    }
+  }
+  const bool timing0 = c->timing;
+  auto timed = [&](int cls, double* ms) -> int {
+    t_resolve(c);
+    c->timing = true;
+    for (int k = 0; k < kTimingClasses; ++k) c->t_ms[k] = c->t_n[k] = 0;
+    for (int q = 0; q < o->steps; ++q) {
+      int rc = c->fast ? do_step<float>(c) : do_step<double>(c);
+      if (rc) return rc;
+    }
+    t_resolve(c);
+    *ms = c->t_ms[cls] / o->steps;
+    return check_err(c);
+  };
+  auto set_split = [&](int K) {
+    c->sf.K = K;
+    c->sd.K = K;
+    c->fa.K = K;
+  };
+  pic_tune_out res{};
+  int best_k = ks[0];
+  double best = 1e300;
+  for (size_t q = 0; q < ks.size(); ++q) {
+    set_split(ks[q]);
+    double ms = 0;
+    int rc = timed(0, &ms);
+    if (rc) return rc;
+    res.split[q] = ks[q];
+    res.particle_ms[q] = ms;
+    if (ms < best) {
+      best = ms;
+      best_k = ks[q];
+    }
+  }
+  res.n_split = (int)ks.size();
+  set_split(best_k);
+  res.tile_split = best_k;
+  int best_cap = cgs[0];
+  best = 1e300;
+  for (size_t q = 0; q < cgs.size(); ++q) {
+    assign_cg_blocks(c, cgs[q]);
+    HIPCHK(c, hipMemcpyAsync(c->d_runs, c->hruns.data(), sizeof(DevRun) * c->runs.size(),
+                             hipMemcpyHostToDevice, c->stream));
+    double ms = 0;
+    int rc = timed(5, &ms);
+    if (rc) return rc;
+    res.cg_blocks_tried[q] = c->fa.n_blocks;
+    res.field_ms[q] = ms;
+    if (ms < best) {
+      best = ms;
+      best_cap = cgs[q];
+    }
+  }
+  res.n_cg = (int)cgs.size();
+  assign_cg_blocks(c, best_cap);
+  HIPCHK(c, hipMemcpyAsync(c->d_runs, c->hruns.data(), sizeof(DevRun) * c->runs.size(),
+                           hipMemcpyHostToDevice, c->stream));
+  res.cg_blocks = c->fa.n_blocks;
+  // captured graphs hold the old grids
+  for (int p = 0; p < 2; ++p)
+    if (c->gexec[p]) {
+      (void)hipGraphExecDestroy(c->gexec[p]);
+      c->gexec[p] = nullptr;
+    }
+  t_resolve(c);
+  c->timing = timing0;
+  for (int k = 0; k < kTimingClasses; ++k) c->t_ms[k] = c->t_n[k] = 0;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (out) *out = res;
   return PIC_OK;
 }
 

@@ -1,0 +1,44 @@
+"""Launch-schedule autotuner for a workload: the tile shape, then the
+work-groups per tile and the field-solve work-groups.
+
+A tile shape fixes the layout of the particle store and the LDS footprint,
+so each candidate shape gets its own context (pic_plan rejects shapes whose
+LDS staging does not fit); on each context pic_tune then picks the launch
+parameters by timing real steps, and the shape whose tuned steps are fastest
+wins. This module only orchestrates: every timed step runs the library's
+kernels.
+"""
+from . import PicError, Sim, make_options, plan
+
+DEFAULT_SHAPES = ((16, 16), (32, 16), (16, 32), (24, 24), (16, 8), (8, 16))
+
+
+def autotune(runs, load, option_kw=None, shapes=DEFAULT_SHAPES, steps=4, warmup=2):
+    """runs: list of pic_run_desc; load(sim) loads the particles (and fields);
+    option_kw: keyword arguments of make_options (tile is overridden).
+    Returns (best, table): best = dict(tile, tile_split, cg_blocks, ms_per_step)."""
+    option_kw = dict(option_kw or {})
+    table = []
+    for shape in shapes:
+        kw = dict(option_kw, tile=shape)
+        try:
+            plan(runs, make_options(**kw))
+        except PicError:
+            continue
+        sim = Sim(runs, make_options(**kw))
+        try:
+            load(sim)
+            sim.step(warmup)
+            tuned = sim.tune(steps)
+            sim.timing(True)
+            sim.step(steps)
+            t = sim.get_timing()
+            ms = sum(v["ms"] for k, v in t.items() if k != "graph_replays") / steps
+            table.append(dict(tile=tuple(shape), tile_split=tuned["tile_split"],
+                              cg_blocks=tuned["cg_blocks"], ms_per_step=ms, tuned=tuned))
+        finally:
+            sim.close()
+    if not table:
+        raise RuntimeError("no candidate tile shape fits the workload")
+    best = min(table, key=lambda r: r["ms_per_step"])
+    return best, table

@@ -1,0 +1,48 @@
+"""The launch-schedule autotuner: pic_tune keeps results unchanged up to
+roundoff while it re-distributes work, and the tile-shape search returns a
+valid configuration."""
+import sys
+
+import pytest
+
+from pic_cases import Case, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def test_tune_keeps_results():
+    _say("pic_tune: same physics with the tuned schedule")
+    case = Case(64, 48, 2, ppc=4, gamma0=10.0, T=0.05, seed=4, field_amp=0.2)
+    a = case.gpu_sim("fp64", tile_split=8)
+    b = case.gpu_sim("fp64", tile_split=8)
+    r = b.tune(steps=2, splits=(1, 2, 8), cg_blocks=(4, 16))
+    assert r["tile_split"] in (1, 2, 8) and set(r["split_ms"]) == {1, 2, 8}
+    assert len(r["cg_ms"]) == 2 and all(v > 0 for v in r["cg_ms"].values())
+    a.step(5 * 2)                          # pic_tune advanced b by 5 x 2 steps
+    b.step(0)
+    for n in ("Ex", "Ey", "Ez", "Bx", "By", "Bz"):
+        assert relerr(b.get_field(0, n), a.get_field(0, n)) <= 1e-10, n
+    a.step(3)
+    b.step(3)
+    for n in ("Ex", "Bz"):
+        assert relerr(b.get_field(0, n), a.get_field(0, n)) <= 1e-10, n
+    a.close()
+    b.close()
+
+
+def test_tile_shape_search():
+    from paper_1412_2480_amd.tune import autotune
+    _say("tile-shape search")
+    case = Case(96, 64, 3, ppc=4, gamma0=20.0, T=0.01, seed=6)
+    best, table = autotune([case.run_desc()], case.load_into,
+                           dict(precision="fp32", track_ids=False),
+                           shapes=((16, 16), (32, 16), (64, 64)), steps=2, warmup=1)
+    shapes = [r["tile"] for r in table]
+    assert (64, 64) not in shapes            # does not fit LDS: skipped by pic_plan
+    assert set(shapes) == {(16, 16), (32, 16)}
+    assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
