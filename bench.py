@@ -47,6 +47,30 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def measured_traffic(precision, tile, tile_split, order, n_particles):
+    """HBM bytes per launch of the particle kernel from the committed counter
+    record (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the same
+    counter reads for a copy of known size), or None when the kernel sources or
+    the launch configuration differ from the ones the counters were taken on."""
+    import glob
+    import hashlib
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*.traffic.json")):
+        with open(path) as f:
+            rec = json.load(f)
+        cfg = rec["config"]
+        if (cfg["precision"], list(cfg["tile"]), cfg["tile_split"], cfg["order"],
+                cfg["particles"]) != (precision, list(tile), tile_split, order, n_particles):
+            continue
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["sources_sha256"]:
+            continue
+        return rec["traffic_bytes"], os.path.relpath(path, ROOT)
+    return None, None
+
+
 GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
 
 
@@ -344,6 +368,7 @@ def main():
 
     n_part = fast["n_particles"]
     achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic("fp32", tile, args.tile_split, cfg["order"], n_part)
     def solve_info(r):
         return None if r is None else dict(
             ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],
@@ -385,9 +410,12 @@ def main():
         },
         "roofline": {"bound": "hbm", "kernel": "fused particle push (gather+Boris+move+deposit)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
-                     "avg_launch_ms": fast["push_ms"]},
+                     "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE["fp32"] * n_part,
+                     "avg_launch_ms": fast["push_ms"], "tile": list(tile),
+                     "tile_split": args.tile_split},
         "autotune": tune,
         "batched_sweep": batched,
         "cpu_baseline": cpu,

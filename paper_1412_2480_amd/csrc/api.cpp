@@ -27,6 +27,7 @@ constexpr int kTimingClasses = 8;
 constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
 constexpr int kDefaultLearnedMaxit = 30;
 constexpr int kDefaultPrecondSlots = 16;
+constexpr double kTuneTie = 0.02;     // autotuner: relative margin treated as a tie
 
 struct Bump {
   uint8_t* base;
@@ -1542,11 +1543,14 @@ int32_t pic_tune(pic_ctx* c, const pic_tune_opts* o, pic_tune_out* out) {
     if (rc) return rc;
     res.split[q] = ks[q];
     res.particle_ms[q] = ms;
-    if (ms < best) {
-      best = ms;
-      best_k = ks[q];
-    }
   }
+  // within kTuneTie of the fastest counts as equal: the earliest candidate wins
+  for (size_t q = 0; q < ks.size(); ++q) best = std::min(best, res.particle_ms[q]);
+  for (size_t q = 0; q < ks.size(); ++q)
+    if (res.particle_ms[q] <= best * (1.0 + kTuneTie)) {
+      best_k = ks[q];
+      break;
+    }
   res.n_split = (int)ks.size();
   set_split(best_k);
   res.tile_split = best_k;
@@ -1561,11 +1565,13 @@ int32_t pic_tune(pic_ctx* c, const pic_tune_opts* o, pic_tune_out* out) {
     if (rc) return rc;
     res.cg_blocks_tried[q] = c->fa.n_blocks;
     res.field_ms[q] = ms;
-    if (ms < best) {
-      best = ms;
-      best_cap = cgs[q];
-    }
   }
+  for (size_t q = 0; q < cgs.size(); ++q) best = std::min(best, res.field_ms[q]);
+  for (size_t q = 0; q < cgs.size(); ++q)
+    if (res.field_ms[q] <= best * (1.0 + kTuneTie)) {
+      best_cap = cgs[q];
+      break;
+    }
   res.n_cg = (int)cgs.size();
   assign_cg_blocks(c, best_cap);
   HIPCHK(c, hipMemcpyAsync(c->d_runs, c->hruns.data(), sizeof(DevRun) * c->runs.size(),

@@ -294,35 +294,45 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           double* jx = sJ;
           double* jy = sJ + plane;
           double* jz = sJ + 2 * plane;
-          // Jx(i+1/2): running sum of Wx along x; the last node's sum is zero
+          // Jx(i+1/2): running sum of Wx along x; the last node's sum is zero.
+          // The constant factors of Jx, Jy, Jz are folded into the per-row and
+          // per-column weights.
 #pragma unroll
           for (int b = 0; b < W; ++b) {
-            const R wy = S0y[b] + R(0.5) * DSy[b];
+            const R wy = (S0y[b] + R(0.5) * DSy[b]) * cjx;
             R acc = R(0);
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) {
               acc += DSx[a] * wy;
-              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], (double)(cjx * acc));
+              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], (double)acc);
             }
+          }
+          // Wz = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3, grouped as
+          // (S0x + DSx/2) S0y + (S0x/2 + DSx/3) DSy; the first factor is Jy's
+          const R czv = cjz * vz;
+          R hy[W], hz[W], zz[W];
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            const R hx = S0x[a] + R(0.5) * DSx[a];
+            hy[a] = hx * cjy;
+            hz[a] = hx * czv;
+            zz[a] = (R(0.5) * S0x[a] + DSx[a] * (R(1) / R(3))) * czv;
           }
 #pragma unroll
           for (int a = 0; a < W; ++a) {
-            const R wx = S0x[a] + R(0.5) * DSx[a];
             R acc = R(0);
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) {
-              acc += DSy[b] * wx;
-              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], (double)(cjy * acc));
+              acc += DSy[b] * hy[a];
+              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], (double)acc);
             }
           }
-          const R czv = cjz * vz;
 #pragma unroll
           for (int b = 0; b < W; ++b)
 #pragma unroll
             for (int a = 0; a < W; ++a) {
-              const R wz = S0x[a] * S0y[b] + R(0.5) * DSx[a] * S0y[b] +
-                           R(0.5) * S0x[a] * DSy[b] + DSx[a] * DSy[b] * (R(1) / R(3));
-              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], (double)(czv * wz));
+              const R wz = hz[a] * S0y[b] + zz[a] * DSy[b];
+              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], (double)wz);
             }
 
           // ---- boundaries: a shock run reflects at x = 0 (after the deposit
