@@ -92,7 +92,7 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
 
 
 def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0,
-              learned=None):
+              learned=None, retune=False):
     """learned: None (plain CG) or dict(form, pairs, epochs, lr): collect that
     many pairs with plain CG, train, then take the learned path."""
     solver = "learned" if learned else "cg"
@@ -112,6 +112,10 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
         train = dict(tr, seconds=time.perf_counter() - t0, pairs=learned["pairs"],
                      epochs=learned["epochs"], form=learned["form"])
         sim.precond_use(True)
+        if retune:
+            # the learned solver has its own best field-solve grid: re-tune it
+            # on this context (the work-groups per tile stay as chosen)
+            train["retune"] = sim.tune(2, splits=(max(1, tile_split),))
     if warmup:
         sim.step(warmup)
     torch.cuda.synchronize()
@@ -246,7 +250,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay captured two-step HIP graphs in every timed form")
     ap.add_argument("--train-pairs", type=int, default=8)
-    ap.add_argument("--train-epochs", type=int, default=10)
+    ap.add_argument("--train-epochs", type=int, default=25)
     ap.add_argument("--also-mfma", action="store_true",
                     help="also time the FP32 form with the BF16 matrix-core network")
     ap.add_argument("--calib-copy", action="store_true",
@@ -329,7 +333,7 @@ def main():
             f"{args.cg_blocks} ({tune['seconds']:.1f} s)")
     log("bench: FP32 form" + ("" if learned is None else f" + learned ({args.learned_form})"))
     fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
-                     args.tile_split, learned)
+                     args.tile_split, learned, retune=not args.no_autotune)
     log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step, field solve "
         f"{fast['field_solve_ms']:.3f} ms, iters {fast['cg_iters']}")
     fast_cg = None

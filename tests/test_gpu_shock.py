@@ -159,3 +159,36 @@ def test_shock_run_keeps_gauss_law(precision):
     for s in range(2):
         assert 0.8 * n0 <= d["n_particles"][s] <= 2.5 * n0
     sim.close()
+
+
+@pytest.mark.parametrize("form", ["collapsed", "mfma"])
+def test_shock_learned_solver(form):
+    """The learned aid on a walled run: trained on the run's own pairs, it
+    reaches the plain-CG residual without the fallback in fewer iterations,
+    and its fields agree with plain CG's to the solver tolerance."""
+    _say(f"shock run with the learned solver ({form})")
+    case = Shock(96, 32, 2, ppc=8, gamma0=20.0, T=0.01)
+    a = case.gpu_sim("fp64")
+    b = case.gpu_sim("fp64", solver="learned", learned_form=form, precond_slots=8)
+    b.precond_use(False)
+    b.precond_collect(True)
+    for step in range(8):
+        _inject_both(case, step, a, None)
+        _inject_both(case, step, b, None)
+        a.step(1)
+        b.step(1)
+    assert b.precond_collect(False) == 8
+    tr = b.precond_train(epochs=20)
+    assert tr["loss_last"] < 0.1 * tr["loss_first"]
+    b.precond_use(True)
+    for step in range(8, 14):
+        _inject_both(case, step, a, None)
+        _inject_both(case, step, b, None)
+        sa = a.step(1)[0]
+        sb = b.step(1)[0]
+        assert sb["fallback"] == 0 and max(sb["relres"]) <= case.rtol
+        assert sum(sb["iters"]) < sum(sa["iters"])
+    for n in EN + BN:
+        assert relerr(b.get_field(0, n), a.get_field(0, n)) <= 1e-6, n
+    a.close()
+    b.close()
