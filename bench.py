@@ -201,6 +201,43 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
                 batched_speedup=seq_ms / ms)
 
 
+NET_FLOP_PER_CELL = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)   # three 3x3 layers, 1->32->32->1
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def net_rate(pic, torch, cfg, reps=20):
+    """Application rate of the learned network N on one field of the workload
+    grid: the BF16 matrix-core form (19,584 FLOP per cell) against the bf16
+    dense peak, and the collapsed 7x7 form (98 FLOP per cell)."""
+    import ctypes
+    run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
+                       [(-1.0, 1.0, 1), (1.0, 1.0, 1)])
+    sim = pic.Sim([run], pic.make_options("fp32", solver="learned", precond_slots=1))
+    x = torch.randn(cfg["ny"], cfg["nx"], dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    out = {}
+    for name, form in (("mfma", pic.PIC_NET_MFMA), ("collapsed", pic.PIC_NET_COLLAPSED)):
+        def call():
+            rc = sim.L.pic_precond_apply(sim.ctx, form, cfg["nx"], cfg["ny"],
+                                         ctypes.c_void_p(x.data_ptr()),
+                                         ctypes.c_void_p(y.data_ptr()))
+            if rc != 0:
+                raise RuntimeError("pic_precond_apply failed")
+        call()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            call()
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        cells = cfg["nx"] * cfg["ny"]
+        flop = (NET_FLOP_PER_CELL if name == "mfma" else 2 * 49) * cells
+        out[name] = dict(ms_per_application=ms, tflops=flop / (ms * 1e-3) / 1e12)
+    out["mfma"]["frac_of_bf16_peak"] = out["mfma"]["tflops"] / MFMA_BF16_PEAK_TFLOPS
+    out["note"] = "one field per call, call includes the library's stream synchronisation"
+    sim.close()
+    return out
+
+
 def cpu_baseline(cfg, seconds=15.0):
     """The FP64 oracle on a 4-row strip of the same workload (same grid width,
     ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
@@ -365,6 +402,13 @@ def main():
         log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs, "
             f"sequential {batched['sequential_ms_per_step']:.3f} ms")
 
+    net = None
+    if not args.no_learned:
+        net = net_rate(pic, torch, cfg)
+        log(f"bench: network application: mfma {net['mfma']['ms_per_application']:.3f} ms "
+            f"({net['mfma']['tflops']:.1f} TFLOP/s), collapsed "
+            f"{net['collapsed']['ms_per_application']:.3f} ms")
+
     cpu = None
     if not args.no_cpu:
         log("bench: oracle CPU baseline")
@@ -421,6 +465,7 @@ def main():
                      "avg_launch_ms": fast["push_ms"], "tile": list(tile),
                      "tile_split": args.tile_split},
         "autotune": tune,
+        "learned_net": net,
         "batched_sweep": batched,
         "cpu_baseline": cpu,
     }

@@ -31,7 +31,9 @@ typedef float net_f32x16 __attribute__((ext_vector_type(16)));
 #define NET_X_E ((NET_T + 6) * (NET_T + 6))        // input with 3-cell halo
 #define NET_H1_E ((NET_T + 4) * (NET_T + 4))       // layer-1 output, 2-cell halo
 #define NET_H2_E (((((NET_T + 2) * (NET_T + 2)) + 31) / 32) * 32)  // layer-2 output, padded
-#define NET_LDS_BYTES (NET_X_E * 4 + NET_H1_E * NET_C * 2 + NET_H2_E * NET_C * 2 + 2 * NET_C * 9 * 4)
+#define NET_W1_PITCH 12                            // W1 row of 9 taps padded to 12 in LDS
+#define NET_LDS_BYTES (NET_X_E * 4 + NET_H1_E * NET_C * 2 + NET_H2_E * NET_C * 2 + \
+                       (NET_C * NET_W1_PITCH + 9 * NET_C) * 4)
 
 #define NET_KT 32                                     // output tile edge, collapsed form
 #define NET_KE (NET_KT + 6)                           // staged edge (3-cell halo)
@@ -60,31 +62,44 @@ __device__ void net_apply_tile(const NetWeights& W, int X0, int Y0, int nx, int 
   float* sx = reinterpret_cast<float*>(lds);
   __bf16* h1 = reinterpret_cast<__bf16*>(lds + NET_X_E * 4);
   __bf16* h2 = h1 + NET_H1_E * NET_C;
-  float* w1 = reinterpret_cast<float*>(h2 + NET_H2_E * NET_C);
-  float* w3 = w1 + NET_C * 9;
+  float* w1 = reinterpret_cast<float*>(h2 + NET_H2_E * NET_C);   // [co][NET_W1_PITCH]
+  float* w3 = w1 + NET_C * NET_W1_PITCH;                           // [tap][ci]
   const int tid = threadIdx.x, nthr = blockDim.x;
   constexpr int XE = NET_T + 6, HE1 = NET_T + 4, HE2 = NET_T + 2;
 
   for (int e = tid; e < NET_C * 9; e += nthr) {
-    w1[e] = W.w[NET_W1 + e];
-    w3[e] = W.w[NET_W3 + e];
+    const int co = e / 9, t = e % 9;
+    w1[co * NET_W1_PITCH + t] = W.w[NET_W1 + e];
+    w3[t * NET_C + co] = W.w[NET_W3 + e];     // W3 is [ci][tap]; e = ci * 9 + tap
   }
   for (int e = tid; e < XE * XE; e += nthr) {
     const int i = net_mod(X0 + e % XE - 3, nx), j = net_mod(Y0 + e / XE - 3, ny);
     sx[e] = (float)rd(i, j);
   }
   __syncthreads();
-  // layer 1: h1[cell][co], cells of the (T+4)^2 region
-  for (int e = tid; e < NET_H1_E * NET_C; e += nthr) {
-    const int co = e % NET_C, cell = e / NET_C;
+  // layer 1: one cell of the (T+4)^2 region per thread, all channels; the
+  // weights are read as broadcasts, the 32 outputs stored as four 16-byte rows
+  for (int cell = tid; cell < NET_H1_E; cell += nthr) {
     const int u = cell % HE1, v = cell / HE1;   // region origin at tile -2
-    float acc = 0.f;
+    float xv[9];
 #pragma unroll
     for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx)
-        acc += w1[co * 9 + dy * 3 + dx] * sx[(v + dy) * XE + (u + dx)];
-    h1[cell * NET_C + co] = (__bf16)acc;
+      for (int dx = 0; dx < 3; ++dx) xv[dy * 3 + dx] = sx[(v + dy) * XE + (u + dx)];
+    __bf16* dst = h1 + cell * NET_C;
+#pragma unroll
+    for (int c8 = 0; c8 < NET_C; c8 += 8) {
+      net_bf16x8 pack;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const float* w = w1 + (c8 + q) * NET_W1_PITCH;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc += w[t] * xv[t];
+        pack[q] = (__bf16)acc;
+      }
+      *reinterpret_cast<net_bf16x8*>(dst + c8) = pack;
+    }
   }
   __syncthreads();
   // layer 2 on the matrix cores: rows = 32 cells of the (T+2)^2 region
@@ -121,20 +136,32 @@ __device__ void net_apply_tile(const NetWeights& W, int X0, int Y0, int nx, int 
     }
   }
   __syncthreads();
-  // layer 3: one output per thread
-  for (int cell = tid; cell < NET_T * NET_T; cell += nthr) {
+  // layer 3: two threads per output cell, 16 channels each, read as two
+  // 16-byte rows per tap; the halves are combined across the lane pair
+  for (int base = 0; base < NET_T * NET_T * 2; base += nthr) {
+    const int e = base + tid;
+    const bool live = e < NET_T * NET_T * 2;
+    const int cell = e >> 1, half = e & 1;
     const int u = cell % NET_T, v = cell / NET_T;
     float acc = 0.f;
+    if (live) {
 #pragma unroll 1
-    for (int dy = 0; dy < 3; ++dy)
+      for (int dy = 0; dy < 3; ++dy)
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx) {
-        const __bf16* hp = h2 + ((v + dy) * HE2 + (u + dx)) * NET_C;
-#pragma unroll 8
-        for (int ci = 0; ci < NET_C; ++ci) acc += w3[ci * 9 + dy * 3 + dx] * (float)hp[ci];
-      }
+        for (int dx = 0; dx < 3; ++dx) {
+          const __bf16* hp = h2 + ((v + dy) * HE2 + (u + dx)) * NET_C + half * 16;
+          const float* w = w3 + (dy * 3 + dx) * NET_C + half * 16;
+          const net_bf16x8 a0 = *reinterpret_cast<const net_bf16x8*>(hp);
+          const net_bf16x8 a1 = *reinterpret_cast<const net_bf16x8*>(hp + 8);
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc += w[q] * (float)a0[q];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc += w[8 + q] * (float)a1[q];
+        }
+    }
+    acc += __shfl_xor(acc, 1, 64);
     const int i = X0 + u, j = Y0 + v;
-    if (i < nx && j < ny) wr(i, j, (double)acc);
+    if (live && half == 0 && i < nx && j < ny) wr(i, j, (double)acc);
   }
   __syncthreads();
 }
