@@ -1,9 +1,17 @@
-"""Parity at the benchmark's full size (periodic 1024 x 256, pair plasma at
-gamma0 = 40, 64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32
-particle path, the tile shape bench.py times) on outputs the FP64 oracle can
-compute piecewise: a sample of particles pushed one by one, the current on
-sampled node boxes from the particles that can reach them, and the field
-solve on the whole grid from the GPU's own current."""
+"""Parity at full size on outputs the FP64 oracle can compute piecewise.
+
+* The benchmark workload (periodic 1024 x 256, pair plasma at gamma0 = 40,
+  64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32 particle
+  path, the launch configuration bench.py times after tuning: 16 x 32 tiles,
+  one work-group per tile): a sample of particles pushed one by one, the
+  current on sampled node boxes from the particles that can reach them, and
+  the field solve on the whole grid from the GPU's own current.
+* The shock workload (4096 x 512 with walls, flow at gamma0 = 40 towards the
+  wall, 32 particles/cell/species, order 2, CFL 1, theta 0.6, FP32 particles,
+  learned CG aid trained on the run's own first pairs): properties that hold
+  at any size (conductor nodes, Gauss's law in the interior, particle
+  bookkeeping with injection and outflow, learned solves at the plain-CG
+  residual)."""
 import sys
 
 import numpy as np
@@ -29,7 +37,7 @@ def test_fullsize_fp32_step_sampled_parity():
     Q = loads.macro_charge(G0, DX, DX, PPC)
     ld = loads.pair_plasma_cells(NX, NY, PPC, G0, 0.01, seed=0)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 16)))
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 32), tile_split=1))
     for s in range(2):
         d = ld[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -114,3 +122,65 @@ def test_fullsize_fp32_step_sampled_parity():
         e = relerr(F1[name] - F0[name], ref.B[k] - F0[name])
         _say(f"  {name} increment relerr {e:.2e}")
         assert e <= 1e-6
+
+
+def test_fullsize_shock_fp32_learned():
+    import paper_1412_2480_amd as pic
+    from synth import loads
+    nx, ny, ppc, g0 = 4096, 512, 32, 40.0
+    x_out = nx - pic.PIC_WALL_GAP
+    Q = loads.macro_charge(g0, DX, DX, ppc)
+    _say("fullsize shock: generating load")
+    ld = loads.shock_load(x_out, ny, ppc, g0, 0.01, 0)
+    run = pic.run_desc(nx, ny, DX, 1.0, 0.6, 2, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8,
+                       bc="shock")
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 32), tile_split=1, slack=1.5,
+                                          exchange_frac=0.5, track_ids=False, solver="learned",
+                                          precond_slots=4))
+    for s in range(2):
+        d = ld[s]
+        sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    n0 = x_out * ny * ppc
+    del ld
+    injected = 0
+
+    def inject(step):
+        nonlocal injected
+        for s, d in enumerate(loads.shock_injection(x_out, ny, ppc, g0, 0.01, 0, step, 1.0)):
+            sim.inject_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
+                                 d["uz"])
+        injected += len(d["ix"])
+
+    _say("fullsize shock: 4 plain-CG steps recording pairs")
+    sim.precond_use(False)
+    sim.precond_collect(True)
+    plain_iters = []
+    for step in range(4):
+        inject(step)
+        st = sim.step(1)[0]
+        plain_iters.append(sum(st["iters"]))
+    assert sim.precond_collect(False) == 4
+    tr = sim.precond_train(epochs=8)
+    _say(f"fullsize shock: trained {tr}")
+    assert tr["loss_last"] < 0.1 * tr["loss_first"]
+    sim.precond_use(True)
+    for step in range(4, 8):
+        inject(step)
+        st = sim.step(1)[0]
+        assert st["fallback"] == 0 and max(st["relres"]) <= 1e-8
+        assert sum(st["iters"]) < min(plain_iters)
+    _say(f"fullsize shock: plain {plain_iters}, learned last {st['iters']}")
+    d = sim.diag(0, divergences=True)
+    rho_scale = 4 * np.pi * Q / (DX * DX)
+    _say(f"fullsize shock: gauss {d['gauss_max']:.3e} (scale {rho_scale:.3e}), "
+         f"particles {d['n_particles']}")
+    assert d["gauss_max"] <= 1e-4 * rho_scale
+    for s in range(2):
+        assert 0.95 * n0 <= d["n_particles"][s] <= n0 + injected
+    F = {k: sim.get_field(0, k) for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    for k in ("Ey", "Ez", "Bx"):
+        assert np.all(F[k][:, 0] == 0) and np.all(F[k][:, nx - 1] == 0), k
+    for k in ("Ex", "By", "Bz"):
+        assert np.all(F[k][:, nx - 1] == 0), k
+    assert np.abs(F["Bz"]).max() > 0
+    sim.close()
