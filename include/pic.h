@@ -184,6 +184,27 @@ int32_t pic_load_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t n
                            const double* fy, const double* ux, const double* uy,
                            const double* uz);
 
+/* Seeded synthetic plasma generated on the device (for loads too large for
+ * the host): ppc particles per cell in the cell columns i < x_cells (0 = all
+ * columns; a shock run's load must stop at x_out), uniform inside the cell,
+ * momenta drifting Maxwell-Juettner with rest-frame temperature T (m c^2) and
+ * bulk Lorentz factor gamma0 along direction * x. Item k (cell k / ppc,
+ * row-major over the loaded columns) draws its numbers from Philox4x32-10
+ * counters keyed by (seed, tag): positions from tag 1, momenta from tag
+ * 2 + 16 * species; this is the recipe of the repository's seeded host
+ * generator, item by item. Replaces the particles of (run, species); ids are
+ * the item numbers. */
+typedef struct pic_plasma_desc {
+  int32_t ppc;
+  int32_t x_cells;
+  double gamma0;
+  double T;
+  int32_t direction;     /* +1 or -1 */
+  uint64_t seed;
+} pic_plasma_desc;
+
+int32_t pic_load_plasma(pic_ctx* ctx, int32_t run, int32_t species, const pic_plasma_desc* desc);
+
 /* Append n host particles to (run, species) of a PIC_BC_SHOCK run between
  * steps (same arrays as pic_load_particles; ix < nx - PIC_WALL_GAP). They get
  * the next ids of the species. At most four cell columns' worth of the run

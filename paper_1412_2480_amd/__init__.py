@@ -26,7 +26,7 @@ FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy"
              "rho": 9}
 STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
           -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
-EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_inject_particles",
+EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_load_plasma", "pic_inject_particles",
            "pic_read_particles", "pic_set_field", "pic_get_field", "pic_gather_push",
            "pic_deposit", "pic_field_solve", "pic_step", "pic_diag", "pic_history",
            "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
@@ -84,6 +84,11 @@ class TrainStats(ctypes.Structure):
                 ("samples", ctypes.c_int32), ("updates", ctypes.c_int32)]
 
 
+class PlasmaDesc(ctypes.Structure):
+    _fields_ = [("ppc", ctypes.c_int32), ("x_cells", ctypes.c_int32), ("gamma0", ctypes.c_double),
+                ("T", ctypes.c_double), ("direction", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
 class TuneOpts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("n_split", ctypes.c_int32),
                 ("split", ctypes.c_int32 * 8), ("n_cg", ctypes.c_int32),
@@ -129,6 +134,8 @@ def lib():
                                ctypes.c_size_t, ctypes.c_void_p, P(ctypes.c_void_p)]
         L.pic_load_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64] + [ctypes.c_void_p] * 7
+        L.pic_load_plasma.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                      P(PlasmaDesc)]
         L.pic_inject_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int64] + [ctypes.c_void_p] * 7
         L.pic_read_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
@@ -280,6 +287,14 @@ class Sim:
         n = a[0].size
         self._check(self.L.pic_load_particles(self.ctx, run, species, n, *[_ptr(v) for v in a]),
                     "load_particles")
+
+    def load_plasma(self, run, species, ppc, gamma0, T, seed, direction=1, x_cells=0):
+        """Seeded synthetic plasma generated on the device (pic_load_plasma)."""
+        d = PlasmaDesc()
+        d.ppc, d.x_cells, d.gamma0, d.T = int(ppc), int(x_cells), float(gamma0), float(T)
+        d.direction, d.seed = int(direction), int(seed)
+        self._check(self.L.pic_load_plasma(self.ctx, run, species, ctypes.byref(d)),
+                    "load_plasma")
 
     def inject_particles(self, run, species, ix, iy, fx, fy, ux, uy, uz):
         a = [np.ascontiguousarray(v, dtype=t) for v, t in

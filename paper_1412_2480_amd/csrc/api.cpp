@@ -1161,6 +1161,66 @@ int32_t pic_load_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n, 
                  : load_impl<double>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz);
 }
 
+int32_t pic_load_plasma(pic_ctx* c, int32_t run, int32_t species, const pic_plasma_desc* d) {
+  if (!c || !d) return PIC_E_INVAL;
+  if (run < 0 || run >= (int)c->runs.size() || species < 0 || species >= c->runs[run].n_species)
+    return fail(c, PIC_E_INVAL, "bad run/species");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "load during a split step");
+  const pic_run_desc& rd = c->runs[run];
+  const int xmax = rd.bc == PIC_BC_SHOCK ? rd.nx - PIC_WALL_GAP : rd.nx;
+  const int xc = d->x_cells > 0 ? d->x_cells : rd.nx;
+  if (d->ppc < 0 || xc > xmax || !(d->gamma0 >= 1.0) || !(d->T >= 0.0) ||
+      (d->direction != 1 && d->direction != -1))
+    return fail(c, PIC_E_INVAL, "plasma load needs ppc >= 0, x_cells within the particle "
+                                "region, gamma0 >= 1, T >= 0, direction +-1");
+  const Tiling& tl = c->tl;
+  // capacity: the fullest tile holds widest x tallest cells
+  const long long per_tile = (long long)tl.TXA * tl.TYA * d->ppc;
+  if (per_tile > c->plan.tile_slots[species])
+    return fail(c, PIC_E_CAPACITY, "tile slots smaller than ppc x tile cells; raise slack or ppc");
+  const long long n = (long long)xc * rd.ny * d->ppc;
+  if (n > (long long)INT32_MAX) return fail(c, PIC_E_INVAL, "too many particles for int32 ids");
+  PlasmaLoad L{};
+  L.seed = d->seed;
+  L.ppc = d->ppc;
+  L.x_cells = xc;
+  L.ny = rd.ny;
+  L.gamma0 = d->gamma0;
+  L.beta = d->gamma0 > 1.0 ? (double)d->direction * std::sqrt(1.0 - 1.0 / (d->gamma0 * d->gamma0))
+                           : 0.0;
+  L.T = d->T;
+  if (d->T > 0.0) {
+    // rejection envelope: chi-3 piece below uc, three-term Gamma mixture above
+    const double T = d->T;
+    const double uc = 5.0 * std::sqrt(T);
+    const double gc = std::sqrt(1.0 + uc * uc);
+    const double s2 = 0.5 * (1.0 + gc) * T;
+    const double sg = std::sqrt(s2);
+    const double mass_a = std::pow(sg, 3.0) * std::sqrt(M_PI / 2.0);
+    const double vc = uc / gc;
+    const double lam = vc / T;
+    const double c1 = uc * uc / lam, c2 = 2.0 * uc / std::pow(lam, 2.0),
+                 c3 = 2.0 / std::pow(lam, 3.0);
+    const double mass_b = std::exp(-(gc - 1.0) / T) * (c1 + c2 + c3);
+    L.pa = mass_a / (mass_a + mass_b);
+    L.s = sg;
+    L.uc = uc;
+    L.gc = gc;
+    L.vc = vc;
+    L.lam = lam;
+    L.mix0 = c1 / (c1 + c2 + c3);
+    L.mix1 = (c1 + c2) / (c1 + c2 + c3);
+  }
+  const int nt = tl.ntx[run] * tl.nty[run];
+  hipError_t e = c->fast
+                     ? pic_launch_load_plasma<float>(c->sf, run, species, L, nt, c->stream)
+                     : pic_launch_load_plasma<double>(c->sd, run, species, L, nt, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("plasma load: ") + hipGetErrorString(e));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->next_id[run][species] = n;
+  return PIC_OK;
+}
+
 int32_t pic_inject_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n,
                              const int32_t* ix, const int32_t* iy, const double* fx,
                              const double* fy, const double* ux, const double* uy,

@@ -102,3 +102,15 @@ hipError_t pic_net_apply(const NetTrain& T, int form, const double* in, double* 
 hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int nx, int ny,
                         hipStream_t s);
 hipError_t pic_net_adam(const NetTrain& T, float lr, int step, hipStream_t s);
+
+// Device-side seeded plasma load (same items as the host generator)
+struct PlasmaLoad {
+  unsigned long long seed;
+  int ppc, x_cells, ny;
+  double gamma0, beta, T;
+  // rejection envelope of the rest-frame Maxwell-Juettner speed
+  double pa, s, uc, gc, vc, lam, mix0, mix1;
+};
+template <typename R>
+hipError_t pic_launch_load_plasma(const DevState<R>& st, int run, int s, const PlasmaLoad& L,
+                                  int n_tiles_run, hipStream_t stream);
