@@ -238,6 +238,41 @@ def net_rate(pic, torch, cfg, reps=20):
     return out
 
 
+def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1):
+    """The large single-GPU share: periodic 8192 x 2048, pair plasma at
+    gamma0 = 40, 64 ppc/species (2.1e9 particles), order 3, CFL 1, theta 0.6,
+    FP32 particles, loaded on the device; plain CG."""
+    from synth import loads
+    nx, ny, ppc = 8192, 2048, 64
+    Q = loads.macro_charge(40.0, 0.1, 0.1, ppc)
+    run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 3, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8)
+    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split,
+                                          track_ids=False))
+    for s in range(2):
+        sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    rc = sim.step_async(steps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    if rc != 0:
+        raise RuntimeError(f"large share pic_step returned {pic.STATUS.get(rc, rc)}")
+    tim = sim.get_timing()
+    st = sim.step(0)[0]
+    n = 2 * nx * ny * ppc
+    push_ms = tim["push"]["ms"] / max(1, tim["push"]["launches"])
+    out = dict(workload="periodic 8192x2048, pair gamma0=40, 64 ppc/species, order 3, CFL 1.0, "
+                        "theta 0.6 (FP32 particles, plain CG)",
+               particles=n, workspace_gb=sim.info.workspace_bytes / 1e9, ms_per_step=ms,
+               particle_steps_per_s=n / (ms * 1e-3), push_ms=push_ms,
+               push_achieved_gbs=BYTES_PER_PARTICLE["fp32"] * n / (push_ms * 1e-3) / 1e9,
+               field_solve_ms=tim["field_solve"]["ms"] / steps, cg_iters=st["iters"])
+    sim.close()
+    return out
+
+
 def cpu_baseline(cfg, seconds=15.0):
     """The FP64 oracle on a 4-row strip of the same workload (same grid width,
     ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
@@ -277,6 +312,8 @@ def main():
     ap.add_argument("--sweep-tiles", default="",
                     help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-run batched sweep")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 8192x2048 large single-GPU share (2.1e9 particles)")
     ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"],
                     help="inference form of the network in the timed form")
     ap.add_argument("--no-learned", action="store_true",
@@ -402,6 +439,13 @@ def main():
         log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs, "
             f"sequential {batched['sequential_ms_per_step']:.3f} ms")
 
+    large = None
+    if not args.no_large:
+        log("bench: large single-GPU share (8192x2048, 2.1e9 particles)")
+        large = large_share(pic, torch, tile=tile, tile_split=max(1, args.tile_split))
+        log(f"bench: large share {large['ms_per_step']:.1f} ms/step, push "
+            f"{large['push_ms']:.1f} ms ({large['push_achieved_gbs']:.0f} GB/s)")
+
     net = None
     if not args.no_learned:
         net = net_rate(pic, torch, cfg)
@@ -466,6 +510,7 @@ def main():
                      "tile_split": args.tile_split},
         "autotune": tune,
         "learned_net": net,
+        "large_share": large,
         "batched_sweep": batched,
         "cpu_baseline": cpu,
     }
