@@ -294,45 +294,55 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           double* jx = sJ;
           double* jy = sJ + plane;
           double* jz = sJ + 2 * plane;
-          // Jx(i+1/2): running sum of Wx along x; the last node's sum is zero.
-          // The constant factors of Jx, Jy, Jz are folded into the per-row and
-          // per-column weights.
+          // The sums run in FP64 from the window weights converted once (an
+          // FP64 FMA issues at the rate of an FP32 one here, and the LDS
+          // accumulators are FP64): Jx(i+1/2) is the running sum of Wx along x
+          // (the last node's sum is zero); the constant factors of Jx, Jy, Jz
+          // are folded into the per-row and per-column weights.
+          double s0x[W], dsx[W], s0y[W], dsy[W];
+#pragma unroll
+          for (int a = 0; a < W; ++a) {
+            s0x[a] = (double)S0x[a];
+            dsx[a] = (double)DSx[a];
+            s0y[a] = (double)S0y[a];
+            dsy[a] = (double)DSy[a];
+          }
+          const double cx = (double)cjx, cy = (double)cjy, cz = (double)cjz * (double)vz;
 #pragma unroll
           for (int b = 0; b < W; ++b) {
-            const R wy = (S0y[b] + R(0.5) * DSy[b]) * cjx;
-            R acc = R(0);
+            const double wy = (s0y[b] + 0.5 * dsy[b]) * cx;
+            double acc = 0.0;
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) {
-              acc += DSx[a] * wy;
-              if (acc != R(0)) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], (double)acc);
+              acc += dsx[a] * wy;
+              if (acc != 0.0) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], acc);
             }
           }
           // Wz = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3, grouped as
           // (S0x + DSx/2) S0y + (S0x/2 + DSx/3) DSy; the first factor is Jy's
-          const R czv = cjz * vz;
-          R hy[W], hz[W], zz[W];
+          double hy[W], hz[W], zz[W];
 #pragma unroll
           for (int a = 0; a < W; ++a) {
-            const R hx = S0x[a] + R(0.5) * DSx[a];
-            hy[a] = hx * cjy;
-            hz[a] = hx * czv;
-            zz[a] = (R(0.5) * S0x[a] + DSx[a] * (R(1) / R(3))) * czv;
+            const double hx = s0x[a] + 0.5 * dsx[a];
+            hy[a] = hx * cy;
+            hz[a] = hx * cz;
+            zz[a] = (0.5 * s0x[a] + dsx[a] * (1.0 / 3.0)) * cz;
           }
 #pragma unroll
           for (int a = 0; a < W; ++a) {
-            R acc = R(0);
+            double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) {
-              acc += DSy[b] * hy[a];
-              if (acc != R(0)) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], (double)acc);
+              acc += dsy[b] * hy[a];
+              if (acc != 0.0) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], acc);
             }
           }
 #pragma unroll
           for (int b = 0; b < W; ++b)
 #pragma unroll
             for (int a = 0; a < W; ++a) {
-              const R wz = hz[a] * S0y[b] + zz[a] * DSy[b];
-              if (wz != R(0)) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], (double)wz);
+              const double wz = hz[a] * s0y[b] + zz[a] * dsy[b];
+              if (wz != 0.0) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], wz);
             }
 
           // ---- boundaries: a shock run reflects at x = 0 (after the deposit
