@@ -157,21 +157,22 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
     runs launched one context at a time; aggregate particle-steps/s."""
     from synth import configs, loads
     table = configs.sweep_runs()
-    descs, lds = [], []
+    descs = []
     for t in table:
         Q = loads.macro_charge(t["gamma0"], t["dx"], t["dx"], t["ppc"])
         descs.append(pic.run_desc(t["nx"], t["ny"], t["dx"], t["cfl"], t["theta"], t["order"],
                                   [(-Q, Q, t["ppc"]), (Q, Q, t["ppc"])], cg_rtol=1e-8))
-        lds.append(loads.pair_plasma_cells(t["nx"], t["ny"], t["ppc"], t["gamma0"], t["T"],
-                                           t["seed"]))
+
+    def load_run(sim, r, t):
+        # the device loader generates the same seeded items as the host generator
+        for s in range(2):
+            sim.load_plasma(r, s, t["ppc"], t["gamma0"], t["T"], t["seed"])
     n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
     opts = pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH)
     sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH,
                                           tile_split=8))
-    for r, ld in enumerate(lds):
-        for s in range(2):
-            d = ld[s]
-            sim.load_particles(r, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    for r, t in enumerate(table):
+        load_run(sim, r, t)
     sim.step(warmup)
     tuned = sim.tune(2)     # work-groups per tile and field-solve work-groups of this mix
     torch.cuda.synchronize()
@@ -183,11 +184,9 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
         raise RuntimeError(f"batched pic_step returned {pic.STATUS.get(rc, rc)}")
     sim.close()
     seq_ms = 0.0
-    for r, ld in enumerate(lds):
+    for r, t in enumerate(table):
         one = pic.Sim([descs[r]], opts)
-        for s in range(2):
-            d = ld[s]
-            one.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+        load_run(one, 0, t)
         one.step(1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
