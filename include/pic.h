@@ -261,9 +261,10 @@ int32_t pic_get_timing(pic_ctx* ctx, pic_timing_out* out);
  * paper, which solves Eq. (7) by plain CG). A linear network N of three 3 x 3
  * periodic convolutions, 1 -> 32 -> 32 -> 1 channels (9792 FP32 weights,
  * layout W1[32][3][3], W2[32][32][3][3], W3[32][3][3], taps [dy][dx] with
- * offset (dx-1, dy-1)), approximates the inverse of Eq. (7)'s operator. Every
- * run of the context must share dx, dy, cfl and theta (one operator). The
- * field solve starts from x0 = N(b) and runs flexible PCG with z = N(r) to
+ * offset (dx-1, dy-1)), approximates the inverse of Eq. (7)'s operator. Runs
+ * that share dx, dy, cfl and theta share one network; each distinct operator
+ * of the context has its own, trained on the pairs of the first run that uses
+ * it. The field solve starts from x0 = N(b) and runs flexible PCG with z = N(r) to
  * cg_rtol; plain CG from the current iterate finishes any component that
  * misses it within learned_maxit, so the result always meets cg_rtol as plain
  * CG would. The weights start at the identity map plus small fixed noise. */
@@ -275,33 +276,37 @@ typedef struct pic_train_opts {
 typedef struct pic_train_stats {
   double loss_first;     /* mean of sum (N(b) - dB)^2 / sum dB^2 over the first epoch */
   double loss_last;      /* the same over the last epoch */
-  int32_t samples;       /* (pair, component) samples per epoch */
+  int32_t samples;       /* (pair, component, network) samples per epoch */
   int32_t updates;       /* Adam updates made */
+  int32_t networks;      /* networks trained (one per distinct operator) */
 } pic_train_stats;
 
-/* Record (b, dB) of run 0 from every following field solve (on != 0) into
- * the ring of precond_slots pairs; n_pairs (nullable) receives the number held. */
+/* Record (b, dB) of each network's first run from every following field
+ * solve (on != 0) into the network's ring of precond_slots pairs; n_pairs
+ * (nullable) receives the number held per network. */
 int32_t pic_precond_collect(pic_ctx* ctx, int32_t on, int32_t* n_pairs);
 
-/* Train N on the recorded pairs: per epoch one Adam update per (pair,
- * component) sample, oldest pair first, all in FP32 on the device; then
- * refresh the BF16 copy and the collapsed filter. Synchronises. */
+/* Train every network on its recorded pairs: per epoch one Adam update per
+ * (pair, component) sample, oldest pair first, all in FP32 on the device;
+ * then refresh the BF16 copies and collapsed filters. Synchronises. */
 int32_t pic_precond_train(pic_ctx* ctx, const pic_train_opts* opts, pic_train_stats* out);
 
 /* Use the learned path in the following field solves (on != 0, the default
  * for PIC_SOLVER_LEARNED_PCG) or plain CG (on == 0). */
 int32_t pic_precond_use(pic_ctx* ctx, int32_t on);
 
-/* Copy the FP32 weights out / in (n must be 9792). set_weights refreshes the
- * derived BF16 copy and collapsed filter. */
+/* Copy the FP32 weights of all networks out / in, network after network in
+ * the order of their first runs (n must be 9792 x networks). set_weights
+ * refreshes the derived BF16 copies and collapsed filters. */
 int32_t pic_precond_get_weights(pic_ctx* ctx, float* host, size_t n);
 int32_t pic_precond_set_weights(pic_ctx* ctx, const float* host, size_t n);
 
 /* For parity checks. apply: d_out = N(d_in) on one nx x ny periodic FP64
  * device field ([ny][nx]) in the given form (PIC_NET_COLLAPSED or
  * PIC_NET_MFMA). grad: FP32 loss and weight gradient of one sample (d_b, d_t
- * device FP64 fields), host_grad receiving n = 9792 floats. Both need
- * nx * ny <= run 0's cell count, nx, ny >= 3, and synchronise. */
+ * device FP64 fields), host_grad receiving n = 9792 floats. Both use the
+ * first network (that of run 0), need nx, ny >= 3 and nx * ny no larger than
+ * the largest first run's cell count, and synchronise. */
 int32_t pic_precond_apply(pic_ctx* ctx, int32_t form, int32_t nx, int32_t ny, const double* d_in,
                           double* d_out);
 int32_t pic_precond_grad(pic_ctx* ctx, int32_t nx, int32_t ny, const double* d_b,

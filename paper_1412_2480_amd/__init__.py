@@ -81,7 +81,8 @@ class TrainOpts(ctypes.Structure):
 
 class TrainStats(ctypes.Structure):
     _fields_ = [("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double),
-                ("samples", ctypes.c_int32), ("updates", ctypes.c_int32)]
+                ("samples", ctypes.c_int32), ("updates", ctypes.c_int32),
+                ("networks", ctypes.c_int32)]
 
 
 class PlasmaDesc(ctypes.Structure):
@@ -397,14 +398,14 @@ class Sim:
         self._check(self.L.pic_precond_train(self.ctx, ctypes.byref(o), ctypes.byref(st)),
                     "precond_train")
         return dict(loss_first=st.loss_first, loss_last=st.loss_last, samples=st.samples,
-                    updates=st.updates)
+                    updates=st.updates, networks=st.networks)
 
     def precond_use(self, on=True):
         self._check(self.L.pic_precond_use(self.ctx, 1 if on else 0), "precond_use")
 
-    def get_weights(self):
-        w = np.empty(NET_NW, np.float32)
-        self._check(self.L.pic_precond_get_weights(self.ctx, _ptr(w), NET_NW), "get_weights")
+    def get_weights(self, networks=1):
+        w = np.empty(NET_NW * networks, np.float32)
+        self._check(self.L.pic_precond_get_weights(self.ctx, _ptr(w), w.size), "get_weights")
         return w
 
     def set_weights(self, w):

@@ -92,11 +92,13 @@ struct pic_ctx {
   bool learned = false;      // storage carved (solver PIC_SOLVER_LEARNED_PCG)
   bool use_learned = false;  // field solves take the learned path
   bool collect = false;
-  NetTrain net{};
-  double* d_pairs = nullptr;
+  std::vector<NetTrain> nets;      // one per distinct operator
+  std::vector<double*> net_pairs;  // pairs ring of each network
+  NetWeights* d_nets = nullptr;
+  std::vector<int> net_of_run, net_first_run;
   int pair_slots = 0;
   long long pairs_written = 0;
-  long long train_cells = 0;
+  long long train_cells = 0;       // cells of the training activations (largest first run)
   int adam_step = 0;
   double* d_history = nullptr;
   // injection staging (shock runs): particles sorted by tile + (tile, first, count) list
@@ -177,13 +179,6 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
       *msg = "learned_maxit and precond_slots must be >= 0";
       return PIC_E_INVAL;
     }
-    // one network approximates one operator of Eq. (7)
-    for (int r = 1; r < n_runs; ++r)
-      if (runs[r].dx != runs[0].dx || runs[r].dy != runs[0].dy || runs[r].cfl != runs[0].cfl ||
-          runs[r].theta != runs[0].theta) {
-        *msg = "the learned solver needs equal dx, dy, cfl and theta in every run";
-        return PIC_E_INVAL;
-      }
   }
   for (int r = 0; r < n_runs; ++r) {
     const pic_run_desc& d = runs[r];
@@ -239,11 +234,35 @@ void make_tiling(const pic_run_desc* runs, int n_runs, const pic_options* o, Til
   t->max_cells = mc;
 }
 
+// Runs that share the operator of Eq. (7) (dx, dy, cfl, theta) share one
+// network of the learned solver; the first run of each group records its
+// training pairs.
+void group_nets(const pic_run_desc* runs, int n_runs, std::vector<int>* net_of,
+                std::vector<int>* first) {
+  net_of->assign(n_runs, -1);
+  first->clear();
+  for (int r = 0; r < n_runs; ++r) {
+    for (size_t g = 0; g < first->size(); ++g) {
+      const pic_run_desc& d = runs[(*first)[g]];
+      if (d.dx == runs[r].dx && d.dy == runs[r].dy && d.cfl == runs[r].cfl &&
+          d.theta == runs[r].theta) {
+        (*net_of)[r] = (int)g;
+        break;
+      }
+    }
+    if ((*net_of)[r] < 0) {
+      (*net_of)[r] = (int)first->size();
+      first->push_back(r);
+    }
+  }
+}
+
 // Carve (or, with base == nullptr, size) the workspace.
 template <typename R>
 size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_runs, bool fast,
-             bool split, bool ids, int hist_cap, int pair_slots, long long train_cells,
-             long long inj_cap, pic_ctx* c, DevState<R>* st) {
+             bool split, bool ids, int hist_cap, int pair_slots,
+             const std::vector<long long>& net_cells, long long inj_cap, pic_ctx* c,
+             DevState<R>* st) {
   Bump b(base);
   const int K = pl.tile_split;
   const long long nc = tl.n_cells;
@@ -272,28 +291,41 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   int* g_active = b.take<int>(4);
   unsigned* bar = b.take<unsigned>(64);
   double* stats = b.take<double>((size_t)n_runs * PIC_STAT_WORDS);
-  NetTrain nt{};
-  double* pairs = nullptr;
-  if (pair_slots > 0) {
-    const size_t n1 = (size_t)train_cells, nC = n1 * NET_C;
-    nt.w = b.take<float>(NET_NW);
-    nt.w2b = b.take<__bf16>(NET_C * NET_C * 9);
-    nt.k49 = b.take<double>(64);
-    nt.grad = b.take<float>(NET_NW);
-    nt.m = b.take<float>(NET_NW);
-    nt.v = b.take<float>(NET_NW);
-    nt.part = b.take<float>((size_t)kWgradBlocks * NET_C * NET_C * 9);
-    nt.xin = b.take<float>(n1);
-    nt.y = b.take<float>(n1);
-    nt.gy = b.take<float>(n1);
-    nt.h1 = b.take<float>(nC);
-    nt.h2 = b.take<float>(nC);
-    nt.gh1 = b.take<float>(nC);
-    nt.gh2 = b.take<float>(nC);
-    nt.dpart = b.take<double>(512);
-    nt.scal = b.take<double>(4);
-    nt.wg_blocks = kWgradBlocks;
-    pairs = b.take<double>((size_t)pair_slots * 6 * n1);
+  // learned solver: per network the FP32 weights, their BF16 copy and
+  // collapsed filter, Adam state and a ring of (b, dB) pairs; the training
+  // activations are shared, sized for the largest network's first run
+  const int n_nets = pair_slots > 0 ? (int)net_cells.size() : 0;
+  std::vector<NetTrain> nets(n_nets);
+  std::vector<double*> net_pairs(n_nets, nullptr);
+  NetWeights* d_nets = nullptr;
+  if (n_nets > 0) {
+    d_nets = b.take<NetWeights>(n_nets);
+    long long n1 = 0;
+    for (long long v : net_cells) n1 = std::max(n1, v);
+    NetTrain sh{};
+    const size_t nC = (size_t)n1 * NET_C;
+    sh.part = b.take<float>((size_t)kWgradBlocks * NET_C * NET_C * 9);
+    sh.xin = b.take<float>(n1);
+    sh.y = b.take<float>(n1);
+    sh.gy = b.take<float>(n1);
+    sh.h1 = b.take<float>(nC);
+    sh.h2 = b.take<float>(nC);
+    sh.gh1 = b.take<float>(nC);
+    sh.gh2 = b.take<float>(nC);
+    sh.dpart = b.take<double>(512);
+    sh.scal = b.take<double>(4);
+    sh.wg_blocks = kWgradBlocks;
+    for (int g = 0; g < n_nets; ++g) {
+      NetTrain nt = sh;
+      nt.w = b.take<float>(NET_NW);
+      nt.w2b = b.take<__bf16>(NET_C * NET_C * 9);
+      nt.k49 = b.take<double>(64);
+      nt.grad = b.take<float>(NET_NW);
+      nt.m = b.take<float>(NET_NW);
+      nt.v = b.take<float>(NET_NW);
+      nets[g] = nt;
+      net_pairs[g] = b.take<double>((size_t)pair_slots * 6 * net_cells[g]);
+    }
   }
   double* history = b.take<double>((size_t)n_runs * hist_cap * PIC_REC_WORDS);
   int* err = b.take<int>(1);
@@ -404,10 +436,10 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   f.K = K;
   f.history = history;
   f.hist_cap = hist_cap;
-  f.net = NetWeights{nt.w, nt.w2b, nt.k49};
-  f.pairs = pairs;
-  c->net = nt;
-  c->d_pairs = pairs;
+  f.nets = d_nets;
+  c->nets = nets;
+  c->net_pairs = net_pairs;
+  c->d_nets = d_nets;
   c->d_runs = d_runs;
   c->d_tile_run = tile_run;
   c->d_stats = stats;
@@ -491,7 +523,12 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   const bool split = true;
   const bool ids = o->track_ids != 0;
   const int slots = pair_slots_of(o);
-  const long long tc = (long long)runs[0].nx * runs[0].ny;
+  std::vector<long long> tc;
+  if (slots > 0) {
+    std::vector<int> net_of, first;
+    group_nets(runs, n_runs, &net_of, &first);
+    for (int r : first) tc.push_back((long long)runs[r].nx * runs[r].ny);
+  }
   const long long ic = inject_cap_of(runs, n_runs);
   p.workspace_bytes = fast ? carve<float>(nullptr, *tl, p, n_runs, true, split, ids, hist_cap,
                                           slots, tc, ic, nullptr, (DevState<float>*)nullptr)
@@ -1063,16 +1100,23 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   c->fast = opt->precision == PIC_FP32_FAST;
   c->ids = opt->track_ids != 0;
   c->pair_slots = pair_slots_of(opt);
-  c->train_cells = (long long)runs[0].nx * runs[0].ny;
   c->learned = c->pair_slots > 0;
+  std::vector<long long> net_cells;
+  if (c->learned) {
+    group_nets(runs, n_runs, &c->net_of_run, &c->net_first_run);
+    for (int r : c->net_first_run) {
+      net_cells.push_back((long long)runs[r].nx * runs[r].ny);
+      c->train_cells = std::max(c->train_cells, net_cells.back());
+    }
+  }
   c->use_learned = c->learned;
   const long long ic = inject_cap_of(runs, n_runs);
   if (c->fast)
     carve<float>(c->ws, c->tl, c->plan, n_runs, true, c->split, c->ids, c->opt.history_cap,
-                 c->pair_slots, c->train_cells, ic, c, &c->sf);
+                 c->pair_slots, net_cells, ic, c, &c->sf);
   else
     carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap,
-                  c->pair_slots, c->train_cells, ic, c, &c->sd);
+                  c->pair_slots, net_cells, ic, c, &c->sd);
   c->next_id.assign(n_runs, std::array<long long, PIC_MAXS>{0, 0});
   c->fa.learned_form = opt->learned_form;
   c->fa.coop = 1;
@@ -1118,6 +1162,10 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     h.theta = d.theta;
     h.cg_rtol = d.cg_rtol;
     h.cg_maxit = d.cg_maxit;
+    if (c->learned) {
+      h.net_id = c->net_of_run[r];
+      if (c->net_first_run[h.net_id] == r) h.pairs = c->net_pairs[h.net_id];
+    }
     for (int s = 0; s < d.n_species; ++s) {
       h.q[s] = d.species[s].q;
       h.m[s] = d.species[s].m;
@@ -1136,9 +1184,18 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     e = hipMemcpyAsync(c->d_tile_run, tile_run.data(), sizeof(int) * tile_run.size(),
                        hipMemcpyHostToDevice, S);
   if (e == hipSuccess && c->learned) {
-    const std::vector<float> w0 = initial_weights();
-    e = hipMemcpyAsync(c->net.w, w0.data(), w0.size() * sizeof(float), hipMemcpyHostToDevice, S);
-    if (e == hipSuccess) e = pic_net_refresh(c->net, S);
+    const std::vector<float> w0 = initial_weights();   // copies complete before the sync below
+    std::vector<NetWeights> hn;
+    for (auto& nt : c->nets) {
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(nt.w, w0.data(), w0.size() * sizeof(float), hipMemcpyHostToDevice, S);
+      if (e == hipSuccess) e = pic_net_refresh(nt, S);
+      hn.push_back(NetWeights{nt.w, nt.w2b, nt.k49});
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c->d_nets, hn.data(), hn.size() * sizeof(NetWeights),
+                         hipMemcpyHostToDevice, S);
+    if (e == hipSuccess) e = hipStreamSynchronize(S);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(S);
   if (e != hipSuccess) {
@@ -1461,37 +1518,45 @@ int32_t pic_precond_train(pic_ctx* c, const pic_train_opts* o, pic_train_stats* 
   const long long have = std::min<long long>(c->pairs_written, c->pair_slots);
   if (have < 1) return fail(c, PIC_E_STATE, "no training pairs recorded");
   const float lr = (float)(o->lr > 0 ? o->lr : 1e-3);
-  const long long n1 = c->train_cells;
-  const pic_run_desc& d = c->runs[0];
   hipStream_t S = c->stream;
   const long long oldest = c->pairs_written - have;
+  const int n_nets = (int)c->nets.size();
   double first = 0, last = 0;
   int updates = 0;
   for (int ep = 0; ep < o->epochs; ++ep) {
-    HIPCHK(c, hipMemsetAsync(c->net.scal, 0, 4 * sizeof(double), S));
-    for (long long k = oldest; k < c->pairs_written; ++k) {
-      const double* pb = c->d_pairs + (size_t)(k % c->pair_slots) * 6 * n1;
-      for (int comp = 0; comp < 3; ++comp) {
-        HIPCHK(c, pic_net_grad(c->net, pb + (size_t)(2 * comp) * n1, pb + (size_t)(2 * comp + 1) * n1,
-                               d.nx, d.ny, S));
-        HIPCHK(c, pic_net_adam(c->net, lr, ++c->adam_step, S));
-        ++updates;
+    double sum = 0;
+    // each network on the pairs of its first run, oldest pair first
+    for (int g = 0; g < n_nets; ++g) {
+      const NetTrain& T = c->nets[g];
+      const pic_run_desc& d = c->runs[c->net_first_run[g]];
+      const long long n1 = (long long)d.nx * d.ny;
+      HIPCHK(c, hipMemsetAsync(T.scal, 0, 4 * sizeof(double), S));
+      for (long long k = oldest; k < c->pairs_written; ++k) {
+        const double* pb = c->net_pairs[g] + (size_t)(k % c->pair_slots) * 6 * n1;
+        for (int comp = 0; comp < 3; ++comp) {
+          HIPCHK(c, pic_net_grad(T, pb + (size_t)(2 * comp) * n1, pb + (size_t)(2 * comp + 1) * n1,
+                                 d.nx, d.ny, S));
+          HIPCHK(c, pic_net_adam(T, lr, ++c->adam_step, S));
+          ++updates;
+        }
       }
+      double scal[4];
+      HIPCHK(c, hipMemcpyAsync(scal, T.scal, sizeof scal, hipMemcpyDeviceToHost, S));
+      HIPCHK(c, hipStreamSynchronize(S));
+      sum += scal[2];
     }
-    double scal[4];
-    HIPCHK(c, hipMemcpyAsync(scal, c->net.scal, sizeof scal, hipMemcpyDeviceToHost, S));
-    HIPCHK(c, hipStreamSynchronize(S));
-    const double mean = scal[2] / (double)(have * 3);
+    const double mean = sum / (double)(have * 3 * n_nets);
     if (ep == 0) first = mean;
     last = mean;
   }
-  HIPCHK(c, pic_net_refresh(c->net, S));
+  for (auto& T : c->nets) HIPCHK(c, pic_net_refresh(T, S));
   HIPCHK(c, hipStreamSynchronize(S));
   if (out) {
     out->loss_first = first;
     out->loss_last = last;
-    out->samples = (int32_t)(have * 3);
+    out->samples = (int32_t)(have * 3 * n_nets);
     out->updates = updates;
+    out->networks = n_nets;
   }
   if (!std::isfinite(last)) return fail(c, PIC_E_NAN, "non-finite training loss");
   return PIC_OK;
@@ -1500,8 +1565,11 @@ int32_t pic_precond_train(pic_ctx* c, const pic_train_opts* o, pic_train_stats* 
 int32_t pic_precond_get_weights(pic_ctx* c, float* host, size_t n) {
   if (!c || !host) return PIC_E_INVAL;
   if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
-  if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "weight count must be 9792");
-  HIPCHK(c, hipMemcpyAsync(host, c->net.w, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  if (n != (size_t)NET_NW * c->nets.size())
+    return fail(c, PIC_E_INVAL, "weight count must be 9792 per network");
+  for (size_t g = 0; g < c->nets.size(); ++g)
+    HIPCHK(c, hipMemcpyAsync(host + g * NET_NW, c->nets[g].w, NET_NW * sizeof(float),
+                             hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PIC_OK;
 }
@@ -1509,11 +1577,15 @@ int32_t pic_precond_get_weights(pic_ctx* c, float* host, size_t n) {
 int32_t pic_precond_set_weights(pic_ctx* c, const float* host, size_t n) {
   if (!c || !host) return PIC_E_INVAL;
   if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
-  if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "weight count must be 9792");
+  if (n != (size_t)NET_NW * c->nets.size())
+    return fail(c, PIC_E_INVAL, "weight count must be 9792 per network");
   for (size_t k = 0; k < n; ++k)
     if (!std::isfinite(host[k])) return fail(c, PIC_E_INVAL, "non-finite weight");
-  HIPCHK(c, hipMemcpyAsync(c->net.w, host, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(c, pic_net_refresh(c->net, c->stream));
+  for (size_t g = 0; g < c->nets.size(); ++g) {
+    HIPCHK(c, hipMemcpyAsync(c->nets[g].w, host + g * NET_NW, NET_NW * sizeof(float),
+                             hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, pic_net_refresh(c->nets[g], c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PIC_OK;
 }
@@ -1525,8 +1597,8 @@ int32_t pic_precond_apply(pic_ctx* c, int32_t form, int32_t nx, int32_t ny, cons
   if (form != PIC_NET_COLLAPSED && form != PIC_NET_MFMA)
     return fail(c, PIC_E_INVAL, "form must be PIC_NET_COLLAPSED or PIC_NET_MFMA");
   if (nx < 3 || ny < 3 || (long long)nx * ny > c->train_cells)
-    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= run 0's cells");
-  HIPCHK(c, pic_net_apply(c->net, form, d_in, d_out, nx, ny, c->stream));
+    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= the largest first run's cells");
+  HIPCHK(c, pic_net_apply(c->nets[0], form, d_in, d_out, nx, ny, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PIC_OK;
 }
@@ -1537,12 +1609,13 @@ int32_t pic_precond_grad(pic_ctx* c, int32_t nx, int32_t ny, const double* d_b, 
   if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
   if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "gradient count must be 9792");
   if (nx < 3 || ny < 3 || (long long)nx * ny > c->train_cells)
-    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= run 0's cells");
-  HIPCHK(c, hipMemsetAsync(c->net.scal, 0, 4 * sizeof(double), c->stream));
-  HIPCHK(c, pic_net_grad(c->net, d_b, d_t, nx, ny, c->stream));
+    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= the largest first run's cells");
+  const NetTrain& T = c->nets[0];
+  HIPCHK(c, hipMemsetAsync(T.scal, 0, 4 * sizeof(double), c->stream));
+  HIPCHK(c, pic_net_grad(T, d_b, d_t, nx, ny, c->stream));
   double scal[4];
-  HIPCHK(c, hipMemcpyAsync(scal, c->net.scal, sizeof scal, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(host_grad, c->net.grad, n * sizeof(float), hipMemcpyDeviceToHost,
+  HIPCHK(c, hipMemcpyAsync(scal, T.scal, sizeof scal, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(host_grad, T.grad, n * sizeof(float), hipMemcpyDeviceToHost,
                            c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (loss) *loss = scal[1];

@@ -224,6 +224,8 @@ k_field_solve(FieldArgs a) {
   // z = N(v) over every tile of every active component, items spread over the
   // run's blocks: rd(c, i, j) gives the input at any cell, wr(c, i, j, z) sees
   // each output of the run's own cells
+  // this run's network (runs that share an operator share it)
+  const NetWeights net = kMode != 0 ? a.nets[R.net_id] : NetWeights{};
   constexpr bool collapsed = kMode == 1;
   constexpr int TE = collapsed ? NET_KT : NET_T;
   const int ntx = (R.nx + TE - 1) / TE, nty = (R.ny + TE - 1) / TE;
@@ -231,7 +233,7 @@ k_field_solve(FieldArgs a) {
     if constexpr (collapsed) {
       // one item = one tile, all three components
       for (int t = lb; t < ntx * nty; t += nb)
-        net_apply_tile_collapsed<3>(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, act, rd,
+        net_apply_tile_collapsed<3>(net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, act, rd,
                                     wr, net_lds);
     } else {
       for (int item = lb; item < ntx * nty * 3; item += nb) {
@@ -239,7 +241,7 @@ k_field_solve(FieldArgs a) {
         if (!act[c]) continue;
         auto rd_c = [&](int i, int j) { return rd(c, i, j); };
         auto wr_c = [&](int i, int j, double v) { wr(c, i, j, v); };
-        net_apply_tile(a.net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c, net_lds);
+        net_apply_tile(net, (t % ntx) * TE, (t / ntx) * TE, R.nx, R.ny, rd_c, wr_c, net_lds);
       }
     }
   };
@@ -610,10 +612,11 @@ k_field_solve(FieldArgs a) {
     }
   }
 
-  // ---- training pairs (b, dB) of run 0, recorded after the solve; the
-  // right-hand side is recomputed from E^n, B^n, J (r1 may be overwritten)
-  if (a.collect && run == 0) {
-    double* const pb = a.pairs + (size_t)a.pair_slot * 6 * ncell;
+  // ---- training pairs (b, dB) of each network's first run, recorded after
+  // the solve; the right-hand side is recomputed from E^n, B^n, J (r1 may be
+  // overwritten)
+  if (a.collect && R.pairs) {
+    double* const pb = R.pairs + (size_t)a.pair_slot * 6 * ncell;
     for (int k = first; k < ncell; k += stride) {
       const int j = k / R.nx, i = k - j * R.nx;
       double cj[3], ce[3];

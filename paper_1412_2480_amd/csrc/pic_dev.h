@@ -33,6 +33,8 @@ struct DevRun {
   double cg_rtol;
   double dx, dy, dt, theta;
   double q[PIC_MAXS], m[PIC_MAXS];
+  int net_id;         // learned solver: network of this run's operator
+  double* pairs;      // learned solver: (b, dB) ring of the network, in its first run only
 };
 
 template <typename R>

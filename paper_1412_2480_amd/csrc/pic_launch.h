@@ -39,10 +39,9 @@ struct FieldArgs {
   int learned;             // x0 = N(b) and flexible CG preconditioned by N
   int learned_form;        // 0: collapsed 7 x 7 filter (FP64), 1: BF16 network
   int learned_maxit;       // iteration budget of the learned solver
-  NetWeights net;
-  int collect;             // record (b, dB) of run 0 into pairs[pair_slot]
-  double* pairs;           // [slot][component][b | dB][ncell of run 0]
-  int pair_slot;
+  const NetWeights* nets;  // one network per distinct operator (DevRun::net_id)
+  int collect;             // record (b, dB) of each network's first run into its ring
+  int pair_slot;           // ring slot: pairs + pair_slot * 6 * ncell, [component][b | dB]
   int coop;                // 1: cooperative launch; 0: ordinary launch (graph capture)
   int any_shock;           // some run has shock walls (selects the kernel variant)
 };

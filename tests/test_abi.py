@@ -73,11 +73,13 @@ def test_plan_learned_solver():
     lrn = pic.plan([_run()], pic.make_options("fp32", solver="learned", precond_slots=4))
     # network, training activations (4 x 32 channels) and 4 pairs of 6 fields
     assert lrn.workspace_bytes >= base.workspace_bytes + 64 * 64 * (4 * 32 * 4 + 4 * 6 * 8)
-    # one network approximates one operator: runs must share dx, dy, cfl, theta
-    with pytest.raises(pic.PicError) as ei:
-        pic.plan([_run(), _run(theta=0.5)], pic.make_options("fp32", solver="learned"))
-    assert ei.value.code == -1
-    pic.plan([_run(), _run(order=3, nx=32)], pic.make_options("fp32", solver="learned"))
+    # one network per distinct operator (dx, dy, cfl, theta): a second theta
+    # adds a second network with its own pairs ring; a second order does not
+    one = pic.plan([_run(), _run(order=3, nx=32)],
+                   pic.make_options("fp32", solver="learned", precond_slots=4))
+    two = pic.plan([_run(), _run(theta=0.5, nx=32)],
+                   pic.make_options("fp32", solver="learned", precond_slots=4))
+    assert two.workspace_bytes >= one.workspace_bytes + 32 * 64 * 4 * 6 * 8 + 9792 * 4 * 4
     o = pic.make_options("fp32", solver="learned")
     o.learned_form = 7
     with pytest.raises(pic.PicError):

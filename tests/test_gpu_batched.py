@@ -80,3 +80,52 @@ def test_sweep_table_runs_in_one_context():
         d = sim.diag(r)
         assert d["n_particles"][:2] == [counts[r], counts[r]]
     sim.close()
+
+
+def test_batched_learned_solver_one_network_per_operator():
+    """The learned aid in a batched context whose runs use four operators
+    (dx, dy, cfl, theta): one network each, trained on the pairs of the
+    operator's first run (the fifth run shares the second run's network).
+    After training every run reaches the plain-CG residual without the
+    fallback, in fewer iterations over the batch, and its fields agree with
+    plain CG's to the solver tolerance."""
+    import paper_1412_2480_amd as pic
+    _say("batched learned solver, four operators")
+    specs = CASES + [dict(nx=48, ny=40, order=2, ppc=3, cfl=1.0, theta=0.6, seed=5)]
+    cases = [Case(c["nx"], c["ny"], c["order"], c["ppc"], gamma0=20.0, T=0.01, cfl=c["cfl"],
+                  theta=c["theta"], seed=c["seed"], rtol=1e-8) for c in specs]
+    descs = [c.run_desc() for c in cases]
+    a = pic.Sim(descs, pic.make_options("fp64", tile=(16, 16)))
+    b = pic.Sim(descs, pic.make_options("fp64", tile=(16, 16), solver="learned",
+                                        precond_slots=8))
+    for r, c in enumerate(cases):
+        c.load_into(a, run=r)
+        c.load_into(b, run=r)
+    b.precond_use(False)
+    b.precond_collect(True)
+    a.step(8)
+    b.step(8)
+    assert b.precond_collect(False) == 8
+    tr = b.precond_train(epochs=20)
+    _say(f"  training: {tr}")
+    assert tr["networks"] == 4 and tr["samples"] == 8 * 3 * 4
+    assert tr["loss_last"] < 0.1 * tr["loss_first"]
+    w = b.get_weights(networks=4).reshape(4, -1)
+    assert all(not np.array_equal(w[0], w[g]) for g in range(1, 4))
+    b.precond_use(True)
+    it_a = it_b = 0
+    for step in range(6):
+        sa = a.step(1)
+        sb = b.step(1)
+        for r in range(len(cases)):
+            assert sb[r]["fallback"] == 0 and max(sb[r]["relres"]) <= 1e-8, (step, r)
+            it_a += sum(sa[r]["iters"])
+            it_b += sum(sb[r]["iters"])
+    _say(f"  CG iterations over 6 steps: plain {it_a}, learned {it_b}")
+    assert it_b < it_a
+    for r in range(len(cases)):
+        for n in NAMES[:6]:
+            e = relerr(b.get_field(r, n), a.get_field(r, n))
+            assert e <= 1e-6, (r, n, e)
+    a.close()
+    b.close()
