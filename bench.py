@@ -152,7 +152,7 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
                 train=train)
 
 
-def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
+def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learned_epochs=50):
     """The 48-run sweep table in one context (FP32 particles) against the same
     runs launched one context at a time; aggregate particle-steps/s."""
     from synth import configs, loads
@@ -169,19 +169,56 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
             sim.load_plasma(r, s, t["ppc"], t["gamma0"], t["T"], t["seed"])
     n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
     opts = pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH)
+
+    def timed(sim):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = sim.step_async(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if rc != 0:
+            raise RuntimeError(f"batched pic_step returned {pic.STATUS.get(rc, rc)}")
+        return ms, sim.step(0)
+
     sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH,
                                           tile_split=8))
     for r, t in enumerate(table):
         load_run(sim, r, t)
     sim.step(warmup)
     tuned = sim.tune(2)     # work-groups per tile and field-solve work-groups of this mix
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    rc = sim.step_async(steps)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    if rc != 0:
-        raise RuntimeError(f"batched pic_step returned {pic.STATUS.get(rc, rc)}")
+    ms, st = timed(sim)
+    cg_iters = sum(sum(s["iters"]) for s in st)
+    sim.close()
+    learned = None
+    if learned_pairs > 0:
+        # the learned aid: one network per distinct (cfl, theta) of the table,
+        # trained on the pairs of that operator's first run
+        sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False,
+                                              graph=GRAPH, tile_split=tuned["tile_split"],
+                                              cg_blocks=tuned["cg_blocks"], solver="learned",
+                                              precond_slots=learned_pairs))
+        for r, t in enumerate(table):
+            load_run(sim, r, t)
+        sim.precond_use(False)
+        sim.precond_collect(True)
+        sim.step(learned_pairs)
+        sim.precond_collect(False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = sim.precond_train(learned_epochs, 0.0)
+        train_s = time.perf_counter() - t0
+        sim.precond_use(True)
+        retuned = sim.tune(2, splits=(tuned["tile_split"],))
+        sim.step(warmup)
+        lms, lst = timed(sim)
+        sim.close()
+        learned = dict(ms_per_step=lms, particle_steps_per_s=n_part / (lms * 1e-3),
+                       networks=tr["networks"], train_seconds=train_s,
+                       loss_first=tr["loss_first"], loss_last=tr["loss_last"],
+                       cg_blocks=retuned["cg_blocks"],
+                       cg_iters_last_step=sum(sum(s["iters"]) for s in lst),
+                       fallbacks_last_step=sum(s["fallback"] for s in lst),
+                       max_relres=max(max(s["relres"]) for s in lst))
     sim.close()
     seq_ms = 0.0
     for r, t in enumerate(table):
@@ -196,8 +233,8 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3):
         one.close()
     return dict(runs=len(table), particles=n_part, ms_per_step=ms,
                 tile_split=tuned["tile_split"], cg_blocks=tuned["cg_blocks"],
-                particle_steps_per_s=n_part / (ms * 1e-3), sequential_ms_per_step=seq_ms,
-                batched_speedup=seq_ms / ms)
+                particle_steps_per_s=n_part / (ms * 1e-3), cg_iters_last_step=cg_iters,
+                sequential_ms_per_step=seq_ms, batched_speedup=seq_ms / ms, learned=learned)
 
 
 NET_FLOP_PER_CELL = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)   # three 3x3 layers, 1->32->32->1
@@ -323,7 +360,7 @@ def main():
     ap.add_argument("--graph", action="store_true",
                     help="replay captured two-step HIP graphs in every timed form")
     ap.add_argument("--train-pairs", type=int, default=8)
-    ap.add_argument("--train-epochs", type=int, default=25)
+    ap.add_argument("--train-epochs", type=int, default=50)
     ap.add_argument("--also-mfma", action="store_true",
                     help="also time the FP32 form with the BF16 matrix-core network")
     ap.add_argument("--calib-copy", action="store_true",
@@ -437,6 +474,12 @@ def main():
         batched = batched_sweep(pic, torch, 20, 3)
         log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs, "
             f"sequential {batched['sequential_ms_per_step']:.3f} ms")
+        if batched["learned"]:
+            bl = batched["learned"]
+            log(f"bench: batched learned {bl['ms_per_step']:.3f} ms/step "
+                f"({bl['networks']} networks, trained in {bl['train_seconds']:.2f} s), "
+                f"CG iterations per step {batched['cg_iters_last_step']} -> "
+                f"{bl['cg_iters_last_step']}")
 
     large = None
     if not args.no_large:

@@ -271,6 +271,8 @@ int32_t pic_get_timing(pic_ctx* ctx, pic_timing_out* out);
 typedef struct pic_train_opts {
   int32_t epochs;        /* passes over the recorded pairs (>= 1) */
   double lr;             /* Adam step size; <= 0 picks 1e-3 */
+  int32_t crop;          /* cells per side of the training window: 0 picks 64,
+                            < 0 trains on whole fields, at most 128 */
 } pic_train_opts;
 
 typedef struct pic_train_stats {
@@ -288,7 +290,12 @@ int32_t pic_precond_collect(pic_ctx* ctx, int32_t on, int32_t* n_pairs);
 
 /* Train every network on its recorded pairs: per epoch one Adam update per
  * (pair, component) sample, oldest pair first, all in FP32 on the device;
- * then refresh the BF16 copies and collapsed filters. Synchronises. */
+ * then refresh the BF16 copies and collapsed filters. Each update sees one
+ * crop x crop window of the sample (its corner a fixed hash of the update
+ * count, the periodic field wrapped), with the loss on the window's cells
+ * only; the network's 7 x 7 reach is inside the window plus a 3-cell halo,
+ * so this is the exact loss of those cells. A window at least as large as the
+ * field in both directions means the whole field. Synchronises. */
 int32_t pic_precond_train(pic_ctx* ctx, const pic_train_opts* opts, pic_train_stats* out);
 
 /* Use the learned path in the following field solves (on != 0, the default
@@ -304,13 +311,17 @@ int32_t pic_precond_set_weights(pic_ctx* ctx, const float* host, size_t n);
 /* For parity checks. apply: d_out = N(d_in) on one nx x ny periodic FP64
  * device field ([ny][nx]) in the given form (PIC_NET_COLLAPSED or
  * PIC_NET_MFMA). grad: FP32 loss and weight gradient of one sample (d_b, d_t
- * device FP64 fields), host_grad receiving n = 9792 floats. Both use the
- * first network (that of run 0), need nx, ny >= 3 and nx * ny no larger than
- * the largest first run's cell count, and synchronise. */
+ * device FP64 fields), host_grad receiving n = 9792 floats; window (nullable)
+ * = {ox, oy, cx, cy} restricts it to the cx x cy cells from corner (ox, oy),
+ * as training does (0 <= ox < nx, 0 <= oy < ny, 1 <= cx <= min(nx, 128),
+ * 1 <= cy <= min(ny, 128)). Both use the first network (that of run 0), need
+ * nx, ny >= 3 and, for whole fields, nx * ny no larger than the largest first
+ * run's cell count, and synchronise. */
 int32_t pic_precond_apply(pic_ctx* ctx, int32_t form, int32_t nx, int32_t ny, const double* d_in,
                           double* d_out);
 int32_t pic_precond_grad(pic_ctx* ctx, int32_t nx, int32_t ny, const double* d_b,
-                         const double* d_t, float* host_grad, size_t n, double* loss);
+                         const double* d_t, const int32_t* window, float* host_grad, size_t n,
+                         double* loss);
 
 /* ---- Autotuning of the launch schedule on a live context (the runs advance
  * by the timed steps). Work-groups per tile of the particle kernel and

@@ -13,7 +13,9 @@ Network: three 3x3 convolutions with periodic padding and no activation,
 Eq. (7), dB = A^{-1} b, is linear in b, so a linear network keeps the
 preconditioner a fixed linear operator.
 
-Loss for one sample (b, t): L = sum (N(b) - t)^2 / sum t^2.
+Loss for one sample (b, t): L = sum (N(b) - t)^2 / sum t^2, over the whole
+field or over a window of its cells (the network still acts on the whole
+periodic field; only the sums are restricted).
 """
 import numpy as np
 
@@ -74,10 +76,23 @@ def forward(W, b):
     return y[0], (x, h1, h2)
 
 
-def loss_and_grad(W, b, t):
+def window_mask(shape, window):
+    """1 on the cx x cy cells from corner (ox, oy) of a periodic [ny][nx]
+    field, 0 elsewhere; window None means every cell."""
+    if window is None:
+        return np.ones(shape)
+    ox, oy, cx, cy = window
+    ny, nx = shape
+    m = np.zeros(shape)
+    m[np.ix_((oy + np.arange(cy)) % ny, (ox + np.arange(cx)) % nx)] = 1.0
+    return m
+
+
+def loss_and_grad(W, b, t, window=None):
+    m = window_mask(b.shape, window)
     y, (x, h1, h2) = forward(W, b)
-    tt = float(np.sum(t * t))
-    r = y - t
+    tt = float(np.sum(m * t * t))
+    r = (y - t) * m
     L = float(np.sum(r * r)) / tt
     gy = (2.0 / tt) * r[None]
     g3 = conv_wgrad(h2, gy)
@@ -88,6 +103,7 @@ def loss_and_grad(W, b, t):
     return L, [g1, g2, g3]
 
 
-def loss(W, b, t):
+def loss(W, b, t, window=None):
+    m = window_mask(b.shape, window)
     y, _ = forward(W, b)
-    return float(np.sum((y - t) ** 2)) / float(np.sum(t * t))
+    return float(np.sum(m * (y - t) ** 2)) / float(np.sum(m * t * t))

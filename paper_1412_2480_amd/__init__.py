@@ -76,7 +76,7 @@ class SolveStats(ctypes.Structure):
 
 
 class TrainOpts(ctypes.Structure):
-    _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_double)]
+    _fields_ = [("epochs", ctypes.c_int32), ("lr", ctypes.c_double), ("crop", ctypes.c_int32)]
 
 
 class TrainStats(ctypes.Structure):
@@ -164,8 +164,8 @@ def lib():
         L.pic_precond_apply.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
         L.pic_precond_grad.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
-                                       ctypes.c_size_t, P(ctypes.c_double)]
+                                       ctypes.c_void_p, ctypes.c_void_p, P(ctypes.c_int32),
+                                       ctypes.c_void_p, ctypes.c_size_t, P(ctypes.c_double)]
         L.pic_tune.argtypes = [ctypes.c_void_p, P(TuneOpts), P(TuneOut)]
         L.pic_sync.argtypes = [ctypes.c_void_p]
         L.pic_destroy.argtypes = [ctypes.c_void_p]
@@ -391,9 +391,9 @@ class Sim:
                     "precond_collect")
         return n.value
 
-    def precond_train(self, epochs=1, lr=0.0):
+    def precond_train(self, epochs=1, lr=0.0, crop=0):
         o = TrainOpts()
-        o.epochs, o.lr = int(epochs), float(lr)
+        o.epochs, o.lr, o.crop = int(epochs), float(lr), int(crop)
         st = TrainStats()
         self._check(self.L.pic_precond_train(self.ctx, ctypes.byref(o), ctypes.byref(st)),
                     "precond_train")
@@ -427,16 +427,18 @@ class Sim:
                                              ctypes.c_void_p(yd.data_ptr())), "precond_apply")
         return yd.cpu().numpy()
 
-    def precond_grad(self, b, t):
-        """(loss, dL/dW) of one sample, L = sum (N(b) - t)^2 / sum t^2."""
+    def precond_grad(self, b, t, window=None):
+        """(loss, dL/dW) of one sample, L = sum (N(b) - t)^2 / sum t^2 over the
+        field or over the window (ox, oy, cx, cy) of it."""
         bd, td = self._device_field(b), self._device_field(t)
         ny, nx = bd.shape
         g = np.empty(NET_NW, np.float32)
         loss = ctypes.c_double(0.0)
+        win = None if window is None else (ctypes.c_int32 * 4)(*[int(v) for v in window])
         self.stream.synchronize()
         self._check(self.L.pic_precond_grad(self.ctx, nx, ny, ctypes.c_void_p(bd.data_ptr()),
-                                            ctypes.c_void_p(td.data_ptr()), _ptr(g), NET_NW,
-                                            ctypes.byref(loss)), "precond_grad")
+                                            ctypes.c_void_p(td.data_ptr()), win, _ptr(g),
+                                            NET_NW, ctypes.byref(loss)), "precond_grad")
         return loss.value, g
 
     def tune(self, steps=3, splits=(), cg_blocks=()):

@@ -25,6 +25,8 @@ constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kTimingClasses = 8;
 constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
+constexpr int kDefaultTrainCrop = 64;  // training window (cells per side) by default
+constexpr int kMaxTrainCrop = 128;     // largest training window per side
 constexpr int kDefaultLearnedMaxit = 30;
 constexpr int kDefaultPrecondSlots = 16;
 constexpr double kTuneTie = 0.02;     // autotuner: relative margin treated as a tie
@@ -300,7 +302,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   NetWeights* d_nets = nullptr;
   if (n_nets > 0) {
     d_nets = b.take<NetWeights>(n_nets);
-    long long n1 = 0;
+    long long n1 = (long long)(kMaxTrainCrop + 6) * (kMaxTrainCrop + 6);
     for (long long v : net_cells) n1 = std::max(n1, v);
     NetTrain sh{};
     const size_t nC = (size_t)n1 * NET_C;
@@ -308,6 +310,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     sh.xin = b.take<float>(n1);
     sh.y = b.take<float>(n1);
     sh.gy = b.take<float>(n1);
+    sh.tc = b.take<double>(n1);
     sh.h1 = b.take<float>(nC);
     sh.h2 = b.take<float>(nC);
     sh.gh1 = b.take<float>(nC);
@@ -1064,6 +1067,17 @@ std::vector<float> initial_weights() {
   return w;
 }
 
+// Corner of the training window of Adam update k: a splitmix64 hash of k
+// mapped onto the field.
+void crop_corner(long long k, int nx, int ny, int* ox, int* oy) {
+  uint64_t x = 0x9E3779B97F4A7C15ULL * (uint64_t)(k + 1);
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBULL;
+  x ^= x >> 31;
+  *ox = (int)((x & 0xFFFFFFFFULL) % (uint64_t)nx);
+  *oy = (int)((x >> 32) % (uint64_t)ny);
+}
+
 }  // namespace
 
 extern "C" {
@@ -1515,6 +1529,8 @@ int32_t pic_precond_train(pic_ctx* c, const pic_train_opts* o, pic_train_stats* 
   if (!c || !o) return PIC_E_INVAL;
   if (!c->learned) return fail(c, PIC_E_STATE, "training needs solver PIC_SOLVER_LEARNED_PCG");
   if (o->epochs < 1) return fail(c, PIC_E_INVAL, "epochs must be >= 1");
+  if (o->crop > kMaxTrainCrop) return fail(c, PIC_E_INVAL, "crop must be <= 128");
+  const int crop = o->crop == 0 ? kDefaultTrainCrop : o->crop;
   const long long have = std::min<long long>(c->pairs_written, c->pair_slots);
   if (have < 1) return fail(c, PIC_E_STATE, "no training pairs recorded");
   const float lr = (float)(o->lr > 0 ? o->lr : 1e-3);
@@ -1531,11 +1547,16 @@ int32_t pic_precond_train(pic_ctx* c, const pic_train_opts* o, pic_train_stats* 
       const pic_run_desc& d = c->runs[c->net_first_run[g]];
       const long long n1 = (long long)d.nx * d.ny;
       HIPCHK(c, hipMemsetAsync(T.scal, 0, 4 * sizeof(double), S));
+      // a window, unless it would cover the whole field
+      const bool whole = crop < 0 || (crop >= d.nx && crop >= d.ny);
+      const int cx = whole ? 0 : std::min(crop, d.nx), cy = whole ? 0 : std::min(crop, d.ny);
       for (long long k = oldest; k < c->pairs_written; ++k) {
         const double* pb = c->net_pairs[g] + (size_t)(k % c->pair_slots) * 6 * n1;
         for (int comp = 0; comp < 3; ++comp) {
+          int ox = 0, oy = 0;
+          crop_corner(c->adam_step, d.nx, d.ny, &ox, &oy);
           HIPCHK(c, pic_net_grad(T, pb + (size_t)(2 * comp) * n1, pb + (size_t)(2 * comp + 1) * n1,
-                                 d.nx, d.ny, S));
+                                 d.nx, d.ny, ox, oy, cx, cy, S));
           HIPCHK(c, pic_net_adam(T, lr, ++c->adam_step, S));
           ++updates;
         }
@@ -1604,15 +1625,27 @@ int32_t pic_precond_apply(pic_ctx* c, int32_t form, int32_t nx, int32_t ny, cons
 }
 
 int32_t pic_precond_grad(pic_ctx* c, int32_t nx, int32_t ny, const double* d_b, const double* d_t,
-                         float* host_grad, size_t n, double* loss) {
+                         const int32_t* window, float* host_grad, size_t n, double* loss) {
   if (!c || !d_b || !d_t || !host_grad) return PIC_E_INVAL;
   if (!c->learned) return fail(c, PIC_E_STATE, "no network (solver is not PIC_SOLVER_LEARNED_PCG)");
   if (n != (size_t)NET_NW) return fail(c, PIC_E_INVAL, "gradient count must be 9792");
-  if (nx < 3 || ny < 3 || (long long)nx * ny > c->train_cells)
-    return fail(c, PIC_E_INVAL, "need nx, ny >= 3 and nx * ny <= the largest first run's cells");
+  if (nx < 3 || ny < 3)
+    return fail(c, PIC_E_INVAL, "need nx, ny >= 3");
+  int ox = 0, oy = 0, cx = 0, cy = 0;
+  if (window) {
+    ox = window[0];
+    oy = window[1];
+    cx = window[2];
+    cy = window[3];
+    if (ox < 0 || ox >= nx || oy < 0 || oy >= ny || cx < 1 || cy < 1 || cx > nx || cy > ny ||
+        cx > kMaxTrainCrop || cy > kMaxTrainCrop)
+      return fail(c, PIC_E_INVAL, "window corner outside the field or size outside [1, min(n, 128)]");
+  } else if ((long long)nx * ny > c->train_cells) {
+    return fail(c, PIC_E_INVAL, "need nx * ny <= the largest first run's cells");
+  }
   const NetTrain& T = c->nets[0];
   HIPCHK(c, hipMemsetAsync(T.scal, 0, 4 * sizeof(double), c->stream));
-  HIPCHK(c, pic_net_grad(T, d_b, d_t, nx, ny, c->stream));
+  HIPCHK(c, pic_net_grad(T, d_b, d_t, nx, ny, ox, oy, cx, cy, c->stream));
   double scal[4];
   HIPCHK(c, hipMemcpyAsync(scal, T.scal, sizeof scal, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(host_grad, T.grad, n * sizeof(float), hipMemcpyDeviceToHost,

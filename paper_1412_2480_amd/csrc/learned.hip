@@ -1,9 +1,13 @@
 // Training and test-inference kernels of the learned CG aid (net_dev.h).
-// Training runs in FP32 on the vector ALUs on whole periodic fields of one
-// run: forward through the three linear 3x3 layers, the relative squared
-// error against the recorded solution dB, backward through the adjoint
-// convolutions, weight gradients reduced per block and then in a fixed block
-// order, and an Adam update. Inference inside the solver uses net_apply_tile
+// Training runs in FP32 on the vector ALUs, on a whole periodic field of one
+// run or on a crop of it: forward through the three linear 3x3 layers, the
+// relative squared error against the recorded solution dB, backward through
+// the adjoint convolutions, weight gradients reduced per block and then in a
+// fixed block order, and an Adam update. A crop is the cx x cy window plus a
+// 3-cell halo, taken with the field's periodic wrap and treated as a periodic
+// field of its own; the three layers reach 3 cells, so the wrap of the window
+// only affects its halo, which the loss leaves out: the loss and gradient are
+// exactly those of the network on the window's cx x cy cells. Inference inside the solver uses net_apply_tile
 // (BF16 matrix cores); k_net_apply runs that same routine on a whole field.
 #include <math.h>
 
@@ -98,13 +102,34 @@ __global__ void __launch_bounds__(256) k_to_float(const double* a, float* b, lon
   if (e < n) b[e] = (float)a[e];
 }
 
+// the w x h window with corner (ox, oy) of an nx x ny periodic field: b as
+// FP32 network input, t copied
+__global__ void __launch_bounds__(256) k_crop(const double* b, const double* t, int nx, int ny,
+                                              int ox, int oy, int w, int h, float* xin,
+                                              double* tc) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= w * h) return;
+  const int i = e % w, j = e / w;
+  const long long src = (long long)((oy + j) % ny) * nx + (ox + i) % nx;
+  xin[e] = (float)b[src];
+  tc[e] = t[src];
+}
+
+// cells of a w x h field that enter the loss: all but a border of bw cells
+__device__ __forceinline__ bool in_loss(long long e, int w, int h, int bw) {
+  const int i = (int)(e % w), j = (int)(e / w);
+  return i >= bw && i < w - bw && j >= bw && j < h - bw;
+}
+
 // partial sums of t^2 (slot 0) and (y - t)^2 (slot 1) per block
 __global__ void __launch_bounds__(256) k_sums(const float* y, const double* t, double* part,
-                                              long long n) {
+                                              int w, int h, int bw) {
   __shared__ double s0[256], s1[256];
   double a0 = 0.0, a1 = 0.0;
+  const long long n = (long long)w * h;
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
+    if (!in_loss(e, w, h, bw)) continue;
     const double tv = t[e];
     const double r = (double)y[e] - tv;
     a0 += tv * tv;
@@ -139,13 +164,14 @@ __global__ void k_finish_sums(const double* part, int nblk, double* scal) {
   scal[2] += scal[1];
 }
 
-// gy = 2 (y - t) / sum t^2
+// gy = 2 (y - t) / sum t^2 on the loss cells, 0 on the border
 __global__ void __launch_bounds__(256) k_loss_grad(const float* y, const double* t,
-                                                   const double* scal, float* gy, long long n) {
+                                                   const double* scal, float* gy, int w, int h,
+                                                   int bw) {
   const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
+  if (e >= (long long)w * h) return;
   const double t2 = scal[0];
-  gy[e] = t2 > 0.0 ? (float)(2.0 * ((double)y[e] - t[e]) / t2) : 0.f;
+  gy[e] = t2 > 0.0 && in_loss(e, w, h, bw) ? (float)(2.0 * ((double)y[e] - t[e]) / t2) : 0.f;
 }
 
 __global__ void __launch_bounds__(256) k_adam(float* w, const float* g, float* m, float* v, int n,
@@ -248,22 +274,37 @@ hipError_t pic_net_apply(const NetTrain& T, int form, const double* in, double* 
 }
 
 // One loss/gradient evaluation on the sample (b, t) of an nx x ny periodic
-// field; grad receives dL/dW (all 9792 weights); scal[1] the loss, scal[2]
-// accumulates it.
+// field, whole (cx <= 0) or on the cx x cy window with corner (ox, oy) and its
+// 3-cell halo; grad receives dL/dW (all 9792 weights); scal[1] the loss,
+// scal[2] accumulates it.
 hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int nx, int ny,
-                        hipStream_t s) {
+                        int ox, int oy, int cx, int cy, hipStream_t s) {
+  int w = nx, h = ny, bw = 0;
+  const double* tt = t;
+  if (cx > 0) {
+    constexpr int H = 3;   // receptive-field radius of the three layers
+    w = cx + 2 * H;
+    h = cy + 2 * H;
+    bw = H;
+    k_crop<<<nblk((long long)w * h), 256, 0, s>>>(b, t, nx, ny, ((ox - H) % nx + nx) % nx,
+                                                   ((oy - H) % ny + ny) % ny, w, h, T.xin, T.tc);
+    tt = T.tc;
+  } else {
+    k_to_float<<<nblk((long long)w * h), 256, 0, s>>>(b, T.xin, (long long)w * h);
+  }
+  nx = w;
+  ny = h;
   const long long n = (long long)nx * ny;
   const int C = NET_C;
   const float* W1 = T.w + NET_W1;
   const float* W2 = T.w + NET_W2;
   const float* W3 = T.w + NET_W3;
-  k_to_float<<<nblk(n), 256, 0, s>>>(b, T.xin, n);
   k_conv_fwd<<<nblk(n * C), 256, 0, s>>>(T.xin, 1, W1, C, T.h1, nx, ny);
   k_conv_fwd<<<nblk(n * C), 256, 0, s>>>(T.h1, C, W2, C, T.h2, nx, ny);
   k_conv_fwd<<<nblk(n), 256, 0, s>>>(T.h2, C, W3, 1, T.y, nx, ny);
-  k_sums<<<256, 256, 0, s>>>(T.y, t, T.dpart, n);
+  k_sums<<<256, 256, 0, s>>>(T.y, tt, T.dpart, w, h, bw);
   k_finish_sums<<<1, 64, 0, s>>>(T.dpart, 256, T.scal);
-  k_loss_grad<<<nblk(n), 256, 0, s>>>(T.y, t, T.scal, T.gy, n);
+  k_loss_grad<<<nblk(n), 256, 0, s>>>(T.y, tt, T.scal, T.gy, w, h, bw);
   const int cpb = (int)((n + T.wg_blocks - 1) / T.wg_blocks);
   // layer 3
   k_conv_wgrad<<<T.wg_blocks, 256, 0, s>>>(T.h2, C, T.gy, 1, T.part, nx, ny, cpb);

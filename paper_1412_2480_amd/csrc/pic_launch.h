@@ -87,6 +87,7 @@ struct NetTrain {
   float *grad, *m, *v;   // [NET_NW]
   float* part;           // [wg_blocks][NET_C * NET_C * 9]
   float *xin, *y, *gy;   // [ncell]
+  double* tc;            // [ncell]: target of a training crop
   float *h1, *h2, *gh1, *gh2;   // [NET_C][ncell]
   double* dpart;         // [256][2]
   double* scal;          // [4]: sum t^2, loss, loss accumulator
@@ -98,8 +99,11 @@ hipError_t pic_net_refresh(const NetTrain& T, hipStream_t s);
 // out = N(in) on an nx x ny periodic field (form 0 collapsed, 1 network)
 hipError_t pic_net_apply(const NetTrain& T, int form, const double* in, double* out, int nx,
                          int ny, hipStream_t s);
+// loss and weight gradient of one sample: the whole nx x ny periodic field
+// (cx <= 0) or the cx x cy window at (ox, oy); the training buffers must hold
+// (cx + 6) (cy + 6) cells
 hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int nx, int ny,
-                        hipStream_t s);
+                        int ox, int oy, int cx, int cy, hipStream_t s);
 hipError_t pic_net_adam(const NetTrain& T, float lr, int step, hipStream_t s);
 
 // Device-side seeded plasma load (same items as the host generator)

@@ -89,15 +89,21 @@ def test_mfma_network_within_bf16_bound(net_sim, shape):
     assert relerr(y, y_ref) > 0.0   # BF16 is really in the loop
 
 
-def test_gradient_matches_oracle(net_sim):
-    _say("training gradient vs oracle")
+# whole field; windows wrapping in both directions, one cell, and a window
+# as large as the field (training windows: a crop plus a 3-cell halo)
+WINDOWS = [None, (35, 30, 16, 12), (3, 4, 1, 1), (0, 0, 40, 36), (7, 2, 33, 5)]
+
+
+@pytest.mark.parametrize("window", WINDOWS)
+def test_gradient_matches_oracle(net_sim, window):
+    _say(f"training gradient vs oracle, window {window}")
     w = _random_weights(5, noise=0.1)
     net_sim.set_weights(w)
     rng = np.random.default_rng(6)
     b = rng.standard_normal((36, 40))
     t = rng.standard_normal((36, 40))
-    loss, g = net_sim.precond_grad(b, t)
-    L_ref, G_ref = ocn.loss_and_grad(_split(w), b, t)
+    loss, g = net_sim.precond_grad(b, t, window=window)
+    L_ref, G_ref = ocn.loss_and_grad(_split(w), b, t, window=window)
     assert abs(loss - L_ref) <= 1e-5 * abs(L_ref)
     # FP32 forward/backward against FP64: layer by layer, normwise
     G = _split(g)
@@ -114,6 +120,10 @@ def test_apply_rejects_bad_sizes(net_sim):
         net_sim.precond_apply(np.zeros((40, 40)))   # more cells than run 0 holds
     with pytest.raises(pic.PicError):
         net_sim.set_weights(np.zeros(10, np.float32))
+    z = np.zeros((36, 40))
+    for win in ((40, 0, 4, 4), (0, -1, 4, 4), (0, 0, 41, 4), (0, 0, 4, 0)):
+        with pytest.raises(pic.PicError):
+            net_sim.precond_grad(z, z, window=win)
 
 
 def test_precond_calls_need_learned_solver():
