@@ -274,18 +274,39 @@ def net_rate(pic, torch, cfg, reps=20):
     return out
 
 
-def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1):
+def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1, pairs=8, epochs=50):
     """The large single-GPU share: periodic 8192 x 2048, pair plasma at
     gamma0 = 40, 64 ppc/species (2.1e9 particles), order 3, CFL 1, theta 0.6,
-    FP32 particles, loaded on the device; plain CG."""
+    FP32 particles, loaded on the device, with the learned aid: the first
+    `pairs` steps run plain CG (timed, and recorded as training pairs), the
+    network is trained, then the timed steps use the learned solver."""
     from synth import loads
     nx, ny, ppc = 8192, 2048, 64
     Q = loads.macro_charge(40.0, 0.1, 0.1, ppc)
     run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 3, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8)
     sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split,
-                                          track_ids=False))
+                                          track_ids=False, solver="learned",
+                                          precond_slots=pairs))
     for s in range(2):
         sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
+    n = 2 * nx * ny * ppc
+    # plain CG steps, recorded as training pairs
+    sim.precond_use(False)
+    sim.precond_collect(True)
+    sim.timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_plain = sim.step(pairs)[0]
+    plain_ms = (time.perf_counter() - t0) * 1e3 / pairs
+    tim_plain = sim.get_timing()
+    sim.timing(False)
+    sim.precond_collect(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tr = sim.precond_train(epochs, 0.0)
+    train_s = time.perf_counter() - t0
+    sim.precond_use(True)
+    retune = sim.tune(1, splits=(tile_split,))
     sim.step(warmup)
     torch.cuda.synchronize()
     sim.timing(True)
@@ -297,14 +318,22 @@ def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1):
         raise RuntimeError(f"large share pic_step returned {pic.STATUS.get(rc, rc)}")
     tim = sim.get_timing()
     st = sim.step(0)[0]
-    n = 2 * nx * ny * ppc
     push_ms = tim["push"]["ms"] / max(1, tim["push"]["launches"])
     out = dict(workload="periodic 8192x2048, pair gamma0=40, 64 ppc/species, order 3, CFL 1.0, "
-                        "theta 0.6 (FP32 particles, plain CG)",
+                        "theta 0.6 (FP32 particles, learned aid)",
                particles=n, workspace_gb=sim.info.workspace_bytes / 1e9, ms_per_step=ms,
                particle_steps_per_s=n / (ms * 1e-3), push_ms=push_ms,
                push_achieved_gbs=BYTES_PER_PARTICLE["fp32"] * n / (push_ms * 1e-3) / 1e9,
-               field_solve_ms=tim["field_solve"]["ms"] / steps, cg_iters=st["iters"])
+               field_solve_ms=tim["field_solve"]["ms"] / steps, cg_iters=st["iters"],
+               learned_iters=st["learned_iters"], fallback=st["fallback"],
+               max_relres=max(st["relres"]), cg_blocks=retune["cg_blocks"],
+               training=dict(pairs=pairs, epochs=epochs, seconds=train_s,
+                             loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
+               plain_cg=dict(ms_per_step=plain_ms, particle_steps_per_s=n / (plain_ms * 1e-3),
+                             field_solve_ms=tim_plain["field_solve"]["ms"] / pairs,
+                             cg_iters=st_plain["iters"],
+                             note=f"the {pairs} collection steps (untuned field-solve grid, "
+                                  "pair recording included)"))
     sim.close()
     return out
 
@@ -486,7 +515,10 @@ def main():
         log("bench: large single-GPU share (8192x2048, 2.1e9 particles)")
         large = large_share(pic, torch, tile=tile, tile_split=max(1, args.tile_split))
         log(f"bench: large share {large['ms_per_step']:.1f} ms/step, push "
-            f"{large['push_ms']:.1f} ms ({large['push_achieved_gbs']:.0f} GB/s)")
+            f"{large['push_ms']:.1f} ms ({large['push_achieved_gbs']:.0f} GB/s), field solve "
+            f"{large['field_solve_ms']:.1f} ms learned vs "
+            f"{large['plain_cg']['field_solve_ms']:.1f} ms plain CG, trained in "
+            f"{large['training']['seconds']:.2f} s")
 
     net = None
     if not args.no_learned:

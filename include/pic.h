@@ -28,7 +28,8 @@
  * passed in are borrowed for the duration of the call and copied.
  *
  * Errors: every call returns an int32 status (PIC_OK = 0, negative on error);
- * no exception crosses the ABI. pic_last_error() gives a message. EINVAL
+ * no exception crosses the ABI. pic_last_error() gives a message (with a
+ * null context: that of the last failed pic_init on this thread). EINVAL
  * leaves the state unchanged. Kernel faults surface at the next call that
  * synchronises (pic_sync, pic_diag, reads, the end of pic_step).
  * Threading: one context per host thread; all work is ordered on the

@@ -128,6 +128,10 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -c 'import __graft_entry__ as g; g.build()'`")
+        # torch first: its HIP runtime is then the one libpic.so binds to (the
+        # same soname). Loaded the other way round, torch would bring a second
+        # HIP/HSA runtime into the process and one of the two sees no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.POINTER
         L.pic_plan.argtypes = [P(RunDesc), ctypes.c_int32, P(Options), P(PlanInfo)]
@@ -261,7 +265,7 @@ class Sim:
                              int(self.info.workspace_bytes),
                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(ctx))
         if rc != 0:
-            raise PicError(rc, "pic_init failed")
+            raise PicError(rc, f"pic_init failed: {self.L.pic_last_error(None).decode()}")
         self.ctx = ctx
 
     def _check(self, rc, what, allow=()):

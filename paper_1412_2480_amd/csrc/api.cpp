@@ -25,6 +25,8 @@ constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kTimingClasses = 8;
 constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
+// message of the last failed pic_init on this thread (pic_last_error(NULL))
+thread_local std::string g_init_err;
 constexpr int kDefaultTrainCrop = 64;  // training window (cells per side) by default
 constexpr int kMaxTrainCrop = 128;     // largest training window per side
 constexpr int kDefaultLearnedMaxit = 30;
@@ -1094,15 +1096,18 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
                  void* d_workspace, size_t ws_bytes, void* hip_stream, pic_ctx** out) {
   if (!out) return PIC_E_INVAL;
   *out = nullptr;
+  g_init_err.clear();
   pic_ctx* c = new pic_ctx();
   std::string msg;
   int rc = plan_impl(runs, n_runs, opt, &c->plan, &c->tl, &msg);
   if (rc) {
     delete c;
+    g_init_err = msg;
     return rc;
   }
   if (!d_workspace || ws_bytes < c->plan.workspace_bytes) {
     delete c;
+    g_init_err = "workspace missing or smaller than pic_plan's workspace_bytes";
     return PIC_E_NOMEM;
   }
   c->runs.assign(runs, runs + n_runs);
@@ -1141,17 +1146,33 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
 
   // CG work-groups: as many as can be co-resident, split over runs by cells
   int dev = 0, n_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+  // an error left pending by an earlier runtime call of the process (not by
+  // this library) is reported with the message, then cleared
+  const hipError_t pending = hipGetLastError();
+  hipError_t he = hipGetDevice(&dev);
+  const char* what = "hipGetDevice";
+  if (he == hipSuccess) {
+    he = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    what = "hipDeviceGetAttribute";
+  }
+  if (he != hipSuccess) {
     delete c;
+    g_init_err = std::string(what) + ": " + hipGetErrorString(he) +
+                 (pending != hipSuccess ? std::string(" (pending before pic_init: ") +
+                                              hipGetErrorString(pending) + ")"
+                                        : std::string());
     return PIC_E_HIP;
   }
+  if (pending != hipSuccess)
+    c->err = std::string("note: an error was pending before pic_init and was cleared: ") +
+             hipGetErrorString(pending);
   // the plain and the learned variant must both fit the same grid
   int maxb = pic_field_solve_max_blocks(n_cu, 0, 0);
   if (c->learned)
     maxb = std::min(maxb, pic_field_solve_max_blocks(n_cu, 1, opt->learned_form));
   if (maxb < n_runs) {
     delete c;
+    g_init_err = "fewer co-resident field-solve work-groups than runs";
     return PIC_E_HIP;
   }
   c->max_cg_blocks = std::min(maxb, kMaxCgBlocks);
@@ -1191,13 +1212,17 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     for (int t = 0; t < c->tl.ntx[r] * c->tl.nty[r]; ++t) tile_run[c->tl.tile0[r] + t] = r;
 
   hipStream_t S = c->stream;
+  const char* step = "workspace clear";
   hipError_t e = hipMemsetAsync(c->ws, 0, c->plan.workspace_bytes, S);
-  if (e == hipSuccess)
+  if (e == hipSuccess) {
+    step = "run table upload";
     e = hipMemcpyAsync(c->d_runs, c->hruns.data(), sizeof(DevRun) * n_runs, hipMemcpyHostToDevice, S);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(c->d_tile_run, tile_run.data(), sizeof(int) * tile_run.size(),
                        hipMemcpyHostToDevice, S);
   if (e == hipSuccess && c->learned) {
+    step = "network set-up";
     const std::vector<float> w0 = initial_weights();   // copies complete before the sync below
     std::vector<NetWeights> hn;
     for (auto& nt : c->nets) {
@@ -1211,9 +1236,13 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
                          hipMemcpyHostToDevice, S);
     if (e == hipSuccess) e = hipStreamSynchronize(S);
   }
-  if (e == hipSuccess) e = hipStreamSynchronize(S);
+  if (e == hipSuccess) {
+    step = "initial synchronisation";
+    e = hipStreamSynchronize(S);
+  }
   if (e != hipSuccess) {
     delete c;
+    g_init_err = std::string(step) + ": " + hipGetErrorString(e);
     return PIC_E_HIP;
   }
   *out = c;
@@ -1774,7 +1803,10 @@ int32_t pic_destroy(pic_ctx* c) {
   return PIC_OK;
 }
 
-const char* pic_last_error(const pic_ctx* c) { return c ? c->err.c_str() : "null context"; }
+const char* pic_last_error(const pic_ctx* c) {
+  if (c) return c->err.c_str();
+  return g_init_err.empty() ? "null context" : g_init_err.c_str();
+}
 
 const char* pic_status_str(int32_t s) {
   switch (s) {

@@ -84,3 +84,21 @@ def test_plan_learned_solver():
     o.learned_form = 7
     with pytest.raises(pic.PicError):
         pic.plan([_run()], o)
+
+
+def test_library_binds_to_torchs_hip_runtime():
+    """Loading the library (as pic_plan does) before any GPU use must leave one
+    HIP runtime in the process, the one torch uses: the loaded libamdhip64
+    copies are counted in a fresh interpreter."""
+    import subprocess
+    import sys
+    code = ("import paper_1412_2480_amd as pic\n"
+            "pic.lib()\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().splitlines()\n"
+            "print(len({l.split()[-1] for l in maps if 'libamdhip64' in l}))\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         cwd=root, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1", out.stdout

@@ -1,7 +1,8 @@
 """The device-side plasma loader against the seeded host generator, and the
 large single-GPU share (periodic 8192 x 2048, pair plasma at gamma0 = 40,
 64 particles/cell/species: 2.1e9 particles in FP32, cubic shape, CFL 1,
-theta 0.6) at full size on outputs the FP64 oracle can compute piecewise."""
+theta 0.6, with the learned aid) at full size on outputs the FP64 oracle can
+compute piecewise or whole (the field solve)."""
 import sys
 
 import numpy as np
@@ -65,13 +66,19 @@ def test_large_share_fullsize_fp32():
     NX, NY, PPC, G0, ORDER, T, SEED = 8192, 2048, 64, 40.0, 3, 0.01, 0
     Q = loads.macro_charge(G0, DX, DX, PPC)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    opts = pic.make_options("fp32", tile=(16, 32), tile_split=1, track_ids=False)
+    # the learned aid as the timed configuration uses it: plain CG first,
+    # recording training pairs, then the trained network
+    opts = pic.make_options("fp32", tile=(16, 32), tile_split=1, track_ids=False,
+                            solver="learned", precond_slots=4)
     _say(f"large share: workspace {pic.plan([run], opts).workspace_bytes / 1e9:.1f} GB")
     sim = pic.Sim([run], opts)
+    _say(f"large share: context created ({sim.L.pic_last_error(sim.ctx).decode() or 'ok'})")
     for s in range(2):
         sim.load_plasma(0, s, PPC, G0, T, SEED)
     d0 = sim.diag(0)
     assert d0["n_particles"] == [NX * NY * PPC] * 2
+    sim.precond_use(False)
+    sim.precond_collect(True)
     _say("large share: first step (fields start at zero)")
     sim.step(1)
     J = [sim.get_field(0, k) for k in ("Jx", "Jy", "Jz")]
@@ -132,9 +139,34 @@ def test_large_share_fullsize_fp32():
     _say("large share: 3 more steps, Gauss's law")
     st = sim.step(3)[0]
     assert max(st["relres"]) <= 1e-8
+    assert sim.precond_collect(False) == 4
     d = sim.diag(0, divergences=True)
     rho_scale = 4 * np.pi * Q / (DX * DX)
     _say(f"  gauss {d['gauss_max']:.3e} (scale {rho_scale:.3e}), cg {st['iters']}")
     assert d["gauss_max"] <= 1e-4 * rho_scale
     assert d["n_particles"] == [NX * NY * PPC] * 2
+    # ---- learned aid at full size: trained on the 4 recorded pairs (64-cell
+    # windows), then one step whose field solve is checked against the
+    # oracle's from the same E^n, B^n and J^{n+1/2}
+    tr = sim.precond_train(epochs=25)
+    _say(f"large share: trained, loss {tr['loss_first']:.2e} -> {tr['loss_last']:.2e}")
+    assert tr["loss_last"] < 0.01 * tr["loss_first"]
+    sim.precond_use(True)
+    F0 = {k: sim.get_field(0, k) for k in ("Ex", "Ey", "Ez", "Bx", "By", "Bz")}
+    sl = sim.step(1)[0]
+    _say(f"  learned step: iterations {sl['learned_iters']}, fallback {sl['fallback']}, "
+         f"relres {max(sl['relres']):.2e} (plain CG {st['iters']})")
+    assert sl["fallback"] == 0 and max(sl["relres"]) <= 1e-8
+    assert sum(sl["learned_iters"]) < sum(st["iters"])
+    ref = oracle.Sim(NX, NY, DX, DX, 1.0, 0.6, ORDER, [], rtol=1e-8)
+    for k in range(3):
+        ref.E[k][...] = F0[("Ex", "Ey", "Ez")[k]]
+        ref.B[k][...] = F0[("Bx", "By", "Bz")[k]]
+        ref.J[k][...] = sim.get_field(0, ("Jx", "Jy", "Jz")[k])
+    del F0
+    ref.field_solve()
+    for k, name in enumerate(("Ex", "Ey", "Ez", "Bx", "By", "Bz")):
+        e = relerr(sim.get_field(0, name), ref.E[k] if k < 3 else ref.B[k - 3])
+        _say(f"  {name} relerr {e:.2e}")
+        assert e <= 1e-6
     sim.close()
