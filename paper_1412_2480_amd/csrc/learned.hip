@@ -66,7 +66,8 @@ __global__ void __launch_bounds__(256) k_conv_adj(const float* g, int Cout, cons
 }
 
 // per-block partial weight gradients: part[b][co][ci][tap] =
-// sum over the block's cells of g[co][cell] in[ci][cell + (dx-1, dy-1)]
+// sum over the block's cells of g[co][cell] in[ci][cell + (dx-1, dy-1)];
+// one thread per (co, ci) pair keeps the 9 taps as independent sums
 __global__ void __launch_bounds__(256) k_conv_wgrad(const float* in, int Cin, const float* g,
                                                     int Cout, float* part, int nx, int ny,
                                                     int cells_per_block) {
@@ -74,27 +75,62 @@ __global__ void __launch_bounds__(256) k_conv_wgrad(const float* in, int Cin, co
   const int c0 = blockIdx.x * cells_per_block;
   const int c1 = min(n, c0 + cells_per_block);
   const int nw = Cout * Cin * 9;
-  for (int w = threadIdx.x; w < nw; w += blockDim.x) {
-    const int tap = w % 9, ci = (w / 9) % Cin, co = w / (9 * Cin);
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+  for (int pr = threadIdx.x; pr < Cout * Cin; pr += blockDim.x) {
+    const int co = pr / Cin, ci = pr - co * Cin;
     const float* gs = g + (size_t)co * n;
     const float* xs = in + (size_t)ci * n;
-    float acc = 0.f;
+    float acc[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) acc[k] = 0.f;
+    int j = c0 / nx, i = c0 - (c0 / nx) * nx;
     for (int cell = c0; cell < c1; ++cell) {
-      const int j = cell / nx, i = cell - j * nx;
-      acc += gs[cell] * xs[(size_t)wrapc(j + dy, ny) * nx + wrapc(i + dx, nx)];
+      const float gv = gs[cell];
+      const int im = i == 0 ? nx - 1 : i - 1, ip = i == nx - 1 ? 0 : i + 1;
+      const float* rm = xs + (size_t)(j == 0 ? ny - 1 : j - 1) * nx;
+      const float* r0 = xs + (size_t)j * nx;
+      const float* rp = xs + (size_t)(j == ny - 1 ? 0 : j + 1) * nx;
+      acc[0] += gv * rm[im];
+      acc[1] += gv * rm[i];
+      acc[2] += gv * rm[ip];
+      acc[3] += gv * r0[im];
+      acc[4] += gv * r0[i];
+      acc[5] += gv * r0[ip];
+      acc[6] += gv * rp[im];
+      acc[7] += gv * rp[i];
+      acc[8] += gv * rp[ip];
+      if (++i == nx) {
+        i = 0;
+        ++j;
+      }
     }
-    part[(size_t)blockIdx.x * nw + w] = acc;
+    float* out = part + (size_t)blockIdx.x * nw + (size_t)pr * 9;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) out[k] = acc[k];
   }
 }
 
-__global__ void __launch_bounds__(256) k_reduce_parts(const float* part, int nblk, int nw,
-                                                      float* grad) {
-  const int w = blockIdx.x * blockDim.x + threadIdx.x;
-  if (w >= nw) return;
+// grad[w] = sum_b part[b][w] for 32 weights per work-group: 8 threads per
+// weight each sum a strided eighth of the blocks, then the eight partial sums
+// are added in a fixed order (deterministic)
+constexpr int kRedW = 32, kRedT = 8;
+__global__ void __launch_bounds__(kRedW * kRedT) k_reduce_parts(const float* part, int nblk,
+                                                                int nw, float* grad) {
+  __shared__ float acc[kRedT][kRedW];
+  const int wl = threadIdx.x % kRedW, t = threadIdx.x / kRedW;
+  const int w = blockIdx.x * kRedW + wl;
   float s = 0.f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * nw + w];
-  grad[w] = s;
+  if (w < nw) {
+#pragma unroll 4
+    for (int b = t; b < nblk; b += kRedT) s += part[(size_t)b * nw + w];
+  }
+  acc[t][wl] = s;
+  __syncthreads();
+  if (t == 0 && w < nw) {
+    float r = acc[0][wl];
+#pragma unroll
+    for (int k = 1; k < kRedT; ++k) r += acc[k][wl];
+    grad[w] = r;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_to_float(const double* a, float* b, long long n) {
@@ -151,17 +187,24 @@ __global__ void __launch_bounds__(256) k_sums(const float* y, const double* t, d
   }
 }
 
-// scal[0] = sum t^2, scal[1] = loss = sum (y-t)^2 / sum t^2, added into scal[2]
-__global__ void k_finish_sums(const double* part, int nblk, double* scal) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// scal[0] = sum t^2, scal[1] = loss = sum (y-t)^2 / sum t^2, added into
+// scal[2]; one wavefront: each lane sums a strided share of the block
+// partials, then a fixed butterfly adds the lanes (deterministic)
+__global__ void __launch_bounds__(64) k_finish_sums(const double* part, int nblk, double* scal) {
   double t2 = 0.0, r2 = 0.0;
-  for (int b = 0; b < nblk; ++b) {
+  for (int b = threadIdx.x; b < nblk; b += 64) {
     t2 += part[2 * b];
     r2 += part[2 * b + 1];
   }
-  scal[0] = t2;
-  scal[1] = t2 > 0.0 ? r2 / t2 : 0.0;
-  scal[2] += scal[1];
+  for (int off = 32; off > 0; off >>= 1) {
+    t2 += __shfl_xor(t2, off, 64);
+    r2 += __shfl_xor(r2, off, 64);
+  }
+  if (threadIdx.x == 0) {
+    scal[0] = t2;
+    scal[1] = t2 > 0.0 ? r2 / t2 : 0.0;
+    scal[2] += scal[1];
+  }
 }
 
 // gy = 2 (y - t) / sum t^2 on the loss cells, 0 on the border
@@ -308,15 +351,18 @@ hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int
   const int cpb = (int)((n + T.wg_blocks - 1) / T.wg_blocks);
   // layer 3
   k_conv_wgrad<<<T.wg_blocks, 256, 0, s>>>(T.h2, C, T.gy, 1, T.part, nx, ny, cpb);
-  k_reduce_parts<<<nblk(C * 9), 256, 0, s>>>(T.part, T.wg_blocks, C * 9, T.grad + NET_W3);
+  k_reduce_parts<<<nblk(C * 9, kRedW), kRedW * kRedT, 0, s>>>(T.part, T.wg_blocks, C * 9,
+                                                               T.grad + NET_W3);
   k_conv_adj<<<nblk(n * C), 256, 0, s>>>(T.gy, 1, W3, C, T.gh2, nx, ny);
   // layer 2
   k_conv_wgrad<<<T.wg_blocks, 256, 0, s>>>(T.h1, C, T.gh2, C, T.part, nx, ny, cpb);
-  k_reduce_parts<<<nblk(C * C * 9), 256, 0, s>>>(T.part, T.wg_blocks, C * C * 9, T.grad + NET_W2);
+  k_reduce_parts<<<nblk(C * C * 9, kRedW), kRedW * kRedT, 0, s>>>(T.part, T.wg_blocks,
+                                                                   C * C * 9, T.grad + NET_W2);
   k_conv_adj<<<nblk(n * C), 256, 0, s>>>(T.gh2, C, W2, C, T.gh1, nx, ny);
   // layer 1
   k_conv_wgrad<<<T.wg_blocks, 256, 0, s>>>(T.xin, 1, T.gh1, C, T.part, nx, ny, cpb);
-  k_reduce_parts<<<nblk(C * 9), 256, 0, s>>>(T.part, T.wg_blocks, C * 9, T.grad + NET_W1);
+  k_reduce_parts<<<nblk(C * 9, kRedW), kRedW * kRedT, 0, s>>>(T.part, T.wg_blocks, C * 9,
+                                                               T.grad + NET_W1);
   return hipGetLastError();
 }
 
