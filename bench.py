@@ -72,6 +72,7 @@ def measured_traffic(precision, tile, tile_split, order, n_particles):
 
 
 GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
+SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
 
 
 def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
@@ -84,7 +85,7 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
                                           cg_blocks=cg_blocks, track_ids=False,
                                           tile_split=tile_split, solver=solver,
                                           learned_form=form, precond_slots=slots,
-                                          graph=GRAPH))
+                                          graph=GRAPH, sort_every=SORT))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -146,6 +147,7 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
                 push_ms=push_ms, field_solve_ms=tim["field_solve"]["ms"] / max(1, steps_t),
                 rebin_ms=tim["rebin"]["ms"] / max(1, steps_t),
                 current_sum_ms=tim["current_sum"]["ms"] / max(1, steps_t),
+                sort_ms_per_step=tim["sort"]["ms"] / max(1, steps_t),
                 graph_replays=replays,
                 cg_iters=st[0]["iters"], learned_iters=st[0]["learned_iters"],
                 fallback=st[0]["fallback"], relres=st[0]["relres"], n_particles=n_part,
@@ -286,7 +288,7 @@ def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1, pai
     run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 3, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8)
     sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split,
                                           track_ids=False, solver="learned",
-                                          precond_slots=pairs))
+                                          precond_slots=pairs, sort_every=SORT))
     for s in range(2):
         sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
     n = 2 * nx * ny * ppc
@@ -388,6 +390,9 @@ def main():
                          "field-solve work-groups) and use --tile/--tile-split/--cg-blocks")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured two-step HIP graphs in every timed form")
+    ap.add_argument("--sort-every", type=int, default=-1,
+                    help="reorder each tile's particles by cell every n steps in the timed "
+                         "forms (0 = never); default: picked by the autotuner (0 without it)")
     ap.add_argument("--train-pairs", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=50)
     ap.add_argument("--also-mfma", action="store_true",
@@ -404,8 +409,9 @@ def main():
     import torch
     import paper_1412_2480_amd as pic
     from synth import loads
-    global GRAPH
+    global GRAPH, SORT
     GRAPH = args.graph
+    SORT = max(0, args.sort_every)
 
     cfg = CONFIGS[args.config]
     tile = tuple(int(v) for v in args.tile.split("x"))
@@ -470,6 +476,17 @@ def main():
         args.cg_blocks = best["cg_blocks"]
         log(f"bench: autotune picked tile {tile} split {args.tile_split} cg_blocks "
             f"{args.cg_blocks} ({tune['seconds']:.1f} s)")
+        if args.sort_every < 0:
+            from paper_1412_2480_amd.tune import tune_sort_every
+            t0 = time.perf_counter()
+            SORT, sort_table = tune_sort_every(
+                [run], _load, dict(precision="fp32", track_ids=False, tile=tile,
+                                   tile_split=args.tile_split, cg_blocks=args.cg_blocks))
+            tune["sort_every"] = SORT
+            tune["sort_table"] = sort_table
+            tune["seconds"] += time.perf_counter() - t0
+            log(f"bench: autotune picked sort_every {SORT} " + ", ".join(
+                f"{r['sort_every']}: {r['ms_per_step']:.3f} ms" for r in sort_table))
     log("bench: FP32 form" + ("" if learned is None else f" + learned ({args.learned_form})"))
     fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
                      args.tile_split, learned, retune=not args.no_autotune)
@@ -557,14 +574,14 @@ def main():
                                                     f", learned aid ({args.learned_form})"),
         "data": "synthetic (seeded Maxwell-Juettner pair plasma)",
         "config": {"workload": cfg["label"], "particles": n_part, "cells": cfg["nx"] * cfg["ny"],
-                   "tile": list(tile), "cg_rtol": 1e-8},
+                   "tile": list(tile), "sort_every": SORT, "cg_rtol": 1e-8},
         "field_solve_ms_per_step": fast["field_solve_ms"],
         "cg_iters_last_step": fast["cg_iters"],
         "learned": solve_info(fast) if learned is not None else None,
         "fp32_plain_cg": solve_info(fast_cg),
         "fp32_learned_mfma": solve_info(mfma),
         "breakdown_ms": {k: fast[k] for k in ("push_ms", "rebin_ms", "current_sum_ms",
-                                              "field_solve_ms")},
+                                              "sort_ms_per_step", "field_solve_ms")},
         "plain_fp64": None if plain is None else {
             "particle_steps_per_s": plain["particle_steps_per_s"],
             "ms_per_step": plain["ms_per_step"],
@@ -581,7 +598,7 @@ def main():
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
                      "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE["fp32"] * n_part,
                      "avg_launch_ms": fast["push_ms"], "tile": list(tile),
-                     "tile_split": args.tile_split},
+                     "tile_split": args.tile_split, "sort_every": SORT},
         "autotune": tune,
         "learned_net": net,
         "large_share": large,

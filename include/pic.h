@@ -123,6 +123,8 @@ typedef struct pic_options {
                             particle double buffer returns to its arrangement after two)
                             whenever no diagnostics record, timing or pair collection
                             falls in them; 0: plain launches */
+  int32_t sort_every;    /* pic_step reorders every tile's particles by cell every
+                            this many steps (0 = never); see pic_step */
 } pic_options;
 
 typedef struct pic_plan_info {
@@ -159,9 +161,9 @@ typedef struct pic_timing_out {
   /* accumulated device time (ms) and launch counts per kernel class since
      timing was switched on: 0 particle push (fused or split), 1 deposit
      (split path), 2 rebin, 3 current reduction, 4 field RHS, 5 CG,
-     6 field update, 7 diagnostics */
-  double ms[8];
-  int64_t launches[8];
+     6 field update, 7 diagnostics, 8 particle reordering */
+  double ms[9];
+  int64_t launches[9];
   int64_t graph_replays; /* two-step graph replays since pic_init (graph mode) */
 } pic_timing_out;
 
@@ -241,7 +243,12 @@ int32_t pic_field_solve(pic_ctx* ctx, pic_solve_stats* stats);
 
 /* nsteps fused steps (gather+push+move+deposit in one kernel per tile, then
  * re-binning, the current reduction and the field solve). Synchronises once at
- * the end to report overflow and CG status. last: NULL or n_runs entries. */
+ * the end to report overflow and CG status. last: NULL or n_runs entries.
+ * With sort_every = K > 0, after the re-binning of every K-th step each
+ * tile's particles are reordered: sorted by cell, then dealt out so that each
+ * wavefront of the particle kernel takes 64 distinct cells spread over the
+ * tile (the order the loaders produce; compaction mixes it step by step).
+ * This changes storage order only; reads with track_ids return id order. */
 int32_t pic_step(pic_ctx* ctx, int32_t nsteps, pic_solve_stats* last);
 
 /* Diagnostics of the current state of one run (synchronises): energies of

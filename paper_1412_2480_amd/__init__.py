@@ -57,7 +57,7 @@ class Options(ctypes.Structure):
                 ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32),
                 ("tile_split", ctypes.c_int32), ("learned_form", ctypes.c_int32),
                 ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("sort_every", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -112,11 +112,12 @@ class DiagOut(ctypes.Structure):
 
 
 class TimingOut(ctypes.Structure):
-    _fields_ = [("ms", ctypes.c_double * 8), ("launches", ctypes.c_int64 * 8),
+    _fields_ = [("ms", ctypes.c_double * 9), ("launches", ctypes.c_int64 * 9),
                 ("graph_replays", ctypes.c_int64)]
 
 
-TIMING_CLASSES = ["push", "deposit", "rebin", "current_sum", "rhs", "field_solve", "update", "diag"]
+TIMING_CLASSES = ["push", "deposit", "rebin", "current_sum", "rhs", "field_solve", "update", "diag",
+                  "sort"]
 
 _lib = None
 
@@ -210,7 +211,7 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
                  diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0,
                  solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0,
-                 graph=False):
+                 graph=False, sort_every=0):
     """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma"."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
@@ -221,6 +222,7 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     o.learned_maxit = int(learned_maxit)
     o.precond_slots = int(precond_slots)
     o.graph = 1 if graph else 0
+    o.sort_every = int(sort_every)
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)

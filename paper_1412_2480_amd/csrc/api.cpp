@@ -23,7 +23,7 @@ constexpr int kMaxCgBlocks = 4096;
 // each), so the default keeps the persistent grid small; pic_tune measures
 constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
-constexpr int kTimingClasses = 8;
+constexpr int kTimingClasses = 9;
 constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
 // message of the last failed pic_init on this thread (pic_last_error(NULL))
 thread_local std::string g_init_err;
@@ -172,6 +172,10 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
   }
   if (o->solver != PIC_SOLVER_CG && o->solver != PIC_SOLVER_LEARNED_PCG) {
     *msg = "unknown solver";
+    return PIC_E_INVAL;
+  }
+  if (o->sort_every < 0) {
+    *msg = "sort_every must be >= 0";
     return PIC_E_INVAL;
   }
   if (o->solver == PIC_SOLVER_LEARNED_PCG) {
@@ -702,6 +706,25 @@ int do_deposit(pic_ctx* c) {
   if (rc) return rc;
   return launch_exchange<R>(c);
 }
+// steps after whose re-binning the particles are reordered
+bool sort_step(const pic_ctx* c, long long step) {
+  const int k = c->opt.sort_every;
+  return k > 0 && (step + 1) % k == 0;
+}
+
+template <typename R>
+int launch_sort(pic_ctx* c) {
+  int ns = 0;
+  for (auto& r : c->runs) ns = std::max(ns, r.n_species);
+  t_begin(c, 8);
+  hipError_t e = pic_launch_sort<R>(state<R>(c), ns, c->tl.TXA * c->tl.TYA, c->stream);
+  t_end(c);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("sort: ") + hipGetErrorString(e));
+  swap_buffers(state<R>(c));
+  c->parity ^= 1;
+  return PIC_OK;
+}
+
 template <typename R>
 int do_step(pic_ctx* c) {
   const int diag = diag_step(c) ? 1 : 0;
@@ -709,6 +732,10 @@ int do_step(pic_ctx* c) {
   if (rc) return rc;
   rc = launch_exchange<R>(c);
   if (rc) return rc;
+  if (sort_step(c, c->step)) {
+    rc = launch_sort<R>(c);
+    if (rc) return rc;
+  }
   rc = launch_field(c, diag);
   if (rc) return rc;
   c->step += 1;
@@ -724,6 +751,8 @@ bool graph_usable(pic_ctx* c) {
   if (!c->opt.graph || !c->graph_ok || c->timing || c->collect) return false;
   const int de = c->opt.diag_every;
   if (de > 0 && ((c->step % de) == 0 || ((c->step + 1) % de) == 0)) return false;
+  // a reordering in the two steps would change the buffer pattern captured
+  if (sort_step(c, c->step) || sort_step(c, c->step + 1)) return false;
   return true;
 }
 

@@ -569,6 +569,154 @@ __global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
   }
 }
 
+// Reordering of a tile's particles (every sort_every steps, after the
+// re-binning): the compaction of stayers mixes the storage order over the
+// steps, so that the 64 lanes of a wavefront land on random cells of the tile
+// and the particle kernel's LDS atomics and gathers collide in banks more and
+// more. A counting sort by cell gives each particle a position p in
+// cell-major order; lane l of every wavefront then takes the l-th contiguous
+// 1/64 of that order (run length L or L - 1), so one wavefront covers 64
+// distinct cells spread over the tile: storage q = w * 64 + l for the w-th
+// particle of lane l's run. The current store is read, the next one written
+// in storage order (the reads gather through the inverse permutation).
+constexpr int kSortBatch = 8;
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_sort(DevState<R> st) {
+  extern __shared__ int s_cell[];   // [cells of the widest tile]: counts, then cursors
+  __shared__ int s_carry;
+  const int per = gridDim.x / 8;
+  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (tile >= st.n_tiles) return;
+  const int s = blockIdx.y;
+  const DevRun& run = st.runs[st.tile_run[tile]];
+  if (s >= run.nspecies) return;
+  const int lt = tile - run.tile0;
+  const int tx = lt % run.ntx, ty = lt / run.ntx;
+  const int x0 = tx * st.TX, y0 = ty * st.TY;
+  const int tw = pic_tile_width(tx, st.TX, run.ntx, run.nx);
+  const int th = pic_tile_width(ty, st.TY, run.nty, run.ny);
+  const int nc = tw * th;
+  const int n = st.cnt[s][tile];
+  const long long base = (long long)tile * st.tile_slots[s];
+  __shared__ int s_bad;
+  for (int c = threadIdx.x; c < nc; c += blockDim.x) s_cell[c] = 0;
+  if (threadIdx.x == 0) s_bad = 0;
+  __syncthreads();
+  // kSortBatch loads in flight per thread before their LDS updates
+  const int stride = (int)blockDim.x * kSortBatch;
+  for (int k0 = threadIdx.x; k0 < n; k0 += stride) {
+    int cell[kSortBatch];
+#pragma unroll
+    for (int u = 0; u < kSortBatch; ++u) {
+      const int k = k0 + u * (int)blockDim.x;
+      cell[u] = k < n ? st.cell[s][base + k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortBatch; ++u) {
+      if (cell[u] < 0) continue;
+      const int lx = pic_cell_ix(cell[u]) - x0, ly = pic_cell_iy(cell[u]) - y0;
+      if (lx < 0 || lx >= tw || ly < 0 || ly >= th)
+        s_bad = 1;   // not in this tile: the store is inconsistent
+      else
+        atomicAdd(&s_cell[ly * tw + lx], 1);
+    }
+  }
+  __syncthreads();
+  if (s_bad) {
+    // keep the order (copy) and flag the run
+    for (int k = threadIdx.x; k < n; k += blockDim.x) {
+      const long long i = base + k;
+      st.ncell[s][i] = st.cell[s][i];
+      st.nox[s][i] = st.ox[s][i];
+      st.noy[s][i] = st.oy[s][i];
+      st.nux[s][i] = st.ux[s][i];
+      st.nuy[s][i] = st.uy[s][i];
+      st.nuz[s][i] = st.uz[s][i];
+      if (st.id[s]) st.nid[s][i] = st.id[s][i];
+    }
+    if (threadIdx.x == 0) atomicOr(st.err, PIC_ERRBIT_TILE);
+    return;
+  }
+  // exclusive scan of the counts, blockDim cells at a time: a shuffle scan
+  // per wavefront, the wavefront totals, and a carry over the chunks
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nc; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    const int v = c < nc ? s_cell[c] : 0;
+    // inclusive scan within the wavefront
+    int x = v;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int off = 1; off < 64; off <<= 1) {
+      const int y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    __shared__ int s_wave[4];
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int before = s_carry;
+    for (int w = 0; w < wave; ++w) before += s_wave[w];
+    if (c < nc) s_cell[c] = before + x - v;   // exclusive start = cursor
+    __syncthreads();
+    if (threadIdx.x == blockDim.x - 1) s_carry = before + x;
+    __syncthreads();
+  }
+  // the source of every destination, in the split path's old-cell array
+  // (free during pic_step): cell-sorted position p is the w-th particle of
+  // lane l's run (runs of L or L - 1, the longer first), destination 64 w + l
+  const int L = (n + 63) / 64;
+  const int full = n - 64 * (L - 1);   // lanes whose run has L particles
+  int* const inv = st.old_cell[s] + base;
+  for (int k0 = threadIdx.x; k0 < n; k0 += stride) {
+    int cell[kSortBatch];
+#pragma unroll
+    for (int u = 0; u < kSortBatch; ++u) {
+      const int k = k0 + u * (int)blockDim.x;
+      cell[u] = k < n ? st.cell[s][base + k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < kSortBatch; ++u) {
+      if (cell[u] < 0) continue;
+      const int c = (pic_cell_iy(cell[u]) - y0) * tw + pic_cell_ix(cell[u]) - x0;
+      const int p = atomicAdd(&s_cell[c], 1);
+      int l, w;
+      if (p < full * L) {
+        l = p / L;
+        w = p - l * L;
+      } else {
+        const int p2 = p - full * L;   // here L >= 2, since p < n
+        l = full + p2 / (L - 1);
+        w = p2 - (l - full) * (L - 1);
+      }
+      inv[w * 64 + l] = k0 + u * (int)blockDim.x;
+    }
+  }
+  __syncthreads();
+  // destination order: contiguous stores, the loads gather
+  constexpr int B3 = kSortBatch / 2;
+  for (int q0 = threadIdx.x; q0 < n; q0 += (int)blockDim.x * B3) {
+    long long src[B3];
+#pragma unroll
+    for (int u = 0; u < B3; ++u) {
+      const int q = q0 + u * (int)blockDim.x;
+      src[u] = q < n ? base + inv[q] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < B3; ++u) {
+      if (src[u] < 0) continue;
+      const long long dst = base + q0 + u * (int)blockDim.x;
+      st.ncell[s][dst] = st.cell[s][src[u]];
+      st.nox[s][dst] = st.ox[s][src[u]];
+      st.noy[s][dst] = st.oy[s][src[u]];
+      st.nux[s][dst] = st.ux[s][src[u]];
+      st.nuy[s][dst] = st.uy[s][src[u]];
+      st.nuz[s][dst] = st.uz[s][src[u]];
+      if (st.id[s]) st.nid[s][dst] = st.id[s][src[u]];
+    }
+  }
+}
+
 // Injection: staged particles (sorted by tile) are appended to the current
 // store of their tile; entry e of the list is (tile, first staged index,
 // count) and each tile appears once, so one work-group owns a tile's count.
@@ -753,6 +901,14 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
 }
 
 template <typename R>
+hipError_t pic_launch_sort(const DevState<R>& st, int n_species, int max_tile_cells,
+                           hipStream_t s) {
+  k_sort<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256),
+              (size_t)max_tile_cells * sizeof(int), s>>>(st);
+  return hipGetLastError();
+}
+
+template <typename R>
 hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s) {
   k_rebin<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), 0, s>>>(st);
   return hipGetLastError();
@@ -795,6 +951,8 @@ template size_t pic_particle_smem<double>(const DevState<double>&, int);
 template hipError_t pic_launch_particles<float>(const DevState<float>&, int, int, int, hipStream_t);
 template hipError_t pic_launch_particles<double>(const DevState<double>&, int, int, int, hipStream_t);
 template hipError_t pic_launch_rebin<float>(const DevState<float>&, int, hipStream_t);
+template hipError_t pic_launch_sort<float>(const DevState<float>&, int, int, hipStream_t);
+template hipError_t pic_launch_sort<double>(const DevState<double>&, int, int, hipStream_t);
 template hipError_t pic_launch_rebin<double>(const DevState<double>&, int, hipStream_t);
 template hipError_t pic_launch_inject<float>(const DevState<float>&, int, int, const int*,
                                              const int*, const float*, const float*,

@@ -59,6 +59,11 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
                                 hipStream_t s);
 template <typename R>
 hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s);
+// reorder every tile's current particles into the next store (cell-sorted,
+// one contiguous run per wavefront lane); max_tile_cells = widest tile's cells
+template <typename R>
+hipError_t pic_launch_sort(const DevState<R>& st, int n_species, int max_tile_cells,
+                           hipStream_t s);
 // append staged particles (list of (tile, first, count)) to the current store
 template <typename R>
 hipError_t pic_launch_inject(const DevState<R>& st, int s, int n_entries, const int* list,

@@ -46,3 +46,31 @@ def autotune(runs, load, option_kw=None, shapes=DEFAULT_SHAPES, steps=4, warmup=
     fastest = min(r["ms_per_step"] for r in table)
     best = next(r for r in table if r["ms_per_step"] <= fastest * (1.0 + TIE))
     return best, table
+
+
+def tune_sort_every(runs, load, option_kw=None, candidates=(0, 8, 16, 32), steps=64,
+                    warmup=8):
+    """Pick pic_options.sort_every (how often pic_step reorders each tile's
+    particles by cell) by timing `steps` real steps per candidate on a fresh
+    context with the given options; the kernel time of a step includes the
+    reordering launches. Within TIE of the fastest the earlier candidate wins.
+    Returns (best sort_every, table)."""
+    option_kw = dict(option_kw or {})
+    table = []
+    for k in candidates:
+        sim = Sim(runs, make_options(**dict(option_kw, sort_every=k)))
+        try:
+            load(sim)
+            sim.step(warmup)
+            sim.timing(True)
+            sim.step(steps)
+            t = sim.get_timing()
+            ms = sum(v["ms"] for name, v in t.items() if name != "graph_replays") / steps
+            table.append(dict(sort_every=k, ms_per_step=ms,
+                              push_ms=t["push"]["ms"] / max(1, t["push"]["launches"]),
+                              sort_ms=t["sort"]["ms"] / max(1, t["sort"]["launches"])))
+        finally:
+            sim.close()
+    fastest = min(r["ms_per_step"] for r in table)
+    best = next(r for r in table if r["ms_per_step"] <= fastest * (1.0 + TIE))
+    return best["sort_every"], table
