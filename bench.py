@@ -47,7 +47,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(precision, tile, tile_split, order, n_particles):
+def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every=0):
     """HBM bytes per launch of the particle kernel from the committed counter
     record (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the same
     counter reads for a copy of known size), or None when the kernel sources or
@@ -59,7 +59,8 @@ def measured_traffic(precision, tile, tile_split, order, n_particles):
             rec = json.load(f)
         cfg = rec["config"]
         if (cfg["precision"], list(cfg["tile"]), cfg["tile_split"], cfg["order"],
-                cfg["particles"]) != (precision, list(tile), tile_split, order, n_particles):
+                cfg["particles"], cfg.get("sort_every", 0)) != (precision, list(tile), tile_split,
+                                                               order, n_particles, sort_every):
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
@@ -551,7 +552,8 @@ def main():
 
     n_part = fast["n_particles"]
     achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
-    traffic, traffic_src = measured_traffic("fp32", tile, args.tile_split, cfg["order"], n_part)
+    traffic, traffic_src = measured_traffic("fp32", tile, args.tile_split, cfg["order"], n_part,
+                                            SORT)
     def solve_info(r):
         return None if r is None else dict(
             ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],

@@ -693,28 +693,28 @@ __global__ void __launch_bounds__(256) k_sort(DevState<R> st) {
     }
   }
   __syncthreads();
-  // destination order: contiguous stores, the loads gather
-  constexpr int B3 = kSortBatch / 2;
-  for (int q0 = threadIdx.x; q0 < n; q0 += (int)blockDim.x * B3) {
-    long long src[B3];
+  // destination order, one array at a time (the gathers of a work-group then
+  // stay within one array's region of the tile): contiguous stores
+  auto move = [&](auto* dst, const auto* srcp) {
+    for (int q0 = threadIdx.x; q0 < n; q0 += (int)blockDim.x * kSortBatch) {
+      int from[kSortBatch];
 #pragma unroll
-    for (int u = 0; u < B3; ++u) {
-      const int q = q0 + u * (int)blockDim.x;
-      src[u] = q < n ? base + inv[q] : -1;
-    }
+      for (int u = 0; u < kSortBatch; ++u) {
+        const int q = q0 + u * (int)blockDim.x;
+        from[u] = q < n ? inv[q] : -1;
+      }
 #pragma unroll
-    for (int u = 0; u < B3; ++u) {
-      if (src[u] < 0) continue;
-      const long long dst = base + q0 + u * (int)blockDim.x;
-      st.ncell[s][dst] = st.cell[s][src[u]];
-      st.nox[s][dst] = st.ox[s][src[u]];
-      st.noy[s][dst] = st.oy[s][src[u]];
-      st.nux[s][dst] = st.ux[s][src[u]];
-      st.nuy[s][dst] = st.uy[s][src[u]];
-      st.nuz[s][dst] = st.uz[s][src[u]];
-      if (st.id[s]) st.nid[s][dst] = st.id[s][src[u]];
+      for (int u = 0; u < kSortBatch; ++u)
+        if (from[u] >= 0) dst[base + q0 + u * (int)blockDim.x] = srcp[base + from[u]];
     }
-  }
+  };
+  move(st.ncell[s], st.cell[s]);
+  move(st.nox[s], st.ox[s]);
+  move(st.noy[s], st.oy[s]);
+  move(st.nux[s], st.ux[s]);
+  move(st.nuy[s], st.uy[s]);
+  move(st.nuz[s], st.uz[s]);
+  if (st.id[s]) move(st.nid[s], st.id[s]);
 }
 
 // Injection: staged particles (sorted by tile) are appended to the current
