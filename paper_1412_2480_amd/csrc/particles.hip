@@ -68,6 +68,19 @@ __device__ __forceinline__ int bspline_weights(R t, R (&w)[P + 1]) {
   }
 }
 
+// 1/sqrt(x) and 1/x: in the FP32 form the hardware's approximations (1 ulp,
+// against the 6e-8 unit roundoff the form already carries); in FP64 exact
+template <typename R> __device__ __forceinline__ R inv_sqrt(R x);
+template <> __device__ __forceinline__ float inv_sqrt<float>(float x) {
+  return __builtin_amdgcn_rsqf(x);
+}
+template <> __device__ __forceinline__ double inv_sqrt<double>(double x) { return 1.0 / sqrt(x); }
+template <typename R> __device__ __forceinline__ R recip(R x);
+template <> __device__ __forceinline__ float recip<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <> __device__ __forceinline__ double recip<double>(double x) { return 1.0 / x; }
+
 // sum_{jj,ii} F(x0+ii, y0+jj) wx[ii] wy[jj] from an LDS plane with pitch PW
 template <int P, typename R, typename F>
 __device__ __forceinline__ R interp(const F* f, int PW, int x0, int y0, const R (&wx)[P + 1],
@@ -234,10 +247,17 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
                                      (double)uz * uz) - 1.0);
           // ---- relativistic Boris push u^{n-1/2} -> u^{n+1/2}
           const R umx = ux + qdt_2m * ex, umy = uy + qdt_2m * ey, umz = uz + qdt_2m * ez;
-          const R gm = sqrt(R(1) + umx * umx + umy * umy + umz * umz);
-          const R tf = qdt_2m / gm;
+          R tf;
+          if constexpr (std::is_same<R, float>::value)
+            tf = qdt_2m * inv_sqrt<R>(R(1) + umx * umx + umy * umy + umz * umz);
+          else
+            tf = qdt_2m / sqrt(R(1) + umx * umx + umy * umy + umz * umz);
           const R tx_ = tf * bx, ty_ = tf * by, tz_ = tf * bz;
-          const R sf = R(2) / (R(1) + tx_ * tx_ + ty_ * ty_ + tz_ * tz_);
+          R sf;
+          if constexpr (std::is_same<R, float>::value)
+            sf = R(2) * recip<R>(R(1) + tx_ * tx_ + ty_ * ty_ + tz_ * tz_);
+          else
+            sf = R(2) / (R(1) + tx_ * tx_ + ty_ * ty_ + tz_ * tz_);
           const R sx = sf * tx_, sy = sf * ty_, sz = sf * tz_;
           const R upx = umx + (umy * tz_ - umz * ty_);
           const R upy = umy + (umz * tx_ - umx * tz_);
@@ -246,7 +266,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           uy = umy + (upz * sx - upx * sz) + qdt_2m * ey;
           uz = umz + (upx * sy - upy * sx) + qdt_2m * ez;
           // ---- move x^n -> x^{n+1}
-          const R ig = R(1) / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+          const R ig = inv_sqrt<R>(R(1) + ux * ux + uy * uy + uz * uz);
           if (diag) wk[s][1] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
                                               (double)uz * uz) - 1.0);
           R dx_ = ux * ig * dtdx, dy_ = uy * ig * dtdy;
@@ -290,7 +310,11 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             DSy[a] = place<P, R>(w1y, o1y, a) - S0y[a];
           }
           const int ax0 = lx + Ax + G, ay0 = ly + Ay + G;
-          const R vz = uz / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
+          R vz;
+          if constexpr (std::is_same<R, float>::value)
+            vz = uz * inv_sqrt<R>(R(1) + ux * ux + uy * uy + uz * uz);
+          else
+            vz = uz / sqrt(R(1) + ux * ux + uy * uy + uz * uz);
           double* jx = sJ;
           double* jy = sJ + plane;
           double* jz = sJ + 2 * plane;
