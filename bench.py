@@ -74,6 +74,8 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
 
 GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
 SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
+EXF = 0.5       # inbox slots per tile (fraction of the tile's slots): narrow tiles in the
+                # flow direction exchange up to a quarter of their particles per step
 
 
 def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
@@ -86,7 +88,7 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
                                           cg_blocks=cg_blocks, track_ids=False,
                                           tile_split=tile_split, solver=solver,
                                           learned_form=form, precond_slots=slots,
-                                          graph=GRAPH, sort_every=SORT))
+                                          graph=GRAPH, sort_every=SORT, exchange_frac=EXF))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -289,7 +291,8 @@ def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1, pai
     run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 3, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8)
     sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split,
                                           track_ids=False, solver="learned",
-                                          precond_slots=pairs, sort_every=SORT))
+                                          precond_slots=pairs, sort_every=SORT,
+                                          exchange_frac=EXF))
     for s in range(2):
         sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
     n = 2 * nx * ny * ppc
@@ -465,8 +468,12 @@ def main():
                 sim.load_particles(0, s_, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
                                    d["uz"])
         t0 = time.perf_counter()
+        # the shape search runs with reordering on (it changes the ranking);
+        # the reordering period is tuned on the chosen shape afterwards
         best, table = autotune([run], _load, dict(precision="fp32", track_ids=False,
-                                                  tile_split=8))
+                                                  tile_split=8, exchange_frac=EXF,
+                                                  sort_every=16 if args.sort_every < 0
+                                                  else args.sort_every))
         tune = dict(best={k: best[k] for k in ("tile", "tile_split", "cg_blocks",
                                                "ms_per_step")},
                     table=[{k: r[k] for k in ("tile", "tile_split", "cg_blocks",
@@ -482,7 +489,8 @@ def main():
             t0 = time.perf_counter()
             SORT, sort_table = tune_sort_every(
                 [run], _load, dict(precision="fp32", track_ids=False, tile=tile,
-                                   tile_split=args.tile_split, cg_blocks=args.cg_blocks))
+                                   tile_split=args.tile_split, cg_blocks=args.cg_blocks,
+                                   exchange_frac=EXF))
             tune["sort_every"] = SORT
             tune["sort_table"] = sort_table
             tune["seconds"] += time.perf_counter() - t0

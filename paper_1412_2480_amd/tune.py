@@ -10,7 +10,9 @@ kernels.
 """
 from . import PicError, Sim, make_options, plan
 
-DEFAULT_SHAPES = ((16, 16), (16, 32), (32, 16), (24, 24), (8, 16), (16, 8))
+# narrow tiles along x pay when the flow drifts along x and particles are
+# reordered (their inboxes need exchange_frac near 0.5)
+DEFAULT_SHAPES = ((4, 32), (8, 32), (16, 32), (16, 16), (32, 16), (2, 64), (8, 16))
 TIE = 0.02
 
 
@@ -37,6 +39,9 @@ def autotune(runs, load, option_kw=None, shapes=DEFAULT_SHAPES, steps=4, warmup=
             ms = sum(v["ms"] for k, v in t.items() if k != "graph_replays") / steps
             table.append(dict(tile=tuple(shape), tile_split=tuned["tile_split"],
                               cg_blocks=tuned["cg_blocks"], ms_per_step=ms, tuned=tuned))
+        except PicError as e:
+            if e.code != -5:      # only an exchange overflow disqualifies a shape
+                raise
         finally:
             sim.close()
     if not table:

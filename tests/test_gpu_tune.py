@@ -45,4 +45,8 @@ def test_tile_shape_search():
     shapes = [r["tile"] for r in table]
     assert (64, 64) not in shapes            # does not fit LDS: skipped by pic_plan
     assert set(shapes) == {(16, 16), (32, 16)}
-    assert best["ms_per_step"] == min(r["ms_per_step"] for r in table)
+    # the earliest candidate within the tie margin of the fastest
+    from paper_1412_2480_amd.tune import TIE
+    fastest = min(r["ms_per_step"] for r in table)
+    assert best["ms_per_step"] <= fastest * (1.0 + TIE)
+    assert best is next(r for r in table if r["ms_per_step"] <= fastest * (1.0 + TIE))
