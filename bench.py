@@ -79,7 +79,7 @@ EXF = 0.5       # inbox slots per tile (fraction of the tile's slots): narrow ti
 
 
 def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
-             form="collapsed", slots=0):
+             form="collapsed", slots=0, sort_every=None):
     from synth import loads
     Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
     run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
@@ -88,7 +88,9 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
                                           cg_blocks=cg_blocks, track_ids=False,
                                           tile_split=tile_split, solver=solver,
                                           learned_form=form, precond_slots=slots,
-                                          graph=GRAPH, sort_every=SORT, exchange_frac=EXF))
+                                          graph=GRAPH,
+                                          sort_every=SORT if sort_every is None else sort_every,
+                                          exchange_frac=EXF))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -96,13 +98,13 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
 
 
 def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0,
-              learned=None, retune=False):
+              learned=None, retune=False, sort_every=None):
     """learned: None (plain CG) or dict(form, pairs, epochs, lr): collect that
     many pairs with plain CG, train, then take the learned path."""
     solver = "learned" if learned else "cg"
     sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split, solver,
                    learned["form"] if learned else "collapsed",
-                   learned["pairs"] if learned else 0)
+                   learned["pairs"] if learned else 0, sort_every)
     n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
     train = None
     if learned:
@@ -517,9 +519,29 @@ def main():
             f"{mfma['field_solve_ms']:.3f} ms, iters {mfma['cg_iters']}")
     plain = None
     if not args.no_fp64:
+        # the baseline gets its own schedule: shape search and reordering
+        # period tuned for the FP64 form
+        t64 = dict(tile=tile, tile_split=args.tile_split, cg_blocks=args.cg_blocks,
+                   sort_every=SORT)
+        if tune is not None:
+            from paper_1412_2480_amd.tune import autotune, tune_sort_every
+            b64, _ = autotune([run], _load, dict(precision="fp64", track_ids=False, tile_split=8,
+                                                 exchange_frac=EXF, sort_every=16),
+                              shapes=((4, 32), (8, 32), (16, 32), (16, 16)))
+            k64, _ = tune_sort_every([run], _load, dict(precision="fp64", track_ids=False,
+                                                        tile=b64["tile"],
+                                                        tile_split=b64["tile_split"],
+                                                        cg_blocks=b64["cg_blocks"],
+                                                        exchange_frac=EXF),
+                                     candidates=(0, 8, 16))
+            t64 = dict(tile=tuple(b64["tile"]), tile_split=b64["tile_split"],
+                       cg_blocks=b64["cg_blocks"], sort_every=k64)
+            tune["fp64_schedule"] = dict(t64, tile=list(t64["tile"]))
+            log(f"bench: FP64 schedule: tile {t64['tile']} split {t64['tile_split']} cg_blocks "
+                f"{t64['cg_blocks']} sort_every {k64}")
         log("bench: FP64 form")
-        plain = time_form(pic, torch, cfg, load, "fp64", tile, args.steps, args.warmup,
-                          args.cg_blocks, args.tile_split)
+        plain = time_form(pic, torch, cfg, load, "fp64", t64["tile"], args.steps, args.warmup,
+                          t64["cg_blocks"], t64["tile_split"], sort_every=t64["sort_every"])
         log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
     del load
 
@@ -600,6 +622,7 @@ def main():
             "cg_iters_last_step": plain["cg_iters"],
             "speedup_of_timed_form": plain["ms_per_step"] / fast["ms_per_step"],
             "field_solve_speedup_of_timed_form": plain["field_solve_ms"] / fast["field_solve_ms"],
+            "schedule": None if tune is None else tune.get("fp64_schedule"),
         },
         "roofline": {"bound": "hbm", "kernel": "fused particle push (gather+Boris+move+deposit)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
