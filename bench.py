@@ -74,6 +74,8 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
 
 GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
 SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
+# (tile shape, reordering period) candidates of the 48-run sweep
+SWEEP_SCHEDULES = (((16, 16), 0), ((4, 32), 8), ((8, 16), 8))
 EXF = 0.5       # inbox slots per tile (fraction of the tile's slots): narrow tiles in the
                 # flow direction exchange up to a quarter of their particles per step
 
@@ -175,24 +177,42 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
         for s in range(2):
             sim.load_plasma(r, s, t["ppc"], t["gamma0"], t["T"], t["seed"])
     n_part = sum(2 * t["nx"] * t["ny"] * t["ppc"] for t in table)
-    opts = pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH)
 
-    def timed(sim):
+    def timed(sim, n=steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rc = sim.step_async(steps)
+        rc = sim.step_async(n)
         torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3 / steps
+        ms = (time.perf_counter() - t0) * 1e3 / n
         if rc != 0:
             raise RuntimeError(f"batched pic_step returned {pic.STATUS.get(rc, rc)}")
         return ms, sim.step(0)
 
-    sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False, graph=GRAPH,
-                                          tile_split=8))
+    # schedule of this mix: a few (tile shape, reordering period) candidates,
+    # each with the library's tuning of work-groups per tile and field-solve
+    # work-groups, timed over 16 steps; the fastest is timed again below
+    sched = []
+    for tile, se in SWEEP_SCHEDULES:
+        sim = pic.Sim(descs, pic.make_options("fp32", tile=tile, track_ids=False, graph=GRAPH,
+                                              tile_split=8, sort_every=se, exchange_frac=EXF))
+        for r, t in enumerate(table):
+            load_run(sim, r, t)
+        sim.step(warmup)
+        tuned = sim.tune(2)
+        sim.step(8)
+        cms, _ = timed(sim, 16)
+        sched.append(dict(tile=tile, sort_every=se, tile_split=tuned["tile_split"],
+                          cg_blocks=tuned["cg_blocks"], ms_per_step=cms))
+        sim.close()
+    best = min(sched, key=lambda r: r["ms_per_step"])
+    sim = pic.Sim(descs, pic.make_options("fp32", tile=best["tile"], track_ids=False,
+                                          graph=GRAPH, tile_split=best["tile_split"],
+                                          cg_blocks=best["cg_blocks"],
+                                          sort_every=best["sort_every"], exchange_frac=EXF))
     for r, t in enumerate(table):
         load_run(sim, r, t)
-    sim.step(warmup)
-    tuned = sim.tune(2)     # work-groups per tile and field-solve work-groups of this mix
+    sim.step(warmup + 8)
+    tuned = dict(tile_split=best["tile_split"], cg_blocks=best["cg_blocks"])
     ms, st = timed(sim)
     cg_iters = sum(sum(s["iters"]) for s in st)
     sim.close()
@@ -200,10 +220,11 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
     if learned_pairs > 0:
         # the learned aid: one network per distinct (cfl, theta) of the table,
         # trained on the pairs of that operator's first run
-        sim = pic.Sim(descs, pic.make_options("fp32", tile=(16, 16), track_ids=False,
+        sim = pic.Sim(descs, pic.make_options("fp32", tile=best["tile"], track_ids=False,
                                               graph=GRAPH, tile_split=tuned["tile_split"],
                                               cg_blocks=tuned["cg_blocks"], solver="learned",
-                                              precond_slots=learned_pairs))
+                                              precond_slots=learned_pairs,
+                                              sort_every=best["sort_every"], exchange_frac=EXF))
         for r, t in enumerate(table):
             load_run(sim, r, t)
         sim.precond_use(False)
@@ -216,7 +237,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
         train_s = time.perf_counter() - t0
         sim.precond_use(True)
         retuned = sim.tune(2, splits=(tuned["tile_split"],))
-        sim.step(warmup)
+        sim.step(warmup + 8)
         lms, lst = timed(sim)
         sim.close()
         learned = dict(ms_per_step=lms, particle_steps_per_s=n_part / (lms * 1e-3),
@@ -228,6 +249,9 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
                        max_relres=max(max(s["relres"]) for s in lst))
     sim.close()
     seq_ms = 0.0
+    # one context per run, same tile shape and reordering period
+    opts = pic.make_options("fp32", tile=best["tile"], track_ids=False, graph=GRAPH,
+                            sort_every=best["sort_every"], exchange_frac=EXF)
     for r, t in enumerate(table):
         one = pic.Sim([descs[r]], opts)
         load_run(one, 0, t)
@@ -238,7 +262,9 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
         torch.cuda.synchronize()
         seq_ms += (time.perf_counter() - t0) * 1e3 / seq_steps
         one.close()
-    return dict(runs=len(table), particles=n_part, ms_per_step=ms,
+    return dict(runs=len(table), particles=n_part, ms_per_step=ms, tile=list(best["tile"]),
+                sort_every=best["sort_every"], schedules=[dict(r, tile=list(r["tile"]))
+                                                          for r in sched],
                 tile_split=tuned["tile_split"], cg_blocks=tuned["cg_blocks"],
                 particle_steps_per_s=n_part / (ms * 1e-3), cg_iters_last_step=cg_iters,
                 sequential_ms_per_step=seq_ms, batched_speedup=seq_ms / ms, learned=learned)
@@ -549,7 +575,8 @@ def main():
     if not args.no_batched:
         log("bench: batched 48-run sweep")
         batched = batched_sweep(pic, torch, 20, 3)
-        log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs, "
+        log(f"bench: batched {batched['ms_per_step']:.3f} ms/step for {batched['runs']} runs "
+            f"(tile {tuple(batched['tile'])}, sort_every {batched['sort_every']}), "
             f"sequential {batched['sequential_ms_per_step']:.3f} ms")
         if batched["learned"]:
             bl = batched["learned"]
