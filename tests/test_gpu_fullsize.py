@@ -2,7 +2,10 @@
 
 * The benchmark workload (periodic 1024 x 256, pair plasma at gamma0 = 40,
   64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32 particle
-  path, the launch configuration bench.py times after tuning: 16 x 32 tiles,
+  path, in the launch configurations bench.py picks after tuning: 4 x 32
+  tiles with particles reordered by cell (here every 2 steps, so that the
+  measured step starts from a reordered store and ends with a reordering)
+  and inboxes of half the tile slots, and 16 x 32 tiles without reordering;
   one work-group per tile): a sample of particles pushed one by one, the
   current on sampled node boxes from the particles that can reach them, and
   the field solve on the whole grid from the GPU's own current.
@@ -30,14 +33,16 @@ def _say(m):
     sys.stdout.flush()
 
 
-def test_fullsize_fp32_step_sampled_parity():
+@pytest.mark.parametrize("tile,sort_every,exf", [((4, 32), 2, 0.5), ((16, 32), 0, 0.25)])
+def test_fullsize_fp32_step_sampled_parity(tile, sort_every, exf):
     import paper_1412_2480_amd as pic
     from synth import loads
-    _say("fullsize: generating load")
+    _say(f"fullsize: generating load (tile {tile}, sort_every {sort_every})")
     Q = loads.macro_charge(G0, DX, DX, PPC)
     ld = loads.pair_plasma_cells(NX, NY, PPC, G0, 0.01, seed=0)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 32), tile_split=1))
+    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=1, sort_every=sort_every,
+                                          exchange_frac=exf))
     for s in range(2):
         d = ld[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
