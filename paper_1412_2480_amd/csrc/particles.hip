@@ -604,10 +604,19 @@ __global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
 // particle of lane l's run. The current store is read, the next one written
 // in storage order (the reads gather through the inverse permutation).
 constexpr int kSortBatch = 8;
+// dynamic LDS of the staged reordering, leaving room for the static words
+// within the 64 KB a work-group may hold
+constexpr size_t kSortStageBytes = 63 * 1024;
 
+// Staged form: with max_slots (the largest tile's slots) small enough, the
+// permutation (16 bit) and one array's tile region at a time live in LDS, so
+// the gathers read LDS and every global access is contiguous.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sort(DevState<R> st) {
-  extern __shared__ int s_cell[];   // [cells of the widest tile]: counts, then cursors
+__global__ void __launch_bounds__(256) k_sort(DevState<R> st, int max_cells, int max_slots,
+                                              int staged) {
+  // dynamic LDS: [max_cells] counts then cursors; staged: [max_slots] u16
+  // permutation, then [max_slots] elements of the array being moved
+  extern __shared__ __align__(16) int s_cell[];
   __shared__ int s_carry;
   const int per = gridDim.x / 8;
   const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -692,6 +701,12 @@ __global__ void __launch_bounds__(256) k_sort(DevState<R> st) {
   const int L = (n + 63) / 64;
   const int full = n - 64 * (L - 1);   // lanes whose run has L particles
   int* const inv = st.old_cell[s] + base;
+  // region offsets rounded to 16 bytes (the staged elements may be FP64)
+  unsigned char* const lds = reinterpret_cast<unsigned char*>(s_cell);
+  unsigned short* const inv16 =
+      reinterpret_cast<unsigned short*>(lds + (((size_t)max_cells * 4 + 15) & ~(size_t)15));
+  unsigned char* const stage = reinterpret_cast<unsigned char*>(inv16) +
+                               (((size_t)max_slots * 2 + 15) & ~(size_t)15);
   for (int k0 = threadIdx.x; k0 < n; k0 += stride) {
     int cell[kSortBatch];
 #pragma unroll
@@ -713,10 +728,45 @@ __global__ void __launch_bounds__(256) k_sort(DevState<R> st) {
         l = full + p2 / (L - 1);
         w = p2 - (l - full) * (L - 1);
       }
-      inv[w * 64 + l] = k0 + u * (int)blockDim.x;
+      if (staged)
+        inv16[w * 64 + l] = (unsigned short)(k0 + u * (int)blockDim.x);
+      else
+        inv[w * 64 + l] = k0 + u * (int)blockDim.x;
     }
   }
   __syncthreads();
+  if (staged) {
+    // one array at a time: contiguous load of the tile region into LDS, then
+    // contiguous stores of the permuted elements
+    auto move_lds = [&](auto* dst, const auto* srcp) {
+      using T = typename std::remove_const<typename std::remove_pointer<decltype(srcp)>::type>::type;
+      T* const buf = reinterpret_cast<T*>(stage);
+      for (int k0 = threadIdx.x; k0 < n; k0 += stride) {
+        T v[kSortBatch];
+#pragma unroll
+        for (int u = 0; u < kSortBatch; ++u) {
+          const int k = k0 + u * (int)blockDim.x;
+          if (k < n) v[u] = srcp[base + k];
+        }
+#pragma unroll
+        for (int u = 0; u < kSortBatch; ++u) {
+          const int k = k0 + u * (int)blockDim.x;
+          if (k < n) buf[k] = v[u];
+        }
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < n; q += blockDim.x) dst[base + q] = buf[inv16[q]];
+      __syncthreads();
+    };
+    move_lds(st.ncell[s], st.cell[s]);
+    move_lds(st.nox[s], st.ox[s]);
+    move_lds(st.noy[s], st.oy[s]);
+    move_lds(st.nux[s], st.ux[s]);
+    move_lds(st.nuy[s], st.uy[s]);
+    move_lds(st.nuz[s], st.uz[s]);
+    if (st.id[s]) move_lds(st.nid[s], st.id[s]);
+    return;
+  }
   // destination order, one array at a time (the gathers of a work-group then
   // stay within one array's region of the tile): contiguous stores
   auto move = [&](auto* dst, const auto* srcp) {
@@ -927,8 +977,15 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
 template <typename R>
 hipError_t pic_launch_sort(const DevState<R>& st, int n_species, int max_tile_cells,
                            hipStream_t s) {
-  k_sort<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256),
-              (size_t)max_tile_cells * sizeof(int), s>>>(st);
+  int max_slots = 0;
+  for (int k = 0; k < n_species; ++k) max_slots = st.tile_slots[k] > max_slots ? st.tile_slots[k] : max_slots;
+  const size_t cells_b = (size_t)max_tile_cells * sizeof(int);
+  const size_t staged_b = ((cells_b + 15) & ~(size_t)15) +
+                          (((size_t)max_slots * 2 + 15) & ~(size_t)15) +
+                          (size_t)max_slots * (sizeof(R) > sizeof(int) ? sizeof(R) : sizeof(int));
+  const int staged = max_slots <= 65535 && staged_b <= kSortStageBytes ? 1 : 0;
+  k_sort<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), staged ? staged_b : cells_b,
+              s>>>(st, max_tile_cells, max_slots, staged);
   return hipGetLastError();
 }
 
