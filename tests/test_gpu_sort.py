@@ -33,12 +33,19 @@ def _compare(a, b, case, tol, run=0):
             assert np.abs(pa[k] - pb[k]).max() <= tol * max(1.0, np.abs(pb[k]).max()), (s, k)
 
 
-@pytest.mark.parametrize("precision,every", [("fp64", 1), ("fp64", 3), ("fp32", 2)])
-def test_sorted_run_equals_unsorted(precision, every):
-    _say(f"sort_every={every} vs none, {precision}")
-    case = Case(64, 48, 3, ppc=6, gamma0=5.0, T=0.05, seed=7, field_amp=0.3, rtol=1e-12)
-    a = case.gpu_sim(precision)
-    b = case.gpu_sim(precision, sort_every=every)
+# (precision, period, tile, ppc): at 6 particles/cell a tile reorders through
+# LDS; at 40 (12,800 slots per tile) it does not fit and takes the path that
+# gathers from global memory
+SORT_CASES = [("fp64", 1, (16, 16), 6), ("fp64", 3, (16, 16), 6), ("fp32", 2, (16, 16), 6),
+              ("fp32", 2, (16, 16), 40), ("fp64", 2, (16, 16), 40)]
+
+
+@pytest.mark.parametrize("precision,every,tile,ppc", SORT_CASES)
+def test_sorted_run_equals_unsorted(precision, every, tile, ppc):
+    _say(f"sort_every={every} vs none, {precision}, tile {tile}, ppc {ppc}")
+    case = Case(64, 48, 3, ppc=ppc, gamma0=5.0, T=0.05, seed=7, field_amp=0.3, rtol=1e-12)
+    a = case.gpu_sim(precision, tile=tile)
+    b = case.gpu_sim(precision, tile=tile, sort_every=every)
     a.timing(True)
     b.timing(True)
     a.step(7)
@@ -50,20 +57,21 @@ def test_sorted_run_equals_unsorted(precision, every):
     b.close()
 
 
-def test_sorted_storage_order():
-    """One 16 x 16 tile, ids off (reads return storage order): after a sorted
-    step, position q = 64 w + l holds the w-th particle of lane l's run of the
-    cell-sorted order (runs of L or L - 1, the longer ones first)."""
-    import paper_1412_2480_amd as pic
-    _say("sorted storage order")
-    case = Case(16, 16, 2, ppc=9, gamma0=3.0, T=0.1, seed=3, field_amp=0.2)
-    sim = case.gpu_sim("fp64", track_ids=False, sort_every=1)
+@pytest.mark.parametrize("side,ppc", [(16, 9), (16, 40)])
+def test_sorted_storage_order(side, ppc):
+    """One side x side tile, ids off (reads return storage order): after a
+    sorted step, position q = 64 w + l holds the w-th particle of lane l's run
+    of the cell-sorted order (runs of L or L - 1, the longer ones first). At
+    40 particles/cell the tile takes the global-memory path."""
+    _say(f"sorted storage order, {side}x{side} tile, ppc {ppc}")
+    case = Case(side, side, 2, ppc=ppc, gamma0=3.0, T=0.1, seed=3, field_amp=0.2)
+    sim = case.gpu_sim("fp64", tile=(side, side), track_ids=False, sort_every=1)
     sim.step(2)
     for s in range(2):
-        g = sim.read_particles(0, s, 4096)
+        g = sim.read_particles(0, s, 1 << 16)
         n = len(g["ix"])
         assert n == case.species[s].n
-        cell = g["iy"].astype(np.int64) * 16 + g["ix"]
+        cell = g["iy"].astype(np.int64) * side + g["ix"]
         L = (n + 63) // 64
         full = n - 64 * (L - 1)
         # sorted position of every storage position
