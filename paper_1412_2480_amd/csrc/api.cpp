@@ -297,7 +297,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   }
   double* part = b.take<double>((size_t)kMaxCgBlocks * 24);
   int* g_active = b.take<int>(4);
-  unsigned* bar = b.take<unsigned>(64);
+  unsigned* bar = b.take<unsigned>(kBarWords);
   double* stats = b.take<double>((size_t)n_runs * PIC_STAT_WORDS);
   // learned solver: per network the FP32 weights, their BF16 copy and
   // collapsed filter, Adam state and a ring of (b, dB) pairs; the training

