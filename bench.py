@@ -372,6 +372,71 @@ def large_share(pic, torch, steps=10, warmup=2, tile=(16, 32), tile_split=1, pai
     return out
 
 
+def shock_share(pic, torch, tile, tile_split, steps=20, warmup=2, pairs=8, epochs=50):
+    """The shock workload: 4096 x 512 with conducting walls in x, pair flow at
+    gamma0 = 40 towards the reflecting wall at x = 0, 32 ppc/species, order 2,
+    CFL 1, theta 0.6, FP32 particles, learned aid (pairs from the first
+    steps). Every step first injects the flow entering at x_out (host-generated
+    slabs, prepared before the timed region; the injection call copies them to
+    the device and is inside the timed region)."""
+    from synth import loads
+    nx, ny, ppc, g0 = 4096, 512, 32, 40.0
+    x_out = nx - pic.PIC_WALL_GAP
+    Q = loads.macro_charge(g0, 0.1, 0.1, ppc)
+    run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 2, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8,
+                       bc="shock")
+    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split, slack=1.5,
+                                          exchange_frac=EXF, track_ids=False, solver="learned",
+                                          precond_slots=pairs, sort_every=SORT))
+    for s in range(2):
+        sim.load_plasma(0, s, ppc, g0, 0.01, 0, direction=-1, x_cells=x_out)
+    total = pairs + warmup + steps
+    slabs = [loads.shock_injection(x_out, ny, ppc, g0, 0.01, 0, k, 1.0) for k in range(total)]
+
+    def inject(k):
+        for s, d in enumerate(slabs[k]):
+            sim.inject_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
+                                 d["uz"])
+    sim.precond_use(False)
+    sim.precond_collect(True)
+    for k in range(pairs):
+        inject(k)
+        sim.step(1)
+    st_plain = sim.step(0)[0]
+    sim.precond_collect(False)
+    tr = sim.precond_train(epochs, 0.0)
+    sim.precond_use(True)
+    for k in range(pairs, pairs + warmup):
+        inject(k)
+        sim.step(1)
+    torch.cuda.synchronize()
+    sim.timing(True)
+    t0 = time.perf_counter()
+    for k in range(pairs + warmup, total):
+        inject(k)
+        rc = sim.step_async(1)
+        if rc != 0:
+            raise RuntimeError(f"shock pic_step returned {pic.STATUS.get(rc, rc)}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    tim = sim.get_timing()
+    st = sim.step(0)[0]
+    d = sim.diag(0)
+    n = sum(d["n_particles"][:2])
+    sim.close()
+    return dict(workload="shock 4096x512 (walls in x, reflection at x=0, injection at x_out), "
+                         "pair flow gamma0=40, 32 ppc/species, order 2, CFL 1.0, theta 0.6 "
+                         "(FP32 particles, learned aid)",
+                particles=n, ms_per_step=ms, particle_steps_per_s=n / (ms * 1e-3),
+                push_ms=tim["push"]["ms"] / max(1, tim["push"]["launches"]),
+                field_solve_ms=tim["field_solve"]["ms"] / steps,
+                cg_iters_plain=st_plain["iters"], learned_iters=st["learned_iters"],
+                fallback=st["fallback"], max_relres=max(st["relres"]),
+                training=dict(loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
+                note="ms_per_step includes the per-step injection call (host slab copied to "
+                     "the device)")
+
+
 def cpu_baseline(cfg, seconds=15.0):
     """The FP64 oracle on a 4-row strip of the same workload (same grid width,
     ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
@@ -411,6 +476,8 @@ def main():
     ap.add_argument("--sweep-tiles", default="",
                     help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-run batched sweep")
+    ap.add_argument("--no-shock", action="store_true",
+                    help="skip the 4096x512 shock workload (walls, reflection, injection)")
     ap.add_argument("--no-large", action="store_true",
                     help="skip the 8192x2048 large single-GPU share (2.1e9 particles)")
     ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"],
@@ -595,6 +662,15 @@ def main():
             f"{large['plain_cg']['field_solve_ms']:.1f} ms plain CG, trained in "
             f"{large['training']['seconds']:.2f} s")
 
+    shock = None
+    if not args.no_shock:
+        log("bench: shock workload (4096x512, walls, injection)")
+        shock = shock_share(pic, torch, tile, max(1, args.tile_split))
+        log(f"bench: shock {shock['ms_per_step']:.2f} ms/step ({shock['particles']:.3g} "
+            f"particles), push {shock['push_ms']:.2f} ms, field solve "
+            f"{shock['field_solve_ms']:.2f} ms, CG iterations {shock['cg_iters_plain']} -> "
+            f"{shock['learned_iters']}")
+
     net = None
     if not args.no_learned:
         net = net_rate(pic, torch, cfg)
@@ -662,6 +738,7 @@ def main():
         "autotune": tune,
         "learned_net": net,
         "large_share": large,
+        "shock": shock,
         "batched_sweep": batched,
         "cpu_baseline": cpu,
     }
