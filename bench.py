@@ -72,7 +72,7 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
     return None, None
 
 
-GRAPH = False   # set from --graph: pic_step replays captured two-step HIP graphs
+GRAPH = True    # pic_step replays captured two-step HIP graphs (--no-graph: plain launches)
 SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
 # (tile shape, reordering period) candidates of the 48-run sweep
 SWEEP_SCHEDULES = (((16, 16), 0), ((4, 32), 8), ((8, 16), 8))
@@ -487,8 +487,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip the library's autotuner (tile shape, work-groups per tile, "
                          "field-solve work-groups) and use --tile/--tile-split/--cg-blocks")
-    ap.add_argument("--graph", action="store_true",
-                    help="replay captured two-step HIP graphs in every timed form")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="plain launches instead of replaying captured two-step HIP graphs in "
+                         "the timed forms")
     ap.add_argument("--sort-every", type=int, default=-1,
                     help="reorder each tile's particles by cell every n steps in the timed "
                          "forms (0 = never); default: picked by the autotuner (0 without it)")
@@ -509,7 +510,7 @@ def main():
     import paper_1412_2480_amd as pic
     from synth import loads
     global GRAPH, SORT
-    GRAPH = args.graph
+    GRAPH = not args.no_graph
     SORT = max(0, args.sort_every)
 
     cfg = CONFIGS[args.config]
@@ -709,7 +710,7 @@ def main():
                                                     f", learned aid ({args.learned_form})"),
         "data": "synthetic (seeded Maxwell-Juettner pair plasma)",
         "config": {"workload": cfg["label"], "particles": n_part, "cells": cfg["nx"] * cfg["ny"],
-                   "tile": list(tile), "sort_every": SORT, "cg_rtol": 1e-8},
+                   "tile": list(tile), "sort_every": SORT, "graph": GRAPH, "cg_rtol": 1e-8},
         "field_solve_ms_per_step": fast["field_solve_ms"],
         "cg_iters_last_step": fast["cg_iters"],
         "learned": solve_info(fast) if learned is not None else None,
