@@ -13,9 +13,15 @@ CG aid: the network is trained on the (b, dB) pairs of the first steps (solved
 by plain CG), then every timed step starts the field solve from x0 = N(b) and
 runs flexible PCG to the same 1e-8 relative residual. Training is a one-time
 set-up, timed and reported on its own. The same workload with plain CG in the
-FP32 form and the plain FP64 form are timed on the same GPU beside it. Inputs
-are synthetic (seeded Maxwell-Juettner load) and resident in HBM before the
-timed region.
+FP32 form and the plain FP64 form (on a schedule tuned for it) are timed on
+the same GPU beside it. The schedule (tile shape, work-groups per tile,
+field-solve work-groups, reordering period) is autotuned first; the timed
+steps are replayed from captured two-step HIP graphs (--no-graph: plain
+launches). Inputs are synthetic (seeded Maxwell-Juettner load) and resident
+in HBM before the timed region. Further legs: the 48-run sweep in one
+context, the large single-GPU share (8192 x 2048, 2.1e9 particles), the shock
+workload (walls, injection), the network's application rate and the CPU
+oracle on a strip of the workload.
 
 Prints one JSON line.
 """
