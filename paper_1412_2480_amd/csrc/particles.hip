@@ -607,13 +607,16 @@ constexpr int kSortBatch = 8;
 // dynamic LDS of the staged reordering, leaving room for the static words
 // within the 64 KB a work-group may hold
 constexpr size_t kSortStageBytes = 63 * 1024;
+constexpr long long kSortMaxPasses = 4;   // staging passes per array at most
 
 // Staged form: with max_slots (the largest tile's slots) small enough, the
-// permutation (16 bit) and one array's tile region at a time live in LDS, so
-// the gathers read LDS and every global access is contiguous.
+// permutation (16 bit) lives in LDS and each array's tile region is staged
+// there too, `chunk` elements at a time (one pass per chunk writes the
+// destinations whose source lies in it), so the gathers read LDS and every
+// global access is contiguous.
 template <typename R>
 __global__ void __launch_bounds__(256) k_sort(DevState<R> st, int max_cells, int max_slots,
-                                              int staged) {
+                                              int staged, int chunk) {
   // dynamic LDS: [max_cells] counts then cursors; staged: [max_slots] u16
   // permutation, then [max_slots] elements of the array being moved
   extern __shared__ __align__(16) int s_cell[];
@@ -741,22 +744,32 @@ __global__ void __launch_bounds__(256) k_sort(DevState<R> st, int max_cells, int
     auto move_lds = [&](auto* dst, const auto* srcp) {
       using T = typename std::remove_const<typename std::remove_pointer<decltype(srcp)>::type>::type;
       T* const buf = reinterpret_cast<T*>(stage);
-      for (int k0 = threadIdx.x; k0 < n; k0 += stride) {
-        T v[kSortBatch];
+      for (int c0 = 0; c0 < n; c0 += chunk) {
+        const int cn = n - c0 < chunk ? n - c0 : chunk;
+        for (int k0 = threadIdx.x; k0 < cn; k0 += stride) {
+          T v[kSortBatch];
 #pragma unroll
-        for (int u = 0; u < kSortBatch; ++u) {
-          const int k = k0 + u * (int)blockDim.x;
-          if (k < n) v[u] = srcp[base + k];
-        }
+          for (int u = 0; u < kSortBatch; ++u) {
+            const int k = k0 + u * (int)blockDim.x;
+            if (k < cn) v[u] = srcp[base + c0 + k];
+          }
 #pragma unroll
-        for (int u = 0; u < kSortBatch; ++u) {
-          const int k = k0 + u * (int)blockDim.x;
-          if (k < n) buf[k] = v[u];
+          for (int u = 0; u < kSortBatch; ++u) {
+            const int k = k0 + u * (int)blockDim.x;
+            if (k < cn) buf[k] = v[u];
+          }
         }
+        __syncthreads();
+        if (cn == n) {
+          for (int q = threadIdx.x; q < n; q += blockDim.x) dst[base + q] = buf[inv16[q]];
+        } else {
+          for (int q = threadIdx.x; q < n; q += blockDim.x) {
+            const int k = (int)inv16[q] - c0;
+            if (k >= 0 && k < cn) dst[base + q] = buf[k];
+          }
+        }
+        __syncthreads();
       }
-      __syncthreads();
-      for (int q = threadIdx.x; q < n; q += blockDim.x) dst[base + q] = buf[inv16[q]];
-      __syncthreads();
     };
     move_lds(st.ncell[s], st.cell[s]);
     move_lds(st.nox[s], st.ox[s]);
@@ -980,12 +993,19 @@ hipError_t pic_launch_sort(const DevState<R>& st, int n_species, int max_tile_ce
   int max_slots = 0;
   for (int k = 0; k < n_species; ++k) max_slots = st.tile_slots[k] > max_slots ? st.tile_slots[k] : max_slots;
   const size_t cells_b = (size_t)max_tile_cells * sizeof(int);
-  const size_t staged_b = ((cells_b + 15) & ~(size_t)15) +
-                          (((size_t)max_slots * 2 + 15) & ~(size_t)15) +
-                          (size_t)max_slots * (sizeof(R) > sizeof(int) ? sizeof(R) : sizeof(int));
-  const int staged = max_slots <= 65535 && staged_b <= kSortStageBytes ? 1 : 0;
-  k_sort<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), staged ? staged_b : cells_b,
-              s>>>(st, max_tile_cells, max_slots, staged);
+  const size_t fixed_b = ((cells_b + 15) & ~(size_t)15) + (((size_t)max_slots * 2 + 15) & ~(size_t)15);
+  const size_t elem = sizeof(R) > sizeof(int) ? sizeof(R) : sizeof(int);
+  // staging chunk: what the remaining LDS holds, in whole 256-element blocks;
+  // staged when the permutation is 16-bit and at most kSortMaxPasses passes
+  // cover the largest tile
+  long long chunk = fixed_b < kSortStageBytes ? (long long)((kSortStageBytes - fixed_b) / elem) : 0;
+  chunk = chunk / 256 * 256;
+  if (chunk > max_slots) chunk = max_slots;
+  const int staged = max_slots <= 65535 && chunk >= 256 &&
+                     chunk * kSortMaxPasses >= max_slots ? 1 : 0;
+  const size_t smem = staged ? fixed_b + (size_t)chunk * elem : cells_b;
+  k_sort<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), smem, s>>>(
+      st, max_tile_cells, max_slots, staged, staged ? (int)chunk : 0);
   return hipGetLastError();
 }
 

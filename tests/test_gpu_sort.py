@@ -33,11 +33,13 @@ def _compare(a, b, case, tol, run=0):
             assert np.abs(pa[k] - pb[k]).max() <= tol * max(1.0, np.abs(pb[k]).max()), (s, k)
 
 
-# (precision, period, tile, ppc): at 6 particles/cell a tile reorders through
-# LDS; at 40 (12,800 slots per tile) it does not fit and takes the path that
-# gathers from global memory
+# (precision, period, tile, ppc) on 16 x 16 tiles: at 6 particles/cell a
+# tile's arrays are staged in LDS whole; at 40 (12,800 slots) in 2 (FP32) or 3
+# (FP64) chunks; at 64 in FP64 and 96 in FP32 more than 4 chunks would be
+# needed and the path that gathers from global memory is taken
 SORT_CASES = [("fp64", 1, (16, 16), 6), ("fp64", 3, (16, 16), 6), ("fp32", 2, (16, 16), 6),
-              ("fp32", 2, (16, 16), 40), ("fp64", 2, (16, 16), 40)]
+              ("fp32", 2, (16, 16), 40), ("fp64", 2, (16, 16), 40),
+              ("fp64", 2, (16, 16), 64), ("fp32", 2, (16, 16), 96)]
 
 
 @pytest.mark.parametrize("precision,every,tile,ppc", SORT_CASES)
@@ -57,12 +59,13 @@ def test_sorted_run_equals_unsorted(precision, every, tile, ppc):
     b.close()
 
 
-@pytest.mark.parametrize("side,ppc", [(16, 9), (16, 40)])
+@pytest.mark.parametrize("side,ppc", [(16, 9), (16, 40), (16, 64)])
 def test_sorted_storage_order(side, ppc):
     """One side x side tile, ids off (reads return storage order): after a
     sorted step, position q = 64 w + l holds the w-th particle of lane l's run
-    of the cell-sorted order (runs of L or L - 1, the longer ones first). At
-    40 particles/cell the tile takes the global-memory path."""
+    of the cell-sorted order (runs of L or L - 1, the longer ones first). The
+    FP64 arrays are staged whole at 9 particles/cell, in 3 chunks at 40, and
+    gathered from global memory at 64."""
     _say(f"sorted storage order, {side}x{side} tile, ppc {ppc}")
     case = Case(side, side, 2, ppc=ppc, gamma0=3.0, T=0.1, seed=3, field_amp=0.2)
     sim = case.gpu_sim("fp64", tile=(side, side), track_ids=False, sort_every=1)
