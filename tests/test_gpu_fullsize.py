@@ -189,3 +189,51 @@ def test_fullsize_shock_fp32_learned():
         assert np.all(F[k][:, nx - 1] == 0), k
     assert np.abs(F["Bz"]).max() > 0
     sim.close()
+
+
+def test_fullsize_tuned_schedule_full_length():
+    """The benchmark workload for its full run length (2000 steps) in the
+    timed configuration: 4 x 32 tiles with half again the mean tile occupancy as
+    slots (the bunching after the numerical Cherenkov instability saturates
+    near step 300 overflows the default quarter), reordering every 8 steps,
+    graph replay, the learned aid trained on the first 8 solves. No inbox or
+    tile overflows in 2000 steps, the last solve of every 249-step stretch meets
+    the plain-CG residual without the fallback, every particle is kept, Gauss's
+    law holds at FP32 roundoff and the energies stay finite."""
+    import paper_1412_2480_amd as pic
+    from synth import loads
+    Q = loads.macro_charge(G0, DX, DX, PPC)
+    run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=1, sort_every=8,
+                                          exchange_frac=0.5, slack=0.5, track_ids=False,
+                                          graph=True,
+                                          solver="learned", precond_slots=8, diag_every=250,
+                                          history_cap=16))
+    for s in range(2):
+        sim.load_plasma(0, s, PPC, G0, 0.01, 0)
+    sim.precond_use(False)
+    sim.precond_collect(True)
+    sim.step(8)
+    sim.precond_collect(False)
+    tr = sim.precond_train(epochs=50)
+    assert tr["loss_last"] < 1e-3 * tr["loss_first"]
+    sim.precond_use(True)
+    for chunk in range(8):
+        st = sim.step(249)[0]
+        _say(f"  step {8 + 249 * (chunk + 1)}: learned {st['learned_iters']}, relres "
+             f"{max(st['relres']):.1e}, fallback {st['fallback']}")
+        assert st["fallback"] == 0 and max(st["relres"]) <= 1e-8
+    assert sim.get_timing()["graph_replays"] > 500
+    d = sim.diag(0, divergences=True)
+    rho_scale = 4 * np.pi * Q / (DX * DX)
+    _say(f"  gauss {d['gauss_max']:.2e} (scale {rho_scale:.2e}), particles {d['n_particles']}")
+    assert d["n_particles"][:2] == [NX * NY * PPC] * 2
+    assert d["gauss_max"] <= 1e-4 * rho_scale
+    h = sim.history(0)
+    assert len(h) >= 8
+    for r in h:
+        tot = r["W_E"] + r["W_B"] + 0.5 * (r["W_K_minus"] + r["W_K_plus"])
+        assert np.isfinite(tot) and tot > 0
+    _say("  energy history: " + ", ".join(
+        f"{r['step']}: {r['W_E'] + r['W_B']:.3e}" for r in h))
+    sim.close()
