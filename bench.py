@@ -53,7 +53,7 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every=0):
+def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every=0, warmup=0):
     """HBM bytes per launch of the particle kernel from the committed counter
     record (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the same
     counter reads for a copy of known size), or None when the kernel sources or
@@ -64,9 +64,12 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
         with open(path) as f:
             rec = json.load(f)
         cfg = rec["config"]
+        # the warm-up length counts: the hot, bunched plasma after the
+        # instability saturates moves other bytes than the cold start
         if (cfg["precision"], list(cfg["tile"]), cfg["tile_split"], cfg["order"],
-                cfg["particles"], cfg.get("sort_every", 0)) != (precision, list(tile), tile_split,
-                                                               order, n_particles, sort_every):
+                cfg["particles"], cfg.get("sort_every", 0),
+                cfg.get("warmup", 0)) != (precision, list(tile), tile_split, order, n_particles,
+                                          sort_every, warmup):
             continue
         h = hashlib.sha256()
         for src in rec["sources"]:
@@ -118,12 +121,13 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
                    learned["pairs"] if learned else 0, sort_every)
     n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
     train = None
-    # the warm-up comes first, so the learned aid is trained on pairs of the
-    # state that the timed steps see
+    # the warm-up comes first (plain CG: the network is not trained yet), so
+    # the learned aid is trained on pairs of the state that the timed steps see
+    if learned:
+        sim.precond_use(False)
     if warmup:
         sim.step(warmup)
     if learned:
-        sim.precond_use(False)
         sim.precond_collect(True)
         sim.step(learned["pairs"])
         sim.precond_collect(False)
@@ -704,7 +708,7 @@ def main():
     n_part = fast["n_particles"]
     achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
     traffic, traffic_src = measured_traffic("fp32", tile, args.tile_split, cfg["order"], n_part,
-                                            SORT)
+                                            SORT, args.warmup)
     def solve_info(r):
         return None if r is None else dict(
             ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],

@@ -1,6 +1,7 @@
 """Host logic of bench.py's traffic figure: the committed counter record is
 reported only for the launch configuration and the kernel sources it was
-taken on (a changed source, tile shape or reordering period gives null)."""
+taken on (a changed source, tile shape, reordering period or warm-up length
+gives null)."""
 import json
 import os
 import shutil
@@ -22,7 +23,8 @@ def test_record_matches_its_configuration():
     rec = _record()
     cfg = rec["config"]
     t, src = bench.measured_traffic(cfg["precision"], tuple(cfg["tile"]), cfg["tile_split"],
-                                    cfg["order"], cfg["particles"], cfg.get("sort_every", 0))
+                                    cfg["order"], cfg["particles"], cfg.get("sort_every", 0),
+                                    cfg.get("warmup", 0))
     assert t == rec["traffic_bytes"] and src.endswith(".traffic.json")
     # traffic within a few percent of the algorithmic bytes (nothing re-read)
     assert 1.0 <= rec["traffic_bytes"] / rec["algorithmic_bytes"] <= 1.1
@@ -32,9 +34,9 @@ def test_other_configurations_get_no_figure():
     rec = _record()
     cfg = rec["config"]
     args = [cfg["precision"], tuple(cfg["tile"]), cfg["tile_split"], cfg["order"],
-            cfg["particles"], cfg.get("sort_every", 0)]
+            cfg["particles"], cfg.get("sort_every", 0), cfg.get("warmup", 0)]
     for k, v in ((1, (16, 16)), (2, cfg["tile_split"] + 1), (5, cfg.get("sort_every", 0) + 1),
-                 (0, "fp64")):
+                 (6, cfg.get("warmup", 0) + 1), (0, "fp64")):
         a = list(args)
         a[k] = v
         assert bench.measured_traffic(*a) == (None, None), k
@@ -54,7 +56,7 @@ def test_changed_source_gets_no_figure(tmp_path, monkeypatch):
     monkeypatch.setattr(bench, "ROOT", str(root))
     cfg = rec["config"]
     args = (cfg["precision"], tuple(cfg["tile"]), cfg["tile_split"], cfg["order"],
-            cfg["particles"], cfg.get("sort_every", 0))
+            cfg["particles"], cfg.get("sort_every", 0), cfg.get("warmup", 0))
     assert bench.measured_traffic(*args)[0] == rec["traffic_bytes"]
     with open(root / rec["sources"][0], "a") as f:
         f.write("\n// edited\n")
