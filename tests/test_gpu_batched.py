@@ -129,3 +129,36 @@ def test_batched_learned_solver_one_network_per_operator():
             assert e <= 1e-6, (r, n, e)
     a.close()
     b.close()
+
+
+def test_sweep_table_full_length():
+    """The 48-run sweep at its full size and length (8-32 ppc/species, 500
+    steps) in one context on the schedule the sweep benchmark uses (4 x 32
+    tiles, reordering every 8 steps, inboxes of half the tile slots, slack
+    0.5): no tile or inbox overflows, every run keeps its particles, the last
+    solve of every run meets the 1e-8 residual and the field energies stay
+    finite."""
+    import paper_1412_2480_amd as pic
+    from synth import configs, loads
+    table = configs.sweep_runs()
+    descs = []
+    for t in table:
+        Q = loads.macro_charge(t["gamma0"], t["dx"], t["dx"], t["ppc"])
+        descs.append(pic.run_desc(t["nx"], t["ny"], t["dx"], t["cfl"], t["theta"], t["order"],
+                                  [(-Q, Q, t["ppc"]), (Q, Q, t["ppc"])], cg_rtol=1e-8))
+    sim = pic.Sim(descs, pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=8,
+                                          exchange_frac=0.5, slack=0.5, track_ids=False,
+                                          graph=True))
+    for r, t in enumerate(table):
+        for s in range(2):
+            sim.load_plasma(r, s, t["ppc"], t["gamma0"], t["T"], t["seed"])
+    for chunk in range(5):
+        st = sim.step(100)
+        _say(f"  step {100 * (chunk + 1)}: max relres {max(max(x['relres']) for x in st):.1e}")
+        assert all(max(x["relres"]) <= 1e-8 for x in st)
+    for r, t in enumerate(table):
+        d = sim.diag(r)
+        n = t["nx"] * t["ny"] * t["ppc"]
+        assert d["n_particles"][:2] == [n, n], r
+        assert np.isfinite(d["W_E"]) and np.isfinite(d["W_B"]), r
+    sim.close()
