@@ -17,7 +17,12 @@ FP32 form and the plain FP64 form (on a schedule tuned for it) are timed on
 the same GPU beside it. The schedule (tile shape, work-groups per tile,
 field-solve work-groups, reordering period) is autotuned first; the timed
 steps are replayed from captured two-step HIP graphs (--no-graph: plain
-launches). Inputs are synthetic (seeded Maxwell-Juettner load) and resident
+launches). The timed steps follow 300 untimed ones (--warmup): by then the
+numerical Cherenkov instability of the drifting plasma has saturated, and the
+timed steps see the hot, bunched state in which a 2000-step run spends most
+of its steps (the particle kernel is ~40% slower there than at the cold
+start); the tuner's candidates get the same warm-up, and the learned aid is
+trained on pairs taken after it. Inputs are synthetic (seeded Maxwell-Juettner load) and resident
 in HBM before the timed region. Further legs: the 48-run sweep in one
 context, the large single-GPU share (8192 x 2048, 2.1e9 particles), the shock
 workload (walls, injection), the network's application rate and the CPU
