@@ -187,20 +187,41 @@ __device__ void net_apply_tile_collapsed(const NetWeights& W, int X0, int Y0, in
       if (act[c]) sx[c * E * E + e] = rd(c, i, j);
   }
   __syncthreads();
-  for (int cell = tid; cell < NET_KT * NET_KT; cell += nthr) {
-    const int u = cell % NET_KT, v = cell / NET_KT;
+  // each thread forms two vertically adjacent outputs from 8 staged rows:
+  // per row 7 values and that row's 7 filter weights are read once, the
+  // previous row's weights serve the lower output (112 LDS reads for 2 x 49
+  // products instead of 196); each sum keeps a single output's order
+  for (int pr = tid; pr < NET_KT * NET_KT / 2; pr += nthr) {
+    const int u = pr % NET_KT, v = 2 * (pr / NET_KT);
     const int i = X0 + u, j = Y0 + v;
     if (i >= nx || j >= ny) continue;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       if (!act[c]) continue;
       const double* x = sx + c * E * E;
-      double acc = 0.0;
+      double a0 = 0.0, a1 = 0.0;
+      double kp[7];
 #pragma unroll 1
-      for (int dy = 0; dy < 7; ++dy)
+      for (int dy = 0; dy < 8; ++dy) {
+        double row[7], kc[7];
 #pragma unroll
-        for (int dx = 0; dx < 7; ++dx) acc += sk[dy * 7 + dx] * x[(v + dy) * E + (u + dx)];
-      wr(c, i, j, acc);
+        for (int dx = 0; dx < 7; ++dx) {
+          row[dx] = x[(v + dy) * E + (u + dx)];
+          kc[dx] = dy < 7 ? sk[dy * 7 + dx] : 0.0;
+        }
+        if (dy < 7) {
+#pragma unroll
+          for (int dx = 0; dx < 7; ++dx) a0 += kc[dx] * row[dx];
+        }
+        if (dy >= 1) {
+#pragma unroll
+          for (int dx = 0; dx < 7; ++dx) a1 += kp[dx] * row[dx];
+        }
+#pragma unroll
+        for (int dx = 0; dx < 7; ++dx) kp[dx] = kc[dx];
+      }
+      wr(c, i, j, a0);
+      if (j + 1 < ny) wr(c, i, j + 1, a1);
     }
   }
   __syncthreads();
