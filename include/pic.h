@@ -123,8 +123,8 @@ typedef struct pic_options {
   int32_t learned_maxit; /* iteration budget of the learned PCG before the plain-CG
                             fallback; 0 = 30 */
   int32_t precond_slots; /* (b, dB) training pairs kept (ring); 0 = 16 */
-  int32_t graph;         /* 1: pic_step replays HIP graphs of two captured steps (the
-                            particle double buffer returns to its arrangement after two)
+  int32_t graph;         /* 1: pic_step replays HIP graphs of two captured steps (one
+                            per buffer parity, reordering pattern and solver variant)
                             whenever no diagnostics record, timing or pair collection
                             falls in them; 0: plain launches */
   int32_t sort_every;    /* pic_step reorders every tile's particles by cell every

@@ -124,11 +124,12 @@ struct pic_ctx {
   int parity = 0;                 // particle buffer swaps since init, mod 2
   int max_cg_blocks = 0;          // co-resident limit of the field-solve grid
   int cg_cap = 0;                 // requested work-groups of the field solve
-  // graph mode: executable graphs of two steps per starting parity
+  // graph mode: executable graphs of two steps per starting parity and
+  // reordering pattern (index parity + 2 * pattern, see graph_two_steps)
   bool graph_ok = true;
   hipStream_t cap_stream = nullptr;
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int gkey[2] = {-1, -1};
+  hipGraphExec_t gexec[8] = {};
+  int gkey[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   long long graph_replays = 0;
   long long diag_count = 0;
   std::vector<long long> hist_step;  // steps recorded (host mirror)
@@ -742,28 +743,29 @@ int do_step(pic_ctx* c) {
   return PIC_OK;
 }
 
-// Graph mode: two steps are captured once per starting buffer parity (and
-// solver variant) on an internal stream and replayed on the caller's stream.
-// Everything a step reads that changes between steps lives in device memory
-// (counts, fields, weights); what is baked into the graph (buffer pointers,
-// the solver variant, the diagnostics/collection switches) is the key.
+// Graph mode: two steps are captured once per starting buffer parity,
+// reordering pattern and solver variant on an internal stream and replayed
+// on the caller's stream. Everything a step reads that changes between steps
+// lives in device memory (counts, fields, weights); what is baked into the
+// graph (buffer pointers, which of the two steps end with a reordering, the
+// solver variant, the diagnostics/collection switches) is the key.
 bool graph_usable(pic_ctx* c) {
   if (!c->opt.graph || !c->graph_ok || c->timing || c->collect) return false;
   const int de = c->opt.diag_every;
   if (de > 0 && ((c->step % de) == 0 || ((c->step + 1) % de) == 0)) return false;
-  // a reordering in the two steps would change the buffer pattern captured
-  if (sort_step(c, c->step) || sort_step(c, c->step + 1)) return false;
   return true;
 }
 
 template <typename R>
 int graph_two_steps(pic_ctx* c) {
-  const int par = c->parity;
+  // bit 0: the first step ends with a reordering, bit 1: the second
+  const int pattern = (sort_step(c, c->step) ? 1 : 0) | (sort_step(c, c->step + 1) ? 2 : 0);
+  const int slot = c->parity + 2 * pattern;
   const int key = c->use_learned ? 1 : 0;
-  if (!c->gexec[par] || c->gkey[par] != key) {
-    if (c->gexec[par]) {
-      (void)hipGraphExecDestroy(c->gexec[par]);
-      c->gexec[par] = nullptr;
+  if (!c->gexec[slot] || c->gkey[slot] != key) {
+    if (c->gexec[slot]) {
+      (void)hipGraphExecDestroy(c->gexec[slot]);
+      c->gexec[slot] = nullptr;
     }
     if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
       c->graph_ok = false;
@@ -771,6 +773,10 @@ int graph_two_steps(pic_ctx* c) {
     }
     hipStream_t user = c->stream;
     const long long step0 = c->step, pairs0 = c->pairs_written, diag0 = c->diag_count;
+    // the capture swaps the host's buffer pointers as the two steps do (twice
+    // for the re-binnings, once per reordering): on success they stand where
+    // the first replay leaves the device, on failure they are put back
+    const int parity0 = c->parity;
     c->stream = c->cap_stream;
     c->fa.coop = 0;
     hipGraph_t g = nullptr;
@@ -793,14 +799,23 @@ int graph_two_steps(pic_ctx* c) {
     if (g) (void)hipGraphDestroy(g);
     if (rc != PIC_OK) {
       // capture is not available: stay with plain launches from now on
+      if (c->parity != parity0) {
+        swap_buffers(state<R>(c));
+        c->parity = parity0;
+      }
       c->graph_ok = false;
       (void)hipGetLastError();
       return rc;
     }
-    c->gexec[par] = ex;
-    c->gkey[par] = key;
+    c->gexec[slot] = ex;
+    c->gkey[slot] = key;
+  } else if (pattern == 1 || pattern == 2) {
+    // a replay of a cached graph with one reordering: the device buffers end
+    // swapped once against the start
+    swap_buffers(state<R>(c));
+    c->parity ^= 1;
   }
-  HIPCHK(c, hipGraphLaunch(c->gexec[par], c->stream));
+  HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream));
   c->step += 2;
   c->graph_replays += 1;
   return PIC_OK;
@@ -1802,10 +1817,10 @@ int32_t pic_tune(pic_ctx* c, const pic_tune_opts* o, pic_tune_out* out) {
                            hipMemcpyHostToDevice, c->stream));
   res.cg_blocks = c->fa.n_blocks;
   // captured graphs hold the old grids
-  for (int p = 0; p < 2; ++p)
-    if (c->gexec[p]) {
-      (void)hipGraphExecDestroy(c->gexec[p]);
-      c->gexec[p] = nullptr;
+  for (auto& g : c->gexec)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
     }
   t_resolve(c);
   c->timing = timing0;

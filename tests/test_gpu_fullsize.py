@@ -3,10 +3,11 @@
 * The benchmark workload (periodic 1024 x 256, pair plasma at gamma0 = 40,
   64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32 particle
   path, in the launch configurations bench.py picks after tuning: 4 x 32
-  tiles with particles reordered by cell (here every 2 steps, so that the
-  measured step starts from a reordered store and ends with a reordering)
-  and inboxes of half the tile slots, and 16 x 32 tiles without reordering;
-  one work-group per tile): a sample of particles pushed one by one, the
+  tiles, two work-groups per tile, particles reordered by cell (here every 2
+  steps, so that the measured step starts from a reordered store and ends
+  with a reordering), inboxes of half the tile slots and slack 0.5; and
+  16 x 32 tiles, one work-group per tile, without reordering): a sample of
+  particles pushed one by one, the
   current on sampled node boxes from the particles that can reach them, and
   the field solve on the whole grid from the GPU's own current.
 * The shock workload (4096 x 512 with walls, flow at gamma0 = 40 towards the
@@ -33,16 +34,17 @@ def _say(m):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("tile,sort_every,exf", [((4, 32), 2, 0.5), ((16, 32), 0, 0.25)])
-def test_fullsize_fp32_step_sampled_parity(tile, sort_every, exf):
+@pytest.mark.parametrize("tile,split,sort_every,exf,slack",
+                         [((4, 32), 2, 2, 0.5, 0.5), ((16, 32), 1, 0, 0.25, 0.25)])
+def test_fullsize_fp32_step_sampled_parity(tile, split, sort_every, exf, slack):
     import paper_1412_2480_amd as pic
     from synth import loads
     _say(f"fullsize: generating load (tile {tile}, sort_every {sort_every})")
     Q = loads.macro_charge(G0, DX, DX, PPC)
     ld = loads.pair_plasma_cells(NX, NY, PPC, G0, 0.01, seed=0)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=1, sort_every=sort_every,
-                                          exchange_frac=exf))
+    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=split,
+                                          sort_every=sort_every, exchange_frac=exf, slack=slack))
     for s in range(2):
         d = ld[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -193,9 +195,10 @@ def test_fullsize_shock_fp32_learned():
 
 def test_fullsize_tuned_schedule_full_length():
     """The benchmark workload for its full run length (2000 steps) in the
-    timed configuration: 4 x 32 tiles with half again the mean tile occupancy as
-    slots (the bunching after the numerical Cherenkov instability saturates
-    near step 300 overflows the default quarter), reordering every 8 steps,
+    timed configuration: 4 x 32 tiles, two work-groups per tile, half again
+    the mean tile occupancy as slots (the bunching after the numerical
+    Cherenkov instability saturates near step 300 overflows the default
+    quarter), reordering every 4 steps,
     graph replay, the learned aid trained on the first 8 solves. No inbox or
     tile overflows in 2000 steps, the last solve of every 249-step stretch meets
     the plain-CG residual without the fallback, every particle is kept, Gauss's
@@ -204,7 +207,7 @@ def test_fullsize_tuned_schedule_full_length():
     from synth import loads
     Q = loads.macro_charge(G0, DX, DX, PPC)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=1, sort_every=8,
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=4,
                                           exchange_frac=0.5, slack=0.5, track_ids=False,
                                           graph=True,
                                           solver="learned", precond_slots=8, diag_every=250,

@@ -118,14 +118,19 @@ def test_sorted_shock_run_with_injection():
     b.close()
 
 
-def test_sorted_graph_mode():
-    _say("graph mode with sort_every=4")
+@pytest.mark.parametrize("sort_every", [4, 3, 1])
+def test_sorted_graph_mode(sort_every):
+    """Every two-step window replays from a graph, also those that end a step
+    with a reordering (period 4: after the second step; 3: after the first or
+    the second, from either buffer parity; 1: after both), and the run agrees
+    with plain launches without reordering."""
+    _say(f"graph mode with sort_every={sort_every}")
     case = Case(48, 32, 2, ppc=4, gamma0=5.0, T=0.05, seed=9, field_amp=0.3, rtol=1e-12)
     a = case.gpu_sim("fp64")
-    b = case.gpu_sim("fp64", graph=True, sort_every=4)
-    a.step(12)
-    b.step(12)
-    assert b.get_timing()["graph_replays"] > 0
+    b = case.gpu_sim("fp64", graph=True, sort_every=sort_every)
+    a.step(24)
+    b.step(24)
+    assert b.get_timing()["graph_replays"] == 12
     _compare(a, b, case, 1e-12)
     a.close()
     b.close()
