@@ -22,11 +22,11 @@ numerical Cherenkov instability of the drifting plasma has saturated, and the
 timed steps see the hot, bunched state in which a 2000-step run spends most
 of its steps (the particle kernel is ~40% slower there than at the cold
 start); the tuner's candidates get the same warm-up, and the learned aid is
-trained on pairs taken after it. Inputs are synthetic (seeded Maxwell-Juettner load) and resident
-in HBM before the timed region. Further legs: the 48-run sweep in one
-context, the large single-GPU share (8192 x 2048, 2.1e9 particles), the shock
-workload (walls, injection), the network's application rate and the CPU
-oracle on a strip of the workload.
+trained on the pairs of the first steps, before it. Inputs are synthetic
+(seeded Maxwell-Juettner load) and resident in HBM before the timed region.
+Further legs: the 48-run sweep in one context, the large single-GPU share
+(8192 x 2048, 2.1e9 particles), the shock workload (walls, injection), the
+network's application rate and the CPU oracle on a strip of the workload.
 
 Prints one JSON line.
 """
@@ -120,20 +120,18 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
 def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0, tile_split=0,
               learned=None, retune=False, sort_every=None):
     """learned: None (plain CG) or dict(form, pairs, epochs, lr): collect that
-    many pairs with plain CG, train, then take the learned path."""
+    many pairs with plain CG in the first steps, train, then take the learned
+    path for the warm-up and the timed steps (as a run would: trained on
+    the first steps' pairs the network needs 3 iterations per component after
+    the instability has saturated, trained on pairs taken there 4)."""
     solver = "learned" if learned else "cg"
     sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split, solver,
                    learned["form"] if learned else "collapsed",
                    learned["pairs"] if learned else 0, sort_every)
     n_part = 2 * cfg["nx"] * cfg["ny"] * cfg["ppc"]
     train = None
-    # the warm-up comes first (plain CG: the network is not trained yet), so
-    # the learned aid is trained on pairs of the state that the timed steps see
     if learned:
         sim.precond_use(False)
-    if warmup:
-        sim.step(warmup)
-    if learned:
         sim.precond_collect(True)
         sim.step(learned["pairs"])
         sim.precond_collect(False)
@@ -147,6 +145,8 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
             # the learned solver has its own best field-solve grid: re-tune it
             # on this context (the work-groups per tile stay as chosen)
             train["retune"] = sim.tune(2, splits=(max(1, tile_split),))
+    if warmup:
+        sim.step(warmup)
     torch.cuda.synchronize()
     # event timing switches graph replay off, so with graphs the timed region
     # runs without events and a few plain steps afterwards give the breakdown
@@ -335,11 +335,11 @@ def large_share(pic, torch, steps=10, warmup=300, tile=(16, 32), tile_split=1, p
                 epochs=50):
     """The large single-GPU share: periodic 8192 x 2048, pair plasma at
     gamma0 = 40, 64 ppc/species (2.1e9 particles), order 3, CFL 1, theta 0.6,
-    FP32 particles, loaded on the device, with the learned aid: `warmup`
-    untimed plain-CG steps (past the saturation of the numerical Cherenkov
-    instability, as in the 1024 x 256 form), then `pairs` steps of plain CG
-    (timed, and recorded as training pairs), training, and the timed steps on
-    the learned solver."""
+    FP32 particles, loaded on the device, with the learned aid: the first
+    `pairs` steps run plain CG (timed, and recorded as training pairs), the
+    network is trained, `warmup` untimed steps on the learned solver take the
+    run past the saturation of the numerical Cherenkov instability (as in the
+    1024 x 256 form), then the timed steps."""
     from synth import loads
     nx, ny, ppc = 8192, 2048, 64
     Q = loads.macro_charge(40.0, 0.1, 0.1, ppc)
@@ -351,11 +351,8 @@ def large_share(pic, torch, steps=10, warmup=300, tile=(16, 32), tile_split=1, p
     for s in range(2):
         sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
     n = 2 * nx * ny * ppc
-    sim.precond_use(False)
-    if warmup:
-        log(f"bench: large share: {warmup} untimed steps")
-        sim.step(warmup)
     # plain CG steps, recorded as training pairs
+    sim.precond_use(False)
     sim.precond_collect(True)
     sim.timing(True)
     torch.cuda.synchronize()
@@ -371,7 +368,9 @@ def large_share(pic, torch, steps=10, warmup=300, tile=(16, 32), tile_split=1, p
     train_s = time.perf_counter() - t0
     sim.precond_use(True)
     retune = sim.tune(1, splits=(tile_split,))
-    sim.step(2)
+    if warmup:
+        log(f"bench: large share: {warmup} untimed steps")
+        sim.step(warmup)
     torch.cuda.synchronize()
     sim.timing(True)
     t0 = time.perf_counter()
