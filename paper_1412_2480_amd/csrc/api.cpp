@@ -762,7 +762,8 @@ int graph_two_steps(pic_ctx* c) {
   const int pattern = (sort_step(c, c->step) ? 1 : 0) | (sort_step(c, c->step + 1) ? 2 : 0);
   const int slot = c->parity + 2 * pattern;
   const int key = c->use_learned ? 1 : 0;
-  if (!c->gexec[slot] || c->gkey[slot] != key) {
+  const bool cached = c->gexec[slot] && c->gkey[slot] == key;
+  if (!cached) {
     if (c->gexec[slot]) {
       (void)hipGraphExecDestroy(c->gexec[slot]);
       c->gexec[slot] = nullptr;
@@ -809,13 +810,14 @@ int graph_two_steps(pic_ctx* c) {
     }
     c->gexec[slot] = ex;
     c->gkey[slot] = key;
-  } else if (pattern == 1 || pattern == 2) {
+  }
+  HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream));
+  if (cached && (pattern == 1 || pattern == 2)) {
     // a replay of a cached graph with one reordering: the device buffers end
-    // swapped once against the start
+    // swapped once against the start (a fresh capture has swapped already)
     swap_buffers(state<R>(c));
     c->parity ^= 1;
   }
-  HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream));
   c->step += 2;
   c->graph_replays += 1;
   return PIC_OK;
