@@ -622,7 +622,7 @@ def main():
                 [run], _load, dict(precision="fp32", track_ids=False, tile=tile,
                                    tile_split=args.tile_split, cg_blocks=args.cg_blocks,
                                    exchange_frac=EXF, slack=SLACK),
-                candidates=(0, 4, 8, 16), warmup=args.warmup)
+                candidates=(0, 3, 4, 8, 16), warmup=args.warmup)
             tune["sort_every"] = SORT
             tune["sort_table"] = sort_table
             tune["seconds"] += time.perf_counter() - t0
