@@ -59,6 +59,20 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def run_leg(name, fn):
+    """Run one secondary leg of the benchmark: its result, or {"error": ...}
+    when it raises (the line still prints the timed form's figures). The
+    failed leg's context, and with it its workspace, is released before the
+    next leg allocates."""
+    try:
+        return fn()
+    except Exception as e:
+        log(f"bench: {name} failed: {type(e).__name__}: {e}")
+        err = {"error": f"{type(e).__name__}: {e}"}
+    gc.collect()
+    return err
+
+
 def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every=0, warmup=0):
     """HBM bytes per launch of the particle kernel from the committed counter
     record (rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by what the same
@@ -675,17 +689,6 @@ def main():
         log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
     del load
 
-    def leg(name, fn):
-        # a secondary leg that fails is reported in the line; the timed form's
-        # figures above still print
-        try:
-            return fn()
-        except Exception as e:
-            log(f"bench: {name} failed: {type(e).__name__}: {e}")
-            err = {"error": f"{type(e).__name__}: {e}"}
-        gc.collect()     # releases the failed leg's context and its workspace
-        return err
-
     def run_batched():
         log("bench: batched 48-run sweep")
         b = batched_sweep(pic, torch, 20, 3)
@@ -731,11 +734,11 @@ def main():
         log("bench: oracle CPU baseline")
         return cpu_baseline(cfg, args.cpu_seconds)
 
-    batched = None if args.no_batched else leg("batched sweep", run_batched)
-    large = None if args.no_large else leg("large share", run_large)
-    shock = None if args.no_shock else leg("shock workload", run_shock)
-    net = None if args.no_learned else leg("network rate", run_net)
-    cpu = None if args.no_cpu else leg("CPU baseline", run_cpu)
+    batched = None if args.no_batched else run_leg("batched sweep", run_batched)
+    large = None if args.no_large else run_leg("large share", run_large)
+    shock = None if args.no_shock else run_leg("shock workload", run_shock)
+    net = None if args.no_learned else run_leg("network rate", run_net)
+    cpu = None if args.no_cpu else run_leg("CPU baseline", run_cpu)
 
     n_part = fast["n_particles"]
     achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9

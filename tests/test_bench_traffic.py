@@ -1,7 +1,8 @@
-"""Host logic of bench.py's traffic figure: the committed counter record is
-reported only for the launch configuration and the kernel sources it was
-taken on (a changed source, tile shape, reordering period or warm-up length
-gives null)."""
+"""Host logic of bench.py: the committed counter record is reported as the
+traffic figure only for the launch configuration and the kernel sources it
+was taken on (a changed source, tile shape, reordering period or warm-up
+length gives null); a secondary leg that fails is reported in the line and
+its resources are released."""
 import json
 import os
 import shutil
@@ -61,3 +62,23 @@ def test_changed_source_gets_no_figure(tmp_path, monkeypatch):
     with open(root / rec["sources"][0], "a") as f:
         f.write("\n// edited\n")
     assert bench.measured_traffic(*args) == (None, None)
+
+
+def test_failed_leg_is_reported_not_raised():
+    class Held:
+        alive = 0
+
+        def __init__(self):
+            Held.alive += 1
+
+        def __del__(self):
+            Held.alive -= 1
+
+    def failing():
+        ctx = Held()   # stands for a context holding a workspace
+        raise RuntimeError(f"batched pic_step returned PIC_E_CAPACITY ({ctx is not None})")
+
+    out = bench.run_leg("batched sweep", failing)
+    assert out == {"error": "RuntimeError: batched pic_step returned PIC_E_CAPACITY (True)"}
+    assert Held.alive == 0
+    assert bench.run_leg("network rate", lambda: {"ms": 1.0}) == {"ms": 1.0}
