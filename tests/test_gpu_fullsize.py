@@ -198,7 +198,7 @@ def test_fullsize_tuned_schedule_full_length():
     timed configuration: 4 x 32 tiles, two work-groups per tile, half again
     the mean tile occupancy as slots (the bunching after the numerical
     Cherenkov instability saturates near step 300 overflows the default
-    quarter), reordering every 4 steps,
+    quarter), reordering every 3 steps,
     graph replay, the learned aid trained on the first 8 solves. No inbox or
     tile overflows in 2000 steps, the last solve of every 249-step stretch meets
     the plain-CG residual without the fallback, every particle is kept, Gauss's
@@ -207,7 +207,7 @@ def test_fullsize_tuned_schedule_full_length():
     from synth import loads
     Q = loads.macro_charge(G0, DX, DX, PPC)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=4,
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=3,
                                           exchange_frac=0.5, slack=0.5, track_ids=False,
                                           graph=True,
                                           solver="learned", precond_slots=8, diag_every=250,
