@@ -44,6 +44,16 @@ def lib():
     return _lib
 
 
+def set_threads(n):
+    """OpenMP threads of the oracle's loops (results depend on the count only
+    through the fixed order of the per-thread partial sums)."""
+    lib().ora_set_threads(int(n))
+
+
+def get_threads():
+    return int(lib().ora_get_threads())
+
+
 def _d(a):
     assert a.dtype == np.float64 and a.flags.c_contiguous
     return a.ctypes.data_as(_D)
@@ -186,6 +196,12 @@ def update(nx, ny, dx, dy, dt, theta, e3, b3, db3, j3):
                      ctypes.c_double(theta), _dpp(e3), _dpp(b3), _dpp(db3), _dpp(j3))
 
 
+def update_explicit(nx, ny, dx, dy, dt, e3, b3, j3):
+    """Explicit FDTD advance of Eqs. (3)-(4) in place (B at integer times)."""
+    lib().ora_update_explicit(nx, ny, ctypes.c_double(dx), ctypes.c_double(dy),
+                              ctypes.c_double(dt), _dpp(e3), _dpp(b3), _dpp(j3))
+
+
 def charge(nx, ny, order, dx, dy, p, rho=None):
     rho = np.zeros((ny, nx)) if rho is None else rho
     lib().ora_charge(nx, ny, order, ctypes.c_double(dx), ctypes.c_double(dy),
@@ -290,17 +306,22 @@ class Sim:
     After step(): J holds J^{n+1/2} of the step just taken, `last` holds that
     step's record (energies, CG iterations and residuals).
     bc: "periodic" (both directions) or "shock" (walls in x, see oracle.h).
+    scheme: "implicit" (Eqs. (5)-(7), the paper's solver) or "explicit"
+    (the Yee FDTD of Eqs. (3)-(4), periodic only; theta is not used).
     """
 
     def __init__(self, nx, ny, dx, dy, cfl, theta, order, species, rtol=1e-8, maxit=200,
-                 bc="periodic"):
+                 bc="periodic", scheme="implicit"):
         self.nx, self.ny, self.dx, self.dy = nx, ny, float(dx), float(dy)
         self.dt = cfl * dx        # sigma = c dt/dx with c = 1 (Sec. 3.1)
         self.theta, self.order = float(theta), int(order)
         self.species = species
         self.rtol, self.maxit = rtol, maxit
         assert bc in ("periodic", "shock")
+        assert scheme in ("implicit", "explicit")
+        assert scheme == "implicit" or bc == "periodic"
         self.bc = bc
+        self.scheme = scheme
         self.next_id = [p.n for p in species]
         self.E = [np.zeros((ny, nx)) for _ in range(3)]
         self.B = [np.zeros((ny, nx)) for _ in range(3)]
@@ -345,6 +366,10 @@ class Sim:
 
     def field_solve(self, x0=None):
         nx, ny, dx, dy, dt, th = self.nx, self.ny, self.dx, self.dy, self.dt, self.theta
+        if self.scheme == "explicit":
+            B0 = [a.copy() for a in self.B]
+            update_explicit(nx, ny, dx, dy, dt, self.E, self.B, self.J)
+            return [b - a for a, b in zip(B0, self.B)], [0, 0, 0], [0.0, 0.0, 0.0]
         wall = self.bc == "shock"
         b = (rhs_wall if wall else rhs)(nx, ny, dx, dy, dt, th, self.E, self.B, self.J)
         db, its, rels = [], [], []

@@ -1,5 +1,5 @@
 """Compile the C oracle into oracle/liboracle.so with gcc (plain FP64, no
-fast-math, no FMA contraction). TEST INFRASTRUCTURE ONLY."""
+fast-math, no FMA contraction, OpenMP threads). TEST INFRASTRUCTURE ONLY."""
 import os
 import subprocess
 
@@ -12,8 +12,8 @@ def build(force=True):
     if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(src):
         return LIB
     tmp = LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fPIC",
-           "-shared", "-o", tmp, src, "-lm"]
+    cmd = ["gcc", "-O2", "-std=c99", "-D_DEFAULT_SOURCE", "-ffp-contract=off", "-fopenmp",
+           "-fPIC", "-shared", "-o", tmp, src, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
     return LIB

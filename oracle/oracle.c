@@ -13,8 +13,34 @@
 #include "oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads: particle loops and grid loops run over OpenMP threads with a
+ * static schedule (independent iterations). Sums into shared arrays (the
+ * deposit, the charge) go to one buffer per thread, which are then added in
+ * thread order; dot products add per-thread partial sums in thread order.
+ * The result is therefore a fixed function of the thread count. */
+static int g_default_threads = 0;   /* OMP_NUM_THREADS or the cores, as at first use */
+void ora_set_threads(int n) {
+  if (g_default_threads == 0) g_default_threads = omp_get_max_threads();
+  omp_set_num_threads(n > 0 ? n : g_default_threads);
+}
+int ora_get_threads(void) { return omp_get_max_threads(); }
+
+/* loops shorter than this run on one thread (thread start-up would dominate) */
+#define ORA_PAR_MIN 32768
+
+/* sum of nt per-thread buffers of n values into out (out += buf[0] + ...) */
+static void add_buffers(int64_t n, int nt, double* const* buf, double* out) {
+#pragma omp parallel for schedule(static) if (n >= ORA_PAR_MIN)
+  for (int64_t k = 0; k < n; ++k) {
+    double v = out[k];
+    for (int t = 0; t < nt; ++t) v += buf[t][k];
+    out[k] = v;
+  }
+}
 
 static inline int wrapi(int i, int n) { int r = i % n; return r < 0 ? r + n : r; }
 static inline int64_t at(int nx, int ny, int i, int j) {
@@ -52,6 +78,7 @@ static const double STAG_Y[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
 void ora_gather(int nx, int ny, int order, const double* const* f6,
                 int64_t np, const int32_t* ix, const int32_t* iy,
                 const double* fx, const double* fy, double* out6) {
+#pragma omp parallel for schedule(static) if (np >= ORA_PAR_MIN)
   for (int64_t k = 0; k < np; ++k) {
     for (int c = 0; c < 6; ++c) {
       double sum = 0.0;
@@ -76,6 +103,7 @@ void ora_gather(int nx, int ny, int order, const double* const* f6,
  *   u   = u+ + (q dt/2m) E                                                   */
 void ora_boris(int64_t np, double qdt_2m, const double* e3, const double* b3,
                double* ux, double* uy, double* uz) {
+#pragma omp parallel for schedule(static) if (np >= ORA_PAR_MIN)
   for (int64_t k = 0; k < np; ++k) {
     double ex = e3[k], ey = e3[np + k], ez = e3[2 * np + k];
     double bx = b3[k], by = b3[np + k], bz = b3[2 * np + k];
@@ -121,6 +149,7 @@ static void advance(int32_t* cell, double* off, double disp) {
 void ora_move(int64_t np, double dt, double dx, double dy,
               const double* ux, const double* uy, const double* uz,
               int32_t* ix, int32_t* iy, double* fx, double* fy) {
+#pragma omp parallel for schedule(static) if (np >= ORA_PAR_MIN)
   for (int64_t k = 0; k < np; ++k) {
     double g = sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]);
     advance(&ix[k], &fx[k], dt * ux[k] / (g * dx));
@@ -137,14 +166,14 @@ void ora_move(int64_t np, double dt, double dx, double dy,
  *   Jz(i, j)     =  q vz Wz(i, j)/(dx dy).
  * The window of 6 nodes per axis, [i0-2, i0+3], holds both supports for all
  * orders because a particle moves less than one cell per step. */
-void ora_deposit(int nx, int ny, int order, double dx, double dy, double dt,
-                 double q, int64_t np,
+static void deposit_range(int nx, int ny, int order, double dx, double dy, double dt,
+                          double q, int64_t k0, int64_t k1,
                  const int32_t* ix0, const int32_t* iy0, const double* fx0, const double* fy0,
                  const int32_t* ix1, const int32_t* iy1, const double* fx1, const double* fy1,
                  const double* ux, const double* uy, const double* uz,
                  double* jx, double* jy, double* jz) {
   enum { W = 6 };
-  for (int64_t k = 0; k < np; ++k) {
+  for (int64_t k = k0; k < k1; ++k) {
     double s0x[W], s1x[W], dsx[W], s0y[W], s1y[W], dsy[W];
     int bi = ix0[k] - 2, bj = iy0[k] - 2;
     for (int a = 0; a < W; ++a) {
@@ -180,6 +209,40 @@ void ora_deposit(int nx, int ny, int order, double dx, double dy, double dt,
         jz[at(nx, ny, bi + a, bj + b)] += cz * wz;
       }
   }
+}
+
+void ora_deposit(int nx, int ny, int order, double dx, double dy, double dt,
+                 double q, int64_t np,
+                 const int32_t* ix0, const int32_t* iy0, const double* fx0, const double* fy0,
+                 const int32_t* ix1, const int32_t* iy1, const double* fx1, const double* fy1,
+                 const double* ux, const double* uy, const double* uz,
+                 double* jx, double* jy, double* jz) {
+  const int nt = np >= ORA_PAR_MIN ? omp_get_max_threads() : 1;
+  if (nt == 1) {
+    deposit_range(nx, ny, order, dx, dy, dt, q, 0, np, ix0, iy0, fx0, fy0, ix1, iy1, fx1, fy1,
+                  ux, uy, uz, jx, jy, jz);
+    return;
+  }
+  /* thread t deposits the particles [t np/nt, (t+1) np/nt) into its own
+   * zeroed copies of Jx, Jy, Jz; the copies are then added in thread order */
+  const int64_t n = (int64_t)nx * ny;
+  double** buf = malloc(sizeof(double*) * 3 * nt);
+  for (int t = 0; t < 3 * nt; ++t) buf[t] = calloc((size_t)n, sizeof(double));
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    deposit_range(nx, ny, order, dx, dy, dt, q, np * t / nt, np * (t + 1) / nt, ix0, iy0, fx0,
+                  fy0, ix1, iy1, fx1, fy1, ux, uy, uz, buf[3 * t], buf[3 * t + 1],
+                  buf[3 * t + 2]);
+  }
+  double* const out[3] = {jx, jy, jz};
+  for (int c = 0; c < 3; ++c) {
+    double* bc[nt];
+    for (int t = 0; t < nt; ++t) bc[t] = buf[3 * t + c];
+    add_buffers(n, nt, bc, out[c]);
+  }
+  for (int t = 0; t < 3 * nt; ++t) free(buf[t]);
+  free(buf);
 }
 
 void ora_wrap_periodic(int nx, int ny, int64_t np, int32_t* ix, int32_t* iy) {
@@ -224,6 +287,7 @@ void ora_rhs(int nx, int ny, double dx, double dy, double dt, double theta,
              const double* const* e3, const double* const* b3, const double* const* j3,
              double* const* b_out) {
   const double four_pi = 4.0 * M_PI;
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       double cj[3], ce[3];
@@ -240,14 +304,30 @@ void ora_rhs(int nx, int ny, double dx, double dy, double dt, double theta,
 void ora_apply_A(int nx, int ny, double dx, double dy, double dt, double theta,
                  const double* x, double* y) {
   double a = (theta * dt) * (theta * dt);
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i)
       y[at(nx, ny, i, j)] = x[at(nx, ny, i, j)] - a * lap(nx, ny, dx, dy, x, i, j);
 }
 
 static double dot(int64_t n, const double* a, const double* b) {
+  const int nt = n >= ORA_PAR_MIN ? omp_get_max_threads() : 1;
+  if (nt == 1) {
+    double s = 0.0;
+    for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+    return s;
+  }
+  /* per-thread partial sums over contiguous ranges, added in thread order */
+  double part[nt];
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    double s = 0.0;
+    for (int64_t k = n * t / nt; k < n * (t + 1) / nt; ++k) s += a[k] * b[k];
+    part[t] = s;
+  }
   double s = 0.0;
-  for (int64_t k = 0; k < n; ++k) s += a[k] * b[k];
+  for (int t = 0; t < nt; ++t) s += part[t];
   return s;
 }
 
@@ -268,6 +348,7 @@ static int cg_generic(int64_t n, void (*apply)(const void*, const double*, doubl
   double* p = malloc(sizeof(double) * n);
   double* q = malloc(sizeof(double) * n);
   apply(ctx, x, q);
+#pragma omp parallel for schedule(static) if (n >= ORA_PAR_MIN)
   for (int64_t k = 0; k < n; ++k) {
     r[k] = b[k] - q[k];
     p[k] = r[k];
@@ -277,12 +358,14 @@ static int cg_generic(int64_t n, void (*apply)(const void*, const double*, doubl
   while (it < maxit && sqrt(rr) > rtol * bnorm) {
     apply(ctx, p, q);
     double alpha = rr / dot(n, p, q);
+#pragma omp parallel for schedule(static) if (n >= ORA_PAR_MIN)
     for (int64_t k = 0; k < n; ++k) {
       x[k] += alpha * p[k];
       r[k] -= alpha * q[k];
     }
     double rr_new = dot(n, r, r);
     double beta = rr_new / rr;
+#pragma omp parallel for schedule(static) if (n >= ORA_PAR_MIN)
     for (int64_t k = 0; k < n; ++k) p[k] = r[k] + beta * p[k];
     rr = rr_new;
     ++it;
@@ -325,6 +408,7 @@ void ora_update(int nx, int ny, double dx, double dy, double dt, double theta,
     for (int64_t k = 0; k < n; ++k) bt[c][k] = b3[c][k] + theta * db3[c][k];
   }
   const double four_pi = 4.0 * M_PI;
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       double cb[3];
@@ -340,10 +424,52 @@ void ora_update(int nx, int ny, double dx, double dy, double dt, double theta,
   }
 }
 
-void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
-                const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
-                double* rho) {
-  for (int64_t k = 0; k < np; ++k)
+/* Explicit FDTD (Yee) variant of the field advance, Eqs. (3)-(4): leapfrog
+ * with B at half steps, B^{n+1/2} = B^{n-1/2} - c dt curl E^n and
+ * E^{n+1} = E^n + c dt curl B^{n+1/2} - 4 pi dt J^{n+1/2}. The particles are
+ * pushed with B at integer time, carried here as B^n = (B^{n-1/2} +
+ * B^{n+1/2})/2, so the advance from (E^n, B^n) is three sweeps:
+ *   B^{n+1/2} = B^n - (c dt/2) curl_E E^n
+ *   E^{n+1}   = E^n + c dt curl_B B^{n+1/2} - 4 pi dt J^{n+1/2}
+ *   B^{n+1}   = B^{n+1/2} - (c dt/2) curl_E E^{n+1}
+ * whose half-step values satisfy Eqs. (3)-(4) exactly. */
+void ora_update_explicit(int nx, int ny, double dx, double dy, double dt, double* const* e3,
+                         double* const* b3, const double* const* j3) {
+  const int64_t n = (int64_t)nx * ny;
+  const double four_pi = 4.0 * M_PI;
+  double* bh[3];
+  for (int c = 0; c < 3; ++c) bh[c] = malloc(sizeof(double) * n);
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double ce[3];
+      curl_e(nx, ny, dx, dy, (const double* const*)e3, i, j, ce);
+      for (int c = 0; c < 3; ++c) bh[c][at(nx, ny, i, j)] = b3[c][at(nx, ny, i, j)] - 0.5 * dt * ce[c];
+    }
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double cb[3];
+      curl_b(nx, ny, dx, dy, (const double* const*)bh, i, j, cb);
+      for (int c = 0; c < 3; ++c) {
+        const int64_t k = at(nx, ny, i, j);
+        e3[c][k] += dt * cb[c] - four_pi * dt * j3[c][k];
+      }
+    }
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      double ce[3];
+      curl_e(nx, ny, dx, dy, (const double* const*)e3, i, j, ce);
+      for (int c = 0; c < 3; ++c) b3[c][at(nx, ny, i, j)] = bh[c][at(nx, ny, i, j)] - 0.5 * dt * ce[c];
+    }
+  for (int c = 0; c < 3; ++c) free(bh[c]);
+}
+
+static void charge_range(int nx, int ny, int order, double dx, double dy, double q, int64_t k0,
+                         int64_t k1, const int32_t* ix, const int32_t* iy, const double* fx,
+                         const double* fy, double* rho) {
+  for (int64_t k = k0; k < k1; ++k)
     for (int j = iy[k] - 2; j <= iy[k] + 3; ++j) {
       double wy = ora_shape(order, (double)(iy[k] - j) + fy[k]);
       for (int i = ix[k] - 2; i <= ix[k] + 3; ++i) {
@@ -351,6 +477,28 @@ void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64
         rho[at(nx, ny, i, j)] += q * wx * wy / (dx * dy);
       }
     }
+}
+
+void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64_t np,
+                const int32_t* ix, const int32_t* iy, const double* fx, const double* fy,
+                double* rho) {
+  const int nt = np >= ORA_PAR_MIN ? omp_get_max_threads() : 1;
+  if (nt == 1) {
+    charge_range(nx, ny, order, dx, dy, q, 0, np, ix, iy, fx, fy, rho);
+    return;
+  }
+  const int64_t n = (int64_t)nx * ny;
+  double** buf = malloc(sizeof(double*) * nt);
+  for (int t = 0; t < nt; ++t) buf[t] = calloc((size_t)n, sizeof(double));
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    charge_range(nx, ny, order, dx, dy, q, np * t / nt, np * (t + 1) / nt, ix, iy, fx, fy,
+                 buf[t]);
+  }
+  add_buffers(n, nt, buf, rho);
+  for (int t = 0; t < nt; ++t) free(buf[t]);
+  free(buf);
 }
 
 void ora_div_e(int nx, int ny, double dx, double dy, const double* ex, const double* ey,
@@ -370,9 +518,18 @@ void ora_div_b(int nx, int ny, double dx, double dy, const double* bx, const dou
 }
 
 double ora_kinetic(int64_t np, double m, const double* ux, const double* uy, const double* uz) {
+  const int nt = np >= ORA_PAR_MIN ? omp_get_max_threads() : 1;
+  double part[nt];
+#pragma omp parallel num_threads(nt)
+  {
+    const int t = omp_get_thread_num();
+    double s = 0.0;
+    for (int64_t k = np * t / nt; k < np * (t + 1) / nt; ++k)
+      s += m * (sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]) - 1.0);
+    part[t] = s;
+  }
   double s = 0.0;
-  for (int64_t k = 0; k < np; ++k)
-    s += m * (sqrt(1.0 + ux[k] * ux[k] + uy[k] * uy[k] + uz[k] * uz[k]) - 1.0);
+  for (int t = 0; t < nt; ++t) s += part[t];
   return s;
 }
 
@@ -549,6 +706,7 @@ void ora_rhs_wall(int nx, int ny, double dx, double dy, double dt, double theta,
                   const double* const* e3, const double* const* b3, const double* const* j3,
                   double* const* b_out) {
   const double four_pi = 4.0 * M_PI;
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= ORA_PAR_MIN)
   for (int j = 0; j < ny; ++j)
     for (int i = 0; i < nx; ++i) {
       double cj[3], ce[3];

@@ -30,6 +30,12 @@
 extern "C" {
 #endif
 
+/* OpenMP threads of the following calls (n <= 0: back to the default,
+ * OMP_NUM_THREADS or the host's cores); results are a fixed function of the
+ * thread count. */
+void ora_set_threads(int n);
+int ora_get_threads(void);
+
 /* B-spline shape of degree `order` (1, 2 or 3), evaluated at distance d in
  * cell units; shared by gather and charge assignment (Sec. 1, Sec. 3). */
 double ora_shape(int order, double d);
@@ -91,6 +97,14 @@ int ora_cg(int nx, int ny, double dx, double dy, double dt, double theta,
 void ora_update(int nx, int ny, double dx, double dy, double dt, double theta,
                 double* const* e3, double* const* b3, const double* const* db3,
                 const double* const* j3);
+
+/* Explicit FDTD (Yee) field advance of Eqs. (3)-(4) (the scheme the paper
+ * contrasts with the implicit one, Sec. 2): B carried at integer times for
+ * the particle push as the mean of the half-step values; E^n, B^n -> E^{n+1},
+ * B^{n+1} with J^{n+1/2}, periodic. Stable for c dt sqrt(1/dx^2 + 1/dy^2) <= 1;
+ * a vacuum mode's amplification obeys Eq. (16). */
+void ora_update_explicit(int nx, int ny, double dx, double dy, double dt, double* const* e3,
+                         double* const* b3, const double* const* j3);
 
 /* Charge density at nodes, rho(i,j) += q S(X-i) S(Y-j)/(dx dy). */
 void ora_charge(int nx, int ny, int order, double dx, double dy, double q, int64_t np,

@@ -83,6 +83,16 @@ def omega_explicit(S):
     return 2.0 * np.arcsin(S)
 
 
+def z_explicit(S):
+    """Both amplification factors z = exp(i omega dt) of Eq. (16):
+    sin^2(omega dt/2) = S^2 gives z + 1/z = 2 - 4 S^2, so
+    z = 1 - 2 S^2 +- 2 S sqrt(S^2 - 1) (complex, |z| = 1, for S <= 1; real
+    with |z| > 1 for S > 1, the Courant instability)."""
+    S = np.asarray(S, dtype=np.complex128)
+    r = 2.0 * S * np.sqrt(S * S - 1.0)
+    return 1.0 - 2.0 * S * S + r, 1.0 - 2.0 * S * S - r
+
+
 def cherenkov_ky(kx_dx, V, sigma_x, sigma_y):
     """Eq. (17): ky dy where omega = V kx meets Eq. (15); NaN where none."""
     # omega dt = V kx dt = V sigma_x (kx dx) with c = 1

@@ -239,3 +239,118 @@ def test_cherenkov_locus_on_cn_surface():
     assert ok.sum() > 10
     S = np.hypot(*spectral.S_param(kx[ok], ky[ok], sigma, sigma))
     assert np.allclose(spectral.omega_cn(S), V * sigma * kx[ok], atol=1e-12)
+
+
+# ---------------------------------------------------------------- explicit FDTD (Eqs. (3)-(4))
+def _mode_map(ora, nx, ny, dx, dy, k, kind, step):
+    """3x3 one-step map of a scheme on the complex amplitudes of one Fourier
+    mode of the TE (Ex, Ey, Bz) or TM (Ez, Bx, By) triple, each component
+    projected at its own staggered points."""
+    jj, ii = np.mgrid[0:ny, 0:nx]
+    if kind == "TE":
+        comps = [("E", 0, (0.5, 0.0)), ("E", 1, (0.0, 0.5)), ("B", 2, (0.5, 0.5))]
+    else:
+        comps = [("E", 2, (0.0, 0.0)), ("B", 0, (0.0, 0.5)), ("B", 1, (0.5, 0.0))]
+
+    def phase(s):
+        return np.exp(1j * (k[0] * (ii + s[0]) * dx + k[1] * (jj + s[1]) * dy))
+
+    M = np.zeros((3, 3), dtype=complex)
+    for col, (f, c, s) in enumerate(comps):
+        E = [np.zeros((ny, nx)) for _ in range(3)]
+        B = [np.zeros((ny, nx)) for _ in range(3)]
+        (E if f == "E" else B)[c][...] = np.real(phase(s))
+        step(E, B)
+        for row, (f2, c2, s2) in enumerate(comps):
+            arr = (E if f2 == "E" else B)[c2]
+            M[row, col] = 2.0 * np.sum(arr * np.conj(phase(s2))) / (nx * ny)
+    return M
+
+
+@pytest.mark.parametrize("sigma", [0.3, 0.5, 0.7])
+@pytest.mark.parametrize("kind", ["TE", "TM"])
+def test_explicit_vacuum_mode_eq16(ora, sigma, kind):
+    """The explicit FDTD advance moves a vacuum Fourier mode by the roots of
+    Eq. (16): the one-step map on the mode has eigenvalues
+    z = 1 - 2S^2 +- 2S sqrt(S^2 - 1) (|z| = 1 below the Courant limit) and 1
+    (the static mode)."""
+    nx, ny, dx, dy = 16, 12, 0.1, 0.1
+    dt = sigma * dx
+    k = (2 * np.pi * 3 / (nx * dx), 2 * np.pi * 2 / (ny * dy))
+    S = np.hypot(*spectral.S_param(k[0] * dx, k[1] * dy, dt / dx, dt / dy))
+    J0 = [np.zeros((ny, nx)) for _ in range(3)]
+    M = _mode_map(ora, nx, ny, dx, dy, k, kind,
+                  lambda E, B: ora.update_explicit(nx, ny, dx, dy, dt, E, B, J0))
+    ev = sorted(np.linalg.eigvals(M), key=lambda z: abs(z - 1.0))
+    em = sorted(ev[1:], key=lambda z: z.imag)
+    want = sorted(spectral.z_explicit(S), key=lambda z: z.imag)
+    assert abs(ev[0] - 1.0) < 1e-9
+    for a, b in zip(em, want):
+        assert abs(a - b) < 1e-10, (em, want)
+    assert abs(abs(want[0]) - 1.0) < 1e-14
+    # the phase of the root is Eq. (16)'s omega dt
+    assert abs(abs(np.angle(want[1])) - spectral.omega_explicit(S)) < 1e-12
+
+
+def test_explicit_courant_instability(ora):
+    """Beyond the Courant limit (sigma = 0.8 > 1/sqrt(2) at dx = dy) a short
+    mode (k dx = k dy = 5 pi/6, S = 0.8 sqrt(2) sin(5 pi/12) > 1) grows by the
+    real root of Eq. (16) with |z| > 1 per step."""
+    nx = ny = 12
+    dx = dy = 0.1
+    dt = 0.8 * dx
+    k = (5 * np.pi / 6 / dx, 5 * np.pi / 6 / dy)
+    S = np.hypot(*spectral.S_param(5 * np.pi / 6, 5 * np.pi / 6, 0.8, 0.8))
+    assert S > 1.0
+    J0 = [np.zeros((ny, nx)) for _ in range(3)]
+    M = _mode_map(ora, nx, ny, dx, dy, k, "TM",
+                  lambda E, B: ora.update_explicit(nx, ny, dx, dy, dt, E, B, J0))
+    ev = np.linalg.eigvals(M)
+    zp, zm = spectral.z_explicit(S)
+    assert abs(zm.imag) < 1e-15 and abs(zm.real) > 1.0
+    assert min(abs(ev - zm)) < 1e-9 and min(abs(ev - zp)) < 1e-9
+
+
+def test_explicit_is_the_yee_leapfrog(ora):
+    """Two explicit steps from (E^0, B^0) with currents J^{1/2}, J^{3/2}
+    reproduce the leapfrog of Eqs. (3)-(4) written out here with B at half
+    steps (B^{1/2} = B^0 - dt/2 curl E^0): E^1, E^2 agree, and the carried
+    B^1 is the mean of B^{1/2} and B^{3/2}."""
+    nx, ny, dx, dy = 20, 14, 0.1, 0.08
+    dt = 0.5 * dx
+    rng = np.random.default_rng(17)
+    E, B, J0 = _random_state(rng, nx, ny, dx, dy)
+    J1 = [rng.normal(size=(ny, nx)) for _ in range(3)]
+    Eh = [a.copy() for a in E]
+    bh0 = [b - 0.5 * dt * c for b, c in zip(B, _curl_e(nx, ny, dx, dy, Eh))]
+    e1 = [e + dt * c - 4 * np.pi * dt * j for e, c, j in zip(Eh, _curl_b(nx, ny, dx, dy, bh0), J0)]
+    bh1 = [b - dt * c for b, c in zip(bh0, _curl_e(nx, ny, dx, dy, e1))]
+    e2 = [e + dt * c - 4 * np.pi * dt * j for e, c, j in zip(e1, _curl_b(nx, ny, dx, dy, bh1), J1)]
+    ora.update_explicit(nx, ny, dx, dy, dt, E, B, J0)
+    for c in range(3):
+        assert np.abs(E[c] - e1[c]).max() <= 1e-12 * np.abs(e1[c]).max()
+        assert np.abs(B[c] - 0.5 * (bh0[c] + bh1[c])).max() <= 1e-12 * np.abs(bh1[c]).max()
+    ora.update_explicit(nx, ny, dx, dy, dt, E, B, J1)
+    for c in range(3):
+        assert np.abs(E[c] - e2[c]).max() <= 1e-12 * np.abs(e2[c]).max()
+
+
+def test_explicit_vacuum_energy_invariant(ora):
+    """In vacuum the Yee leapfrog conserves sum(E^n . E^n + B^{n-1/2} . B^{n+1/2})
+    below the Courant limit, with B^{n -/+ 1/2} = B^n +/- dt/2 curl E^n."""
+    nx, ny, dx, dy = 16, 16, 0.1, 0.1
+    dt = 0.6 * dx
+    rng = np.random.default_rng(5)
+    E, B, _ = _random_state(rng, nx, ny, dx, dy)
+    J0 = [np.zeros((ny, nx)) for _ in range(3)]
+
+    def invariant():
+        ce = _curl_e(nx, ny, dx, dy, E)
+        bm = [b + 0.5 * dt * c for b, c in zip(B, ce)]
+        bp = [b - 0.5 * dt * c for b, c in zip(B, ce)]
+        return sum(float((e * e).sum()) for e in E) + sum(float((a * b).sum())
+                                                          for a, b in zip(bm, bp))
+    w0 = invariant()
+    for _ in range(25):
+        ora.update_explicit(nx, ny, dx, dy, dt, E, B, J0)
+        assert abs(invariant() / w0 - 1) < 1e-12

@@ -59,6 +59,41 @@ def _particles(ora, rng, n, nx, ny, lo=3, hi=None):
 STAG = [(0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5)]
 
 
+def _second_moment(order, t):
+    """sum_i S_p(t - i) i^2 - t^2: (p+1)/12 for p >= 2, frac(t)(1 - frac(t))
+    for p = 1 (closed forms of the B-spline's second moment)."""
+    f = t - np.floor(t)
+    return np.full_like(t, (order + 1) / 12.0) if order >= 2 else f * (1 - f)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_gather_quadratic_pins_shape_order_per_axis(ora, order):
+    """A field quadratic in one coordinate of each component's own staggered
+    points gathers to t^2 + m_p(t) along that axis, with m_p the order-p
+    second moment: every component must use the full order-p shape in both
+    directions (momentum-conserving interpolation, the same shape as the
+    deposit). A component interpolated with a lower order along its staggered
+    direction, or a wrong stagger offset, fails."""
+    nx = ny = 20
+    rng = np.random.default_rng(40 + order)
+    p = _particles(ora, rng, 300, nx, ny, lo=4, hi=nx - 4)
+    J, I = np.mgrid[0:ny, 0:nx].astype(float)
+    X = p.ix + p.fx
+    Y = p.iy + p.fy
+    for axis in (0, 1):
+        f = []
+        for sx, sy in STAG:
+            t = (I + sx) if axis == 0 else (J + sy)
+            f.append(0.2 + t * t)
+        g = ora.gather(nx, ny, order, f, p)
+        for c, (sx, sy) in enumerate(STAG):
+            # sum_i S(P - s - i) (i + s)^2 = P^2 + m_p(P - s), P the particle's
+            # coordinate and s the component's stagger along the axis
+            P, sh = (X, sx) if axis == 0 else (Y, sy)
+            want = 0.2 + P ** 2 + _second_moment(order, P - sh)
+            assert np.allclose(g[c], want, rtol=0, atol=1e-11), (axis, c)
+
+
 @pytest.mark.parametrize("order", ORDERS)
 def test_gather_uniform_and_linear(ora, order):
     """Uniform fields are reproduced exactly; a field linear in the physical

@@ -187,3 +187,94 @@ def test_crank_nicolson_vacuum_energy_with_walls():
         sim.field_solve()
     w1 = sum(sim.field_energy())
     assert abs(w1 - w0) <= 1e-10 * w0
+
+
+# staggered offsets (cells) of Ex, Ey, Ez, Bx, By, Bz on the Yee grid
+STAG = [(0.5, 0.0), (0.0, 0.5), (0.0, 0.0), (0.0, 0.5), (0.5, 0.0), (0.5, 0.5)]
+ODD = (False, True, True, True, False, False)   # conductor image of each component
+
+
+def _near_wall(order, n=300, seed=0):
+    rng = np.random.default_rng(seed + order)
+    # within the reach of the shape behind the wall: x in [0, 2.5) cells
+    return _p(rng.uniform(0.0, 2.5, n), rng.uniform(3.0, 7.0, n), np.zeros(n), np.zeros(n),
+              np.zeros(n))
+
+
+def _interp_x(order, X, s, value_at):
+    """sum_i S_p(X - s - i) value_at(i) over the support (numpy, for the
+    values that a wrong image rule would give)"""
+    out = np.zeros_like(X)
+    for k, x in enumerate(X):
+        for i in range(int(np.floor(x - s)) - 2, int(np.floor(x - s)) + 3):
+            out[k] += oracle.shape(order, x - s - i) * value_at(i)
+    return out
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_wall_gather_odd_images(order):
+    """Integer-x components (Ey, Ez, Bx) vanish on the wall line and continue
+    as odd images behind it: a field a x (y + 1) with x their own coordinate
+    is reproduced exactly at every particle near the wall, as the odd
+    extension of a x is a x itself. An even image, or a mirror one column off,
+    would give other values there (checked below: the shape reaches behind
+    the wall)."""
+    nx, ny = 24, 10
+    p = _near_wall(order)
+    X, Y = p.ix + p.fx, p.iy + p.fy
+    J, I = np.mgrid[0:ny, 0:nx].astype(float)
+    f = []
+    for (sx, sy), odd in zip(STAG, ODD):
+        f.append(0.7 * (I + sx) * (J + sy + 1.0) if odd else np.zeros((ny, nx)))
+    g = oracle.gather_wall(nx, ny, order, f, p)
+    for c, odd in enumerate(ODD):
+        if odd:
+            assert np.allclose(g[c], 0.7 * X * (Y + 1.0), rtol=0, atol=1e-12), c
+    # the test separates the image rules: along x, an even image (|i|) or a
+    # mirror one column off (i + 1 behind the wall) differ from x itself
+    # (the linear shape of order 1 never reaches an integer column behind x = 0)
+    exact = _interp_x(order, X, 0.0, lambda i: float(i))
+    assert np.allclose(exact, X, atol=1e-12)
+    for wrong in (lambda i: float(abs(i)), lambda i: float(i if i >= 0 else i + 1)):
+        d = np.abs(_interp_x(order, X, 0.0, wrong) - X).max()
+        assert (d > 1e-2) if order >= 2 else (d < 1e-12)
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_wall_gather_even_images(order):
+    """Half-integer-x components (Ex, By, Bz) continue as even images about
+    the wall line (index -i-1 mirrors i, both at distance i + 1/2): a field
+    b + x^2 in their own coordinate gathers to b + X^2 + m_p(X - 1/2), the
+    value of the even extension (the shape's second moment m_p is (p+1)/12
+    for p >= 2 and f(1 - f) for p = 1). A uniform field is reproduced exactly.
+    An odd image or a mirror one column off would give other values."""
+    nx, ny = 24, 10
+    p = _near_wall(order, seed=10)
+    X = p.ix + p.fx
+    J, I = np.mgrid[0:ny, 0:nx].astype(float)
+    f = []
+    for (sx, sy), odd in zip(STAG, ODD):
+        f.append(np.zeros((ny, nx)) if odd else 0.4 + (I + sx) ** 2)
+    g = oracle.gather_wall(nx, ny, order, f, p)
+    t = X - 0.5
+    fr = t - np.floor(t)
+    m = (order + 1) / 12.0 if order >= 2 else fr * (1 - fr)
+    want = 0.4 + X ** 2 + m
+    for c, odd in enumerate(ODD):
+        if not odd:
+            assert np.allclose(g[c], want, rtol=0, atol=1e-11), c
+    u = [np.zeros((ny, nx)) if odd else np.full((ny, nx), -1.3) for odd in ODD]
+    gu = oracle.gather_wall(nx, ny, order, u, p)
+    for c, odd in enumerate(ODD):
+        if not odd:
+            assert np.allclose(gu[c], -1.3, rtol=0, atol=1e-13), c
+    # the test separates the image rules: index i >= 0 holds 0.4 + (i + 1/2)^2;
+    # behind the wall the even image (index -i-1) holds the same function of
+    # the position, an odd image its negative, a mirror one column off (-i)
+    # the value one cell further out
+    val = lambda i: 0.4 + (i + 0.5) ** 2
+    exact = _interp_x(order, X, 0.5, lambda i: val(i) if i >= 0 else val(-i - 1))
+    assert np.allclose(exact, want, atol=1e-11)
+    for wrong in (lambda i: val(i) if i >= 0 else -val(-i - 1),
+                  lambda i: val(i) if i >= 0 else val(-i)):
+        assert np.abs(_interp_x(order, X, 0.5, wrong) - want).max() > 1e-2
