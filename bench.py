@@ -1,32 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the PIC hot path on one MI355X.
 
-Workload (default): periodic 1024 x 256 grid, dx = 0.1 c/omega_pe, pair plasma
-at gamma0 = 40 with T = 0.01 m c^2, 64 particles/cell/species (33,554,432
-particles), cubic (order-3) shape, CFL 1.0, theta = 0.6, field CG to 1e-8.
-One step = gather + Boris push + move + Esirkepov deposit of every particle,
-tile re-binning, the current reduction and the implicit field solve (RHS of
-Eq. (7), CG, update of Eqs. (5)-(6)).
+Headline workload (the largest single-GPU configuration): periodic
+8192 x 2048 grid, dx = 0.1 c/omega_pe, pair plasma at gamma0 = 40 with
+T = 0.01 m c^2, 64 particles/cell/species (2^31 = 2,147,483,648 particles,
+FP32 SoA, loaded on the device from the seeded generator), cubic (order-3)
+shape, CFL 1.0, theta = 0.6, field CG to 1e-8, FP32 particles with the
+learned CG aid. One step = gather + Boris push + move + Esirkepov deposit of
+every particle, tile re-binning, the current reduction and the implicit
+field solve (RHS of Eq. (7), learned PCG, update of Eqs. (5)-(6)).
 
-The timed form is the FP32 particle path (FP64 fields and CG) with the learned
-CG aid: the network is trained on the (b, dB) pairs of the first steps (solved
-by plain CG), then every timed step starts the field solve from x0 = N(b) and
-runs flexible PCG to the same 1e-8 relative residual. Training is a one-time
-set-up, timed and reported on its own. The same workload with plain CG in the
-FP32 form and the plain FP64 form (on a schedule tuned for it) are timed on
-the same GPU beside it. The schedule (tile shape, work-groups per tile,
-field-solve work-groups, reordering period) is autotuned first; the timed
-steps are replayed from captured two-step HIP graphs (--no-graph: plain
-launches). The timed steps follow 300 untimed ones (--warmup): by then the
-numerical Cherenkov instability of the drifting plasma has saturated, and the
-timed steps see the hot, bunched state in which a 2000-step run spends most
-of its steps (the particle kernel is ~40% slower there than at the cold
-start); the tuner's candidates get the same warm-up, and the learned aid is
-trained on the pairs of the first steps, before it. Inputs are synthetic
-(seeded Maxwell-Juettner load) and resident in HBM before the timed region.
-Further legs: the 48-run sweep in one context, the large single-GPU share
-(8192 x 2048, 2.1e9 particles), the shock workload (walls, injection), the
-network's application rate and the CPU oracle on a strip of the workload.
+The network is trained on the (b, dB) pairs of the first steps, solved by
+plain CG (those steps also give the plain-CG field-solve time); training is a
+one-time set-up, timed and reported on its own and folded into a whole-run
+figure. Then --warmup untimed steps and --steps timed steps; the particle
+kernel's launches inside the timed region are timed with HIP events on the
+context's stream (the roofline's achieved bandwidth). The same workload is
+then taken on, untimed, past the saturation of the numerical Cherenkov
+instability (--saturated-after steps) and timed again: the state in which a
+long run spends most of its steps.
+
+Further legs: the 1024 x 256 single run (FP32 + learned, FP32 with plain CG,
+and the plain FP64 form on a schedule tuned for it: the FP32-vs-FP64 factor
+on the same GPU), the 48-run sweep in one context, the shock workload
+(walls, device injection), the explicit FDTD variant against the implicit
+scheme, the network's application rate, and the FP64 CPU oracle on a strip of
+the headline workload (one thread and all threads).
 
 Prints one JSON line.
 """
@@ -43,6 +42,13 @@ sys.path.insert(0, ROOT)
 # algorithmic HBM bytes per particle-step: read + write of the particle state
 BYTES_PER_PARTICLE = {"fp32": 2 * (4 + 5 * 4), "fp64": 2 * (4 + 5 * 8)}
 HBM_PEAK_GBS = 8000.0
+
+C5 = dict(nx=8192, ny=2048, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
+          label="periodic 8192x2048, pair gamma0=40, 64 ppc/species (2^31 particles), "
+                "order 3, CFL 1.0, theta 0.6")
+# schedule of the headline workload (measured: tiles narrow along the flow,
+# two work-groups per tile, reordering every 4 steps; see tune.autotune)
+C5_TILE, C5_SPLIT, C5_SORT = (4, 32), 2, 4
 
 CONFIGS = {
     # name: nx, ny, ppc, gamma0, order, cfl, theta
@@ -345,34 +351,36 @@ def net_rate(pic, torch, cfg, reps=20):
     return out
 
 
-def large_share(pic, torch, steps=10, warmup=300, tile=(16, 32), tile_split=1, pairs=8,
-                epochs=50):
-    """The large single-GPU share: periodic 8192 x 2048, pair plasma at
-    gamma0 = 40, 64 ppc/species (2.1e9 particles), order 3, CFL 1, theta 0.6,
-    FP32 particles, loaded on the device, with the learned aid: the first
-    `pairs` steps run plain CG (timed, and recorded as training pairs), the
-    network is trained, `warmup` untimed steps on the learned solver take the
-    run past the saturation of the numerical Cherenkov instability (as in the
-    1024 x 256 form), then the timed steps."""
+def headline(pic, torch, steps, warmup, saturated_after=300, pairs=8, epochs=50):
+    """The headline workload (C5 dict): 2^31 particles loaded on the device,
+    FP32 particles with the learned aid. Returns the timed figures: wall
+    clock over `steps` steps after `warmup` untimed ones, the particle
+    kernel's average launch time from HIP events on the context stream over
+    the same launches, the field solve, and (if saturated_after > 0) the
+    same after that many further untimed steps."""
     from synth import loads
-    nx, ny, ppc = 8192, 2048, 64
-    Q = loads.macro_charge(40.0, 0.1, 0.1, ppc)
-    run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 3, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split,
+    c = C5
+    nx, ny, ppc = c["nx"], c["ny"], c["ppc"]
+    Q = loads.macro_charge(c["gamma0"], 0.1, 0.1, ppc)
+    run = pic.run_desc(nx, ny, 0.1, c["cfl"], c["theta"], c["order"], [(-Q, Q, ppc), (Q, Q, ppc)],
+                       cg_rtol=1e-8, cg_maxit=200)
+    sim = pic.Sim([run], pic.make_options("fp32", tile=C5_TILE, tile_split=C5_SPLIT,
                                           track_ids=False, solver="learned",
-                                          precond_slots=pairs, sort_every=SORT,
+                                          precond_slots=pairs, sort_every=C5_SORT,
                                           exchange_frac=EXF, slack=SLACK))
+    t0 = time.perf_counter()
     for s in range(2):
-        sim.load_plasma(0, s, ppc, 40.0, 0.01, 0)
+        sim.load_plasma(0, s, ppc, c["gamma0"], 0.01, 0)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t0
     n = 2 * nx * ny * ppc
-    # plain CG steps, recorded as training pairs
+    # the first steps: plain CG, recorded as training pairs
     sim.precond_use(False)
     sim.precond_collect(True)
     sim.timing(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     st_plain = sim.step(pairs)[0]
-    plain_ms = (time.perf_counter() - t0) * 1e3 / pairs
+    plain_s = time.perf_counter() - t0
     tim_plain = sim.get_timing()
     sim.timing(False)
     sim.precond_collect(False)
@@ -381,48 +389,69 @@ def large_share(pic, torch, steps=10, warmup=300, tile=(16, 32), tile_split=1, p
     tr = sim.precond_train(epochs, 0.0)
     train_s = time.perf_counter() - t0
     sim.precond_use(True)
-    retune = sim.tune(1, splits=(tile_split,))
-    if warmup:
-        log(f"bench: large share: {warmup} untimed steps")
-        sim.step(warmup)
-    torch.cuda.synchronize()
-    sim.timing(True)
     t0 = time.perf_counter()
-    rc = sim.step_async(steps)
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    if rc != 0:
-        raise RuntimeError(f"large share pic_step returned {pic.STATUS.get(rc, rc)}")
-    tim = sim.get_timing()
-    st = sim.step(0)[0]
-    push_ms = tim["push"]["ms"] / max(1, tim["push"]["launches"])
-    out = dict(workload="periodic 8192x2048, pair gamma0=40, 64 ppc/species, order 3, CFL 1.0, "
-                        "theta 0.6 (FP32 particles, learned aid)",
-               particles=n, workspace_gb=sim.info.workspace_bytes / 1e9, warmup=warmup,
-               ms_per_step=ms,
-               particle_steps_per_s=n / (ms * 1e-3), push_ms=push_ms,
-               push_achieved_gbs=BYTES_PER_PARTICLE["fp32"] * n / (push_ms * 1e-3) / 1e9,
-               field_solve_ms=tim["field_solve"]["ms"] / steps, cg_iters=st["iters"],
-               learned_iters=st["learned_iters"], fallback=st["fallback"],
-               max_relres=max(st["relres"]), cg_blocks=retune["cg_blocks"],
-               training=dict(pairs=pairs, epochs=epochs, seconds=train_s,
+    retune = sim.tune(1, splits=(C5_SPLIT,))
+    tune_s = time.perf_counter() - t0
+
+    def timed(k):
+        torch.cuda.synchronize()
+        sim.timing(True)
+        t0 = time.perf_counter()
+        rc = sim.step_async(k)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / k
+        if rc != 0:
+            raise RuntimeError(f"headline pic_step returned {pic.STATUS.get(rc, rc)}")
+        tim = sim.get_timing()
+        sim.timing(False)
+        st = sim.step(0)[0]
+        push = tim["push"]
+        return dict(ms_per_step=ms, particle_steps_per_s=n / (ms * 1e-3),
+                    push_ms=push["ms"] / max(1, push["launches"]), push_launches=push["launches"],
+                    field_solve_ms=tim["field_solve"]["ms"] / k,
+                    rebin_ms=tim["rebin"]["ms"] / k, current_sum_ms=tim["current_sum"]["ms"] / k,
+                    sort_ms_per_step=tim["sort"]["ms"] / k, cg_iters=st["iters"],
+                    learned_iters=st["learned_iters"], fallback=st["fallback"],
+                    max_relres=max(st["relres"]))
+
+    if warmup:
+        sim.step(warmup)
+    main_t = timed(steps)
+    sat = None
+    if saturated_after > 0:
+        log(f"bench: headline: {saturated_after} more untimed steps (saturated phase)")
+        sim.step(saturated_after)
+        sat = dict(timed(min(steps, 10)), after_steps=pairs + warmup + steps + saturated_after)
+    d = sim.diag(0)
+    out = dict(workload=c["label"] + " (FP32 particles, learned aid)", particles=n,
+               workspace_gb=sim.info.workspace_bytes / 1e9, load_seconds=load_s,
+               tile=list(C5_TILE), tile_split=C5_SPLIT, sort_every=C5_SORT,
+               cg_blocks=retune["cg_blocks"], timed=main_t, saturated=sat,
+               training=dict(pairs=pairs, epochs=epochs, seconds=train_s, tune_seconds=tune_s,
                              loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
-               plain_cg=dict(ms_per_step=plain_ms, particle_steps_per_s=n / (plain_ms * 1e-3),
+               plain_cg=dict(ms_per_step=plain_s * 1e3 / pairs,
                              field_solve_ms=tim_plain["field_solve"]["ms"] / pairs,
                              cg_iters=st_plain["iters"],
-                             note=f"the {pairs} collection steps (untuned field-solve grid, "
-                                  "pair recording included)"))
+                             note=f"the first {pairs} steps (plain CG, pairs recorded)"),
+               gauss_max=d["gauss_max"], n_particles=d["n_particles"][:2])
+    # a 1000-step run (the workload's length): collection steps, training and
+    # 1000 - pairs steps at the timed rate
+    run_s = plain_s + train_s + tune_s + (1000 - pairs) * main_t["ms_per_step"] * 1e-3
+    out["whole_run_1000_steps"] = dict(
+        seconds=run_s, ms_per_step=run_s * 1e3 / 1000,
+        note=f"the {pairs} collection steps, training, tuning and {1000 - pairs} steps at the "
+             "timed rate")
     sim.close()
     return out
 
 
-def shock_share(pic, torch, tile, tile_split, steps=20, warmup=2, pairs=8, epochs=50):
+def shock_share(pic, torch, tile, tile_split, steps=20, warmup=5, pairs=8, epochs=50):
     """The shock workload: 4096 x 512 with conducting walls in x, pair flow at
     gamma0 = 40 towards the reflecting wall at x = 0, 32 ppc/species, order 2,
     CFL 1, theta 0.6, FP32 particles, learned aid (pairs from the first
-    steps). Every step first injects the flow entering at x_out (host-generated
-    slabs, prepared before the timed region; the injection call copies them to
-    the device and is inside the timed region)."""
+    steps); the flow entering at x_out is generated on the device before every
+    step (pic_set_inflow), inside the timed region, and the steps replay
+    captured graphs. Also times the same steps with plain CG."""
     from synth import loads
     nx, ny, ppc, g0 = 4096, 512, 32, 40.0
     x_out = nx - pic.PIC_WALL_GAP
@@ -431,122 +460,265 @@ def shock_share(pic, torch, tile, tile_split, steps=20, warmup=2, pairs=8, epoch
                        bc="shock")
     sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split, slack=1.5,
                                           exchange_frac=EXF, track_ids=False, solver="learned",
-                                          precond_slots=pairs, sort_every=SORT))
+                                          precond_slots=pairs, sort_every=4, graph=GRAPH))
     for s in range(2):
         sim.load_plasma(0, s, ppc, g0, 0.01, 0, direction=-1, x_cells=x_out)
-    total = pairs + warmup + steps
-    slabs = [loads.shock_injection(x_out, ny, ppc, g0, 0.01, 0, k, 1.0) for k in range(total)]
-
-    def inject(k):
-        for s, d in enumerate(slabs[k]):
-            sim.inject_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
-                                 d["uz"])
+    sim.set_inflow(0, ppc, g0, 0.01, 0)
     sim.precond_use(False)
     sim.precond_collect(True)
-    for k in range(pairs):
-        inject(k)
-        sim.step(1)
+    sim.timing(True)
+    sim.step(pairs)
+    tim_plain = sim.get_timing()
+    sim.timing(False)
     st_plain = sim.step(0)[0]
     sim.precond_collect(False)
     tr = sim.precond_train(epochs, 0.0)
     sim.precond_use(True)
-    for k in range(pairs, pairs + warmup):
-        inject(k)
-        sim.step(1)
-    torch.cuda.synchronize()
-    sim.timing(True)
-    t0 = time.perf_counter()
-    for k in range(pairs + warmup, total):
-        inject(k)
-        rc = sim.step_async(1)
+    sim.step(warmup)
+
+    def timed():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = sim.step_async(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
         if rc != 0:
             raise RuntimeError(f"shock pic_step returned {pic.STATUS.get(rc, rc)}")
-    torch.cuda.synchronize()
-    ms = (time.perf_counter() - t0) * 1e3 / steps
-    tim = sim.get_timing()
+        sim.timing(True)
+        sim.step(4)
+        tim = sim.get_timing()
+        sim.timing(False)
+        return ms, tim
+    ms, tim = timed()
     st = sim.step(0)[0]
     d = sim.diag(0)
     n = sum(d["n_particles"][:2])
+    out = dict(workload="shock 4096x512 (walls in x, reflection at x=0, device inflow at x_out), "
+                        "pair flow gamma0=40, 32 ppc/species, order 2, CFL 1.0, theta 0.6 "
+                        "(FP32 particles, learned aid)",
+               particles=n, ms_per_step=ms, particle_steps_per_s=n / (ms * 1e-3),
+               push_ms=tim["push"]["ms"] / max(1, tim["push"]["launches"]),
+               field_solve_ms=tim["field_solve"]["ms"] / 4,
+               field_solve_ms_plain_cg=tim_plain["field_solve"]["ms"] / pairs,
+               cg_iters_plain=st_plain["iters"], learned_iters=st["learned_iters"],
+               fallback=st["fallback"], max_relres=max(st["relres"]),
+               training=dict(pairs=pairs, loss_first=tr["loss_first"],
+                             loss_last=tr["loss_last"]),
+               note="ms_per_step includes the device injection of the entering flow")
+    sim.precond_use(False)
+    ms_cg, tim_cg = timed()
+    out["plain_cg"] = dict(ms_per_step=ms_cg, field_solve_ms=tim_cg["field_solve"]["ms"] / 4,
+                           cg_iters=sim.step(0)[0]["iters"])
     sim.close()
-    return dict(workload="shock 4096x512 (walls in x, reflection at x=0, injection at x_out), "
-                         "pair flow gamma0=40, 32 ppc/species, order 2, CFL 1.0, theta 0.6 "
-                         "(FP32 particles, learned aid)",
-                particles=n, ms_per_step=ms, particle_steps_per_s=n / (ms * 1e-3),
-                push_ms=tim["push"]["ms"] / max(1, tim["push"]["launches"]),
-                field_solve_ms=tim["field_solve"]["ms"] / steps,
-                cg_iters_plain=st_plain["iters"], learned_iters=st["learned_iters"],
-                fallback=st["fallback"], max_relres=max(st["relres"]),
-                training=dict(loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
-                note="ms_per_step includes the per-step injection call (host slab copied to "
-                     "the device)")
+    return out
 
 
-def cpu_baseline(cfg, seconds=15.0):
-    """The FP64 oracle on a 4-row strip of the same workload (same grid width,
-    ppc, order, gamma0), single-threaded; particle-steps/s of whole steps."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, seconds=10.0, rows=4):
+    """The FP64 oracle (plain C with OpenMP) on a strip of the headline
+    workload: the full width, `rows` rows, the same ppc, order, gamma0, CFL
+    and theta; particle-steps/s of whole steps, on one thread and on all the
+    host's threads (about `seconds` of CPU work each)."""
     import oracle
     from synth import loads
-    nx, ny = cfg["nx"], 4
+    nx, ny = cfg["nx"], rows
     Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
     ld = loads.pair_plasma_cells(nx, ny, cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
-    sp = [oracle.Particles(d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"], q, Q)
-          for d, q in zip(ld, (-Q, Q))]
-    sim = oracle.Sim(nx, ny, 0.1, 0.1, cfg["cfl"], cfg["theta"], cfg["order"], sp)
-    n = sum(p.n for p in sp)
-    sim.step()
-    steps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < seconds or steps < 2:
+    nproc = os.cpu_count() or 1
+    out = {}
+    for threads in (1, nproc):
+        oracle.set_threads(threads)
+        sp = [oracle.Particles(d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"],
+                               q, Q) for d, q in zip(ld, (-Q, Q))]
+        sim = oracle.Sim(nx, ny, 0.1, 0.1, cfg["cfl"], cfg["theta"], cfg["order"], sp)
+        n = sum(p.n for p in sp)
         sim.step()
-        steps += 1
-    dt = time.perf_counter() - t0
-    return dict(value=n * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"{nx}x{ny} strip of the workload ({n} particles), {steps} whole "
-                       f"steps after 1 warm-up step, 1 thread, {dt:.1f} s")
+        steps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds or steps < 2:
+            sim.step()
+            steps += 1
+        dt = time.perf_counter() - t0
+        out[threads] = dict(value=n * steps / dt, steps=steps, seconds=dt, particles=n)
+    oracle.set_threads(0)
+    best = out[nproc]
+    return dict(value=best["value"], unit="particle-steps/s", cores=nproc, kind="oracle",
+                sample=f"{nx}x{ny} strip of the headline workload ({best['particles']} "
+                       f"particles), {best['steps']} whole steps after 1 warm-up step on "
+                       f"{nproc} threads ({best['seconds']:.1f} s); a per-particle-step rate "
+                       "extrapolated to the full grid",
+                one_thread=dict(value=out[1]["value"], steps=out[1]["steps"],
+                                seconds=out[1]["seconds"]),
+                nproc=nproc, cpu_model=_cpu_model())
+
+
+def c2_legs(pic, torch, args, learned):
+    """The 1024 x 256 single run: FP32 + learned, FP32 with plain CG and the
+    plain FP64 form, each on its own tuned schedule; returns the three
+    timings, the tuning tables and the FP32/FP64 factor."""
+    from synth import loads
+    global SORT
+    cfg = CONFIGS["c2"]
+    log(f"bench: generating load {cfg['label']}")
+    load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
+    tile = (4, 32)
+    split, cgb = 2, 128
+    Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
+    run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
+                       [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8)
+
+    def _load(sim):
+        for s_ in range(2):
+            d = load[s_]
+            sim.load_particles(0, s_, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    tune = None
+    if not args.no_autotune:
+        from paper_1412_2480_amd.tune import autotune, tune_sort_every
+        t0 = time.perf_counter()
+        best, table = autotune([run], _load, dict(precision="fp32", track_ids=False,
+                                                  tile_split=8, exchange_frac=EXF, slack=SLACK,
+                                                  sort_every=8), warmup=args.warmup)
+        tile, split, cgb = tuple(best["tile"]), best["tile_split"], best["cg_blocks"]
+        SORT, sort_table = tune_sort_every(
+            [run], _load, dict(precision="fp32", track_ids=False, tile=tile, tile_split=split,
+                               cg_blocks=cgb, exchange_frac=EXF, slack=SLACK),
+            candidates=(0, 3, 4, 8), warmup=args.warmup)
+        tune = dict(best=dict(tile=list(tile), tile_split=split, cg_blocks=cgb,
+                              sort_every=SORT),
+                    table=[{k: r[k] for k in ("tile", "tile_split", "cg_blocks", "ms_per_step")}
+                           for r in table], sort_table=sort_table,
+                    seconds=time.perf_counter() - t0)
+        log(f"bench: c2 autotune: tile {tile} split {split} cg_blocks {cgb} sort_every {SORT}")
+    else:
+        SORT = 4
+    fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split,
+                     learned, retune=not args.no_autotune)
+    log(f"bench: c2 FP32 + learned {fast['ms_per_step']:.3f} ms/step, push {fast['push_ms']:.3f}, "
+        f"field solve {fast['field_solve_ms']:.3f} ms, iters {fast['cg_iters']}")
+    fast_cg = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split)
+    log(f"bench: c2 FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
+        f"{fast_cg['field_solve_ms']:.3f} ms, iters {fast_cg['cg_iters']}")
+    mfma = None
+    if args.also_mfma and learned is not None:
+        mfma = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split,
+                         dict(learned, form="mfma"))
+        log(f"bench: c2 FP32 + learned (mfma) {mfma['ms_per_step']:.3f} ms/step, field solve "
+            f"{mfma['field_solve_ms']:.3f} ms")
+    plain = None
+    if not args.no_fp64:
+        t64 = dict(tile=tile, tile_split=1, cg_blocks=256, sort_every=0)
+        if tune is not None:
+            from paper_1412_2480_amd.tune import autotune, tune_sort_every
+            b64, _ = autotune([run], _load, dict(precision="fp64", track_ids=False, tile_split=8,
+                                                 exchange_frac=EXF, slack=SLACK, sort_every=8),
+                              shapes=((4, 32), (8, 32), (16, 16)), warmup=args.warmup)
+            k64, _ = tune_sort_every([run], _load, dict(precision="fp64", track_ids=False,
+                                                        tile=b64["tile"],
+                                                        tile_split=b64["tile_split"],
+                                                        cg_blocks=b64["cg_blocks"],
+                                                        exchange_frac=EXF, slack=SLACK),
+                                     candidates=(0, 4, 8), warmup=args.warmup)
+            t64 = dict(tile=tuple(b64["tile"]), tile_split=b64["tile_split"],
+                       cg_blocks=b64["cg_blocks"], sort_every=k64)
+            tune["fp64_schedule"] = dict(t64, tile=list(t64["tile"]))
+        plain = time_form(pic, torch, cfg, load, "fp64", t64["tile"], args.steps, args.warmup,
+                          t64["cg_blocks"], t64["tile_split"], sort_every=t64["sort_every"])
+        log(f"bench: c2 FP64 {plain['ms_per_step']:.3f} ms/step, field solve "
+            f"{plain['field_solve_ms']:.3f} ms")
+    del load
+
+    def info(r):
+        return None if r is None else dict(
+            ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],
+            push_ms=r["push_ms"], field_solve_ms_per_step=r["field_solve_ms"],
+            cg_iters_last_step=r["cg_iters"], learned_iters_last_step=r["learned_iters"],
+            fallback=r["fallback"], relres_last_step=r["relres"], training=r["train"])
+    out = dict(workload=cfg["label"], particles=fast["n_particles"], tile=list(tile),
+               tile_split=split, sort_every=SORT, fp32_learned=info(fast),
+               fp32_plain_cg=info(fast_cg), fp32_learned_mfma=info(mfma), plain_fp64=info(plain),
+               breakdown_ms={k: fast[k] for k in ("push_ms", "rebin_ms", "current_sum_ms",
+                                                  "sort_ms_per_step", "field_solve_ms")},
+               autotune=tune)
+    if plain is not None:
+        out["speedup_fp32_learned_vs_fp64"] = plain["ms_per_step"] / fast["ms_per_step"]
+        out["field_solve_speedup_vs_fp64"] = plain["field_solve_ms"] / fast["field_solve_ms"]
+    return out
+
+
+def explicit_vs_implicit(pic, torch, steps=20, warmup=5):
+    """The explicit Yee FDTD variant (Eqs. (3)-(4)) at its stable CFL 0.5
+    against the implicit scheme at CFL 1.0 on the 1024 x 256 workload (FP32
+    particles): time per step and per unit of simulated time."""
+    cfg = CONFIGS["c2"]
+    from synth import loads
+    out = {}
+    for scheme, cfl in (("explicit", 0.5), ("implicit", 1.0)):
+        Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
+        run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfl, 0.6, cfg["order"],
+                           [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8)
+        sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=4,
+                                              track_ids=False, exchange_frac=EXF, slack=SLACK,
+                                              scheme=scheme, graph=GRAPH))
+        for s in range(2):
+            sim.load_plasma(0, s, cfg["ppc"], cfg["gamma0"], 0.01, 0)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = sim.step_async(steps)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        if rc != 0:
+            raise RuntimeError(f"{scheme} pic_step returned {pic.STATUS.get(rc, rc)}")
+        sim.timing(True)
+        sim.step(5)
+        tim = sim.get_timing()
+        sim.close()
+        out[scheme] = dict(cfl=cfl, ms_per_step=ms, ms_per_unit_time=ms / (cfl * 0.1),
+                           field_ms=tim["field_solve"]["ms"] / 5)
+    out["note"] = ("time per step and per 1/omega_pe of simulated time (dt = cfl dx); the "
+                   "explicit scheme is stable only for cfl^2 (1 + dx^2/dy^2) <= 1")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=300,
-                    help="untimed steps before the timed ones (also before each autotuner "
-                         "candidate): by step 300 the numerical Cherenkov instability of the "
-                         "drifting pair plasma has saturated, and the timed steps see the hot, "
-                         "bunched state the rest of a 2000-step run spends its steps in")
-    ap.add_argument("--config", default="c2", choices=sorted(CONFIGS))
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--saturated-after", type=int, default=300,
+                    help="untimed headline steps before the saturated-phase timing (0 = skip): "
+                         "by step ~300 the numerical Cherenkov instability of the drifting "
+                         "pair plasma has saturated, the state a long run spends most steps in")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload (for profiling runs)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the 1024x256 legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--cg-blocks", type=int, default=0, help="field-solve work-groups (0 = auto)")
-    ap.add_argument("--sweep-cg", default="", help="comma list of cg_blocks to time (FP32 form)")
-    ap.add_argument("--tile-split", type=int, default=0, help="work-groups per tile (0 = auto)")
-    ap.add_argument("--sweep-tiles", default="",
-                    help="comma list of TXxTY:K tile shapes and splits to time (FP32 form)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-batched", action="store_true", help="skip the 48-run batched sweep")
-    ap.add_argument("--no-shock", action="store_true",
-                    help="skip the 4096x512 shock workload (walls, reflection, injection)")
-    ap.add_argument("--no-large", action="store_true",
-                    help="skip the 8192x2048 large single-GPU share (2.1e9 particles)")
-    ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"],
-                    help="inference form of the network in the timed form")
-    ap.add_argument("--no-learned", action="store_true",
-                    help="time the FP32 form with plain CG only")
+    ap.add_argument("--no-shock", action="store_true", help="skip the shock workload")
+    ap.add_argument("--no-explicit", action="store_true",
+                    help="skip the explicit-vs-implicit scheme leg")
+    ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"])
+    ap.add_argument("--also-mfma", action="store_true",
+                    help="also time the 1024x256 FP32 form with the BF16 matrix-core network")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="skip the library's autotuner (tile shape, work-groups per tile, "
-                         "field-solve work-groups) and use --tile/--tile-split/--cg-blocks")
+                    help="fixed schedules for the 1024x256 legs instead of the autotuner")
     ap.add_argument("--no-graph", action="store_true",
-                    help="plain launches instead of replaying captured two-step HIP graphs in "
-                         "the timed forms")
-    ap.add_argument("--sort-every", type=int, default=-1,
-                    help="reorder each tile's particles by cell every n steps in the timed "
-                         "forms (0 = never); default: picked by the autotuner (0 without it)")
+                    help="plain launches instead of captured two-step HIP graphs (1024x256 legs)")
     ap.add_argument("--train-pairs", type=int, default=8)
     ap.add_argument("--train-epochs", type=int, default=50)
-    ap.add_argument("--also-mfma", action="store_true",
-                    help="also time the FP32 form with the BF16 matrix-core network")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="first copy a 512 MiB buffer three times (a plain copy kernel of known "
+                    help="first a plain multiply of a 1 GiB buffer (a copy kernel of known "
                          "size, for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -556,13 +728,8 @@ def main():
 
     import torch
     import paper_1412_2480_amd as pic
-    from synth import loads
-    global GRAPH, SORT
+    global GRAPH
     GRAPH = not args.no_graph
-    SORT = max(0, args.sort_every)
-
-    cfg = CONFIGS[args.config]
-    tile = tuple(int(v) for v in args.tile.split("x"))
     if args.calib_copy:
         # A plain elementwise kernel of known size for scaling the HBM traffic
         # counters: the source is written first, then a second 1 GiB buffer is
@@ -576,229 +743,78 @@ def main():
         torch.cuda.synchronize()
         del src, dst, flush
         log("bench: calibration multiply done (reads 1 GiB, writes 1 GiB)")
-    log(f"bench: generating load {cfg['label']}")
-    t0 = time.perf_counter()
-    load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
-    log(f"bench: load ready in {time.perf_counter() - t0:.1f} s")
 
-    learned = None if args.no_learned else dict(form=args.learned_form, pairs=args.train_pairs,
-                                                 epochs=args.train_epochs, lr=1e-3)
-    if args.sweep_cg:
-        for nb in [int(v) for v in args.sweep_cg.split(",")]:
-            for lrn in ([None] if learned is None else [None, learned]):
-                r = time_form(pic, torch, cfg, load, "fp32", tile, 10, 2, nb, args.tile_split,
-                              lrn)
-                log(f"bench: cg_blocks={nb} {'learned' if lrn else 'plain'}: field solve "
-                    f"{r['field_solve_ms']:.3f} ms/step, iters {r['cg_iters']}")
-    if args.sweep_tiles:
-        for item in args.sweep_tiles.split(","):
-            shape, k = item.split(":")
-            tt = tuple(int(v) for v in shape.split("x"))
-            for prec in ("fp32", "fp64"):
-                r = time_form(pic, torch, cfg, load, prec, tt, 20, 20, args.cg_blocks, int(k))
-                log(f"bench: {prec} tile {shape} split {k}: push {r['push_ms']:.3f} ms, "
-                    f"step {r['ms_per_step']:.3f} ms")
-    tune = None
-    if not args.no_autotune:
-        from paper_1412_2480_amd.tune import autotune
-        from synth import loads as _l
-        Q = _l.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
-        run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
-                           [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8)
+    learned = dict(form=args.learned_form, pairs=args.train_pairs, epochs=args.train_epochs,
+                   lr=1e-3)
+    log(f"bench: headline {C5['label']}")
+    h = headline(pic, torch, args.steps, args.warmup,
+                 0 if args.headline_only else args.saturated_after, args.train_pairs,
+                 args.train_epochs)
+    t = h["timed"]
+    log(f"bench: headline {t['ms_per_step']:.2f} ms/step ({t['particle_steps_per_s']:.3g} "
+        f"particle-steps/s), push {t['push_ms']:.2f} ms, field solve {t['field_solve_ms']:.2f} ms "
+        f"(plain CG {h['plain_cg']['field_solve_ms']:.2f} ms)")
+    if h["saturated"]:
+        sa = h["saturated"]
+        log(f"bench: headline saturated phase {sa['ms_per_step']:.2f} ms/step, push "
+            f"{sa['push_ms']:.2f} ms")
+    gc.collect()
+    torch.cuda.empty_cache()
 
-        def _load(sim):
-            for s_ in range(2):
-                d = load[s_]
-                sim.load_particles(0, s_, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
-                                   d["uz"])
-        t0 = time.perf_counter()
-        # the shape search runs with reordering on (it changes the ranking);
-        # the reordering period is tuned on the chosen shape afterwards
-        best, table = autotune([run], _load, dict(precision="fp32", track_ids=False,
-                                                  tile_split=8, exchange_frac=EXF, slack=SLACK,
-                                                  sort_every=8 if args.sort_every < 0
-                                                  else args.sort_every),
-                               warmup=args.warmup)
-        tune = dict(best={k: best[k] for k in ("tile", "tile_split", "cg_blocks",
-                                               "ms_per_step")},
-                    table=[{k: r[k] for k in ("tile", "tile_split", "cg_blocks",
-                                              "ms_per_step")} for r in table],
-                    seconds=time.perf_counter() - t0)
-        tile = tuple(best["tile"])
-        args.tile_split = best["tile_split"]
-        args.cg_blocks = best["cg_blocks"]
-        log(f"bench: autotune picked tile {tile} split {args.tile_split} cg_blocks "
-            f"{args.cg_blocks} ({tune['seconds']:.1f} s)")
-        if args.sort_every < 0:
-            from paper_1412_2480_amd.tune import tune_sort_every
-            t0 = time.perf_counter()
-            SORT, sort_table = tune_sort_every(
-                [run], _load, dict(precision="fp32", track_ids=False, tile=tile,
-                                   tile_split=args.tile_split, cg_blocks=args.cg_blocks,
-                                   exchange_frac=EXF, slack=SLACK),
-                candidates=(0, 3, 4, 8, 16), warmup=args.warmup)
-            tune["sort_every"] = SORT
-            tune["sort_table"] = sort_table
-            tune["seconds"] += time.perf_counter() - t0
-            log(f"bench: autotune picked sort_every {SORT} " + ", ".join(
-                f"{r['sort_every']}: {r['ms_per_step']:.3f} ms" for r in sort_table))
-    log("bench: FP32 form" + ("" if learned is None else f" + learned ({args.learned_form})"))
-    fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, args.cg_blocks,
-                     args.tile_split, learned, retune=not args.no_autotune)
-    log(f"bench: FP32 {fast['ms_per_step']:.3f} ms/step, field solve "
-        f"{fast['field_solve_ms']:.3f} ms, iters {fast['cg_iters']}")
-    fast_cg = None
-    if learned is not None:
-        log("bench: FP32 form, plain CG")
-        fast_cg = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup,
-                            args.cg_blocks, args.tile_split)
-        log(f"bench: FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
-            f"{fast_cg['field_solve_ms']:.3f} ms, iters {fast_cg['cg_iters']}")
-    mfma = None
-    if args.also_mfma and learned is not None and args.learned_form != "mfma":
-        log("bench: FP32 form + learned (mfma)")
-        mfma = time_form(pic, torch, cfg, load, "fp32", tile, max(10, args.steps // 4),
-                         args.warmup, args.cg_blocks, args.tile_split, dict(learned, form="mfma"))
-        log(f"bench: FP32 mfma {mfma['ms_per_step']:.3f} ms/step, field solve "
-            f"{mfma['field_solve_ms']:.3f} ms, iters {mfma['cg_iters']}")
-    plain = None
-    if not args.no_fp64:
-        # the baseline gets its own schedule: shape search and reordering
-        # period tuned for the FP64 form
-        t64 = dict(tile=tile, tile_split=args.tile_split, cg_blocks=args.cg_blocks,
-                   sort_every=SORT)
-        if tune is not None:
-            from paper_1412_2480_amd.tune import autotune, tune_sort_every
-            b64, _ = autotune([run], _load, dict(precision="fp64", track_ids=False, tile_split=8,
-                                                 exchange_frac=EXF, slack=SLACK, sort_every=8),
-                              shapes=((4, 32), (8, 32), (16, 32), (16, 16)), warmup=args.warmup)
-            k64, _ = tune_sort_every([run], _load, dict(precision="fp64", track_ids=False,
-                                                        tile=b64["tile"],
-                                                        tile_split=b64["tile_split"],
-                                                        cg_blocks=b64["cg_blocks"],
-                                                        exchange_frac=EXF, slack=SLACK),
-                                     candidates=(0, 4, 8, 16), warmup=args.warmup)
-            t64 = dict(tile=tuple(b64["tile"]), tile_split=b64["tile_split"],
-                       cg_blocks=b64["cg_blocks"], sort_every=k64)
-            tune["fp64_schedule"] = dict(t64, tile=list(t64["tile"]))
-            log(f"bench: FP64 schedule: tile {t64['tile']} split {t64['tile_split']} cg_blocks "
-                f"{t64['cg_blocks']} sort_every {k64}")
-        log("bench: FP64 form")
-        plain = time_form(pic, torch, cfg, load, "fp64", t64["tile"], args.steps, args.warmup,
-                          t64["cg_blocks"], t64["tile_split"], sort_every=t64["sort_every"])
-        log(f"bench: FP64 {plain['ms_per_step']:.3f} ms/step")
-    del load
-
-    def run_batched():
-        log("bench: batched 48-run sweep")
-        b = batched_sweep(pic, torch, 20, 3)
-        log(f"bench: batched {b['ms_per_step']:.3f} ms/step for {b['runs']} runs "
-            f"(tile {tuple(b['tile'])}, sort_every {b['sort_every']}), "
-            f"sequential {b['sequential_ms_per_step']:.3f} ms")
-        if b["learned"]:
-            bl = b["learned"]
-            log(f"bench: batched learned {bl['ms_per_step']:.3f} ms/step "
-                f"({bl['networks']} networks, trained in {bl['train_seconds']:.2f} s), "
-                f"CG iterations per step {b['cg_iters_last_step']} -> "
-                f"{bl['cg_iters_last_step']}")
-        return b
-
-    def run_large():
-        log("bench: large single-GPU share (8192x2048, 2.1e9 particles)")
-        g = large_share(pic, torch, tile=tile, tile_split=max(1, args.tile_split),
-                        warmup=args.warmup)
-        log(f"bench: large share {g['ms_per_step']:.1f} ms/step, push "
-            f"{g['push_ms']:.1f} ms ({g['push_achieved_gbs']:.0f} GB/s), field solve "
-            f"{g['field_solve_ms']:.1f} ms learned vs "
-            f"{g['plain_cg']['field_solve_ms']:.1f} ms plain CG, trained in "
-            f"{g['training']['seconds']:.2f} s")
-        return g
-
-    def run_shock():
-        log("bench: shock workload (4096x512, walls, injection)")
-        k = shock_share(pic, torch, tile, max(1, args.tile_split))
-        log(f"bench: shock {k['ms_per_step']:.2f} ms/step ({k['particles']:.3g} "
-            f"particles), push {k['push_ms']:.2f} ms, field solve "
-            f"{k['field_solve_ms']:.2f} ms, CG iterations {k['cg_iters_plain']} -> "
-            f"{k['learned_iters']}")
-        return k
-
-    def run_net():
-        r = net_rate(pic, torch, cfg)
-        log(f"bench: network application: mfma {r['mfma']['ms_per_application']:.3f} ms "
-            f"({r['mfma']['tflops']:.1f} TFLOP/s), collapsed "
-            f"{r['collapsed']['ms_per_application']:.3f} ms")
-        return r
-
-    def run_cpu():
+    legs = {}
+    if not args.headline_only:
+        if not args.no_c2:
+            legs["c2"] = run_leg("1024x256 legs", lambda: c2_legs(pic, torch, args, learned))
+        if not args.no_explicit:
+            legs["explicit_vs_implicit"] = run_leg("explicit scheme",
+                                                   lambda: explicit_vs_implicit(pic, torch))
+        if not args.no_batched:
+            legs["batched_sweep"] = run_leg("batched sweep",
+                                            lambda: batched_sweep(pic, torch, 20, 3))
+        if not args.no_shock:
+            legs["shock"] = run_leg("shock workload",
+                                    lambda: shock_share(pic, torch, (4, 32), 2))
+        legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch,
+                                                                       CONFIGS["c2"]))
+    cpu = None
+    if not args.no_cpu and not args.headline_only:
         log("bench: oracle CPU baseline")
-        return cpu_baseline(cfg, args.cpu_seconds)
+        cpu = run_leg("CPU baseline", lambda: cpu_baseline(C5, args.cpu_seconds))
 
-    batched = None if args.no_batched else run_leg("batched sweep", run_batched)
-    large = None if args.no_large else run_leg("large share", run_large)
-    shock = None if args.no_shock else run_leg("shock workload", run_shock)
-    net = None if args.no_learned else run_leg("network rate", run_net)
-    cpu = None if args.no_cpu else run_leg("CPU baseline", run_cpu)
-
-    n_part = fast["n_particles"]
-    achieved = BYTES_PER_PARTICLE["fp32"] * n_part / (fast["push_ms"] * 1e-3) / 1e9
-    traffic, traffic_src = measured_traffic("fp32", tile, args.tile_split, cfg["order"], n_part,
-                                            SORT, args.warmup)
-    def solve_info(r):
-        return None if r is None else dict(
-            ms_per_step=r["ms_per_step"], particle_steps_per_s=r["particle_steps_per_s"],
-            field_solve_ms_per_step=r["field_solve_ms"], cg_iters_last_step=r["cg_iters"],
-            learned_iters_last_step=r["learned_iters"], fallback=r["fallback"],
-            relres_last_step=r["relres"], training=r["train"])
-
+    n_part = h["particles"]
+    alg = BYTES_PER_PARTICLE["fp32"] * n_part
+    achieved = alg / (t["push_ms"] * 1e-3) / 1e9
+    traffic, traffic_src = measured_traffic("fp32", C5_TILE, C5_SPLIT, C5["order"], n_part,
+                                            C5_SORT, args.warmup)
     line = {
         "metric": "particle-steps/s + field-solve ms/step; FP32+learned vs plain FP64, same GPU",
-        "value": fast["particle_steps_per_s"],
+        "value": t["particle_steps_per_s"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": fast["ms_per_step"],
+        "ms_per_step": t["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 particles, f64 fields/CG" + ("" if learned is None else
-                                                    f", learned aid ({args.learned_form})"),
-        "data": "synthetic (seeded Maxwell-Juettner pair plasma)",
-        "config": {"workload": cfg["label"], "particles": n_part, "cells": cfg["nx"] * cfg["ny"],
-                   "tile": list(tile), "sort_every": SORT, "graph": GRAPH, "cg_rtol": 1e-8},
-        "field_solve_ms_per_step": fast["field_solve_ms"],
-        "cg_iters_last_step": fast["cg_iters"],
-        "learned": solve_info(fast) if learned is not None else None,
-        "fp32_plain_cg": solve_info(fast_cg),
-        "fp32_learned_mfma": solve_info(mfma),
-        "breakdown_ms": {k: fast[k] for k in ("push_ms", "rebin_ms", "current_sum_ms",
-                                              "sort_ms_per_step", "field_solve_ms")},
-        "plain_fp64": None if plain is None else {
-            "particle_steps_per_s": plain["particle_steps_per_s"],
-            "ms_per_step": plain["ms_per_step"],
-            "field_solve_ms_per_step": plain["field_solve_ms"],
-            "push_ms": plain["push_ms"],
-            "cg_iters_last_step": plain["cg_iters"],
-            "speedup_of_timed_form": plain["ms_per_step"] / fast["ms_per_step"],
-            "field_solve_speedup_of_timed_form": plain["field_solve_ms"] / fast["field_solve_ms"],
-            "schedule": None if tune is None else tune.get("fp64_schedule"),
-        },
-        "roofline": {"bound": "hbm", "kernel": "fused particle push (gather+Boris+move+deposit)",
+        "dtype": "f32 particles, f64 fields/CG, learned aid (" + args.learned_form + ")",
+        "data": "synthetic (seeded Maxwell-Juettner pair plasma, loaded on the device)",
+        "config": {"workload": C5["label"], "particles": n_part, "cells": C5["nx"] * C5["ny"],
+                   "tile": list(C5_TILE), "tile_split": C5_SPLIT, "sort_every": C5_SORT,
+                   "cg_rtol": 1e-8},
+        "field_solve_ms_per_step": t["field_solve_ms"],
+        "cg_iters_last_step": t["cg_iters"],
+        "roofline": {"bound": "hbm", "kernel": "k_particles (fused gather+Boris+move+deposit)",
                      "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
-                     "algorithmic_bytes_per_launch": BYTES_PER_PARTICLE["fp32"] * n_part,
-                     "avg_launch_ms": fast["push_ms"], "tile": list(tile),
-                     "tile_split": args.tile_split, "sort_every": SORT},
-        "autotune": tune,
-        "learned_net": net,
-        "large_share": large,
-        "shock": shock,
-        "batched_sweep": batched,
+                     "algorithmic_bytes_per_launch": alg, "avg_launch_ms": t["push_ms"],
+                     "launches_timed": t["push_launches"]},
+        "headline": h,
         "cpu_baseline": cpu,
     }
+    line.update(legs)
     print(json.dumps(line), flush=True)
 
 

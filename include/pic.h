@@ -129,7 +129,22 @@ typedef struct pic_options {
                             falls in them; 0: plain launches */
   int32_t sort_every;    /* pic_step reorders every tile's particles by cell every
                             this many steps (0 = never); see pic_step */
+  int32_t cg_x0;         /* initial iterate of the plain field CG: PIC_X0_ZERO (the
+                            paper's solve, the default) or PIC_X0_PREV (the previous
+                            step's dB; the stopping test is the same relative residual).
+                            The learned solver always starts from N(b). */
+  int32_t field_scheme;  /* PIC_SCHEME_IMPLICIT: the theta-weighted implicit solve of
+                            Eqs. (5)-(7) (the paper's method, the default);
+                            PIC_SCHEME_EXPLICIT: the explicit Yee FDTD of Eqs. (3)-(4)
+                            (the scheme the paper contrasts it with, Sec. 2), B carried at
+                            integer times for the push as the mean of its half-step
+                            values; periodic runs, solver PIC_SOLVER_CG, and the Courant
+                            condition cfl^2 (1 + dx^2/dy^2) <= 1 (dispersion Eq. (16));
+                            theta and the CG fields are not used */
 } pic_options;
+
+enum pic_cg_x0 { PIC_X0_ZERO = 0, PIC_X0_PREV = 1 };
+enum pic_field_scheme { PIC_SCHEME_IMPLICIT = 0, PIC_SCHEME_EXPLICIT = 1 };
 
 typedef struct pic_plan_info {
   uint64_t workspace_bytes;
@@ -142,23 +157,41 @@ typedef struct pic_plan_info {
   int64_t n_cells;                         /* over all runs */
 } pic_plan_info;
 
+/* Statistics of the last field solve of one run (Eq. (7), per B component). */
 typedef struct pic_solve_stats {
   int32_t iters[3];      /* CG iterations per B component (learned + plain) */
-  double relres[3];      /* recursive relative residual ||r||/||b|| at exit */
+  double relres[3];      /* true relative residual ||b - A dB||_2/||b||_2 of the applied dB,
+                            recomputed in FP64 from E^n, B^n, J after the solve */
   double bnorm[3];       /* ||b||_2 of Eq. (7)'s right-hand side */
   int32_t learned_iters[3]; /* iterations of the learned PCG (0 with plain CG) */
   int32_t fallback;      /* 1 if the learned PCG missed cg_rtol and plain CG finished */
+  double relres_recursive[3]; /* the solver's recursive residual ||r_k||/||b|| at exit,
+                            which its stopping test compares with cg_rtol */
 } pic_solve_stats;
 
+/* Diagnostics of one run. The energy record (step .. cg_relres) is written
+ * by the field solve every diag_every steps; the energy balance it allows is
+ * the one the paper reports its runs by (total energy within 1%, Sec. 3.2):
+ * W_E(n) + W_B(n) + (W_K(n-1/2) + W_K(n+1/2))/2. pic_diag fills the fields
+ * after n_particles from the current state; history records leave them 0. */
 typedef struct pic_diag_out {
-  int64_t step;          /* step index n of the record */
+  int64_t step;          /* step index n of the record (-1: none recorded yet) */
   double t;              /* n dt */
   double W_E, W_B;       /* field energies at step n: sum |F|^2 dx dy/(8 pi) */
   double W_K_minus;      /* sum m (gamma - 1) at n - 1/2 */
   double W_K_plus;       /* sum m (gamma - 1) at n + 1/2 */
   int32_t cg_iters[3];
-  double cg_relres[3];
+  double cg_relres[3];   /* true relative residual of the step's solve */
   int64_t n_particles[PIC_MAX_SPECIES];
+  double gauss_max;      /* max |div E - 4 pi rho| over the nodes (Gauss's law, which
+                            the Esirkepov deposit and Eqs. (5)-(6) keep at its initial
+                            value); a shock run is measured on node columns
+                            1 .. x_out - 4 (the wall line carries the conductor's surface
+                            charge and particles leave at x_out) */
+  double divb_max;       /* max |div B| over the cells */
+  double total_charge;   /* sum rho dx dy of the particles' charge density */
+  int64_t fallbacks;     /* learned-solver solves finished by plain CG, since pic_init */
+  int64_t solves;        /* field solves since pic_init */
 } pic_diag_out;
 
 typedef struct pic_timing_out {
@@ -222,6 +255,35 @@ int32_t pic_inject_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t
                              const double* fy, const double* ux, const double* uy,
                              const double* uz);
 
+/* Inflow of a PIC_BC_SHOCK run generated on the device (the shock set-up of
+ * Sec. 4: the flow is injected at one side; a reading of its details): from
+ * the next step on, every step (pic_step, and pic_gather_push of the split
+ * path) first appends the flow entering through x_out = (nx - PIC_WALL_GAP) dx
+ * to the tiles of the cell column x_out - 1, for every species of the run,
+ * with no host transfer (graph replay included). The stream moves
+ * w = beta0 cfl cells per step (beta0 = sqrt(1 - 1/gamma0^2)); before the
+ * run's injection step n each row receives floor(ppc w (n+1)) -
+ * floor(ppc w n) particles at x = x_out - w r0, y uniform in the row,
+ * momenta drifting Maxwell-Juettner at (gamma0, T) towards -x; electrons and
+ * positrons co-located. The numbers come from the Philox streams of
+ * pic_load_plasma with items continuing after x_out * ny * ppc (the initial
+ * load of the flow region), item = first + row * per_row + j; ids are the item
+ * numbers (int32: meaningful while the items stay below 2^31). This is the recipe of the repository's seeded host generator of
+ * injection slabs, item by item. first_step: the injection step index of the
+ * next step (0 after a fresh load); it advances on the device. d = NULL
+ * switches the inflow off. Do not mix with pic_inject_particles on one run
+ * (their ids would collide). PIC_E_CAPACITY if a tile could not hold a full
+ * load plus one step's inflow. */
+typedef struct pic_inflow_desc {
+  int32_t ppc;           /* particles per cell per species of the flow */
+  double gamma0;         /* bulk Lorentz factor, > 1 (the flow moves towards -x) */
+  double T;              /* rest-frame temperature (m c^2) */
+  uint64_t seed;         /* Philox key (as for pic_load_plasma) */
+  int64_t first_step;    /* injection step index of the next step */
+} pic_inflow_desc;
+
+int32_t pic_set_inflow(pic_ctx* ctx, int32_t run, const pic_inflow_desc* d);
+
 /* Copy the particles of (run, species) to the host, with n_out = count (at
  * most cap), in ascending id order when ids are tracked (ids are load order,
  * then injection order; removed particles leave gaps), storage order
@@ -245,9 +307,13 @@ int32_t pic_gather_push(pic_ctx* ctx);
 int32_t pic_deposit(pic_ctx* ctx);
 int32_t pic_field_solve(pic_ctx* ctx, pic_solve_stats* stats);
 
-/* nsteps fused steps (gather+push+move+deposit in one kernel per tile, then
- * re-binning, the current reduction and the field solve). Synchronises once at
- * the end to report overflow and CG status. last: NULL or n_runs entries.
+/* nsteps fused steps, each one time step n -> n+1 of the method as the paper
+ * states it (Sec. 2, Eqs. (5)-(7): particles advanced with J^{n+1/2}
+ * deposited, then the implicit solve; the PIC ingredients of Sec. 1 and
+ * Sec. 3): gather+push+move+deposit in one kernel per tile, then re-binning,
+ * the current reduction and the field solve. Equal to pic_gather_push,
+ * pic_deposit, pic_field_solve in turn. Synchronises once at the end to
+ * report overflow and CG status. last: NULL or n_runs entries.
  * With sort_every = K > 0, after the re-binning of every K-th step each
  * tile's particles are reordered: sorted by cell, then dealt out so that each
  * wavefront of the particle kernel takes 64 distinct cells spread over the
@@ -255,12 +321,14 @@ int32_t pic_field_solve(pic_ctx* ctx, pic_solve_stats* stats);
  * This changes storage order only; reads with track_ids return id order. */
 int32_t pic_step(pic_ctx* ctx, int32_t nsteps, pic_solve_stats* last);
 
-/* Diagnostics of the current state of one run (synchronises): energies of
- * the last recorded step plus particle counts. gauss/divb (nullable) receive
- * max |div E - 4 pi rho| and max |div B| over the grid (for a shock run the
- * Gauss residual covers the node columns 1 .. x_out - 4: the wall line holds
- * the conductor's surface charge and particles leave at x_out). */
-int32_t pic_diag(pic_ctx* ctx, int32_t run, pic_diag_out* out, double* gauss, double* divb);
+/* Diagnostics of one run (synchronises): the energy record of the last
+ * recorded step, and from the current state the particle counts, Gauss's law
+ * residual with rho deposited by the order-p shape, div B, the total charge
+ * and the solve counters (the quantities by which the paper judges its runs:
+ * energy conservation, Sec. 3.2; and the field energy whose growth measures
+ * the numerical Cherenkov instability, Figs. 4-6). Returns PIC_E_NAN, with out
+ * filled, if any field value, energy, residual or charge is not finite. */
+int32_t pic_diag(pic_ctx* ctx, int32_t run, pic_diag_out* out);
 
 /* History records collected every diag_every steps (oldest first). */
 int32_t pic_history(pic_ctx* ctx, int32_t run, pic_diag_out* out, int32_t cap, int32_t* n_out);

@@ -21,12 +21,16 @@ PIC_SOLVER_CG, PIC_SOLVER_LEARNED_PCG = 0, 1
 PIC_NET_COLLAPSED, PIC_NET_MFMA = 0, 1
 NET_NW = 9792
 PIC_BC_PERIODIC, PIC_BC_SHOCK = 0, 1
+PIC_X0_ZERO, PIC_X0_PREV = 0, 1
+PIC_SCHEME_IMPLICIT, PIC_SCHEME_EXPLICIT = 0, 1
 PIC_WALL_GAP = 4
 FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
              "rho": 9}
+PIC_E_NOCONV, PIC_E_CAPACITY, PIC_E_NAN = -4, -5, -6
 STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
           -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
 EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_load_plasma", "pic_inject_particles",
+           "pic_set_inflow",
            "pic_read_particles", "pic_set_field", "pic_get_field", "pic_gather_push",
            "pic_deposit", "pic_field_solve", "pic_step", "pic_diag", "pic_history",
            "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
@@ -57,7 +61,8 @@ class Options(ctypes.Structure):
                 ("cg_blocks", ctypes.c_int32), ("track_ids", ctypes.c_int32),
                 ("tile_split", ctypes.c_int32), ("learned_form", ctypes.c_int32),
                 ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("sort_every", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("sort_every", ctypes.c_int32),
+                ("cg_x0", ctypes.c_int32), ("field_scheme", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -72,7 +77,7 @@ class PlanInfo(ctypes.Structure):
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32 * 3), ("relres", ctypes.c_double * 3),
                 ("bnorm", ctypes.c_double * 3), ("learned_iters", ctypes.c_int32 * 3),
-                ("fallback", ctypes.c_int32)]
+                ("fallback", ctypes.c_int32), ("relres_recursive", ctypes.c_double * 3)]
 
 
 class TrainOpts(ctypes.Structure):
@@ -88,6 +93,11 @@ class TrainStats(ctypes.Structure):
 class PlasmaDesc(ctypes.Structure):
     _fields_ = [("ppc", ctypes.c_int32), ("x_cells", ctypes.c_int32), ("gamma0", ctypes.c_double),
                 ("T", ctypes.c_double), ("direction", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class InflowDesc(ctypes.Structure):
+    _fields_ = [("ppc", ctypes.c_int32), ("gamma0", ctypes.c_double), ("T", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("first_step", ctypes.c_int64)]
 
 
 class TuneOpts(ctypes.Structure):
@@ -108,7 +118,10 @@ class DiagOut(ctypes.Structure):
                 ("W_B", ctypes.c_double), ("W_K_minus", ctypes.c_double),
                 ("W_K_plus", ctypes.c_double), ("cg_iters", ctypes.c_int32 * 3),
                 ("cg_relres", ctypes.c_double * 3),
-                ("n_particles", ctypes.c_int64 * PIC_MAX_SPECIES)]
+                ("n_particles", ctypes.c_int64 * PIC_MAX_SPECIES),
+                ("gauss_max", ctypes.c_double), ("divb_max", ctypes.c_double),
+                ("total_charge", ctypes.c_double), ("fallbacks", ctypes.c_int64),
+                ("solves", ctypes.c_int64)]
 
 
 class TimingOut(ctypes.Structure):
@@ -144,6 +157,7 @@ def lib():
                                       P(PlasmaDesc)]
         L.pic_inject_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                            ctypes.c_int64] + [ctypes.c_void_p] * 7
+        L.pic_set_inflow.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         L.pic_read_particles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                          ctypes.c_int64] + [ctypes.c_void_p] * 7 + \
                                         [P(ctypes.c_int64)]
@@ -155,8 +169,7 @@ def lib():
         L.pic_deposit.argtypes = [ctypes.c_void_p]
         L.pic_field_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.pic_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
-        L.pic_diag.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(DiagOut), ctypes.c_void_p,
-                               ctypes.c_void_p]
+        L.pic_diag.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(DiagOut)]
         L.pic_history.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                   ctypes.c_int32, P(ctypes.c_int32)]
         L.pic_timing.argtypes = [ctypes.c_void_p, ctypes.c_int32]
@@ -211,8 +224,10 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
                  diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0,
                  solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0,
-                 graph=False, sort_every=0):
-    """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma"."""
+                 graph=False, sort_every=0, cg_x0="zero", scheme="implicit"):
+    """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma";
+    cg_x0: "zero" or "prev" (plain CG from the previous step's dB);
+    scheme: "implicit" (Eqs. (5)-(7)) or "explicit" (Yee FDTD, Eqs. (3)-(4))."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
     o.solver = PIC_SOLVER_LEARNED_PCG if solver in ("learned", PIC_SOLVER_LEARNED_PCG) \
@@ -223,6 +238,9 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     o.precond_slots = int(precond_slots)
     o.graph = 1 if graph else 0
     o.sort_every = int(sort_every)
+    o.cg_x0 = PIC_X0_PREV if cg_x0 in ("prev", PIC_X0_PREV) else PIC_X0_ZERO
+    o.field_scheme = PIC_SCHEME_EXPLICIT if scheme in ("explicit", PIC_SCHEME_EXPLICIT) \
+        else PIC_SCHEME_IMPLICIT
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)
@@ -310,6 +328,17 @@ class Sim:
         self._check(self.L.pic_inject_particles(self.ctx, run, species, a[0].size,
                                                 *[_ptr(v) for v in a]), "inject_particles")
 
+    def set_inflow(self, run, ppc, gamma0, T, seed, first_step=0):
+        """Device-generated inflow of a shock run before every step
+        (pic_set_inflow); ppc=None switches it off."""
+        if ppc is None:
+            self._check(self.L.pic_set_inflow(self.ctx, run, None), "set_inflow")
+            return
+        d = InflowDesc()
+        d.ppc, d.gamma0, d.T, d.seed, d.first_step = (int(ppc), float(gamma0), float(T),
+                                                      int(seed), int(first_step))
+        self._check(self.L.pic_set_inflow(self.ctx, run, ctypes.byref(d)), "set_inflow")
+
     def read_particles(self, run, species, cap):
         out = dict(ix=np.empty(cap, np.int32), iy=np.empty(cap, np.int32),
                    fx=np.empty(cap), fy=np.empty(cap), ux=np.empty(cap), uy=np.empty(cap),
@@ -342,7 +371,8 @@ class Sim:
 
     def _stats(self, st):
         return [dict(iters=list(s.iters), relres=list(s.relres), bnorm=list(s.bnorm),
-                     learned_iters=list(s.learned_iters), fallback=s.fallback) for s in st]
+                     learned_iters=list(s.learned_iters), fallback=s.fallback,
+                     relres_recursive=list(s.relres_recursive)) for s in st]
 
     def field_solve(self, allow_noconv=False):
         st = (SolveStats * len(self.runs))()
@@ -371,16 +401,23 @@ class Sim:
                     W_K_plus=o.W_K_plus, cg_iters=list(o.cg_iters),
                     cg_relres=list(o.cg_relres), n_particles=list(o.n_particles))
 
-    def diag(self, run=0, divergences=False):
+    def diag_status(self, run=0):
+        """(status, record) of pic_diag without raising on PIC_E_NAN."""
         o = DiagOut()
-        g = ctypes.c_double(0.0)
-        d = ctypes.c_double(0.0)
-        self._check(self.L.pic_diag(self.ctx, run, ctypes.byref(o),
-                                    ctypes.byref(g) if divergences else None,
-                                    ctypes.byref(d) if divergences else None), "diag")
+        rc = self._check(self.L.pic_diag(self.ctx, run, ctypes.byref(o)), "diag", allow=(-6,))
         r = self._rec(o)
-        if divergences:
-            r["gauss_max"], r["divb_max"] = g.value, d.value
+        r.update(gauss_max=o.gauss_max, divb_max=o.divb_max, total_charge=o.total_charge,
+                 fallbacks=o.fallbacks, solves=o.solves)
+        return rc, r
+
+    def diag(self, run=0):
+        """pic_diag: the last energy record plus the current state's particle
+        counts, Gauss residual, div B, total charge and solve counters."""
+        o = DiagOut()
+        self._check(self.L.pic_diag(self.ctx, run, ctypes.byref(o)), "diag")
+        r = self._rec(o)
+        r.update(gauss_max=o.gauss_max, divb_max=o.divb_max, total_charge=o.total_charge,
+                 fallbacks=o.fallbacks, solves=o.solves)
         return r
 
     def history(self, run=0):

@@ -23,6 +23,7 @@ constexpr int kMaxCgBlocks = 4096;
 // each), so the default keeps the persistent grid small; pic_tune measures
 constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
+constexpr int kDivWords = 4;          // per-block words of the divergence diagnostics
 constexpr int kTimingClasses = 9;
 constexpr int kWgradBlocks = 256;     // work-groups of the weight-gradient partial sums
 // message of the last failed pic_init on this thread (pic_last_error(NULL))
@@ -116,6 +117,11 @@ struct pic_ctx {
   int* d_inj_id = nullptr;
   int* d_inj_list = nullptr;
   std::vector<std::array<long long, PIC_MAXS>> next_id;   // per run and species
+  // inflow of shock runs generated on the device before every step
+  InflowDev* d_inflow = nullptr;
+  long long* d_inflow_step = nullptr;
+  std::vector<InflowDev> inflow;   // host mirror of the table
+  bool any_inflow = false;
   double* d_rho = nullptr;
   double* d_divpart = nullptr;
   int* d_err = nullptr;
@@ -132,8 +138,9 @@ struct pic_ctx {
   int gkey[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   long long graph_replays = 0;
   long long diag_count = 0;
-  std::vector<long long> hist_step;  // steps recorded (host mirror)
   int threads = 256;
+  int device = 0;
+  std::vector<double> h_stats;    // host copy of the solve statistics (sized at init)
   std::string err;
   // timing
   bool timing = false;
@@ -179,6 +186,14 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     *msg = "sort_every must be >= 0";
     return PIC_E_INVAL;
   }
+  if (o->field_scheme != PIC_SCHEME_IMPLICIT && o->field_scheme != PIC_SCHEME_EXPLICIT) {
+    *msg = "field_scheme must be PIC_SCHEME_IMPLICIT or PIC_SCHEME_EXPLICIT";
+    return PIC_E_INVAL;
+  }
+  if (o->field_scheme == PIC_SCHEME_EXPLICIT && o->solver != PIC_SOLVER_CG) {
+    *msg = "the explicit scheme has no field solve (solver must be PIC_SOLVER_CG)";
+    return PIC_E_INVAL;
+  }
   if (o->solver == PIC_SOLVER_LEARNED_PCG) {
     if (o->learned_form != PIC_NET_COLLAPSED && o->learned_form != PIC_NET_MFMA) {
       *msg = "learned_form must be PIC_NET_COLLAPSED or PIC_NET_MFMA";
@@ -206,6 +221,12 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     if (d.bc != PIC_BC_PERIODIC && d.bc != PIC_BC_SHOCK)
       return bad("bc must be PIC_BC_PERIODIC or PIC_BC_SHOCK");
     if (d.bc == PIC_BC_SHOCK && d.nx < 16) return bad("a shock run needs nx >= 16");
+    if (o->field_scheme == PIC_SCHEME_EXPLICIT) {
+      if (d.bc != PIC_BC_PERIODIC) return bad("the explicit scheme is periodic only");
+      const double r = d.dx / d.dy;
+      if (d.cfl * d.cfl * (1.0 + r * r) > 1.0 + 1e-12)
+        return bad("explicit scheme beyond the Courant limit: cfl^2 (1 + dx^2/dy^2) > 1");
+    }
     if (d.n_species < 1 || d.n_species > PIC_MAX_SPECIES) return bad("n_species out of range");
     for (int s = 0; s < d.n_species; ++s)
       if (!(d.species[s].m > 0) || !std::isfinite(d.species[s].q) || !(d.species[s].ppc >= 0))
@@ -285,8 +306,9 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   float* Ef[6] = {};
   if (fast)
     for (int k = 0; k < 6; ++k) Ef[k] = b.take<float>(nc);
-  double *x[3], *pp[3], *r0[3], *r1[3], *w0[3], *w1[3], *s0[3], *s1[3];
+  double *x[3], *pp[3], *r0[3], *r1[3], *w0[3], *w1[3], *s0[3], *s1[3], *bsv[3];
   for (int k = 0; k < 3; ++k) {
+    bsv[k] = b.take<double>(nc);
     x[k] = b.take<double>(nc);
     pp[k] = b.take<double>(nc);
     r0[k] = b.take<double>(nc);
@@ -353,7 +375,9 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     inj_id = b.take<int>(inj_cap);
     inj_list = b.take<int>((size_t)3 * tl.n_tiles);
   }
-  double* divpart = b.take<double>((size_t)kDivBlocks * 2);
+  double* divpart = b.take<double>((size_t)kDivBlocks * kDivWords);
+  InflowDev* inflow = b.take<InflowDev>(n_runs);
+  long long* inflow_step = b.take<long long>(n_runs);
   double* patch[3];
   for (int k = 0; k < 3; ++k) patch[k] = b.take<double>((size_t)tl.n_tiles * K * plane);
   DevState<R> s{};
@@ -435,6 +459,7 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     f.w1[k] = w1[k];
     f.s0[k] = s0[k];
     f.s1[k] = s1[k];
+    f.bsv[k] = bsv[k];
   }
   for (int k = 0; k < 6; ++k) f.Ef[k] = Ef[k];
   f.part = part;
@@ -455,6 +480,8 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   c->d_stats = stats;
   c->d_history = history;
   c->d_rho = rho;
+  c->d_inflow = inflow;
+  c->d_inflow_step = inflow_step;
   c->inj_cap = inj_cap;
   c->d_inj_cell = inj_cell;
   c->d_inj_ox = inj_ox;
@@ -644,17 +671,14 @@ int launch_field(pic_ctx* c, int diag) {
   hipError_t e = pic_launch_field_solve(a, c->stream);
   t_end(c);
   if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("field solve: ") + hipGetErrorString(e));
-  if (diag) {
-    c->hist_step.push_back(c->step);
-    c->diag_count += 1;
-  }
+  if (diag) c->diag_count += 1;
   if (c->collect) c->pairs_written += 1;
   return PIC_OK;
 }
 
 int read_stats(pic_ctx* c, pic_solve_stats* out) {
   const int n = (int)c->runs.size();
-  std::vector<double> h((size_t)n * PIC_STAT_WORDS);
+  std::vector<double>& h = c->h_stats;
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_stats, h.size() * sizeof(double),
                            hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -664,15 +688,16 @@ int read_stats(pic_ctx* c, pic_solve_stats* out) {
     if (out) out[r].fallback = (int)st[12];
     for (int k = 0; k < 3; ++k) {
       const int it = (int)st[k];
-      const double rel = st[3 + k];
+      const double rel = st[3 + k], rec = st[16 + k];
       if (out) {
         out[r].iters[k] = it;
         out[r].relres[k] = rel;
         out[r].bnorm[k] = st[6 + k];
         out[r].learned_iters[k] = (int)st[9 + k];
+        out[r].relres_recursive[k] = rec;
       }
-      if (!std::isfinite(rel)) rc = PIC_E_NAN;
-      else if (it >= c->runs[r].cg_maxit && rel > c->runs[r].cg_rtol && rc == PIC_OK)
+      if (!std::isfinite(rel) || !std::isfinite(rec)) rc = PIC_E_NAN;
+      else if (it >= c->runs[r].cg_maxit && rec > c->runs[r].cg_rtol && rc == PIC_OK)
         rc = PIC_E_NOCONV;
     }
   }
@@ -697,8 +722,25 @@ int check_err(pic_ctx* c) {
   return PIC_OK;
 }
 
+// device inflow of the shock runs that have one, before the particles move
+template <typename R>
+int launch_inflow(pic_ctx* c) {
+  if (!c->any_inflow) return PIC_OK;
+  int max_nty = 0, ns = 0;
+  for (size_t r = 0; r < c->runs.size(); ++r) {
+    max_nty = std::max(max_nty, c->tl.nty[r]);
+    ns = std::max(ns, c->runs[r].n_species);
+  }
+  hipError_t e = pic_launch_inject_flow<R>(state<R>(c), c->d_inflow, c->d_inflow_step,
+                                           (int)c->runs.size(), max_nty, ns, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("inflow: ") + hipGetErrorString(e));
+  return PIC_OK;
+}
+
 template <typename R>
 int do_gather_push(pic_ctx* c) {
+  int rc = launch_inflow<R>(c);
+  if (rc) return rc;
   return launch_particles<R>(c, PIC_MODE_PUSH, diag_step(c) ? 1 : 0);
 }
 template <typename R>
@@ -729,7 +771,9 @@ int launch_sort(pic_ctx* c) {
 template <typename R>
 int do_step(pic_ctx* c) {
   const int diag = diag_step(c) ? 1 : 0;
-  int rc = launch_particles<R>(c, PIC_MODE_FUSED, diag);
+  int rc = launch_inflow<R>(c);
+  if (rc) return rc;
+  rc = launch_particles<R>(c, PIC_MODE_FUSED, diag);
   if (rc) return rc;
   rc = launch_exchange<R>(c);
   if (rc) return rc;
@@ -823,6 +867,51 @@ int graph_two_steps(pic_ctx* c) {
   return PIC_OK;
 }
 
+// Parameters of the seeded drifting Maxwell-Juettner draw (the same recipe as
+// the host generator): the boost and the rest-frame rejection envelope, a
+// chi-3 piece below uc and a three-term Gamma mixture above.
+PlasmaLoad plasma_load(uint64_t seed, int ppc, int x_cells, int ny, double gamma0, double T,
+                       int direction) {
+  PlasmaLoad L{};
+  L.seed = seed;
+  L.ppc = ppc;
+  L.x_cells = x_cells;
+  L.ny = ny;
+  L.gamma0 = gamma0;
+  L.beta = gamma0 > 1.0 ? (double)direction * std::sqrt(1.0 - 1.0 / (gamma0 * gamma0)) : 0.0;
+  L.T = T;
+  if (T > 0.0) {
+    const double uc = 5.0 * std::sqrt(T);
+    const double gc = std::sqrt(1.0 + uc * uc);
+    const double s2 = 0.5 * (1.0 + gc) * T;
+    const double sg = std::sqrt(s2);
+    const double mass_a = std::pow(sg, 3.0) * std::sqrt(M_PI / 2.0);
+    const double vc = uc / gc;
+    const double lam = vc / T;
+    const double c1 = uc * uc / lam, c2 = 2.0 * uc / std::pow(lam, 2.0),
+                 c3 = 2.0 / std::pow(lam, 3.0);
+    const double mass_b = std::exp(-(gc - 1.0) / T) * (c1 + c2 + c3);
+    L.pa = mass_a / (mass_a + mass_b);
+    L.s = sg;
+    L.uc = uc;
+    L.gc = gc;
+    L.vc = vc;
+    L.lam = lam;
+    L.mix0 = c1 / (c1 + c2 + c3);
+    L.mix1 = (c1 + c2) / (c1 + c2 + c3);
+  }
+  return L;
+}
+
+// In-cell offset in the particle precision. An FP64 offset just below 1 can
+// round up to 1 in FP32; it is clamped to the largest value below 1 so that
+// the particle keeps the cell (and hence the tile) it was binned into.
+template <typename R>
+R offset_below_one(double f) {
+  const R r = (R)f;
+  return r < R(1) ? r : std::nextafter(R(1), R(0));
+}
+
 template <typename R>
 int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const int32_t* iy,
               const double* fx, const double* fy, const double* ux, const double* uy,
@@ -880,11 +969,8 @@ int load_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const in
     const int t = tile_of[k];
     const size_t o = (size_t)t * slots + fill[t]++;
     hcell[o] = (iy[k] << 16) | ix[k];
-    hox[o] = (R)fx[k];
-    hoy[o] = (R)fy[k];
-    // an offset that rounds up to 1 in FP32 moves to the next cell
-    if (hox[o] >= R(1)) { hox[o] = R(0); hcell[o] = (iy[k] << 16) | ((ix[k] + 1) % d.nx); }
-    if (hoy[o] >= R(1)) { hoy[o] = R(0); hcell[o] = ((((hcell[o] >> 16) + 1) % d.ny) << 16) | (hcell[o] & 0xffff); }
+    hox[o] = offset_below_one<R>(fx[k]);
+    hoy[o] = offset_below_one<R>(fy[k]);
     hux[o] = (R)ux[k];
     huy[o] = (R)uy[k];
     huz[o] = (R)uz[k];
@@ -960,10 +1046,8 @@ int inject_impl(pic_ctx* c, int run, int s, int64_t n, const int32_t* ix, const 
   for (int64_t k = 0; k < n; ++k) {
     const int o = pos[tile_of[k]]++;
     hcell[o] = (iy[k] << 16) | ix[k];
-    hox[o] = (R)fx[k];
-    hoy[o] = (R)fy[k];
-    if (hox[o] >= R(1)) { hox[o] = R(0); hcell[o] = (iy[k] << 16) | (ix[k] + 1); }
-    if (hoy[o] >= R(1)) { hoy[o] = R(0); hcell[o] = ((((hcell[o] >> 16) + 1) % d.ny) << 16) | (hcell[o] & 0xffff); }
+    hox[o] = offset_below_one<R>(fx[k]);
+    hoy[o] = offset_below_one<R>(fy[k]);
     hux[o] = (R)ux[k];
     huy[o] = (R)uy[k];
     huz[o] = (R)uz[k];
@@ -1184,6 +1268,8 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
                   c->pair_slots, net_cells, ic, c, &c->sd);
   c->next_id.assign(n_runs, std::array<long long, PIC_MAXS>{0, 0});
   c->fa.learned_form = opt->learned_form;
+  c->fa.cg_x0 = opt->cg_x0 == PIC_X0_PREV ? 1 : 0;
+  c->fa.explicit_fdtd = opt->field_scheme == PIC_SCHEME_EXPLICIT ? 1 : 0;
   c->fa.coop = 1;
   c->fa.any_shock = 0;
   for (int r = 0; r < n_runs; ++r)
@@ -1222,6 +1308,8 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     return PIC_E_HIP;
   }
   c->max_cg_blocks = std::min(maxb, kMaxCgBlocks);
+  c->device = dev;
+  c->h_stats.assign((size_t)n_runs * PIC_STAT_WORDS, 0.0);
   c->hruns.resize(n_runs);
   for (int r = 0; r < n_runs; ++r) {
     const pic_run_desc& d = runs[r];
@@ -1326,37 +1414,7 @@ int32_t pic_load_plasma(pic_ctx* c, int32_t run, int32_t species, const pic_plas
     return fail(c, PIC_E_CAPACITY, "tile slots smaller than ppc x tile cells; raise slack or ppc");
   const long long n = (long long)xc * rd.ny * d->ppc;
   if (n > (long long)INT32_MAX) return fail(c, PIC_E_INVAL, "too many particles for int32 ids");
-  PlasmaLoad L{};
-  L.seed = d->seed;
-  L.ppc = d->ppc;
-  L.x_cells = xc;
-  L.ny = rd.ny;
-  L.gamma0 = d->gamma0;
-  L.beta = d->gamma0 > 1.0 ? (double)d->direction * std::sqrt(1.0 - 1.0 / (d->gamma0 * d->gamma0))
-                           : 0.0;
-  L.T = d->T;
-  if (d->T > 0.0) {
-    // rejection envelope: chi-3 piece below uc, three-term Gamma mixture above
-    const double T = d->T;
-    const double uc = 5.0 * std::sqrt(T);
-    const double gc = std::sqrt(1.0 + uc * uc);
-    const double s2 = 0.5 * (1.0 + gc) * T;
-    const double sg = std::sqrt(s2);
-    const double mass_a = std::pow(sg, 3.0) * std::sqrt(M_PI / 2.0);
-    const double vc = uc / gc;
-    const double lam = vc / T;
-    const double c1 = uc * uc / lam, c2 = 2.0 * uc / std::pow(lam, 2.0),
-                 c3 = 2.0 / std::pow(lam, 3.0);
-    const double mass_b = std::exp(-(gc - 1.0) / T) * (c1 + c2 + c3);
-    L.pa = mass_a / (mass_a + mass_b);
-    L.s = sg;
-    L.uc = uc;
-    L.gc = gc;
-    L.vc = vc;
-    L.lam = lam;
-    L.mix0 = c1 / (c1 + c2 + c3);
-    L.mix1 = (c1 + c2) / (c1 + c2 + c3);
-  }
+  const PlasmaLoad L = plasma_load(d->seed, d->ppc, xc, rd.ny, d->gamma0, d->T, d->direction);
   const int nt = tl.ntx[run] * tl.nty[run];
   hipError_t e = c->fast
                      ? pic_launch_load_plasma<float>(c->sf, run, species, L, nt, c->stream)
@@ -1381,6 +1439,46 @@ int32_t pic_inject_particles(pic_ctx* c, int32_t run, int32_t species, int64_t n
   if (c->phase != 0) return fail(c, PIC_E_STATE, "inject during a split step");
   return c->fast ? inject_impl<float>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz)
                  : inject_impl<double>(c, run, species, n, ix, iy, fx, fy, ux, uy, uz);
+}
+
+int32_t pic_set_inflow(pic_ctx* c, int32_t run, const pic_inflow_desc* d) {
+  if (!c || run < 0 || run >= (int)c->runs.size()) return PIC_E_INVAL;
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "set_inflow during a split step");
+  const pic_run_desc& rd = c->runs[run];
+  InflowDev f{};
+  long long step0 = 0;
+  if (d) {
+    if (rd.bc != PIC_BC_SHOCK) return fail(c, PIC_E_INVAL, "inflow needs a PIC_BC_SHOCK run");
+    if (d->ppc < 1 || !(d->gamma0 > 1.0) || !(d->T >= 0.0) || d->first_step < 0)
+      return fail(c, PIC_E_INVAL, "inflow needs ppc >= 1, gamma0 > 1, T >= 0, first_step >= 0");
+    const int x_out = rd.nx - PIC_WALL_GAP;
+    const double beta0 = std::sqrt(1.0 - 1.0 / (d->gamma0 * d->gamma0));
+    f.on = 1;
+    f.w = beta0 * rd.cfl;
+    f.ppc_w = (double)d->ppc * f.w;
+    f.item0 = (long long)x_out * rd.ny * d->ppc;
+    f.L = plasma_load(d->seed, d->ppc, x_out, rd.ny, d->gamma0, d->T, -1);
+    // a step adds at most ceil(ppc w) particles per row to the tiles of the
+    // entry column: the fullest tile must hold them on top of a full load
+    const long long per_tile =
+        (long long)c->tl.TXA * c->tl.TYA * d->ppc + (long long)std::ceil(f.ppc_w) * c->tl.TYA;
+    for (int s = 0; s < rd.n_species; ++s)
+      if (per_tile > c->plan.tile_slots[s])
+        return fail(c, PIC_E_CAPACITY, "tile slots too few for the inflow; raise slack");
+    step0 = d->first_step;
+  }
+  if (c->inflow.empty()) c->inflow.assign(c->runs.size(), InflowDev{});
+  c->inflow[run] = f;
+  c->any_inflow = false;
+  for (const InflowDev& v : c->inflow) c->any_inflow = c->any_inflow || v.on;
+  HIPCHK(c, hipMemcpyAsync(c->d_inflow + run, &c->inflow[run], sizeof(InflowDev),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->d_inflow_step + run, &step0, sizeof(long long),
+                           hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // captured graphs hold the step's launches: capture again
+  for (int k = 0; k < 8; ++k) c->gkey[k] = -1;
+  return PIC_OK;
 }
 
 int32_t pic_read_particles(pic_ctx* c, int32_t run, int32_t species, int64_t cap, int32_t* ix,
@@ -1507,60 +1605,67 @@ int32_t pic_history(pic_ctx* c, int32_t run, pic_diag_out* out, int32_t cap, int
   return PIC_OK;
 }
 
-int32_t pic_diag(pic_ctx* c, int32_t run, pic_diag_out* out, double* gauss, double* divb) {
-  if (!c || run < 0 || run >= (int)c->runs.size()) return PIC_E_INVAL;
+int32_t pic_diag(pic_ctx* c, int32_t run, pic_diag_out* out) {
+  if (!c || !out || run < 0 || run >= (int)c->runs.size()) return PIC_E_INVAL;
   if (c->phase != 0) return fail(c, PIC_E_STATE, "diag during a split step");
-  int rc = PIC_OK;
-  if (out) {
-    memset(out, 0, sizeof *out);
-    if (c->diag_count > 0) {
-      int n = 0;
-      std::vector<pic_diag_out> all(std::min<long long>(c->diag_count, c->opt.history_cap));
-      rc = pic_history(c, run, all.data(), (int)all.size(), &n);
-      if (rc) return rc;
-      if (n > 0) *out = all[n - 1];
-    } else {
-      out->step = -1;
-    }
-    const Tiling& tl = c->tl;
-    const int nt = tl.ntx[run] * tl.nty[run];
-    for (int s = 0; s < c->runs[run].n_species; ++s) {
-      std::vector<int> cnt(nt);
-      int* src = c->fast ? c->sf.cnt[s] : c->sd.cnt[s];
-      HIPCHK(c, hipMemcpyAsync(cnt.data(), src + tl.tile0[run], nt * sizeof(int),
-                               hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      long long tot = 0;
-      for (int v : cnt) tot += v;
-      out->n_particles[s] = tot;
-    }
-  }
-  if (gauss || divb) {
-    rc = c->fast ? rho_impl<float>(c, run) : rho_impl<double>(c, run);
+  memset(out, 0, sizeof *out);
+  out->step = -1;
+  if (c->diag_count > 0) {
+    int n = 0;
+    std::vector<pic_diag_out> all(std::min<long long>(c->diag_count, c->opt.history_cap));
+    int rc = pic_history(c, run, all.data(), (int)all.size(), &n);
     if (rc) return rc;
-    const double* E[3] = {c->fa.E[0], c->fa.E[1], c->fa.E[2]};
-    const double* B[3] = {c->fa.B[0], c->fa.B[1], c->fa.B[2]};
-    hipError_t e = pic_launch_divergences(c->d_runs, run,
-                                          (long long)c->runs[run].nx * c->runs[run].ny, E, B,
-                                          c->d_rho, c->d_divpart, kDivBlocks, c->stream);
-    if (e != hipSuccess) return fail(c, PIC_E_HIP, hipGetErrorString(e));
-    std::vector<double> h(kDivBlocks * 2);
-    HIPCHK(c, hipMemcpyAsync(h.data(), c->d_divpart, h.size() * sizeof(double),
+    if (n > 0) *out = all[n - 1];
+  }
+  const Tiling& tl = c->tl;
+  const int nt = tl.ntx[run] * tl.nty[run];
+  for (int s = 0; s < c->runs[run].n_species; ++s) {
+    std::vector<int> cnt(nt);
+    int* src = c->fast ? c->sf.cnt[s] : c->sd.cnt[s];
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), src + tl.tile0[run], nt * sizeof(int),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    double g = 0, d = 0;
-    for (int b = 0; b < kDivBlocks; ++b) {
-      if (h[2 * b] > g || std::isnan(h[2 * b])) g = h[2 * b];
-      if (h[2 * b + 1] > d || std::isnan(h[2 * b + 1])) d = h[2 * b + 1];
-    }
-    if (gauss) *gauss = g;
-    if (divb) *divb = d;
-    if (std::isnan(g) || std::isnan(d)) return fail(c, PIC_E_NAN, "non-finite field divergence");
+    long long tot = 0;
+    for (int v : cnt) tot += v;
+    out->n_particles[s] = tot;
   }
-  if (out && (!std::isfinite(out->W_E) || !std::isfinite(out->W_B) ||
-              !std::isfinite(out->W_K_plus)))
+  std::vector<double> st(PIC_STAT_WORDS);
+  HIPCHK(c, hipMemcpyAsync(st.data(), c->d_stats + (size_t)run * PIC_STAT_WORDS,
+                           st.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  int rc = c->fast ? rho_impl<float>(c, run) : rho_impl<double>(c, run);
+  if (rc) return rc;
+  const double* E[3] = {c->fa.E[0], c->fa.E[1], c->fa.E[2]};
+  const double* B[3] = {c->fa.B[0], c->fa.B[1], c->fa.B[2]};
+  hipError_t e = pic_launch_divergences(c->d_runs, run,
+                                        (long long)c->runs[run].nx * c->runs[run].ny, E, B,
+                                        c->d_rho, c->d_divpart, kDivBlocks, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, hipGetErrorString(e));
+  std::vector<double> h(kDivBlocks * kDivWords);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_divpart, h.size() * sizeof(double),
+                           hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  // maxima (NaN wins), the charge in block order, non-finite field values
+  double g = 0, d = 0, q = 0, bad = 0;
+  for (int b = 0; b < kDivBlocks; ++b) {
+    const double* p = h.data() + (size_t)b * kDivWords;
+    if (p[0] > g || std::isnan(p[0])) g = p[0];
+    if (p[1] > d || std::isnan(p[1])) d = p[1];
+    q += p[2];
+    bad += p[3];
+  }
+  const pic_run_desc& rd = c->runs[run];
+  out->gauss_max = g;
+  out->divb_max = d;
+  out->total_charge = q * rd.dx * rd.dy;
+  out->fallbacks = (int64_t)st[13];
+  out->solves = (int64_t)st[14];
+  if (bad > 0) return fail(c, PIC_E_NAN, "non-finite E or B value");
+  if (!std::isfinite(g) || !std::isfinite(d) || !std::isfinite(out->total_charge))
+    return fail(c, PIC_E_NAN, "non-finite Gauss residual, div B or charge");
+  if (out->step >= 0 && (!std::isfinite(out->W_E) || !std::isfinite(out->W_B) ||
+                         !std::isfinite(out->W_K_minus) || !std::isfinite(out->W_K_plus)))
     return fail(c, PIC_E_NAN, "non-finite energy");
-  return rc;
+  return PIC_OK;
 }
 
 int32_t pic_timing(pic_ctx* c, int32_t on) {

@@ -23,6 +23,14 @@
 //   gamma = <r,r>, delta = <w,r>, beta = gamma_{k+1}/gamma_k,
 //   alpha_{k+1} = gamma_{k+1} / (delta_{k+1} - beta_{k+1} gamma_{k+1}/alpha_k).
 //
+// Explicit variant (the Yee FDTD of Eqs. (3)-(4), which the paper contrasts
+// with the implicit solver): B carried at integer times for the particle push,
+// advanced in three sweeps separated by grid barriers,
+//   B^{n+1/2} = B^n - (c dt/2) curl E^n,
+//   E^{n+1}   = E^n + c dt curl B^{n+1/2} - 4 pi dt J^{n+1/2},
+//   B^{n+1}   = B^{n+1/2} - (c dt/2) curl E^{n+1},
+// whose half-step values are the leapfrog of Eqs. (3)-(4).
+//
 // Learned solver (an addition to the method): x_0 = N(b) and flexible CG
 // with z = N(r) as preconditioner and the Polak-Ribiere beta,
 // beta = <z_{k+1}, r_{k+1} - r_k>/<z_k, r_k> = -alpha_k <z_{k+1}, q_k>/<z_k, r_k>,
@@ -155,7 +163,7 @@ __device__ __forceinline__ void curl_fwd(const Loc& L, double* const* F, int i, 
 }
 
 // kMode: 0 plain CG, 1 learned with the collapsed filter, 2 learned with the
-// BF16 network. kShock: some run of the context has shock walls (the wall
+// BF16 network, 3 explicit FDTD (no solve). kShock: some run of the context has shock walls (the wall
 // rows are then tested per run; without it they compile away).
 template <int kMode, bool kShock>
 __global__ void __launch_bounds__(kThreads)
@@ -247,7 +255,7 @@ k_field_solve(FieldArgs a) {
   // run's blocks: rd(c, i, j) gives the input at any cell, wr(c, i, j, z) sees
   // each output of the run's own cells
   // this run's network (runs that share an operator share it)
-  const NetWeights net = kMode != 0 ? a.nets[R.net_id] : NetWeights{};
+  const NetWeights net = (kMode == 1 || kMode == 2) ? a.nets[R.net_id] : NetWeights{};
   constexpr bool collapsed = kMode == 1;
   constexpr int TE = collapsed ? NET_KT : NET_T;
   const int ntx = (R.nx + TE - 1) / TE, nty = (R.ny + TE - 1) / TE;
@@ -268,7 +276,116 @@ k_field_solve(FieldArgs a) {
     }
   };
 
-  // ---- P0: right-hand side of Eq. (7): b into r0 and r1 (kept), x = 0; energies
+  // per-run record (leader block, thread 0): solve statistics and the
+  // energies of step n; tr = squared true residual norms
+  auto write_record = [&](const double (&tr)[3], const int (&its)[3], const double (&b2)[3],
+                          const double (&g2)[3], const int (&lits)[3], int fb, double we,
+                          double wb) {
+    double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
+    for (int c = 0; c < 3; ++c) {
+      st[c] = (double)its[c];
+      st[3 + c] = b2[c] > 0.0 ? sqrt(tr[c] / b2[c]) : 0.0;
+      st[6 + c] = sqrt(b2[c]);
+      st[9 + c] = (double)lits[c];
+      st[16 + c] = b2[c] > 0.0 ? sqrt(g2[c] / b2[c]) : 0.0;
+    }
+    st[12] = (double)fb;
+    st[13] += (double)fb;   // cumulative counters since initialisation
+    st[14] += 1.0;
+    if (a.diag) {
+      double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
+      const int nt = R.ntx * R.nty;
+      for (int t = R.tile0 * a.K; t < (R.tile0 + nt) * a.K; ++t)
+        for (int s = 0; s < R.nspecies; ++s) {
+          wk[s][0] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 0];
+          wk[s][1] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 1];
+        }
+      const double cellv = R.dx * R.dy / (2.0 * kFourPi);
+      double* rec = a.history + ((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS;
+      rec[0] = (double)a.step;
+      rec[1] = (double)a.step * dt;
+      rec[2] = we * cellv;
+      rec[3] = wb * cellv;
+      rec[4] = wk[0][0] + wk[1][0];
+      rec[5] = wk[0][1] + wk[1][1];
+      for (int c = 0; c < 3; ++c) {
+        rec[6 + c] = (double)its[c];
+        rec[9 + c] = st[3 + c];
+      }
+    }
+  };
+  // FP32 copies of E and B for the fast particle path
+  auto write_shadow = [&](long long g) {
+    if (a.Ef[0]) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a.Ef[c][g] = (float)a.E[c][g];
+        a.Ef[3 + c][g] = (float)a.B[c][g];
+      }
+    }
+  };
+
+  if constexpr (kMode == 3) {
+    // ---- X1: B^{n+1/2} = B^n - (dt/2) curl E^n into x; energies of step n
+    double en[2] = {0.0, 0.0};
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      double ce[3];
+      curl_fwd(L, a.E, i, j, idx_, idy_, ce);
+      const long long g = L.base + k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double bb = a.B[c][g];
+        a.x[c][g] = bb - 0.5 * dt * ce[c];
+        if (a.diag) {
+          const double e = a.E[c][g];
+          en[0] += e * e;
+          en[1] += bb * bb;
+        }
+      }
+    }
+    block_sum<2>(en, sm);
+    put_part<2>(part0, en);
+    barrier();
+    // ---- X2: E^{n+1} = E^n + dt curl B^{n+1/2} - 4 pi dt J^{n+1/2}
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      const long long g = L.base + k;
+      const long long gxm = lidx(L, i - 1, j), gym = lidx(L, i, j - 1);
+      const double cx = (a.x[2][g] - a.x[2][gym]) * idy_;
+      const double cy = -(a.x[2][g] - a.x[2][gxm]) * idx_;
+      const double cz = (a.x[1][g] - a.x[1][gxm]) * idx_ - (a.x[0][g] - a.x[0][gym]) * idy_;
+      a.E[0][g] += dt * cx - kFourPi * dt * a.J[0][g];
+      a.E[1][g] += dt * cy - kFourPi * dt * a.J[1][g];
+      a.E[2][g] += dt * cz - kFourPi * dt * a.J[2][g];
+    }
+    barrier();
+    // ---- X3: B^{n+1} = B^{n+1/2} - (dt/2) curl E^{n+1}; FP32 copies
+    for (int k = first; k < ncell; k += stride) {
+      const int j = k / R.nx, i = k - j * R.nx;
+      double ce[3];
+      curl_fwd(L, a.E, i, j, idx_, idy_, ce);
+      const long long g = L.base + k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.B[c][g] = a.x[c][g] - 0.5 * dt * ce[c];
+      write_shadow(g);
+    }
+    if (leader) {
+      double e2[2];
+      run_sum<2>(part0, blo, bhi, e2, sm);
+      if (threadIdx.x == 0) {
+        const double z3[3] = {0.0, 0.0, 0.0};
+        const int zi[3] = {0, 0, 0};
+        write_record(z3, zi, z3, z3, zi, 0, e2[0], e2[1]);
+      }
+    }
+    return;
+  }
+
+  // plain CG from the previous step's dB (kept in x) instead of zero
+  const bool warm = kMode == 0 && a.cg_x0 != 0;
+  // ---- P0: right-hand side of Eq. (7): b into r0, r1 and bsv (kept), x = 0
+  // (or the previous dB); energies
   {
     double en[2] = {0.0, 0.0};
     for (int k = first; k < ncell; k += stride) {
@@ -282,7 +399,8 @@ k_field_solve(FieldArgs a) {
         const double b = rhs_b(c, i, j, cj, ce);
         a.r0[c][g] = b;
         a.r1[c][g] = b;
-        a.x[c][g] = 0.0;
+        a.bsv[c][g] = b;
+        if (!warm) a.x[c][g] = 0.0;
       }
       if (a.diag) {
 #pragma unroll
@@ -313,7 +431,7 @@ k_field_solve(FieldArgs a) {
   double bn2[3] = {0, 0, 0}, gam[3] = {0, 0, 0};
   int iters[3] = {0, 0, 0}, learned_iters[3] = {0, 0, 0};
   bool need_plain[3] = {true, true, true};
-  bool x_nonzero = false;
+  bool x_nonzero = warm;
   int fallback = 0;
 
   if constexpr (kMode != 0) {
@@ -601,64 +719,23 @@ k_field_solve(FieldArgs a) {
     }
   }
 
-  // ---- per-run record: solve statistics and energies of step n
-  if (leader && threadIdx.x == 0) {
-    double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
-    for (int c = 0; c < 3; ++c) {
-      st[c] = (double)iters[c];
-      st[3 + c] = bn2[c] > 0.0 ? sqrt(gam[c] / bn2[c]) : 0.0;
-      st[6 + c] = sqrt(bn2[c]);
-      st[9 + c] = (double)learned_iters[c];
-    }
-    st[12] = (double)fallback;
-    if (a.diag) {
-      double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
-      const int nt = R.ntx * R.nty;
-      for (int t = R.tile0 * a.K; t < (R.tile0 + nt) * a.K; ++t)
-        for (int s = 0; s < R.nspecies; ++s) {
-          wk[s][0] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 0];
-          wk[s][1] += a.wk_part[((size_t)t * PIC_MAXS + s) * 2 + 1];
-        }
-      const double cellv = R.dx * R.dy / (2.0 * kFourPi);
-      double* rec = a.history + ((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS;
-      rec[0] = (double)a.step;
-      rec[1] = (double)a.step * dt;
-      rec[2] = we_tot * cellv;
-      rec[3] = wb_tot * cellv;
-      rec[4] = wk[0][0] + wk[1][0];
-      rec[5] = wk[0][1] + wk[1][1];
-      for (int c = 0; c < 3; ++c) {
-        rec[6 + c] = (double)iters[c];
-        rec[9 + c] = st[3 + c];
-      }
-    }
-  }
-
-  // ---- training pairs (b, dB) of each network's first run, recorded after
-  // the solve; the right-hand side is recomputed from E^n, B^n, J (r1 may be
-  // overwritten)
-  if (a.collect && R.pairs) {
-    double* const pb = R.pairs + (size_t)a.pair_slot * 6 * ncell;
-    for (int k = first; k < ncell; k += stride) {
-      const int j = k / R.nx, i = k - j * R.nx;
-      double cj[3], ce[3];
-      curl_fwd(L, a.J, i, j, idx_, idy_, cj);
-      curl_fwd(L, a.E, i, j, idx_, idy_, ce);
-      const long long g = L.base + k;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        pb[(size_t)(2 * c) * ncell + k] = rhs_b(c, i, j, cj, ce);
-        pb[(size_t)(2 * c + 1) * ncell + k] = a.x[c][g];
-      }
-    }
-  }
-  barrier();
-
-  // ---- E update, Eq. (6): E += dt curl_B(B^n + theta dB) - 4 pi dt J
+  // ---- E update, Eq. (6): E += dt curl_B(B^n + theta dB) - 4 pi dt J; in the
+  // same sweep the training pairs (b, dB) of each network's first run (b kept
+  // from P0). dB is complete (the solve ended on a barrier) and this sweep
+  // writes only E at its own cells.
+  const bool rec_pairs = a.collect && R.pairs;
+  double* const pb = rec_pairs ? R.pairs + (size_t)a.pair_slot * 6 * ncell : nullptr;
   for (int k = first; k < ncell; k += stride) {
     const int j = k / R.nx, i = k - j * R.nx;
     const long long g = L.base + k;
     const long long gxm = lidx(L, i - 1, j), gym = lidx(L, i, j - 1);
+    if (rec_pairs) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pb[(size_t)(2 * c) * ncell + k] = a.bsv[c][g];
+        pb[(size_t)(2 * c + 1) * ncell + k] = a.x[c][g];
+      }
+    }
     const double bz = a.B[2][g] + th * a.x[2][g];
     const double bz_ym = a.B[2][gym] + th * a.x[2][gym];
     const double bz_xm = a.B[2][gxm] + th * a.x[2][gxm];
@@ -680,18 +757,89 @@ k_field_solve(FieldArgs a) {
     }
   }
   barrier();
+
+  // ---- per-run record: solve statistics and energies of step n (the true
+  // residual words are written by k_true_residual_final after this kernel)
+  if (leader && threadIdx.x == 0)
+    write_record(gam, iters, bn2, gam, learned_iters, fallback, we_tot, wb_tot);
+
   // ---- B update, Eq. (5) through dB; FP32 copies for the fast particle path
   for (int k = first; k < ncell; k += stride) {
     const long long g = L.base + k;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double bnew = a.B[c][g] + a.x[c][g];
-      a.B[c][g] = bnew;
-      if (a.Ef[0]) {
-        a.Ef[3 + c][g] = (float)bnew;
-        a.Ef[c][g] = (float)a.E[c][g];
-      }
+    for (int c = 0; c < 3; ++c) a.B[c][g] += a.x[c][g];
+    write_shadow(g);
+  }
+}
+
+}  // namespace
+
+namespace {
+
+// The operator of Eq. (7), (1 - (theta dt)^2 L) v, for component c at cell
+// (i, j) of run R, with the shock runs' wall rows (the solve's operator).
+__device__ double op_at(const DevRun& R, const double* v, int c, int i, int j) {
+  const Loc L{R.cell0, R.nx, R.ny};
+  const long long g = lidx(L, i, j);
+  long long gxp = lidx(L, i + 1, j), gxm = lidx(L, i - 1, j);
+  if (R.bc == 1) {
+    const bool fixed = c == 0 ? (i == 0 || i == R.nx - 1) : i == R.nx - 1;
+    if (fixed) return v[g];
+    if (c > 0) {
+      if (i == 0) gxm = g;
+      if (i == R.nx - 2) gxp = g;
     }
+  }
+  const double a2 = (R.theta * R.dt) * (R.theta * R.dt);
+  const double ax = a2 / (R.dx * R.dx), ay = a2 / (R.dy * R.dy);
+  const double cc = v[g];
+  return cc - ax * (v[gxp] - 2.0 * cc + v[gxm]) -
+         ay * (v[lidx(L, i, j + 1)] - 2.0 * cc + v[lidx(L, i, j - 1)]);
+}
+
+constexpr int kResThreads = 256, kResBlocks = 64;
+
+// True residual ||b - A dB||^2 of the applied dB per component, after the
+// solve: per (work-group, run) partial sums in a fixed reduction tree.
+__global__ void __launch_bounds__(kResThreads) k_true_residual(FieldArgs a) {
+  const int run = blockIdx.y;
+  const DevRun& R = a.runs[run];
+  const int ncell = R.nx * R.ny;
+  double d[3] = {0.0, 0.0, 0.0};
+  for (int k = blockIdx.x * kResThreads + threadIdx.x; k < ncell; k += kResBlocks * kResThreads) {
+    const int j = k / R.nx, i = k - j * R.nx;
+    const long long g = R.cell0 + k;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double r = a.bsv[c][g] - op_at(R, a.x[c], c, i, j);
+      d[c] += r * r;
+    }
+  }
+  __shared__ double sm[3][kResThreads];
+  for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] = d[c];
+  __syncthreads();
+  for (int off = kResThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 3)
+    a.part[((size_t)run * kResBlocks + blockIdx.x) * 4 + threadIdx.x] = sm[threadIdx.x][0];
+}
+
+// sum of the partials in block order; relres = ||b - A dB|| / ||b|| into the
+// solve statistics and the step's history record
+__global__ void k_true_residual_final(FieldArgs a) {
+  const int run = blockIdx.x;
+  if (threadIdx.x != 0) return;
+  double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
+  for (int c = 0; c < 3; ++c) {
+    double s = 0.0;
+    for (int b = 0; b < kResBlocks; ++b) s += a.part[((size_t)run * kResBlocks + b) * 4 + c];
+    const double bn = st[6 + c];
+    st[3 + c] = bn > 0.0 ? sqrt(s) / bn : 0.0;
+    if (a.diag)
+      a.history[((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS + 9 + c] = st[3 + c];
   }
 }
 
@@ -702,7 +850,8 @@ size_t pic_field_solve_smem(int learned, int form) {
 }
 
 namespace {
-const void* solve_kernel(int learned, int form, int shock) {
+const void* solve_kernel(int learned, int form, int shock, int explicit_fdtd) {
+  if (explicit_fdtd) return (const void*)k_field_solve<3, false>;
   if (shock) {
     if (!learned) return (const void*)k_field_solve<0, true>;
     return form == 0 ? (const void*)k_field_solve<1, true> : (const void*)k_field_solve<2, true>;
@@ -714,13 +863,14 @@ const void* solve_kernel(int learned, int form, int shock) {
 
 int pic_field_solve_max_blocks(int n_cu, int learned, int form) {
   int nb = 0;
-  for (int shock = 0; shock < 2; ++shock) {
+  for (int variant = 0; variant < 3; ++variant) {
+    // periodic, shock walls, explicit FDTD
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, solve_kernel(learned, form, shock),
-                                                     kThreads, pic_field_solve_smem(learned, form)) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &v, solve_kernel(learned, form, variant == 1, variant == 2), kThreads,
+            pic_field_solve_smem(learned, form)) != hipSuccess)
       return -1;
-    nb = shock == 0 ? v : (v < nb ? v : nb);
+    nb = variant == 0 ? v : (v < nb ? v : nb);
   }
   return nb * n_cu;
 }
@@ -728,13 +878,22 @@ int pic_field_solve_max_blocks(int n_cu, int learned, int form) {
 hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s) {
   FieldArgs copy = a;
   void* args[] = {(void*)&copy};
-  const void* k = solve_kernel(a.learned, a.learned_form, a.any_shock);
+  const void* k = solve_kernel(a.learned, a.learned_form, a.any_shock, a.explicit_fdtd);
   const size_t smem = pic_field_solve_smem(a.learned, a.learned_form);
+  hipError_t e;
   if (a.coop)
-    return hipLaunchCooperativeKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
-  // ordinary launch (inside a captured graph): the grid is no larger than the
-  // co-resident maximum and the kernel runs alone in its stream, so all
-  // work-groups are resident; a grid that is not still ends through the
-  // barrier's bounded spin with an error bit
-  return hipLaunchKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
+    e = hipLaunchCooperativeKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
+  else
+    // ordinary launch (inside a captured graph): the grid is no larger than
+    // the co-resident maximum and the kernel runs alone in its stream, so all
+    // work-groups are resident; a grid that is not still ends through the
+    // barrier's bounded spin with an error bit
+    e = hipLaunchKernel(k, dim3(a.n_blocks), dim3(kThreads), args, smem, s);
+  if (e != hipSuccess || a.explicit_fdtd) return e;
+  // the true residual of the applied dB: a separate sweep of two small
+  // kernels (inside the persistent solve the same stencil sweep costs about
+  // 0.2 ms at 1024 x 256, measured)
+  k_true_residual<<<dim3(kResBlocks, a.n_runs), kResThreads, 0, s>>>(copy);
+  k_true_residual_final<<<a.n_runs, 64, 0, s>>>(copy);
+  return hipGetLastError();
 }

@@ -100,6 +100,36 @@ __device__ double mj_speed(const Stream& st, long long k, const PlasmaLoad& L) {
   return 0.0;   // not reached in practice (acceptance is about one half per attempt)
 }
 
+// lab-frame momentum of item k: rest-frame magnitude (blocks 2, ...), an
+// isotropic direction (block 0), the flip decision (block 1) and the boost
+// along x with velocity L.beta (Zenitani's flipping method)
+__device__ void draw_momentum(const Stream& mom, long long k, const PlasmaLoad& L, double& ux,
+                              double& uy, double& uz) {
+#pragma clang fp contract(off)
+  const double umag = L.T > 0.0 ? mj_speed(mom, k, L) : 0.0;
+  double d0, d1, f0, unused;
+  mom.u01(k, 0, d0, d1);
+  mom.u01(k, 1, f0, unused);
+  const double mu = 2.0 * d0 - 1.0;
+  const double phi = kTwoPi * d1;
+  const double stt = sqrt(fmax(0.0, 1.0 - mu * mu));
+  ux = umag * mu;
+  uy = umag * stt * cos(phi);
+  uz = umag * stt * sin(phi);
+  if (L.gamma0 > 1.0) {
+    const double gp = sqrt(1.0 + umag * umag);
+    const double vx = ux / gp;
+    if (-L.beta * vx > f0) ux = -ux;
+    ux = L.gamma0 * (ux + L.beta * gp);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R offset_below_one(double f) {
+  const R r = (R)f;
+  return r < R(1) ? r : R(1) - R(sizeof(R) == 4 ? 0x1p-24 : 0x1p-53);
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_load_plasma(DevState<R> st, int run, int s,
                                                      PlasmaLoad L) {
@@ -124,35 +154,13 @@ __global__ void __launch_bounds__(256) k_load_plasma(DevState<R> st, int run, in
                         (long long)(iy - y0) * fw + (ix - x0);
     double fx, fy;
     pos.u01(k, 0, fx, fy);
-    // momentum: direction (block 0), flip decision (block 1), magnitude (2, ...)
-    const double umag = L.T > 0.0 ? mj_speed(mom, k, L) : 0.0;
-    double d0, d1, f0, unused;
-    mom.u01(k, 0, d0, d1);
-    mom.u01(k, 1, f0, unused);
-    const double mu = 2.0 * d0 - 1.0;
-    const double phi = kTwoPi * d1;
-    const double stt = sqrt(fmax(0.0, 1.0 - mu * mu));
-    double ux = umag * mu;
-    const double uy = umag * stt * cos(phi);
-    const double uz = umag * stt * sin(phi);
-    if (L.gamma0 > 1.0) {
-      const double gp = sqrt(1.0 + umag * umag);
-      const double vx = ux / gp;
-      if (-L.beta * vx > f0) ux = -ux;
-      ux = L.gamma0 * (ux + L.beta * gp);
-    }
-    int cx = ix, cy = iy;
-    R ox = (R)fx, oy = (R)fy;
-    // an offset that rounds up to 1 moves to the next cell (as in the host load)
-    if (ox >= R(1)) {
-      ox = R(0);
-      cx = ix + 1;
-    }
-    if (oy >= R(1)) {
-      oy = R(0);
-      cy = iy + 1 < rd.ny ? iy + 1 : 0;
-    }
-    st.cell[s][o] = pic_cell_pack(cx, cy);
+    double ux, uy, uz;
+    draw_momentum(mom, k, L, ux, uy, uz);
+    // an offset that rounds up to 1 in FP32 is clamped to the largest value
+    // below 1, so the particle stays in the cell and tile it is stored in (as
+    // in the host load)
+    const R ox = offset_below_one<R>(fx), oy = offset_below_one<R>(fy);
+    st.cell[s][o] = pic_cell_pack(ix, iy);
     st.ox[s][o] = ox;
     st.oy[s][o] = oy;
     st.ux[s][o] = (R)ux;
@@ -178,7 +186,92 @@ __global__ void __launch_bounds__(256) k_load_counts(DevState<R> st, int run, in
   }
 }
 
+// Inflow of a shock run: before every step the flow entering through x_out
+// is appended to the tiles of the cell column x_out - 1, as the seeded host
+// generator of the injection slabs draws it. The stream moves w = beta0 cfl
+// cells per step, so before step n each row receives
+// floor(ppc w (n+1)) - floor(ppc w n) particles at x = x_out - w r0 (r0, and
+// y's offset r1, from the item's position block), momenta drifting
+// Maxwell-Juettner towards -x; the items continue after the x_out * ny * ppc
+// of the initial load (item = first + row * per_row + j), electrons and
+// positrons co-located. One work-group per (tile row, run, species): the
+// tile's count is read, its rows' particles written after it, the count
+// raised. The step index lives in device memory (graph replay reads it).
+template <typename R>
+__global__ void __launch_bounds__(256) k_inject_flow(DevState<R> st, const InflowDev* tab,
+                                                     const long long* step_ctr) {
+#pragma clang fp contract(off)
+  const int ri = blockIdx.y;
+  const InflowDev& F = tab[ri];
+  if (!F.on) return;
+  const DevRun& rd = st.runs[ri];
+  const int s = blockIdx.z;
+  const int ty = blockIdx.x;
+  if (s >= rd.nspecies || ty >= rd.nty) return;
+  const long long step = step_ctr[ri];
+  const double done = floor(F.ppc_w * (double)step);
+  const int per_row = (int)(floor(F.ppc_w * (double)(step + 1)) - done);
+  const long long first = F.item0 + (long long)done * rd.ny;
+  const int x_out = rd.x_out;
+  const int tx = pic_tile_of(x_out - 1, st.TX, rd.ntx);
+  const int y0 = ty * st.TY;
+  const int th = pic_tile_width(ty, st.TY, rd.nty, rd.ny);
+  const int tile = rd.tile0 + ty * rd.ntx + tx;
+  const int cap = st.tile_slots[s];
+  const int n0 = st.cnt[s][tile];
+  int add = per_row * th;
+  if (n0 + add > cap) {
+    if (threadIdx.x == 0) atomicOr(st.err, PIC_ERRBIT_TILE);
+    add = cap - n0;
+  }
+  const Stream pos(F.L.seed, kTagPos), mom(F.L.seed, kTagMom + 16u * (unsigned)s);
+  const long long base = (long long)tile * cap + n0;
+  for (int e = threadIdx.x; e < add; e += blockDim.x) {
+    const int row = y0 + e / per_row;
+    const long long k = first + (long long)row * per_row + (e - (e / per_row) * per_row);
+    double r0, r1;
+    pos.u01(k, 0, r0, r1);
+    const double X = (double)x_out - F.w * r0;
+    int ix = (int)floor(X);
+    double fx = X - (double)ix;
+    if (ix > x_out - 1) {   // r0 rounds the position onto x_out itself
+      ix = x_out - 1;
+      fx = 1.0;
+    }
+    double ux, uy, uz;
+    draw_momentum(mom, k, F.L, ux, uy, uz);
+    st.cell[s][base + e] = pic_cell_pack(ix, row);
+    st.ox[s][base + e] = offset_below_one<R>(fx);
+    st.oy[s][base + e] = offset_below_one<R>(r1);
+    st.ux[s][base + e] = (R)ux;
+    st.uy[s][base + e] = (R)uy;
+    st.uz[s][base + e] = (R)uz;
+    if (st.id[s]) st.id[s][base + e] = (int)k;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && add > 0) st.cnt[s][tile] = n0 + add;
+}
+
+// the inflow step counters advance once per step, after the injection
+__global__ void k_inflow_advance(const InflowDev* tab, long long* step_ctr, int n_runs) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n_runs && tab[r].on) step_ctr[r] += 1;
+}
+
 }  // namespace
+
+template <typename R>
+hipError_t pic_launch_inject_flow(const DevState<R>& st, const InflowDev* tab, long long* step_ctr,
+                                  int n_runs, int max_nty, int n_species, hipStream_t stream) {
+  k_inject_flow<R><<<dim3(max_nty, n_runs, n_species), 256, 0, stream>>>(st, tab, step_ctr);
+  k_inflow_advance<<<(n_runs + 63) / 64, 64, 0, stream>>>(tab, step_ctr, n_runs);
+  return hipGetLastError();
+}
+
+template hipError_t pic_launch_inject_flow<float>(const DevState<float>&, const InflowDev*,
+                                                  long long*, int, int, int, hipStream_t);
+template hipError_t pic_launch_inject_flow<double>(const DevState<double>&, const InflowDev*,
+                                                   long long*, int, int, int, hipStream_t);
 
 template <typename R>
 hipError_t pic_launch_load_plasma(const DevState<R>& st, int run, int s, const PlasmaLoad& L,

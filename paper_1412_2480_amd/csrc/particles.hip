@@ -154,10 +154,10 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
   return slot;
 }
 
-template <typename R, typename F, int P, int MODE>
+template <typename R, typename F, int P, int MODE, bool DIAG>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
                           int x0, int y0, int tw, int th, const F* sF, double* sJ, int part,
-                          int diag, double (&wk)[PIC_MAXS][2]) {
+                          double (&wk)[PIC_MAXS][2]) {
   constexpr int W = P + 2;   // Esirkepov window: union of old and new supports
   const int PW = st.PW, PH = st.PH;
   const int plane = PW * PH;
@@ -242,7 +242,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           const R bx = interp<P, R, F>(sF + 3 * plane, PW, gx0, gyh, w0x, why);
           const R by = interp<P, R, F>(sF + 4 * plane, PW, gxh, gy0, whx, w0y);
           const R bz = interp<P, R, F>(sF + 5 * plane, PW, gxh, gyh, whx, why);
-          if (diag)
+          if constexpr (DIAG)
             wk[s][0] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
                                      (double)uz * uz) - 1.0);
           // ---- relativistic Boris push u^{n-1/2} -> u^{n+1/2}
@@ -267,8 +267,9 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           uz = umz + (upx * sy - upy * sx) + qdt_2m * ez;
           // ---- move x^n -> x^{n+1}
           const R ig = inv_sqrt<R>(R(1) + ux * ux + uy * uy + uz * uz);
-          if (diag) wk[s][1] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
-                                              (double)uz * uz) - 1.0);
+          if constexpr (DIAG)
+            wk[s][1] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
+                                     (double)uz * uz) - 1.0);
           R dx_ = ux * ig * dtdx, dy_ = uy * ig * dtdy;
           dx_ = dx_ > lim ? lim : (dx_ < -lim ? -lim : dx_);
           dy_ = dy_ > lim ? lim : (dy_ < -lim ? -lim : dy_);
@@ -319,10 +320,13 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           double* jy = sJ + plane;
           double* jz = sJ + 2 * plane;
           // The sums run in FP64 from the window weights converted once (an
-          // FP64 FMA issues at the rate of an FP32 one here, and the LDS
-          // accumulators are FP64): Jx(i+1/2) is the running sum of Wx along x
-          // (the last node's sum is zero); the constant factors of Jx, Jy, Jz
-          // are folded into the per-row and per-column weights.
+          // FP64 FMA issues at the rate of an FP32 one here) into FP64 LDS
+          // accumulators in both forms: measured on gfx950 in this kernel, the
+          // native FP32 LDS atomic add (ds_add_f32) takes the 1024 x 256
+          // order-3 push from 1.3 ms to 10.3 ms, while ds_add_f64 runs near
+          // the LDS bandwidth. Jx(i+1/2) is the running sum of Wx along x (the
+          // last node's sum is zero); the constant factors of Jx, Jy, Jz are
+          // folded into the per-row and per-column weights.
           double s0x[W], dsx[W], s0y[W], dsy[W];
 #pragma unroll
           for (int a = 0; a < W; ++a) {
@@ -452,8 +456,10 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
   }
 }
 
-template <typename R, typename F, int MODE>
-__global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
+// DIAG: the step records the kinetic energies W_K(n -/+ 1/2) (a compile-time
+// variant, so that the ordinary step carries no FP64 accumulators)
+template <typename R, typename F, int MODE, bool DIAG>
+__global__ void __launch_bounds__(256) k_particles(DevState<R> st) {
   // XCD-aware order: consecutive (tile, part) items go to the same XCD
   const int per = gridDim.x / 8;
   const int item = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -471,8 +477,7 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   F* sF = reinterpret_cast<F*>(smem_raw);
   const size_t fbytes = (MODE == MODE_FUSED || MODE == MODE_PUSH) ? 6 * plane * sizeof(F) : 0;
-  // currents accumulate in FP64 LDS in both forms: on gfx950 an FP64 LDS
-  // atomic add retires about 20x faster than an FP32 one
+  // currents (and rho) accumulate in FP64 LDS in both forms
   double* sJ = reinterpret_cast<double*>(smem_raw + fbytes);
   const int nj = (MODE == MODE_PUSH) ? 0 : (MODE == MODE_CHARGE ? 1 : 3);
   __shared__ double s_red[4][PIC_MAXS * 2];
@@ -519,13 +524,13 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
   switch (run.order) {
     case 1:
-      tile_body<R, F, 1, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
+      tile_body<R, F, 1, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
       break;
     case 2:
-      tile_body<R, F, 2, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
+      tile_body<R, F, 2, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
       break;
     default:
-      tile_body<R, F, 3, MODE>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, diag, wk);
+      tile_body<R, F, 3, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
       break;
   }
   __syncthreads();
@@ -536,8 +541,8 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int diag) {
       for (int e = threadIdx.x; e < plane; e += blockDim.x) out[e] = sJ[c * plane + e];
     }
   }
-  if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
-    if (diag) {
+  if constexpr ((MODE == MODE_FUSED || MODE == MODE_PUSH) && DIAG) {
+    {
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
       for (int s = 0; s < PIC_MAXS; ++s)
@@ -912,12 +917,17 @@ __global__ void __launch_bounds__(256) k_current_sum(DevState<R> st, int ncomp, 
   }
 }
 
+// Diagnostics of the current state of one run, per work-group: max Gauss
+// residual |div E - 4 pi rho| at the nodes, max |div B| at the cell centres,
+// sum of rho (fixed reduction tree) and the number of non-finite E or B
+// values (any of the six components)
 __global__ void __launch_bounds__(256)
-k_divergences(const DevRun* runs, int ri, const double* ex, const double* ey,
-              const double* bx, const double* by, const double* rho, double* part) {
+k_divergences(const DevRun* runs, int ri, const double* ex, const double* ey, const double* ez,
+              const double* bx, const double* by, const double* bz, const double* rho,
+              double* part) {
   const DevRun& run = runs[ri];
   const long long ncell = (long long)run.nx * run.ny;
-  double g = 0.0, d = 0.0;
+  double g = 0.0, d = 0.0, q = 0.0, bad = 0.0;
   for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < ncell;
        k += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(k % run.nx), j = (int)(k / run.nx);
@@ -935,22 +945,32 @@ k_divergences(const DevRun* runs, int ri, const double* ex, const double* ey,
     const double divb = fabs((bx[xp] - bx[kk]) / run.dx + (by[yp] - by[kk]) / run.dy);
     g = (gr > g || gr != gr) ? gr : g;
     d = (divb > d || divb != divb) ? divb : d;
+    q += rho[k];
+    const double f6[6] = {ex[kk], ey[kk], ez[kk], bx[kk], by[kk], bz[kk]};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) bad += isfinite(f6[c]) ? 0.0 : 1.0;
   }
-  __shared__ double sg[256], sd[256];
+  __shared__ double sg[256], sd[256], sq[256], sb[256];
   sg[threadIdx.x] = g;
   sd[threadIdx.x] = d;
+  sq[threadIdx.x] = q;
+  sb[threadIdx.x] = bad;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) {
       const double a = sg[threadIdx.x + off], b = sd[threadIdx.x + off];
       if (a > sg[threadIdx.x] || a != a) sg[threadIdx.x] = a;
       if (b > sd[threadIdx.x] || b != b) sd[threadIdx.x] = b;
+      sq[threadIdx.x] += sq[threadIdx.x + off];
+      sb[threadIdx.x] += sb[threadIdx.x + off];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[blockIdx.x * 2 + 0] = sg[0];
-    part[blockIdx.x * 2 + 1] = sd[0];
+    part[blockIdx.x * 4 + 0] = sg[0];
+    part[blockIdx.x * 4 + 1] = sd[0];
+    part[blockIdx.x * 4 + 2] = sq[0];
+    part[blockIdx.x * 4 + 3] = sb[0];
   }
 }
 
@@ -977,16 +997,22 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
   const dim3 grid(grid_tiles(st.n_tiles * st.K)), block(threads);
   switch (mode) {
     case MODE_FUSED:
-      k_particles<R, F, MODE_FUSED><<<grid, block, smem, s>>>(st, diag);
+      if (diag)
+        k_particles<R, F, MODE_FUSED, true><<<grid, block, smem, s>>>(st);
+      else
+        k_particles<R, F, MODE_FUSED, false><<<grid, block, smem, s>>>(st);
       break;
     case MODE_PUSH:
-      k_particles<R, F, MODE_PUSH><<<grid, block, smem, s>>>(st, diag);
+      if (diag)
+        k_particles<R, F, MODE_PUSH, true><<<grid, block, smem, s>>>(st);
+      else
+        k_particles<R, F, MODE_PUSH, false><<<grid, block, smem, s>>>(st);
       break;
     case MODE_DEPOSIT:
-      k_particles<R, F, MODE_DEPOSIT><<<grid, block, smem, s>>>(st, diag);
+      k_particles<R, F, MODE_DEPOSIT, false><<<grid, block, smem, s>>>(st);
       break;
     default:
-      k_particles<R, F, MODE_CHARGE><<<grid, block, smem, s>>>(st, 0);
+      k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st);
       break;
   }
   return hipGetLastError();
@@ -1047,8 +1073,8 @@ hipError_t pic_launch_divergences(const DevRun* runs, int run, long long ncell,
                                   const double* const* E, const double* const* B,
                                   const double* rho, double* partial_max, int n_blocks,
                                   hipStream_t s) {
-  k_divergences<<<dim3(n_blocks), dim3(256), 0, s>>>(runs, run, E[0], E[1], B[0], B[1], rho,
-                                                     partial_max);
+  k_divergences<<<dim3(n_blocks), dim3(256), 0, s>>>(runs, run, E[0], E[1], E[2], B[0], B[1],
+                                                     B[2], rho, partial_max);
   return hipGetLastError();
 }
 

@@ -13,7 +13,10 @@
 // (group counters, top counter and generation, each on its own 128-byte line)
 constexpr unsigned kBarGroups = 16;
 constexpr int kBarWords = 32 * (kBarGroups + 2);
-#define PIC_STAT_WORDS 16     // doubles per run of solve statistics
+// doubles per run of solve statistics: 0-2 iterations, 3-5 true relative
+// residual, 6-8 ||b||, 9-11 learned iterations, 12 fallback, 13 fallbacks and
+// 14 solves since initialisation, 16-18 recursive relative residual
+#define PIC_STAT_WORDS 24
 
 struct FieldArgs {
   int n_runs, n_blocks, diag;
@@ -30,6 +33,7 @@ struct FieldArgs {
   double* w1[3];
   double* s0[3];
   double* s1[3];
+  double* bsv[3];          // b of Eq. (7), kept for the true residual and the pairs
   double* part;            // per-block partial sums, 3 x [block][8]
   int* g_active;           // active-run counters (3)
   unsigned* bar;           // grid barrier: counter at [0], generation at [32]
@@ -48,6 +52,8 @@ struct FieldArgs {
   int pair_slot;           // ring slot: pairs + pair_slot * 6 * ncell, [component][b | dB]
   int coop;                // 1: cooperative launch; 0: ordinary launch (graph capture)
   int any_shock;           // some run has shock walls (selects the kernel variant)
+  int cg_x0;               // 1: plain CG starts from the previous step's dB
+  int explicit_fdtd;       // 1: explicit Yee advance of Eqs. (3)-(4) instead of the solve
 };
 
 size_t pic_field_solve_smem(int learned, int form);
@@ -126,3 +132,15 @@ struct PlasmaLoad {
 template <typename R>
 hipError_t pic_launch_load_plasma(const DevState<R>& st, int run, int s, const PlasmaLoad& L,
                                   int n_tiles_run, hipStream_t stream);
+
+// Inflow of a shock run, injected on the device before every step
+struct InflowDev {
+  int on;
+  double ppc_w;          // ppc * beta0 * cfl: particles per row per step, accumulated
+  double w;              // beta0 * cfl: the slab width in cells
+  long long item0;       // x_out * ny * ppc: first item after the initial load
+  PlasmaLoad L;          // momentum draw (direction -x)
+};
+template <typename R>
+hipError_t pic_launch_inject_flow(const DevState<R>& st, const InflowDev* tab, long long* step_ctr,
+                                  int n_runs, int max_nty, int n_species, hipStream_t stream);

@@ -20,13 +20,26 @@ def _record():
         return json.load(f)
 
 
+def _sources_hash(root, rec):
+    import hashlib
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(root, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
 def test_record_matches_its_configuration():
     rec = _record()
     cfg = rec["config"]
     t, src = bench.measured_traffic(cfg["precision"], tuple(cfg["tile"]), cfg["tile_split"],
                                     cfg["order"], cfg["particles"], cfg.get("sort_every", 0),
                                     cfg.get("warmup", 0))
-    assert t == rec["traffic_bytes"] and src.endswith(".traffic.json")
+    if _sources_hash(ROOT, rec) == rec["sources_sha256"]:
+        assert t == rec["traffic_bytes"] and src.endswith(".traffic.json")
+    else:
+        # the kernel changed since the counters were taken: no figure
+        assert (t, src) == (None, None)
     # traffic within a few percent of the algorithmic bytes (nothing re-read)
     assert 1.0 <= rec["traffic_bytes"] / rec["algorithmic_bytes"] <= 1.1
 
@@ -47,13 +60,15 @@ def test_changed_source_gets_no_figure(tmp_path, monkeypatch):
     rec = _record()
     root = tmp_path / "repo"
     (root / "profiles").mkdir(parents=True)
-    shutil.copy(os.path.join(ROOT, "profiles",
-                             "k_particles_fp32_1024x256_ppc64_order3.traffic.json"),
-                root / "profiles")
     for src in rec["sources"]:
         dst = root / src
         dst.parent.mkdir(parents=True, exist_ok=True)
         shutil.copy(os.path.join(ROOT, src), dst)
+    # a record taken on exactly these sources
+    rec = dict(rec, sources_sha256=_sources_hash(str(root), rec))
+    with open(root / "profiles" / "k_particles_fp32_1024x256_ppc64_order3.traffic.json",
+              "w") as f:
+        json.dump(rec, f)
     monkeypatch.setattr(bench, "ROOT", str(root))
     cfg = rec["config"]
     args = (cfg["precision"], tuple(cfg["tile"]), cfg["tile_split"], cfg["order"],

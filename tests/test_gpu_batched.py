@@ -53,6 +53,38 @@ def test_batched_equals_unbatched(precision):
     batched.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batched_runs_match_their_oracle_runs(precision):
+    """Every run of the mixed 4-run context (uneven grids, orders 1-3, CFL
+    0.5-1.0, theta 0.5/0.6) against its own FP64 oracle run after 4 steps:
+    fields and particles at 1e-12 in the FP64 form (CG at rtol 1e-14), at
+    FP32 roundoff bounds in the fast form."""
+    import paper_1412_2480_amd as pic
+    from pic_cases import compare_particles
+    _say(f"batched vs oracle {precision}")
+    cases = [Case(c["nx"], c["ny"], c["order"], c["ppc"], gamma0=5.0, T=0.05, cfl=c["cfl"],
+                  theta=c["theta"], seed=c["seed"], field_amp=0.3, rtol=1e-14, maxit=500)
+             for c in CASES]
+    batched = pic.Sim([c.run_desc() for c in cases], pic.make_options(precision, tile=(16, 16)))
+    for r, c in enumerate(cases):
+        c.load_into(batched, run=r)
+    batched.step(4)
+    tol = 1e-12 if precision == "fp64" else 2e-5
+    for r, c in enumerate(cases):
+        ref = c.oracle_sim()
+        for _ in range(4):
+            ref.step()
+        for k, n in enumerate(("Ex", "Ey", "Ez")):
+            assert relerr(batched.get_field(r, n), ref.E[k]) <= tol, (r, n)
+        for k, n in enumerate(("Bx", "By", "Bz")):
+            assert relerr(batched.get_field(r, n), ref.B[k]) <= tol, (r, n)
+        for s, p in enumerate(ref.species):
+            g = batched.read_particles(r, s, p.n)
+            pos, mom = compare_particles(g, p, c.nx, c.ny)
+            assert pos <= tol and mom <= tol, (r, s, pos, mom)
+    batched.close()
+
+
 def test_sweep_table_runs_in_one_context():
     """The 48-run sweep table (uneven grids 128x64 ... 512x128, orders 1-3,
     CFL 0.5-1.0, theta 0.5/0.6), reduced to 4 ppc and 3 steps, runs in one

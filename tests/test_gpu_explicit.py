@@ -1,0 +1,123 @@
+"""The explicit Yee FDTD variant (Eqs. (3)-(4), B carried at integer times for
+the push) on the GPU against the FP64 oracle's explicit advance: per-step
+parity at 1e-12 in the FP64 form, a whole run's energy history, Gauss's law,
+batched runs at several CFL numbers, and the Courant check of pic_plan."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from pic_cases import Case, compare_particles, relerr
+
+pytestmark = pytest.mark.gpu
+
+EN = ("Ex", "Ey", "Ez")
+BN = ("Bx", "By", "Bz")
+JN = ("Jx", "Jy", "Jz")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _oracle(case):
+    sim = oracle.Sim(case.nx, case.ny, case.dx, case.dy, case.cfl, case.theta, case.order,
+                     [p.copy() for p in case.species], scheme="explicit")
+    for k, n in enumerate(EN):
+        sim.E[k][...] = case.fields[n]
+    for k, n in enumerate(BN):
+        sim.B[k][...] = case.fields[n]
+    return sim
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+@pytest.mark.parametrize("grid,cfl", [((40, 36), 0.5), ((34, 12), 0.7)])
+def test_explicit_split_step_parity_fp64(order, grid, cfl):
+    nx, ny = grid
+    _say(f"explicit split parity order={order} grid={grid} cfl={cfl}")
+    case = Case(nx, ny, order, ppc=3, gamma0=5.0, T=0.05, field_amp=0.5, seed=20 + order,
+                cfl=cfl)
+    sim = case.gpu_sim("fp64", tile=(16, 16), scheme="explicit")
+    ref = _oracle(case)
+    sim.gather_push()
+    sim.deposit()
+    ref.push_deposit()
+    for k, n in enumerate(JN):
+        assert relerr(sim.get_field(0, n), ref.J[k]) <= 1e-12, n
+    st = sim.field_solve()[0]
+    ref.field_solve()
+    assert st["iters"] == [0, 0, 0]
+    for k, n in enumerate(EN):
+        assert relerr(sim.get_field(0, n), ref.E[k]) <= 1e-12, n
+    for k, n in enumerate(BN):
+        assert relerr(sim.get_field(0, n), ref.B[k]) <= 1e-12, n
+    for s, p in enumerate(ref.species):
+        g = sim.read_particles(0, s, p.n)
+        pos, mom = compare_particles(g, p, nx, ny)
+        assert pos <= 1e-12 and mom <= 1e-12
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_explicit_run_history_and_gauss(precision):
+    """C1-like drifting pair plasma (64 x 64, order 1, gamma0 = 20) with the
+    explicit scheme at sigma = 0.5, 30 steps: the energy history against the
+    oracle's explicit run, and Gauss's law kept at its initial value."""
+    _say(f"explicit run {precision}")
+    case = Case(64, 64, 1, ppc=8, gamma0=20.0, T=0.01, seed=0, cfl=0.5)
+    sim = case.gpu_sim(precision, scheme="explicit", diag_every=1, history_cap=64)
+    ref = _oracle(case)
+    rec = [ref.step() for _ in range(30)]
+    sim.step(30)
+    hist = sim.history(0)
+    assert len(hist) == 30
+    tol_k, tol_f = (1e-11, 1e-8) if precision == "fp64" else (1e-5, 1e-2)
+    for h, r in zip(hist, rec):
+        assert h["step"] == r["step"]
+        for key in ("W_K_minus", "W_K_plus"):
+            assert abs(h[key] - r[key]) <= tol_k * abs(r[key]), key
+        wf = r["W_E"] + r["W_B"]
+        assert abs(h["W_E"] + h["W_B"] - wf) <= tol_f * max(wf, 1e-300) + 1e-14, h["step"]
+    if precision == "fp64":
+        for k, n in enumerate(EN):
+            assert relerr(sim.get_field(0, n), ref.E[k]) <= 1e-8, n
+    d = sim.diag(0)
+    scale = 4 * np.pi * case.Q / (case.dx * case.dy)
+    assert d["gauss_max"] <= (1e-11 if precision == "fp64" else 1e-4) * scale
+    sim.close()
+
+
+def test_explicit_batched_cfl_sweep():
+    """Runs at sigma = 0.4, 0.5, 0.6, 0.7 in one context: each equals its own
+    oracle run after 5 steps (FP64 form)."""
+    import paper_1412_2480_amd as pic
+    _say("explicit batched sweep")
+    cases = [Case(32 + 8 * k, 24, 2, ppc=2, gamma0=10.0, T=0.02, seed=40 + k, cfl=s,
+                  field_amp=0.2) for k, s in enumerate((0.4, 0.5, 0.6, 0.7))]
+    sim = pic.Sim([c.run_desc() for c in cases],
+                  pic.make_options("fp64", tile=(16, 16), scheme="explicit"))
+    for r, c in enumerate(cases):
+        c.load_into(sim, r)
+    refs = [_oracle(c) for c in cases]
+    sim.step(5)
+    for ref in refs:
+        for _ in range(5):
+            ref.step()
+    for r, ref in enumerate(refs):
+        for k, n in enumerate(EN):
+            assert relerr(sim.get_field(r, n), ref.E[k]) <= 1e-11, (r, n)
+        for k, n in enumerate(BN):
+            assert relerr(sim.get_field(r, n), ref.B[k]) <= 1e-11, (r, n)
+    sim.close()
+
+
+def test_explicit_courant_limit_rejected():
+    import paper_1412_2480_amd as pic
+    case = Case(32, 32, 1, ppc=1, cfl=0.75)
+    with pytest.raises(pic.PicError) as ei:
+        pic.plan([case.run_desc()], pic.make_options("fp64", scheme="explicit"))
+    assert ei.value.code == -1
+    ok = Case(32, 32, 1, ppc=1, cfl=0.7)
+    pic.plan([ok.run_desc()], pic.make_options("fp64", scheme="explicit"))

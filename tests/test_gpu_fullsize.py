@@ -177,7 +177,7 @@ def test_fullsize_shock_fp32_learned():
         assert st["fallback"] == 0 and max(st["relres"]) <= 1e-8
         assert sum(st["iters"]) < min(plain_iters)
     _say(f"fullsize shock: plain {plain_iters}, learned last {st['iters']}")
-    d = sim.diag(0, divergences=True)
+    d = sim.diag(0)
     rho_scale = 4 * np.pi * Q / (DX * DX)
     _say(f"fullsize shock: gauss {d['gauss_max']:.3e} (scale {rho_scale:.3e}), "
          f"particles {d['n_particles']}")
@@ -227,7 +227,7 @@ def test_fullsize_tuned_schedule_full_length():
              f"{max(st['relres']):.1e}, fallback {st['fallback']}")
         assert st["fallback"] == 0 and max(st["relres"]) <= 1e-8
     assert sim.get_timing()["graph_replays"] > 500
-    d = sim.diag(0, divergences=True)
+    d = sim.diag(0)
     rho_scale = 4 * np.pi * Q / (DX * DX)
     _say(f"  gauss {d['gauss_max']:.2e} (scale {rho_scale:.2e}), particles {d['n_particles']}")
     assert d["n_particles"][:2] == [NX * NY * PPC] * 2

@@ -140,7 +140,7 @@ def test_large_share_fullsize_fp32():
     st = sim.step(3)[0]
     assert max(st["relres"]) <= 1e-8
     assert sim.precond_collect(False) == 4
-    d = sim.diag(0, divergences=True)
+    d = sim.diag(0)
     rho_scale = 4 * np.pi * Q / (DX * DX)
     _say(f"  gauss {d['gauss_max']:.3e} (scale {rho_scale:.3e}), cg {st['iters']}")
     assert d["gauss_max"] <= 1e-4 * rho_scale

@@ -23,6 +23,8 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "nci_history_128x64.json")
+# the single-run workload itself (1024 x 256, 64 ppc/species, 300 steps)
+GOLDEN_FULL = os.path.join(HERE, "golden", "nci_history_1024x256.json")
 
 
 def _say(msg):
@@ -36,19 +38,27 @@ def golden():
         return json.load(f)
 
 
-def _run(golden, solver, train_after=0):
+def _run(golden, solver, train_after=0, **opt):
     import paper_1412_2480_amd as pic
     c = golden["case"]
     Q = golden["macro_charge"]
     run = pic.run_desc(c["nx"], c["ny"], c["dx"], c["cfl"], c["theta"], c["order"],
                        [(-Q, Q, c["ppc"]), (Q, Q, c["ppc"])], cg_rtol=c["rtol"])
-    opts = pic.make_options("fp32", diag_every=1, history_cap=c["steps"] + 1, slack=1.0,
-                            exchange_frac=0.5, solver=solver, precond_slots=8)
+    kw = dict(slack=1.0, exchange_frac=0.5)
+    kw.update(opt)
+    opts = pic.make_options("fp32", diag_every=1, history_cap=c["steps"] + 1, solver=solver,
+                            precond_slots=8, **kw)
     sim = pic.Sim([run], opts)
-    ld = loads.pair_plasma_cells(c["nx"], c["ny"], c["ppc"], c["gamma0"], c["T"], c["seed"])
-    for s in range(2):
-        d = ld[s]
-        sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
+    if c["nx"] * c["ny"] * c["ppc"] > 1 << 22:
+        # the device loader draws the same seeded items as the host generator
+        for s in range(2):
+            sim.load_plasma(0, s, c["ppc"], c["gamma0"], c["T"], c["seed"])
+    else:
+        ld = loads.pair_plasma_cells(c["nx"], c["ny"], c["ppc"], c["gamma0"], c["T"], c["seed"])
+        for s in range(2):
+            d = ld[s]
+            sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
+                               d["uz"])
     learned_iters = 0
     if solver == "learned":
         # plain CG while pairs are recorded, then train and switch
@@ -106,5 +116,22 @@ def test_fp32_whole_run_matches_oracle(golden):
 def test_fp32_learned_whole_run_matches_oracle(golden):
     _say("whole run, FP32 form, learned CG aid")
     a, it = _run(golden, "learned", train_after=20)
+    _check(golden, a)
+    assert it >= 1
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN_FULL), reason="1024x256 oracle history not written")
+def test_fp32_learned_whole_run_matches_oracle_full_size():
+    """The single-run workload at its own size (1024 x 256, 64 ppc/species,
+    order 3, gamma0 = 40) through the growth and saturation of the numerical
+    Cherenkov instability, 300 steps, in the timed configuration (FP32
+    particles, learned aid trained on the first 20 steps' pairs, 4 x 32 tiles,
+    two work-groups per tile, reordering every 4 steps), against the FP64
+    oracle's history: the 1e-3 history bars and the 5 % growth-rate bar."""
+    with open(GOLDEN_FULL) as f:
+        golden = json.load(f)
+    _say("whole run 1024x256, FP32 form, learned CG aid")
+    a, it = _run(golden, "learned", train_after=20, tile=(4, 32), tile_split=2, sort_every=4,
+                 slack=0.5, track_ids=False)
     _check(golden, a)
     assert it >= 1
