@@ -307,6 +307,18 @@ int32_t pic_gather_push(pic_ctx* ctx);
 int32_t pic_deposit(pic_ctx* ctx);
 int32_t pic_field_solve(pic_ctx* ctx, pic_solve_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * field solve as pic_field_solve, with its scratch (CG vectors, per-block
+ * partial sums, barrier words) in a device array of the library instead of
+ * the context's workspace. The array holds a context of at most 262144 cells
+ * over all runs and 4096 field-solve work-groups (about 57 MB per GPU, kept
+ * until the process ends); larger contexts get PIC_E_INVAL. It calls no
+ * device allocator. Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other contexts or threads) race. The plain CG starts
+ * from x0 = 0 here (cg_x0 is not honoured); no event timing. */
+int32_t pic_field_solve_noalloc(pic_ctx* ctx, pic_solve_stats* stats);
+
 /* nsteps fused steps, each one time step n -> n+1 of the method as the paper
  * states it (Sec. 2, Eqs. (5)-(7): particles advanced with J^{n+1/2}
  * deposited, then the implicit solve; the PIC ingredients of Sec. 1 and

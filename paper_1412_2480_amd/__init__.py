@@ -32,7 +32,7 @@ STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
 EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_load_plasma", "pic_inject_particles",
            "pic_set_inflow",
            "pic_read_particles", "pic_set_field", "pic_get_field", "pic_gather_push",
-           "pic_deposit", "pic_field_solve", "pic_step", "pic_diag", "pic_history",
+           "pic_deposit", "pic_field_solve", "pic_field_solve_noalloc", "pic_step", "pic_diag", "pic_history",
            "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
            "pic_precond_use", "pic_precond_get_weights", "pic_precond_set_weights",
            "pic_precond_apply", "pic_precond_grad", "pic_tune", "pic_sync", "pic_destroy",
@@ -168,6 +168,7 @@ def lib():
         L.pic_gather_push.argtypes = [ctypes.c_void_p]
         L.pic_deposit.argtypes = [ctypes.c_void_p]
         L.pic_field_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        L.pic_field_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.pic_step.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]
         L.pic_diag.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(DiagOut)]
         L.pic_history.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
@@ -377,6 +378,14 @@ class Sim:
     def field_solve(self, allow_noconv=False):
         st = (SolveStats * len(self.runs))()
         self._check(self.L.pic_field_solve(self.ctx, st), "field_solve",
+                    allow=(-4,) if allow_noconv else ())
+        return self._stats(st)
+
+    def field_solve_noalloc(self, allow_noconv=False):
+        """pic_field_solve_noalloc: the same solve with the library's static
+        device scratch instead of the workspace (no device allocation)."""
+        st = (SolveStats * len(self.runs))()
+        self._check(self.L.pic_field_solve_noalloc(self.ctx, st), "field_solve_noalloc",
                     allow=(-4,) if allow_noconv else ())
         return self._stats(st)
 

@@ -659,17 +659,26 @@ int launch_exchange(pic_ctx* c) {
   return PIC_OK;
 }
 
-int launch_field(pic_ctx* c, int diag) {
+int launch_field(pic_ctx* c, int diag, bool noalloc = false) {
   FieldArgs a = c->fa;
+  if (noalloc) {
+    const int r = pic_field_args_noalloc(a, c->device, c->tl.n_cells);
+    if (r == -1) return fail(c, PIC_E_HIP, "the library's device scratch is not set up");
+    if (r == -2)
+      return fail(c, PIC_E_INVAL, "the allocation-free field solve holds at most 262144 cells "
+                                  "(over all runs) and 4096 work-groups");
+  }
   a.diag = diag;
   a.step = c->step;
   a.hist_slot = (int)(c->diag_count % std::max(1, c->opt.history_cap));
   a.learned = c->use_learned ? 1 : 0;
   a.collect = c->collect ? 1 : 0;
   a.pair_slot = c->pair_slots > 0 ? (int)(c->pairs_written % c->pair_slots) : 0;
-  t_begin(c, 5);
+  // (the allocation-free variant takes no event timing: events are created
+  // on demand)
+  if (!noalloc) t_begin(c, 5);
   hipError_t e = pic_launch_field_solve(a, c->stream);
-  t_end(c);
+  if (!noalloc) t_end(c);
   if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("field solve: ") + hipGetErrorString(e));
   if (diag) c->diag_count += 1;
   if (c->collect) c->pairs_written += 1;
@@ -1310,6 +1319,14 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
   c->max_cg_blocks = std::min(maxb, kMaxCgBlocks);
   c->device = dev;
   c->h_stats.assign((size_t)n_runs * PIC_STAT_WORDS, 0.0);
+  // this device's copy of the allocation-free field solve's scratch
+  he = pic_noalloc_scratch_init(dev);
+  if (he != hipSuccess) {
+    delete c;
+    g_init_err = std::string("hipGetSymbolAddress of the field-solve scratch: ") +
+                 hipGetErrorString(he);
+    return PIC_E_HIP;
+  }
   c->hruns.resize(n_runs);
   for (int r = 0; r < n_runs; ++r) {
     const pic_run_desc& d = runs[r];
@@ -1547,6 +1564,18 @@ int32_t pic_field_solve(pic_ctx* c, pic_solve_stats* stats) {
   if (!c) return PIC_E_INVAL;
   if (c->phase != 2) return fail(c, PIC_E_STATE, "field_solve must follow deposit");
   int rc = launch_field(c, diag_step(c) ? 1 : 0);
+  if (rc) return rc;
+  c->phase = 0;
+  c->step += 1;
+  rc = check_err(c);
+  if (rc) return rc;
+  return read_stats(c, stats);
+}
+
+int32_t pic_field_solve_noalloc(pic_ctx* c, pic_solve_stats* stats) {
+  if (!c) return PIC_E_INVAL;
+  if (c->phase != 2) return fail(c, PIC_E_STATE, "field_solve must follow deposit");
+  int rc = launch_field(c, diag_step(c) ? 1 : 0, true);
   if (rc) return rc;
   c->phase = 0;
   c->step += 1;

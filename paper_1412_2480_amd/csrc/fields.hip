@@ -845,6 +845,54 @@ __global__ void k_true_residual_final(FieldArgs a) {
 
 }  // namespace
 
+// ---- allocation-free field solve: its scratch (the CG vectors, per-block
+// partial sums, active-run counters and grid-barrier words) lives in this
+// file-scope device array instead of the context's workspace. One copy per
+// GPU, held until the process ends; calls that overlap on one GPU race on it.
+namespace {
+constexpr long long kScratchCells = PIC_NOALLOC_MAX_CELLS;
+constexpr int kScratchVecs = 27;   // x, p, r0, r1, w0, w1, s0, s1, bsv; 3 components each
+constexpr size_t kScratchPart = (size_t)PIC_NOALLOC_MAX_BLOCKS * 24;   // doubles
+constexpr size_t kScratchBytes = (size_t)kScratchVecs * kScratchCells * sizeof(double) +
+                                 kScratchPart * sizeof(double) + 256 + kBarWords * 4;
+constexpr int kScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+void* g_scratch[kScratchDevices] = {};
+}
+
+hipError_t pic_noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= kScratchDevices) return hipErrorInvalidDevice;
+  if (__atomic_load_n(&g_scratch[dev], __ATOMIC_ACQUIRE)) return hipSuccess;
+  void* ptr = nullptr;
+  // the array's name is a host-side stand-in: its device address (this GPU's
+  // copy) comes from the runtime, with the device current
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  __atomic_store_n(&g_scratch[dev], ptr, __ATOMIC_RELEASE);
+  return hipSuccess;
+}
+
+int pic_field_args_noalloc(FieldArgs& a, int dev, long long n_cells) {
+  if (dev < 0 || dev >= kScratchDevices) return -1;
+  unsigned char* base = (unsigned char*)__atomic_load_n(&g_scratch[dev], __ATOMIC_ACQUIRE);
+  if (!base) return -1;
+  if (n_cells > kScratchCells || a.n_blocks > PIC_NOALLOC_MAX_BLOCKS) return -2;
+  double* v = reinterpret_cast<double*>(base);
+  double** vecs[9] = {a.x, a.p, a.r0, a.r1, a.w0, a.w1, a.s0, a.s1, a.bsv};
+  for (int q = 0; q < 9; ++q)
+    for (int c = 0; c < 3; ++c) vecs[q][c] = v + (size_t)(3 * q + c) * kScratchCells;
+  a.part = v + (size_t)kScratchVecs * kScratchCells;
+  unsigned char* tail = reinterpret_cast<unsigned char*>(a.part + kScratchPart);
+  a.g_active = reinterpret_cast<int*>(tail);
+  a.bar = reinterpret_cast<unsigned*>(tail + 256);
+  a.cg_x0 = 0;   // the previous dB is not kept: every call starts from x0 = 0
+  return 0;
+}
+
 size_t pic_field_solve_smem(int learned, int form) {
   return learned ? (form == 0 ? NET_K_LDS_BYTES : NET_LDS_BYTES) : 0;
 }

@@ -56,6 +56,17 @@ struct FieldArgs {
   int explicit_fdtd;       // 1: explicit Yee advance of Eqs. (3)-(4) instead of the solve
 };
 
+// The allocation-free field solve: largest total cells of a context and
+// largest field-solve grid it serves; its scratch is a device array of the
+// library (about 57 MB per GPU).
+#define PIC_NOALLOC_MAX_CELLS (1LL << 18)
+#define PIC_NOALLOC_MAX_BLOCKS 4096
+// once per device, with it current: look up this GPU's copy of the array
+hipError_t pic_noalloc_scratch_init(int dev);
+// point the scratch of the solve's arguments into it: 0, or -1 (not set up
+// on this device), -2 (more cells or work-groups than it holds)
+int pic_field_args_noalloc(FieldArgs& a, int dev, long long n_cells);
+
 size_t pic_field_solve_smem(int learned, int form);
 // co-resident work-groups of the solve kernel variant (plain, or learned in
 // the given form) over n_cu compute units
