@@ -689,6 +689,35 @@ def explicit_vs_implicit(pic, torch, steps=20, warmup=5):
     return out
 
 
+def nci_scans(pic, torch, t_cfl=400.0, t_theta=5000.0):
+    """The paper's scans of Sec. 3 (Gamma = 100, 128 x 128, 100 ppc/species,
+    cell = Debye length) as batched runs: CFL 0.4 ... 1.0 x orders 1, 2 at
+    theta = 0.501 to t = t_cfl dx/c, and theta 0.5 ... 0.503 x orders 1, 2 at
+    sigma = 1 to t = t_theta dx/c; growth rates of W_B and the time each scan
+    took on the GPU."""
+    from paper_1412_2480_amd import nci
+    out = {}
+    for name, fn, kw in (("cfl", nci.cfl_scan, dict(t_end=t_cfl)),
+                         ("theta", nci.theta_scan, dict(t_end=t_theta))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn(pic, **kw)
+        sec = time.perf_counter() - t0
+        rows = []
+        for r in res:
+            c, g = r["case"], r["growth"]
+            rows.append(dict(cfl=c["cfl"], theta=c["theta"], order=c["order"],
+                             growth_rate_per_dx_over_c=None if g is None else g["rate"],
+                             fit_window=None if g is None else [g["t0"], g["t1"]],
+                             W_B_max=float(r["W_B"].max()), energy_drift=r["energy_drift"]))
+        n_part = sum(2 * r["case"]["n"] ** 2 * r["case"]["ppc"] for r in res)
+        steps = int(res[0]["t"].size)
+        out[name] = dict(runs=len(res), particles=n_part, steps=steps, seconds=sec,
+                         particle_steps_per_s=n_part * steps / sec, rows=rows)
+        log(f"bench: NCI {name} scan: {len(res)} runs, {steps} steps in {sec:.1f} s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -708,6 +737,8 @@ def main():
     ap.add_argument("--no-shock", action="store_true", help="skip the shock workload")
     ap.add_argument("--no-explicit", action="store_true",
                     help="skip the explicit-vs-implicit scheme leg")
+    ap.add_argument("--no-nci", action="store_true",
+                    help="skip the paper's numerical-Cherenkov scans (Sec. 3)")
     ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"])
     ap.add_argument("--also-mfma", action="store_true",
                     help="also time the 1024x256 FP32 form with the BF16 matrix-core network")
@@ -776,6 +807,8 @@ def main():
                                     lambda: shock_share(pic, torch, (4, 32), 2))
         legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch,
                                                                        CONFIGS["c2"]))
+        if not args.no_nci:
+            legs["nci_scans"] = run_leg("NCI scans", lambda: nci_scans(pic, torch))
     cpu = None
     if not args.no_cpu and not args.headline_only:
         log("bench: oracle CPU baseline")

@@ -78,8 +78,13 @@ enum pic_learned_form {
   PIC_NET_COLLAPSED = 0,      /* the network's exact 7 x 7 composite filter, FP64 */
   PIC_NET_MFMA = 1            /* the network itself, BF16 matrix cores, FP32 accumulation */
 };
+/* Field ids. PIC_RHO (charge density) and PIC_N0, PIC_N1 (number density of
+ * species 0, 1: particles per unit area, the density profiles of the shock
+ * runs, Sec. 4, Figs. 7-8) are deposited on demand from the particles with
+ * the order-p shape at the nodes; they are read only. */
 enum pic_field_id {
-  PIC_EX = 0, PIC_EY, PIC_EZ, PIC_BX, PIC_BY, PIC_BZ, PIC_JX, PIC_JY, PIC_JZ, PIC_RHO
+  PIC_EX = 0, PIC_EY, PIC_EZ, PIC_BX, PIC_BY, PIC_BZ, PIC_JX, PIC_JY, PIC_JZ, PIC_RHO,
+  PIC_N0, PIC_N1
 };
 
 typedef struct pic_species_desc {
@@ -297,6 +302,21 @@ int32_t pic_read_particles(pic_ctx* ctx, int32_t run, int32_t species, int64_t c
  * computed on demand from the particles (read only). */
 int32_t pic_set_field(pic_ctx* ctx, int32_t run, int32_t id, const double* host);
 int32_t pic_get_field(pic_ctx* ctx, int32_t run, int32_t id, double* host);
+
+/* Transverse average of a field of one run, profile(i) = (1/ny) sum_j f(i, j)
+ * for i = 0 .. nx-1 (the x profiles of the shock runs, Sec. 4, Figs. 7c and
+ * 8c: density and B_z averaged across the flow); host array of nx doubles.
+ * Synchronises. */
+int32_t pic_transverse_average(pic_ctx* ctx, int32_t run, int32_t id, double* host);
+
+/* k-space diagnostic of the numerical Cherenkov instability (Sec. 3.1,
+ * Fig. 3: B_z in Fourier space, with the resonance locus of Eq. (17)): the
+ * power |F(kx, ky)|^2 / (nx ny)^2 of one field of a run (any field id), F(kx, ky) = sum_{i,j} f(i, j) exp(-2 pi i (kx i / nx + ky j / ny))
+ * in FP64 on the device; host array [ny][nx] in discrete-Fourier-transform
+ * order (index m for wavenumber 2 pi m / (n dx), m > n/2 aliased to m - n).
+ * The staggering of a component changes only phases, not the power.
+ * Synchronises. */
+int32_t pic_field_spectrum(pic_ctx* ctx, int32_t run, int32_t id, double* host);
 
 /* Split step, for parity checks. gather_push: gather, Boris push and move of
  * every particle of every run, keeping x^n (Sec. 1, Sec. 3). deposit:

@@ -93,6 +93,15 @@ def z_explicit(S):
     return 1.0 - 2.0 * S * S + r, 1.0 - 2.0 * S * S - r
 
 
+def power_spectrum(f):
+    """|F(kx, ky)|^2 / (nx ny)^2 of a [ny][nx] field, F the discrete Fourier
+    transform sum f(i, j) exp(-2 pi i (kx i/nx + ky j/ny)) (numpy's FFT), in
+    the transform's index order: the k-space maps of Sec. 3.1 (Fig. 3)."""
+    ny, nx = f.shape
+    F = np.fft.fft2(np.asarray(f, dtype=np.float64))
+    return (np.abs(F) / (nx * ny)) ** 2
+
+
 def cherenkov_ky(kx_dx, V, sigma_x, sigma_y):
     """Eq. (17): ky dy where omega = V kx meets Eq. (15); NaN where none."""
     # omega dt = V kx dt = V sigma_x (kx dx) with c = 1

@@ -25,13 +25,13 @@ PIC_X0_ZERO, PIC_X0_PREV = 0, 1
 PIC_SCHEME_IMPLICIT, PIC_SCHEME_EXPLICIT = 0, 1
 PIC_WALL_GAP = 4
 FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
-             "rho": 9}
+             "rho": 9, "n0": 10, "n1": 11}
 PIC_E_NOCONV, PIC_E_CAPACITY, PIC_E_NAN = -4, -5, -6
 STATUS = {0: "PIC_OK", -1: "PIC_E_INVAL", -2: "PIC_E_NOMEM", -3: "PIC_E_HIP",
           -4: "PIC_E_NOCONV", -5: "PIC_E_CAPACITY", -6: "PIC_E_NAN", -7: "PIC_E_STATE"}
 EXPORTS = ["pic_plan", "pic_init", "pic_load_particles", "pic_load_plasma", "pic_inject_particles",
            "pic_set_inflow",
-           "pic_read_particles", "pic_set_field", "pic_get_field", "pic_gather_push",
+           "pic_read_particles", "pic_set_field", "pic_get_field", "pic_field_spectrum", "pic_transverse_average", "pic_gather_push",
            "pic_deposit", "pic_field_solve", "pic_field_solve_noalloc", "pic_step", "pic_diag", "pic_history",
            "pic_timing", "pic_get_timing", "pic_precond_collect", "pic_precond_train",
            "pic_precond_use", "pic_precond_get_weights", "pic_precond_set_weights",
@@ -165,6 +165,10 @@ def lib():
                                     ctypes.c_void_p]
         L.pic_get_field.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_void_p]
+        L.pic_field_spectrum.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_void_p]
+        L.pic_transverse_average.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_void_p]
         L.pic_gather_push.argtypes = [ctypes.c_void_p]
         L.pic_deposit.argtypes = [ctypes.c_void_p]
         L.pic_field_solve.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -355,6 +359,21 @@ class Sim:
         d = self.runs[run]
         out = np.empty((d.ny, d.nx))
         self._check(self.L.pic_get_field(self.ctx, run, FIELD_IDS[name], _ptr(out)), "get_field")
+        return out
+
+    def spectrum(self, run, name):
+        """|F(kx, ky)|^2 / (nx ny)^2 of one field ([ny][nx], DFT order)."""
+        d = self.runs[run]
+        out = np.empty((d.ny, d.nx))
+        self._check(self.L.pic_field_spectrum(self.ctx, run, FIELD_IDS[name], _ptr(out)),
+                    "field_spectrum")
+        return out
+
+    def transverse_average(self, run, name):
+        """mean over y of one field: an x profile of nx values"""
+        out = np.empty(self.runs[run].nx)
+        self._check(self.L.pic_transverse_average(self.ctx, run, FIELD_IDS[name], _ptr(out)),
+                    "transverse_average")
         return out
 
     def set_field(self, run, name, arr):

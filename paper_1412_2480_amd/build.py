@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpic.so")
-SOURCES = ["api.cpp", "particles.hip", "fields.hip", "learned.hip", "loader.hip"]
+SOURCES = ["api.cpp", "particles.hip", "fields.hip", "learned.hip", "loader.hip", "spectrum.hip"]
 ARCH = os.environ.get("PIC_OFFLOAD_ARCH", "gfx950")
 
 COMMON = [

@@ -1147,9 +1147,10 @@ double* field_ptr(pic_ctx* c, int id) {
   return nullptr;
 }
 
+// charge density (species < 0) or one species' number density into d_rho
 template <typename R>
-int rho_impl(pic_ctx* c, int run) {
-  hipError_t e = pic_launch_particles<R>(state<R>(c), 3, 0, 256, c->stream);
+int rho_impl(pic_ctx* c, int run, int species = -1) {
+  hipError_t e = pic_launch_density<R>(state<R>(c), species, 256, c->stream);
   if (e == hipSuccess)
     e = pic_launch_charge_sum<R>(state<R>(c), run,
                                  (long long)c->runs[run].nx * c->runs[run].ny, c->d_rho, c->stream);
@@ -1508,19 +1509,67 @@ int32_t pic_read_particles(pic_ctx* c, int32_t run, int32_t species, int64_t cap
                  : read_impl<double>(c, run, species, cap, ix, iy, fx, fy, ux, uy, uz, n_out);
 }
 
+// device array of a field of one run; the particle moments (charge, species
+// densities) are deposited on demand into the density buffer
+const double* field_src(pic_ctx* c, int run, int id, int* rc) {
+  *rc = PIC_OK;
+  if (id >= PIC_RHO) {
+    if (id > PIC_RHO && id - PIC_N0 >= c->runs[run].n_species) {
+      *rc = fail(c, PIC_E_INVAL, "no such species");
+      return nullptr;
+    }
+    const int sp = id == PIC_RHO ? -1 : id - PIC_N0;
+    *rc = c->fast ? rho_impl<float>(c, run, sp) : rho_impl<double>(c, run, sp);
+    return *rc ? nullptr : c->d_rho;
+  }
+  return field_ptr(c, id) + c->tl.cell0[run];
+}
+
 int32_t pic_get_field(pic_ctx* c, int32_t run, int32_t id, double* host) {
-  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_RHO)
+  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_N1)
     return fail(c, PIC_E_INVAL, "bad run/field/pointer");
   const long long n = (long long)c->runs[run].nx * c->runs[run].ny;
-  const double* src;
-  if (id == PIC_RHO) {
-    int rc = c->fast ? rho_impl<float>(c, run) : rho_impl<double>(c, run);
-    if (rc) return rc;
-    src = c->d_rho;
-  } else {
-    src = field_ptr(c, id) + c->tl.cell0[run];
-  }
+  int rc = PIC_OK;
+  const double* src = field_src(c, run, id, &rc);
+  if (rc) return rc;
   HIPCHK(c, hipMemcpyAsync(host, src, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_field_spectrum(pic_ctx* c, int32_t run, int32_t id, double* host) {
+  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_N1)
+    return fail(c, PIC_E_INVAL, "bad run/field/pointer");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "spectrum during a split step");
+  const int nx = c->runs[run].nx, ny = c->runs[run].ny;
+  const long long n = (long long)nx * ny;
+  const long long o = c->tl.cell0[run];
+  int rc = PIC_OK;
+  const double* src = field_src(c, run, id, &rc);
+  if (rc) return rc;
+  // scratch: CG vectors, unused between field solves
+  double* xr = c->fa.w0[0] + o;
+  double* xi = c->fa.w0[1] + o;
+  double* pw = c->fa.w1[0] + o;
+  hipError_t e = pic_launch_spectrum(src, nx, ny, xr, xi, pw, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("spectrum: ") + hipGetErrorString(e));
+  HIPCHK(c, hipMemcpyAsync(host, pw, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PIC_OK;
+}
+
+int32_t pic_transverse_average(pic_ctx* c, int32_t run, int32_t id, double* host) {
+  if (!c || !host || run < 0 || run >= (int)c->runs.size() || id < PIC_EX || id > PIC_N1)
+    return fail(c, PIC_E_INVAL, "bad run/field/pointer");
+  if (c->phase != 0) return fail(c, PIC_E_STATE, "average during a split step");
+  const int nx = c->runs[run].nx, ny = c->runs[run].ny;
+  int rc = PIC_OK;
+  const double* src = field_src(c, run, id, &rc);
+  if (rc) return rc;
+  double* out = c->fa.w1[1] + c->tl.cell0[run];   // CG vector, unused between solves
+  hipError_t e = pic_launch_transverse_mean(src, nx, ny, out, c->stream);
+  if (e != hipSuccess) return fail(c, PIC_E_HIP, std::string("average: ") + hipGetErrorString(e));
+  HIPCHK(c, hipMemcpyAsync(host, out, nx * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return PIC_OK;
 }

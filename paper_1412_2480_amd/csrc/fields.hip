@@ -797,7 +797,13 @@ __device__ double op_at(const DevRun& R, const double* v, int c, int i, int j) {
          ay * (v[lidx(L, i, j + 1)] - 2.0 * cc + v[lidx(L, i, j - 1)]);
 }
 
-constexpr int kResThreads = 256, kResBlocks = 64;
+constexpr int kResThreads = 256;
+// work-groups per run of the residual sweep: partials of all runs must fit the
+// solve's partial-sum buffer (PIC_RES_PART_DOUBLES doubles, 4 per work-group)
+inline int res_blocks(int n_runs) {
+  const int b = PIC_RES_PART_DOUBLES / (4 * n_runs);
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
 
 // True residual ||b - A dB||^2 of the applied dB per component, after the
 // solve: per (work-group, run) partial sums in a fixed reduction tree.
@@ -806,7 +812,8 @@ __global__ void __launch_bounds__(kResThreads) k_true_residual(FieldArgs a) {
   const DevRun& R = a.runs[run];
   const int ncell = R.nx * R.ny;
   double d[3] = {0.0, 0.0, 0.0};
-  for (int k = blockIdx.x * kResThreads + threadIdx.x; k < ncell; k += kResBlocks * kResThreads) {
+  for (int k = blockIdx.x * kResThreads + threadIdx.x; k < ncell;
+       k += (int)gridDim.x * kResThreads) {
     const int j = k / R.nx, i = k - j * R.nx;
     const long long g = R.cell0 + k;
 #pragma unroll
@@ -824,18 +831,18 @@ __global__ void __launch_bounds__(kResThreads) k_true_residual(FieldArgs a) {
     __syncthreads();
   }
   if (threadIdx.x < 3)
-    a.part[((size_t)run * kResBlocks + blockIdx.x) * 4 + threadIdx.x] = sm[threadIdx.x][0];
+    a.part[((size_t)run * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = sm[threadIdx.x][0];
 }
 
 // sum of the partials in block order; relres = ||b - A dB|| / ||b|| into the
 // solve statistics and the step's history record
-__global__ void k_true_residual_final(FieldArgs a) {
+__global__ void k_true_residual_final(FieldArgs a, int nblk) {
   const int run = blockIdx.x;
   if (threadIdx.x != 0) return;
   double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
   for (int c = 0; c < 3; ++c) {
     double s = 0.0;
-    for (int b = 0; b < kResBlocks; ++b) s += a.part[((size_t)run * kResBlocks + b) * 4 + c];
+    for (int b = 0; b < nblk; ++b) s += a.part[((size_t)run * nblk + b) * 4 + c];
     const double bn = st[6 + c];
     st[3 + c] = bn > 0.0 ? sqrt(s) / bn : 0.0;
     if (a.diag)
@@ -941,7 +948,8 @@ hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s) {
   // the true residual of the applied dB: a separate sweep of two small
   // kernels (inside the persistent solve the same stencil sweep costs about
   // 0.2 ms at 1024 x 256, measured)
-  k_true_residual<<<dim3(kResBlocks, a.n_runs), kResThreads, 0, s>>>(copy);
-  k_true_residual_final<<<a.n_runs, 64, 0, s>>>(copy);
+  const int nblk = res_blocks(a.n_runs);
+  k_true_residual<<<dim3(nblk, a.n_runs), kResThreads, 0, s>>>(copy);
+  k_true_residual_final<<<a.n_runs, 64, 0, s>>>(copy, nblk);
   return hipGetLastError();
 }

@@ -157,7 +157,7 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
 template <typename R, typename F, int P, int MODE, bool DIAG>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
                           int x0, int y0, int tw, int th, const F* sF, double* sJ, int part,
-                          double (&wk)[PIC_MAXS][2]) {
+                          int sel, double (&wk)[PIC_MAXS][2]) {
   constexpr int W = P + 2;   // Esirkepov window: union of old and new supports
   const int PW = st.PW, PH = st.PH;
   const int plane = PW * PH;
@@ -166,6 +166,8 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
   const R lim = max_disp<R>();
 
   for (int s = 0; s < run.nspecies; ++s) {
+    // the charge mode deposits one species' number density when sel >= 0
+    if (MODE == MODE_CHARGE && sel >= 0 && s != sel) continue;
     const int n_all = st.cnt[s][tile];
     // this work-group's share of the tile's particles
     const int lo = (int)(((long long)n_all * part) / st.K);
@@ -220,7 +222,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
         const int f0y = bspline_weights<P, R>(fy, w0y);
 
         if constexpr (MODE == MODE_CHARGE) {
-          const R cq = R(run.q[s] / (run.dx * run.dy));
+          const R cq = R((sel >= 0 ? 1.0 : run.q[s]) / (run.dx * run.dy));
           const int ax0 = lx + f0x + G, ay0 = ly + f0y + G;
 #pragma unroll
           for (int b = 0; b <= P; ++b)
@@ -459,7 +461,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
 // DIAG: the step records the kinetic energies W_K(n -/+ 1/2) (a compile-time
 // variant, so that the ordinary step carries no FP64 accumulators)
 template <typename R, typename F, int MODE, bool DIAG>
-__global__ void __launch_bounds__(256) k_particles(DevState<R> st) {
+__global__ void __launch_bounds__(256) k_particles(DevState<R> st, int sel) {
   // XCD-aware order: consecutive (tile, part) items go to the same XCD
   const int per = gridDim.x / 8;
   const int item = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -524,13 +526,13 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st) {
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
   switch (run.order) {
     case 1:
-      tile_body<R, F, 1, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
+      tile_body<R, F, 1, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
     case 2:
-      tile_body<R, F, 2, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
+      tile_body<R, F, 2, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
     default:
-      tile_body<R, F, 3, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, wk);
+      tile_body<R, F, 3, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
   }
   __syncthreads();
@@ -998,23 +1000,48 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
   switch (mode) {
     case MODE_FUSED:
       if (diag)
-        k_particles<R, F, MODE_FUSED, true><<<grid, block, smem, s>>>(st);
+        k_particles<R, F, MODE_FUSED, true><<<grid, block, smem, s>>>(st, -1);
       else
-        k_particles<R, F, MODE_FUSED, false><<<grid, block, smem, s>>>(st);
+        k_particles<R, F, MODE_FUSED, false><<<grid, block, smem, s>>>(st, -1);
       break;
     case MODE_PUSH:
       if (diag)
-        k_particles<R, F, MODE_PUSH, true><<<grid, block, smem, s>>>(st);
+        k_particles<R, F, MODE_PUSH, true><<<grid, block, smem, s>>>(st, -1);
       else
-        k_particles<R, F, MODE_PUSH, false><<<grid, block, smem, s>>>(st);
+        k_particles<R, F, MODE_PUSH, false><<<grid, block, smem, s>>>(st, -1);
       break;
     case MODE_DEPOSIT:
-      k_particles<R, F, MODE_DEPOSIT, false><<<grid, block, smem, s>>>(st);
+      k_particles<R, F, MODE_DEPOSIT, false><<<grid, block, smem, s>>>(st, -1);
       break;
     default:
-      k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st);
+      k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st, -1);
       break;
   }
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t pic_launch_density(const DevState<R>& st, int species, int threads, hipStream_t s) {
+  using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
+  const size_t smem = pic_particle_smem(st, MODE_CHARGE);
+  const dim3 grid(grid_tiles(st.n_tiles * st.K)), block(threads);
+  k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st, species);
+  return hipGetLastError();
+}
+
+// Transverse average of one run's [ny][nx] field: profile(i) = mean_j f(i, j)
+__global__ void __launch_bounds__(256) k_transverse_mean(const double* f, int nx, int ny,
+                                                         double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nx) return;
+  double s = 0.0;
+  for (int j = 0; j < ny; ++j) s += f[(long long)j * nx + i];
+  out[i] = s / ny;
+}
+
+hipError_t pic_launch_transverse_mean(const double* f, int nx, int ny, double* out,
+                                      hipStream_t s) {
+  k_transverse_mean<<<(nx + 255) / 256, 256, 0, s>>>(f, nx, ny, out);
   return hipGetLastError();
 }
 
@@ -1082,6 +1109,8 @@ template size_t pic_particle_smem<float>(const DevState<float>&, int);
 template size_t pic_particle_smem<double>(const DevState<double>&, int);
 template hipError_t pic_launch_particles<float>(const DevState<float>&, int, int, int, hipStream_t);
 template hipError_t pic_launch_particles<double>(const DevState<double>&, int, int, int, hipStream_t);
+template hipError_t pic_launch_density<float>(const DevState<float>&, int, int, hipStream_t);
+template hipError_t pic_launch_density<double>(const DevState<double>&, int, int, hipStream_t);
 template hipError_t pic_launch_rebin<float>(const DevState<float>&, int, hipStream_t);
 template hipError_t pic_launch_sort<float>(const DevState<float>&, int, int, hipStream_t);
 template hipError_t pic_launch_sort<double>(const DevState<double>&, int, int, hipStream_t);

@@ -17,6 +17,9 @@ constexpr int kBarWords = 32 * (kBarGroups + 2);
 // residual, 6-8 ||b||, 9-11 learned iterations, 12 fallback, 13 fallbacks and
 // 14 solves since initialisation, 16-18 recursive relative residual
 #define PIC_STAT_WORDS 24
+// doubles of the solve's partial-sum buffer the true-residual sweep may use
+// (the buffer holds 24 per field-solve work-group, at least 4096 of them)
+#define PIC_RES_PART_DOUBLES 98304
 
 struct FieldArgs {
   int n_runs, n_blocks, diag;
@@ -97,6 +100,14 @@ hipError_t pic_launch_charge_sum(const DevState<R>& st, int run, long long ncell
                                  hipStream_t s);
 template <typename R>
 size_t pic_particle_smem(const DevState<R>& st, int mode);
+// node density of one species (species >= 0: particles per unit area) or the
+// charge density (species < 0) into the current patches; pic_launch_charge_sum
+// then sums them
+template <typename R>
+hipError_t pic_launch_density(const DevState<R>& st, int species, int threads, hipStream_t s);
+// profile(i) = mean over j of one [ny][nx] field
+hipError_t pic_launch_transverse_mean(const double* f, int nx, int ny, double* out,
+                                      hipStream_t s);
 
 hipError_t pic_launch_divergences(const DevRun* runs, int run, long long ncell,
                                   const double* const* E, const double* const* B,
@@ -131,6 +142,11 @@ hipError_t pic_net_apply(const NetTrain& T, int form, const double* in, double* 
 hipError_t pic_net_grad(const NetTrain& T, const double* b, const double* t, int nx, int ny,
                         int ox, int oy, int cx, int cy, hipStream_t s);
 hipError_t pic_net_adam(const NetTrain& T, float lr, int step, hipStream_t s);
+
+// power spectrum |F(k)|^2 / (nx ny)^2 of one [ny][nx] field (DFT order);
+// xr, xi: nx * ny doubles of scratch each
+hipError_t pic_launch_spectrum(const double* f, int nx, int ny, double* xr, double* xi,
+                               double* power, hipStream_t s);
 
 // Device-side seeded plasma load (same items as the host generator)
 struct PlasmaLoad {

@@ -141,3 +141,33 @@ def test_offset_rounding_up_keeps_cell_and_tile(precision):
     scale = 4 * np.pi * Q / (dx * dx)   # 4 pi rho of one macro-particle on one node
     assert d["gauss_max"] <= (1e-5 if precision == "fp32" else 1e-11) * scale
     sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_species_density_and_transverse_average(precision):
+    """PIC_N0/PIC_N1: a species' number density deposited with the order-p
+    shape at the nodes, against the oracle's charge deposit of that species
+    with unit charge; pic_transverse_average against the row mean of the
+    field read back."""
+    _say(f"species density {precision}")
+    case = Case(40, 36, 3, ppc=3, gamma0=5.0, T=0.05, field_amp=0.2, seed=12)
+    sim = case.gpu_sim(precision, tile=(16, 16))
+    sim.step(2)
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for s, name in enumerate(("n0", "n1")):
+        g = sim.read_particles(0, s, case.species[s].n)
+        p = oracle.Particles(g["ix"], g["iy"], g["fx"], g["fy"], g["ux"], g["uy"], g["uz"], 1.0,
+                             1.0)
+        ref = oracle.charge(case.nx, case.ny, case.order, case.dx, case.dy, p)
+        got = sim.get_field(0, name)
+        assert relerr(got, ref) <= tol, name
+        # the total is the particle count
+        # the total is the particle count (FP32 weights: to their roundoff)
+        assert abs(got.sum() * case.dx * case.dy - p.n) <= (1e-9 if precision == "fp64"
+                                                            else 1e-6) * p.n
+        prof = sim.transverse_average(0, name)
+        assert np.allclose(prof, got.mean(axis=0), rtol=1e-13, atol=0)
+    bz = sim.get_field(0, "Bz")
+    assert np.allclose(sim.transverse_average(0, "Bz"), bz.mean(axis=0), rtol=1e-13,
+                       atol=1e-18)
+    sim.close()

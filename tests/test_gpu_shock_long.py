@@ -31,9 +31,10 @@ def test_shock_10000_steps_learned():
     Q = loads.macro_charge(g0, 0.1, 0.1, ppc)
     run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, order, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8,
                        cg_maxit=200, bc="shock")
-    # the shock compresses the flow behind it (about 3x) and the reflected
-    # beam adds to that: tiles get 5x the upstream slots
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, slack=4.0,
+    # the shock compresses the flow behind it and the reflected beam adds to
+    # that: with 5x the upstream slots a tile near the wall overflowed near
+    # step 6000, so tiles get 10x
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, slack=9.0,
                                           exchange_frac=0.5, track_ids=False, solver="learned",
                                           precond_slots=16, sort_every=4, graph=True))
     for s in range(2):

@@ -354,3 +354,22 @@ def test_explicit_vacuum_energy_invariant(ora):
     for _ in range(25):
         ora.update_explicit(nx, ny, dx, dy, dt, E, B, J0)
         assert abs(invariant() / w0 - 1) < 1e-12
+
+
+def test_power_spectrum_pins():
+    """The k-space power of the oracle: Parseval (the total power is the mean
+    square of the field), a single real mode puts a quarter of its squared
+    amplitude on each of +k and -k, and a staggered copy of the field (a
+    half-cell shift, as between Yee components) has the same power."""
+    nx, ny = 40, 24
+    rng = np.random.default_rng(3)
+    f = rng.normal(size=(ny, nx))
+    p = spectral.power_spectrum(f)
+    assert abs(p.sum() - (f * f).mean()) < 1e-14 * (f * f).mean()
+    J, I = np.mgrid[0:ny, 0:nx]
+    m = 2.5 * np.cos(2 * np.pi * (3 * I / nx + 5 * J / ny) + 0.3)
+    pm = spectral.power_spectrum(m)
+    assert abs(pm[5, 3] - 2.5 ** 2 / 4) < 1e-13 and abs(pm[ny - 5, nx - 3] - 2.5 ** 2 / 4) < 1e-13
+    assert pm.sum() - pm[5, 3] - pm[ny - 5, nx - 3] < 1e-20
+    shifted = 2.5 * np.cos(2 * np.pi * (3 * (I + 0.5) / nx + 5 * J / ny) + 0.3)
+    assert np.allclose(spectral.power_spectrum(shifted), pm, rtol=0, atol=1e-13)
