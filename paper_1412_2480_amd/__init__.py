@@ -7,8 +7,10 @@ stream; every step of the method runs in the library's HIP kernels. There is
 no CPU fallback: importing works without the library, but creating a Sim
 raises if libpic.so is missing or no GPU is visible.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -268,6 +270,22 @@ def _ptr(a):
     return None if a is None else a.ctypes.data
 
 
+# Contexts still open when the interpreter exits are destroyed by an exit
+# handler, before the HIP runtime and any profiling tool attached to it tear
+# down: a context left to the garbage collector at interpreter shutdown would
+# otherwise release its graph execs and events after the runtime is gone.
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    for s in list(_live):
+        try:
+            s.close()
+        except Exception:
+            pass
+
+
 class Sim:
     """A context of one or more runs on the current torch CUDA (HIP) device."""
 
@@ -292,6 +310,7 @@ class Sim:
         if rc != 0:
             raise PicError(rc, f"pic_init failed: {self.L.pic_last_error(None).decode()}")
         self.ctx = ctx
+        _live.add(self)
 
     def _check(self, rc, what, allow=()):
         if rc != 0 and rc not in allow:

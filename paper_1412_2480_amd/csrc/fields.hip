@@ -834,20 +834,31 @@ __global__ void __launch_bounds__(kResThreads) k_true_residual(FieldArgs a) {
     a.part[((size_t)run * gridDim.x + blockIdx.x) * 4 + threadIdx.x] = sm[threadIdx.x][0];
 }
 
-// sum of the partials in block order; relres = ||b - A dB|| / ||b|| into the
-// solve statistics and the step's history record
-__global__ void k_true_residual_final(FieldArgs a, int nblk) {
+// sum of the partials (each thread a strided subset in block order, then a
+// fixed tree over the threads); relres = ||b - A dB|| / ||b|| into the solve
+// statistics and the step's history record
+__global__ void __launch_bounds__(kResThreads) k_true_residual_final(FieldArgs a, int nblk) {
   const int run = blockIdx.x;
-  if (threadIdx.x != 0) return;
-  double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
-  for (int c = 0; c < 3; ++c) {
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += a.part[((size_t)run * nblk + b) * 4 + c];
-    const double bn = st[6 + c];
-    st[3 + c] = bn > 0.0 ? sqrt(s) / bn : 0.0;
-    if (a.diag)
-      a.history[((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS + 9 + c] = st[3 + c];
+  const double* part = a.part + (size_t)run * nblk * 4;
+  double d[3] = {0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nblk; b += kResThreads)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) d[c] += part[(size_t)b * 4 + c];
+  __shared__ double sm[3][kResThreads];
+  for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] = d[c];
+  __syncthreads();
+  for (int off = kResThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off)
+      for (int c = 0; c < 3; ++c) sm[c][threadIdx.x] += sm[c][threadIdx.x + off];
+    __syncthreads();
   }
+  if (threadIdx.x >= 3) return;
+  const int c = threadIdx.x;
+  double* st = a.stats + (size_t)run * PIC_STAT_WORDS;
+  const double bn = st[6 + c];
+  const double rel = bn > 0.0 ? sqrt(sm[c][0]) / bn : 0.0;
+  st[3 + c] = rel;
+  if (a.diag) a.history[((size_t)run * a.hist_cap + a.hist_slot) * PIC_REC_WORDS + 9 + c] = rel;
 }
 
 }  // namespace
@@ -950,6 +961,6 @@ hipError_t pic_launch_field_solve(const FieldArgs& a, hipStream_t s) {
   // 0.2 ms at 1024 x 256, measured)
   const int nblk = res_blocks(a.n_runs);
   k_true_residual<<<dim3(nblk, a.n_runs), kResThreads, 0, s>>>(copy);
-  k_true_residual_final<<<a.n_runs, 64, 0, s>>>(copy, nblk);
+  k_true_residual_final<<<a.n_runs, kResThreads, 0, s>>>(copy, nblk);
   return hipGetLastError();
 }
