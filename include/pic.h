@@ -54,7 +54,7 @@ enum pic_status {
   PIC_E_NOMEM = -2,    /* workspace smaller than the plan requires */
   PIC_E_HIP = -3,      /* HIP runtime error */
   PIC_E_NOCONV = -4,   /* CG hit cg_maxit; the best iterate was applied */
-  PIC_E_CAPACITY = -5, /* a tile's particle slots or exchange buffers overflowed */
+  PIC_E_CAPACITY = -5, /* a tile's particle slots overflowed (raise slack) */
   PIC_E_NAN = -6,      /* non-finite value found by a diagnostic */
   PIC_E_STATE = -7     /* calls out of order (e.g. deposit before gather_push) */
 };
@@ -110,13 +110,15 @@ typedef struct pic_run_desc {
 typedef struct pic_options {
   int32_t precision;     /* PIC_FP64 or PIC_FP32_FAST (particles in FP32, fields FP64) */
   int32_t solver;        /* PIC_SOLVER_CG or PIC_SOLVER_LEARNED_PCG */
-  int32_t tile_x, tile_y;/* tile shape in cells; 0 picks a default */
+  int32_t tile_x, tile_y;/* tile shape in cells, at least 2 each (PIC_E_INVAL otherwise);
+                            0 picks a default (16) */
   double slack;          /* extra tile slots over ppc*cells (default 0.25 if <= 0); a
                             relativistic drift that goes unstable to numerical Cherenkov
                             radiation bunches the density: the 2000-step gamma0 = 40 run
                             of 1024 x 256 cells needs 0.5 (PIC_E_CAPACITY near step 500
                             at 0.25) */
-  double exchange_frac;  /* inbox/hole slots per tile as a fraction of tile slots (0.25) */
+  double exchange_frac;  /* ignored: particles that change tile are written straight into
+                            the destination tile's slots, so no exchange buffer exists */
   int32_t diag_every;    /* record energies every n steps into the history (0 = never) */
   int32_t history_cap;   /* history records kept per run (ring buffer) */
   int32_t cg_blocks;     /* work-groups of the persistent field solve; 0 = automatic */
@@ -156,7 +158,7 @@ typedef struct pic_plan_info {
   int32_t tile_x, tile_y;
   int32_t n_tiles;                         /* over all runs */
   int32_t tile_slots[PIC_MAX_SPECIES];     /* particle slots per tile per species */
-  int32_t exchange_slots;                  /* inbox slots per tile per species */
+  int32_t exchange_slots;                  /* always 0 (no exchange buffer) */
   int32_t tile_split;                      /* work-groups per tile */
   int64_t particle_slots[PIC_MAX_SPECIES]; /* total slots per species */
   int64_t n_cells;                         /* over all runs */

@@ -178,6 +178,13 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     *msg = "precision must be PIC_FP64 or PIC_FP32_FAST";
     return PIC_E_INVAL;
   }
+  // a particle in the second tile column of a shock run must not reach behind
+  // the wall (whose ghost columns only the first column's patches fold back),
+  // and a one-cell tile loses every particle every step: two cells at least
+  if ((o->tile_x > 0 && o->tile_x < 2) || (o->tile_y > 0 && o->tile_y < 2)) {
+    *msg = "tiles need at least 2 cells along each axis";
+    return PIC_E_INVAL;
+  }
   if (o->solver != PIC_SOLVER_CG && o->solver != PIC_SOLVER_LEARNED_PCG) {
     *msg = "unknown solver";
     return PIC_E_INVAL;
@@ -383,7 +390,6 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   DevState<R> s{};
   for (int sp = 0; sp < PIC_MAXS; ++sp) {
     const size_t slots = (size_t)tl.n_tiles * pl.tile_slots[sp];
-    const size_t ex = (size_t)tl.n_tiles * pl.exchange_slots;
     if (pl.tile_slots[sp] == 0) continue;
     s.cell[sp] = b.take<int>(slots);
     s.ox[sp] = b.take<R>(slots);
@@ -400,17 +406,9 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
     if (ids) {
       s.id[sp] = b.take<int>(slots);
       s.nid[sp] = b.take<int>(slots);
-      s.in_id[sp] = b.take<int>(ex);
     }
     s.cnt[sp] = b.take<int>(tl.n_tiles);
     s.stay_cnt[sp] = b.take<int>(tl.n_tiles);
-    s.in_cnt[sp] = b.take<int>(tl.n_tiles);
-    s.in_cell[sp] = b.take<int>(ex);
-    s.in_ox[sp] = b.take<R>(ex);
-    s.in_oy[sp] = b.take<R>(ex);
-    s.in_ux[sp] = b.take<R>(ex);
-    s.in_uy[sp] = b.take<R>(ex);
-    s.in_uz[sp] = b.take<R>(ex);
     if (split) {
       s.old_cell[sp] = b.take<int>(slots);
       s.old_ox[sp] = b.take<R>(slots);
@@ -429,7 +427,6 @@ size_t carve(uint8_t* base, const Tiling& tl, const pic_plan_info& pl, int n_run
   s.PW = tl.TXA + 5;
   s.PH = tl.TYA + 5;
   for (int sp = 0; sp < PIC_MAXS; ++sp) s.tile_slots[sp] = pl.tile_slots[sp];
-  s.ex_slots = pl.exchange_slots;
   s.K = K;
   s.runs = d_runs;
   s.tile_run = tile_run;
@@ -533,7 +530,6 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
   p.n_tiles = tl->n_tiles;
   p.n_cells = tl->n_cells;
   const double slack = o->slack > 0 ? o->slack : 0.25;
-  const double exf = o->exchange_frac > 0 ? o->exchange_frac : 0.25;
   int max_species = 0;
   for (int r = 0; r < n_runs; ++r) max_species = std::max(max_species, runs[r].n_species);
   for (int s = 0; s < PIC_MAX_SPECIES; ++s) {
@@ -554,8 +550,9 @@ int plan_impl(const pic_run_desc* runs, int n_runs, const pic_options* o, pic_pl
     p.particle_slots[s] = slots * tl->n_tiles;
   }
   p.tile_split = o->tile_split > 0 ? std::min(o->tile_split, 64) : 4;
-  int ts = std::max(p.tile_slots[0], p.tile_slots[1]);
-  p.exchange_slots = std::max(64, (int)(std::ceil(ts * exf) + 63) / 64 * 64);
+  // particles that change tile are written straight into the destination
+  // tile's slots: there is no separate exchange buffer
+  p.exchange_slots = 0;
   const int hist_cap = o->history_cap > 0 ? o->history_cap : 1;
   const bool split = true;
   const bool ids = o->track_ids != 0;
@@ -724,8 +721,8 @@ int check_err(pic_ctx* c) {
   if (h) {
     char buf[160];
     snprintf(buf, sizeof buf,
-             "particle exchange overflow (bits 0x%x: 1 inbox, 4 tile slots); raise slack or "
-             "exchange_frac", h);
+             "tile capacity exceeded (error bits 0x%x): a tile's particles outgrew its "
+             "slots; raise slack", h);
     return fail(c, PIC_E_CAPACITY, buf);
   }
   return PIC_OK;

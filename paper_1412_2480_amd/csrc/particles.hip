@@ -9,12 +9,11 @@
 // LDS, pushes every particle of every species of the tile, accumulates the
 // current of the tile (+ guard nodes) in LDS, and writes that patch out whole.
 // A second pass sums the overlapping patches node by node in a fixed order
-// (no global atomics on J). The particle store is double-buffered: particles
-// that stay in their tile are written compacted into the next buffer (one LDS
-// atomic per wavefront), particles that leave are appended to the
-// destination tile's inbox (one global atomic per wavefront and
-// destination), and the re-binning kernel appends each inbox after the tile's
-// stayers. Every write is contiguous.
+// (no global atomics on J). The particle store is double-buffered: every
+// particle is written once into its (new) tile's region of the next buffer,
+// at a slot taken from that tile's counter (one global atomic per wavefront
+// and destination tile), so a particle that changes tile costs no more than
+// one that stays; the re-binning kernel only commits the counts.
 #include <math.h>
 
 #include <type_traits>
@@ -419,38 +418,33 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
         }
       }
       if constexpr (MODE == MODE_FUSED || MODE == MODE_DEPOSIT) {
-        // stayers: compacted into the next buffer of this tile
+        // Every particle goes straight to its tile's region of the next
+        // buffer: stayers and arrivals from the neighbours take slots from
+        // the same per-tile counter (one atomic per wavefront and distinct
+        // tile), so no separate exchange buffer and no second copy exist. A
+        // tile whose slots run out drops the surplus and flags the run.
+        const int cap = st.tile_slots[s];
         const bool stay = active && !leave && !gone;
         const unsigned long long m = __ballot(stay);
         int wbase = 0;
         if (__lane_id() == 0 && m) wbase = atomicAdd(&st.stay_cnt[s][tile], __popcll(m));
         wbase = __shfl(wbase, 0);
-        if (stay) {
-          const int lane = __lane_id();
-          const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-          const long long o = base + wbase + __popcll(m & below);
-          st.ncell[s][o] = gcell;
-          st.nox[s][o] = fx1;
-          st.noy[s][o] = fy1;
-          st.nux[s][o] = ux;
-          st.nuy[s][o] = uy;
-          st.nuz[s][o] = uz;
-          if (st.nid[s]) st.nid[s][o] = pid;
-        }
-        // leavers: appended to the destination tile's inbox
-        const int slot = wave_reserve(leave, dest, st.in_cnt[s]);
-        if (leave) {
-          if (slot < st.ex_slots) {
-            const long long o = (long long)dest * st.ex_slots + slot;
-            st.in_cell[s][o] = gcell;
-            st.in_ox[s][o] = fx1;
-            st.in_oy[s][o] = fy1;
-            st.in_ux[s][o] = ux;
-            st.in_uy[s][o] = uy;
-            st.in_uz[s][o] = uz;
-            if (st.in_id[s]) st.in_id[s][o] = pid;
+        const int lane = __lane_id();
+        const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        const int moved = wave_reserve(leave, dest, st.stay_cnt[s]);
+        const int slot = stay ? wbase + __popcll(m & below) : moved;
+        if (stay || leave) {
+          if (slot < cap) {
+            const long long o = (long long)(stay ? tile : dest) * cap + slot;
+            st.ncell[s][o] = gcell;
+            st.nox[s][o] = fx1;
+            st.noy[s][o] = fy1;
+            st.nux[s][o] = ux;
+            st.nuy[s][o] = uy;
+            st.nuz[s][o] = uz;
+            if (st.nid[s]) st.nid[s][o] = pid;
           } else {
-            atomicOr(st.err, PIC_ERRBIT_INBOX);
+            atomicOr(st.err, PIC_ERRBIT_TILE);
           }
         }
       }
@@ -564,40 +558,24 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int sel) {
   }
 }
 
-// Re-binning: the tile's inbox is appended after its stayers in the next
-// buffer (contiguous reads and writes); the new count is stayers + arrivals.
+// Re-binning: the particle kernel has already written every particle into its
+// tile's region of the next buffer; the tile's new count is what its counter
+// handed out (at most the tile's slots), and the counter is cleared for the
+// next pass.
 template <typename R>
 __global__ void __launch_bounds__(256) k_rebin(DevState<R> st) {
-  const int per = gridDim.x / 8;
-  const int tile = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int tile = blockIdx.x * blockDim.x + threadIdx.x;
   if (tile >= st.n_tiles) return;
   const int s = blockIdx.y;
   if (s >= st.runs[st.tile_run[tile]].nspecies) return;
-  const int ex = st.ex_slots;
   const int cap = st.tile_slots[s];
-  const int S = st.stay_cnt[s][tile];
-  int A = st.in_cnt[s][tile];
-  A = A > ex ? ex : A;
-  if (S + A > cap) {
-    if (threadIdx.x == 0) atomicOr(st.err, PIC_ERRBIT_TILE);
-    A = cap - S;   // state is no longer consistent; the run is flagged
+  int n = st.stay_cnt[s][tile];
+  if (n > cap) {
+    atomicOr(st.err, PIC_ERRBIT_TILE);
+    n = cap;   // the surplus was dropped; the run is flagged
   }
-  const long long base = (long long)tile * cap + S;
-  const long long ib = (long long)tile * ex;
-  for (int k = threadIdx.x; k < A; k += blockDim.x) {
-    st.ncell[s][base + k] = st.in_cell[s][ib + k];
-    st.nox[s][base + k] = st.in_ox[s][ib + k];
-    st.noy[s][base + k] = st.in_oy[s][ib + k];
-    st.nux[s][base + k] = st.in_ux[s][ib + k];
-    st.nuy[s][base + k] = st.in_uy[s][ib + k];
-    st.nuz[s][base + k] = st.in_uz[s][ib + k];
-    if (st.nid[s]) st.nid[s][base + k] = st.in_id[s][ib + k];
-  }
-  if (threadIdx.x == 0) {
-    st.cnt[s][tile] = S + A;
-    st.in_cnt[s][tile] = 0;
-    st.stay_cnt[s][tile] = 0;
-  }
+  st.cnt[s][tile] = n;
+  st.stay_cnt[s][tile] = 0;
 }
 
 // Reordering of a tile's particles (every sort_every steps, after the
@@ -860,27 +838,26 @@ __global__ void __launch_bounds__(256) k_current_sum(DevState<R> st, int ncomp, 
   const int tx = pic_tile_of(i, TX, run.ntx), ty = pic_tile_of(j, TY, run.nty);
   const bool shock = run.bc == 1;
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int dy = -1; dy <= 1; ++dy) {
-    int t_y = ty + dy, oy;
-    if (t_y < 0) { t_y = run.nty - 1; oy = t_y * TY - run.ny; }
-    else if (t_y >= run.nty) { t_y = 0; oy = run.ny; }
-    else oy = t_y * TY;
+  // a patch reaches PIC_GUARD_LO nodes below its tile and PIC_GUARD_HI - 1
+  // above it, so tiles narrower than the guard have patches reaching past
+  // their neighbours: look as many tiles out as the guard spans
+  constexpr int GMAX = G > PIC_GUARD_HI ? G : PIC_GUARD_HI;
+  const int RX = (GMAX + TX - 1) / TX, RY = (GMAX + TY - 1) / TY;
+  for (int dy = -RY; dy <= RY; ++dy) {
+    // tile row ty + dy, wrapped periodically: origin t_y TY + my ny
+    int t_y = ty + dy, my = 0;
+    while (t_y < 0) { t_y += run.nty; --my; }
+    while (t_y >= run.nty) { t_y -= run.nty; ++my; }
+    const int oy = t_y * TY + my * run.ny;
     const int hy = pic_tile_width(t_y, TY, run.nty, run.ny);
     const int ly = j - oy;
     if (ly < -G || ly > hy + PIC_GUARD_HI - 1) continue;
-    for (int dx = -1; dx <= 1; ++dx) {
-      int t_x = tx + dx, ox;
-      if (t_x < 0) {
-        if (shock) continue;
-        t_x = run.ntx - 1;
-        ox = t_x * TX - run.nx;
-      } else if (t_x >= run.ntx) {
-        if (shock) continue;
-        t_x = 0;
-        ox = run.nx;
-      } else {
-        ox = t_x * TX;
-      }
+    for (int dx = -RX; dx <= RX; ++dx) {
+      int t_x = tx + dx, mx = 0;
+      while (t_x < 0) { t_x += run.ntx; --mx; }
+      while (t_x >= run.ntx) { t_x -= run.ntx; ++mx; }
+      if (shock && mx != 0) continue;
+      const int ox = t_x * TX + mx * run.nx;
       const int hx = pic_tile_width(t_x, TX, run.ntx, run.nx);
       const int lx = i - ox;
       if (lx < -G || lx > hx + PIC_GUARD_HI - 1) continue;
@@ -1069,7 +1046,7 @@ hipError_t pic_launch_sort(const DevState<R>& st, int n_species, int max_tile_ce
 
 template <typename R>
 hipError_t pic_launch_rebin(const DevState<R>& st, int n_species, hipStream_t s) {
-  k_rebin<R><<<dim3(grid_tiles(st.n_tiles), n_species), dim3(256), 0, s>>>(st);
+  k_rebin<R><<<dim3((st.n_tiles + 255) / 256, n_species), dim3(256), 0, s>>>(st);
   return hipGetLastError();
 }
 

@@ -15,8 +15,7 @@
 #define PIC_GUARD_HI 3   // patch / LDS nodes at or above the tile end
 
 // error bits raised by kernels (read back by the host)
-#define PIC_ERRBIT_INBOX 1      // destination inbox full
-#define PIC_ERRBIT_TILE 4       // tile slots full after re-binning
+#define PIC_ERRBIT_TILE 4       // a tile's slots ran out
 #define PIC_ERRBIT_BARRIER 8    // a grid barrier timed out
 
 #define PIC_WALL_GAP 4   // shock runs: particles leave at x >= (nx - PIC_WALL_GAP) dx
@@ -42,7 +41,6 @@ struct DevState {
   int n_runs, n_tiles;
   int TX, TY, TXA, TYA, PW, PH;  // tile shape, widest tile, patch pitch/rows
   int tile_slots[PIC_MAXS];
-  int ex_slots;                   // inbox slots per tile per species
   int K;                          // work-groups per tile (each takes 1/K of its particles)
   const DevRun* runs;
   const int* tile_run;            // run index of each global tile
@@ -72,17 +70,7 @@ struct DevState {
   R* nuz[PIC_MAXS];
   int* nid[PIC_MAXS];
   int* cnt[PIC_MAXS];             // live particles per tile (current arrays)
-  int* stay_cnt[PIC_MAXS];        // particles kept in the tile by the last pass
-
-  // exchange between tiles: inbox of each destination tile
-  int* in_cnt[PIC_MAXS];
-  int* in_cell[PIC_MAXS];
-  R* in_ox[PIC_MAXS];
-  R* in_oy[PIC_MAXS];
-  R* in_ux[PIC_MAXS];
-  R* in_uy[PIC_MAXS];
-  R* in_uz[PIC_MAXS];
-  int* in_id[PIC_MAXS];
+  int* stay_cnt[PIC_MAXS];        // slots handed out in the next arrays by the running pass
 
   // split path: positions before the move
   int* old_cell[PIC_MAXS];

@@ -11,7 +11,7 @@ kernels.
 from . import PicError, Sim, make_options, plan
 
 # narrow tiles along x pay when the flow drifts along x and particles are
-# reordered (their inboxes need exchange_frac near 0.5)
+# reordered
 DEFAULT_SHAPES = ((4, 32), (8, 32), (16, 32), (16, 16), (32, 16), (2, 64), (8, 16))
 TIE = 0.02
 

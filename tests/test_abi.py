@@ -61,6 +61,17 @@ def test_plan_ragged_tiles():
     assert info.n_tiles == 2 * 3
 
 
+def test_plan_tile_shape_limits():
+    # two cells per axis at least; narrow tiles are legal and no exchange
+    # buffer is carved (particles go straight to their destination tile)
+    for tile in ((1, 8), (8, 1)):
+        with pytest.raises(pic.PicError) as ei:
+            pic.plan([_run()], pic.make_options("fp64", tile=tile))
+        assert ei.value.code == -1
+    info = pic.plan([_run()], pic.make_options("fp32", tile=(2, 64)))
+    assert info.n_tiles == 32 and info.exchange_slots == 0
+
+
 def test_plan_batched_runs():
     runs = [_run(nx=128, ny=64), _run(nx=512, ny=128, order=3)]
     info = pic.plan(runs, pic.make_options("fp32"))

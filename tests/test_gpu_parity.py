@@ -210,6 +210,40 @@ def test_exchange_keeps_every_particle(precision):
     sim.close()
 
 
+@pytest.mark.parametrize("order", [1, 3])
+@pytest.mark.parametrize("tile", [(2, 8), (2, 2), (3, 5)])
+def test_narrow_tiles_match_oracle(tile, order):
+    """Tiles narrower than the current patch's guard (2 nodes below a tile, 3
+    at and above its end): a node's current then comes from patches of tiles
+    two or more tiles away, which the reduction must include. A gamma0 = 40
+    drift moves every particle about one cell per step, so particles change
+    tile every step; fields, currents and particles follow the oracle."""
+    _say(f"narrow tiles {tile} order {order}")
+    case = Case(40, 36, order, ppc=3, gamma0=40.0, T=0.05, field_amp=0.3, seed=11 + order,
+                rtol=1e-14, maxit=500)
+    sim = case.gpu_sim("fp64", tile=tile, tile_split=2, slack=1.0)
+    ref = case.oracle_sim()
+    g0 = sim.diag(0)["gauss_max"]
+    for step in range(4):
+        sim.step(1)
+        ref.step()
+        for k, n in enumerate(JN):
+            e = relerr(sim.get_field(0, n), ref.J[k])
+            assert e <= 1e-11, (step, n, e)
+        for k, n in enumerate(EN + BN):
+            a = ref.E[k] if k < 3 else ref.B[k - 3]
+            e = relerr(sim.get_field(0, n), a)
+            assert e <= 1e-11, (step, n, e)
+    for s, p in enumerate(ref.species):
+        g = sim.read_particles(0, s, p.n)
+        pos, mom = compare_particles(g, p, case.nx, case.ny)
+        assert pos <= 1e-11 and mom <= 1e-11, (s, pos, mom)
+    # the Gauss residual of the random initial fields is carried unchanged
+    scale = 4 * np.pi * case.Q / (case.dx * case.dy)
+    assert abs(sim.diag(0)["gauss_max"] - g0) <= 1e-10 * scale
+    sim.close()
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_gauss_law_constant_on_gpu(precision):
     """div E - 4 pi rho stays at its initial value (zero for the neutral load)

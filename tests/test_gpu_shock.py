@@ -82,12 +82,16 @@ def _inject_both(case, step, gpu, ref):
             ref.inject(s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
 
 
-@pytest.mark.parametrize("order", [1, 2, 3])
-def test_shock_steps_match_oracle_fp64(order):
-    _say(f"shock split steps vs oracle, order {order}")
+@pytest.mark.parametrize("order,tile", [(1, (16, 16)), (2, (16, 16)), (3, (16, 16)),
+                                        (2, (2, 8)), (3, (2, 4))])
+def test_shock_steps_match_oracle_fp64(order, tile):
+    """Split steps with reflection, outflow and injection against the oracle;
+    the 2-cell-wide tiles put the wall's ghost columns and the patches that
+    reach two tiles out through the current reduction."""
+    _say(f"shock split steps vs oracle, order {order}, tile {tile}")
     case = Shock(40, 20, order, ppc=3, seed=order, field_amp=0.3, rtol=1e-14)
     ref = case.oracle_sim()
-    sim = case.gpu_sim("fp64")
+    sim = case.gpu_sim("fp64", tile=tile)
     reflected = 0
     for step in range(4):
         _inject_both(case, step, sim, ref)
