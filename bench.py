@@ -46,9 +46,11 @@ HBM_PEAK_GBS = 8000.0
 C5 = dict(nx=8192, ny=2048, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
           label="periodic 8192x2048, pair gamma0=40, 64 ppc/species (2^31 particles), "
                 "order 3, CFL 1.0, theta 0.6")
-# schedule of the headline workload (measured: tiles narrow along the flow,
-# two work-groups per tile, reordering every 4 steps; see tune.autotune)
-C5_TILE, C5_SPLIT, C5_SORT = (4, 32), 2, 4
+# schedule of the headline workload, measured on it (particle kernel, current
+# reduction and reordering per step at the cold start): 2x64 tiles, one
+# work-group per tile, reordering every 4 steps 65.3 ms; 2x64 with two
+# work-groups 70.6; 4x32 with two 80.6; 4x64 78.7; 2x128 96.0
+C5_TILE, C5_SPLIT, C5_SORT = (2, 64), 1, 4
 
 CONFIGS = {
     # name: nx, ny, ppc, gamma0, order, cfl, theta
@@ -110,9 +112,7 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
 GRAPH = True    # pic_step replays captured two-step HIP graphs (--no-graph: plain launches)
 SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
 # (tile shape, reordering period) candidates of the 48-run sweep
-SWEEP_SCHEDULES = (((16, 16), 0), ((4, 32), 8), ((8, 16), 8))
-EXF = 0.5       # inbox slots per tile (fraction of the tile's slots): narrow tiles in the
-                # flow direction exchange up to a quarter of their particles per step
+SWEEP_SCHEDULES = (((16, 16), 0), ((4, 32), 8), ((8, 16), 8), ((2, 32), 8))
 SLACK = 0.5     # tile slots over ppc*cells: once the numerical Cherenkov instability has
                 # saturated (near step 300) the densities bunch and a tile of the default
                 # 0.25 overflows within the 2000-step run
@@ -130,7 +130,7 @@ def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver=
                                           learned_form=form, precond_slots=slots,
                                           graph=GRAPH,
                                           sort_every=SORT if sort_every is None else sort_every,
-                                          exchange_frac=EXF, slack=SLACK))
+                                          slack=SLACK))
     for s in range(2):
         d = load[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -235,7 +235,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
     sched = []
     for tile, se in SWEEP_SCHEDULES:
         sim = pic.Sim(descs, pic.make_options("fp32", tile=tile, track_ids=False, graph=GRAPH,
-                                              tile_split=8, sort_every=se, exchange_frac=EXF,
+                                              tile_split=8, sort_every=se,
                                               slack=SLACK))
         for r, t in enumerate(table):
             load_run(sim, r, t)
@@ -250,7 +250,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
     sim = pic.Sim(descs, pic.make_options("fp32", tile=best["tile"], track_ids=False,
                                           graph=GRAPH, tile_split=best["tile_split"],
                                           cg_blocks=best["cg_blocks"],
-                                          sort_every=best["sort_every"], exchange_frac=EXF,
+                                          sort_every=best["sort_every"],
                                           slack=SLACK))
     for r, t in enumerate(table):
         load_run(sim, r, t)
@@ -267,7 +267,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
                                               graph=GRAPH, tile_split=tuned["tile_split"],
                                               cg_blocks=tuned["cg_blocks"], solver="learned",
                                               precond_slots=learned_pairs,
-                                              sort_every=best["sort_every"], exchange_frac=EXF,
+                                              sort_every=best["sort_every"],
                                           slack=SLACK))
         for r, t in enumerate(table):
             load_run(sim, r, t)
@@ -295,7 +295,7 @@ def batched_sweep(pic, torch, steps, warmup, seq_steps=3, learned_pairs=8, learn
     seq_ms = 0.0
     # one context per run, same tile shape and reordering period
     opts = pic.make_options("fp32", tile=best["tile"], track_ids=False, graph=GRAPH,
-                            sort_every=best["sort_every"], exchange_frac=EXF)
+                            sort_every=best["sort_every"])
     for r, t in enumerate(table):
         one = pic.Sim([descs[r]], opts)
         load_run(one, 0, t)
@@ -366,8 +366,7 @@ def headline(pic, torch, steps, warmup, saturated_after=300, pairs=8, epochs=50)
                        cg_rtol=1e-8, cg_maxit=200)
     sim = pic.Sim([run], pic.make_options("fp32", tile=C5_TILE, tile_split=C5_SPLIT,
                                           track_ids=False, solver="learned",
-                                          precond_slots=pairs, sort_every=C5_SORT,
-                                          exchange_frac=EXF, slack=SLACK))
+                                          precond_slots=pairs, sort_every=C5_SORT, slack=SLACK))
     t0 = time.perf_counter()
     for s in range(2):
         sim.load_plasma(0, s, ppc, c["gamma0"], 0.01, 0)
@@ -458,8 +457,7 @@ def shock_share(pic, torch, tile, tile_split, steps=20, warmup=5, pairs=8, epoch
     Q = loads.macro_charge(g0, 0.1, 0.1, ppc)
     run = pic.run_desc(nx, ny, 0.1, 1.0, 0.6, 2, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8,
                        bc="shock")
-    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split, slack=1.5,
-                                          exchange_frac=EXF, track_ids=False, solver="learned",
+    sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=tile_split, slack=1.5, track_ids=False, solver="learned",
                                           precond_slots=pairs, sort_every=4, graph=GRAPH))
     for s in range(2):
         sim.load_plasma(0, s, ppc, g0, 0.01, 0, direction=-1, x_cells=x_out)
@@ -585,12 +583,12 @@ def c2_legs(pic, torch, args, learned):
         from paper_1412_2480_amd.tune import autotune, tune_sort_every
         t0 = time.perf_counter()
         best, table = autotune([run], _load, dict(precision="fp32", track_ids=False,
-                                                  tile_split=8, exchange_frac=EXF, slack=SLACK,
+                                                  tile_split=8, slack=SLACK,
                                                   sort_every=8), warmup=args.warmup)
         tile, split, cgb = tuple(best["tile"]), best["tile_split"], best["cg_blocks"]
         SORT, sort_table = tune_sort_every(
             [run], _load, dict(precision="fp32", track_ids=False, tile=tile, tile_split=split,
-                               cg_blocks=cgb, exchange_frac=EXF, slack=SLACK),
+                               cg_blocks=cgb, slack=SLACK),
             candidates=(0, 3, 4, 8), warmup=args.warmup)
         tune = dict(best=dict(tile=list(tile), tile_split=split, cg_blocks=cgb,
                               sort_every=SORT),
@@ -618,14 +616,13 @@ def c2_legs(pic, torch, args, learned):
         t64 = dict(tile=tile, tile_split=1, cg_blocks=256, sort_every=0)
         if tune is not None:
             from paper_1412_2480_amd.tune import autotune, tune_sort_every
-            b64, _ = autotune([run], _load, dict(precision="fp64", track_ids=False, tile_split=8,
-                                                 exchange_frac=EXF, slack=SLACK, sort_every=8),
-                              shapes=((4, 32), (8, 32), (16, 16)), warmup=args.warmup)
+            b64, _ = autotune([run], _load, dict(precision="fp64", track_ids=False, tile_split=8, slack=SLACK, sort_every=8),
+                              shapes=((2, 64), (4, 32), (8, 32), (16, 16)),
+                              warmup=args.warmup)
             k64, _ = tune_sort_every([run], _load, dict(precision="fp64", track_ids=False,
                                                         tile=b64["tile"],
                                                         tile_split=b64["tile_split"],
-                                                        cg_blocks=b64["cg_blocks"],
-                                                        exchange_frac=EXF, slack=SLACK),
+                                                        cg_blocks=b64["cg_blocks"], slack=SLACK),
                                      candidates=(0, 4, 8), warmup=args.warmup)
             t64 = dict(tile=tuple(b64["tile"]), tile_split=b64["tile_split"],
                        cg_blocks=b64["cg_blocks"], sort_every=k64)
@@ -665,8 +662,8 @@ def explicit_vs_implicit(pic, torch, steps=20, warmup=5):
         Q = loads.macro_charge(cfg["gamma0"], 0.1, 0.1, cfg["ppc"])
         run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfl, 0.6, cfg["order"],
                            [(-Q, Q, cfg["ppc"]), (Q, Q, cfg["ppc"])], cg_rtol=1e-8)
-        sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=4,
-                                              track_ids=False, exchange_frac=EXF, slack=SLACK,
+        sim = pic.Sim([run], pic.make_options("fp32", tile=(2, 64), tile_split=2, sort_every=4,
+                                              track_ids=False, slack=SLACK,
                                               scheme=scheme, graph=GRAPH))
         for s in range(2):
             sim.load_plasma(0, s, cfg["ppc"], cfg["gamma0"], 0.01, 0)

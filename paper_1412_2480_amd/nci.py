@@ -97,8 +97,7 @@ def run_batch(pic, cases, steps, precision="fp32", spectra_at=None, seed=0, rtol
     power spectrum at the first step with t >= that value."""
     descs = _run_descs(pic, cases, rtol)
     sim = pic.Sim(descs, pic.make_options(precision, tile=tile, track_ids=False, diag_every=1,
-                                          history_cap=steps + 1, slack=1.0,
-                                          exchange_frac=0.5))
+                                          history_cap=steps + 1, slack=1.0))
     for r, c in enumerate(cases):
         for s in range(2):
             sim.load_plasma(r, s, c["ppc"], GAMMA, T_REST, seed + r)

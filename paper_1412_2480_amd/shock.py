@@ -41,7 +41,7 @@ def run(pic, sigma=1.0, t_end=177.0, nx=5650, ny=990, ppc=50, order=2, theta=0.5
     desc = pic.run_desc(nx, ny, DX, sigma, theta, order, [(-Q, Q, ppc), (Q, Q, ppc)],
                         cg_rtol=1e-8, cg_maxit=300, bc="shock")
     sim = pic.Sim([desc], pic.make_options(precision, tile=tile, tile_split=tile_split,
-                                           slack=slack, exchange_frac=0.5, track_ids=False,
+                                           slack=slack, track_ids=False,
                                            solver="learned", precond_slots=learned_pairs,
                                            sort_every=sort_every, graph=True))
     for s in range(2):

@@ -178,8 +178,7 @@ def test_sweep_table_full_length():
         Q = loads.macro_charge(t["gamma0"], t["dx"], t["dx"], t["ppc"])
         descs.append(pic.run_desc(t["nx"], t["ny"], t["dx"], t["cfl"], t["theta"], t["order"],
                                   [(-Q, Q, t["ppc"]), (Q, Q, t["ppc"])], cg_rtol=1e-8))
-    sim = pic.Sim(descs, pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=8,
-                                          exchange_frac=0.5, slack=0.5, track_ids=False,
+    sim = pic.Sim(descs, pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=8, slack=0.5, track_ids=False,
                                           graph=True))
     for r, t in enumerate(table):
         for s in range(2):

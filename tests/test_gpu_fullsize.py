@@ -2,11 +2,11 @@
 
 * The benchmark workload (periodic 1024 x 256, pair plasma at gamma0 = 40,
   64 particles/cell/species, cubic shape, CFL 1, theta 0.6, FP32 particle
-  path, in the launch configurations bench.py picks after tuning: 4 x 32
-  tiles, two work-groups per tile, particles reordered by cell (here every 2
-  steps, so that the measured step starts from a reordered store and ends
-  with a reordering), inboxes of half the tile slots and slack 0.5; and
-  16 x 32 tiles, one work-group per tile, without reordering): a sample of
+  path, in the launch configurations bench.py's tuner picks among: 2 x 64
+  and 4 x 32 tiles, two work-groups per tile, particles reordered by cell
+  (here every 2 steps, so that the measured step starts from a reordered
+  store and ends with a reordering), slack 0.5; and 16 x 32 tiles, one
+  work-group per tile, without reordering): a sample of
   particles pushed one by one, the
   current on sampled node boxes from the particles that can reach them, and
   the field solve on the whole grid from the GPU's own current.
@@ -34,9 +34,9 @@ def _say(m):
     sys.stdout.flush()
 
 
-@pytest.mark.parametrize("tile,split,sort_every,exf,slack",
-                         [((4, 32), 2, 2, 0.5, 0.5), ((16, 32), 1, 0, 0.25, 0.25)])
-def test_fullsize_fp32_step_sampled_parity(tile, split, sort_every, exf, slack):
+@pytest.mark.parametrize("tile,split,sort_every,slack",
+                         [((2, 64), 2, 2, 0.5), ((4, 32), 2, 2, 0.5), ((16, 32), 1, 0, 0.25)])
+def test_fullsize_fp32_step_sampled_parity(tile, split, sort_every, slack):
     import paper_1412_2480_amd as pic
     from synth import loads
     _say(f"fullsize: generating load (tile {tile}, sort_every {sort_every})")
@@ -44,7 +44,7 @@ def test_fullsize_fp32_step_sampled_parity(tile, split, sort_every, exf, slack):
     ld = loads.pair_plasma_cells(NX, NY, PPC, G0, 0.01, seed=0)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
     sim = pic.Sim([run], pic.make_options("fp32", tile=tile, tile_split=split,
-                                          sort_every=sort_every, exchange_frac=exf, slack=slack))
+                                          sort_every=sort_every, slack=slack))
     for s in range(2):
         d = ld[s]
         sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
@@ -141,8 +141,7 @@ def test_fullsize_shock_fp32_learned():
     ld = loads.shock_load(x_out, ny, ppc, g0, 0.01, 0)
     run = pic.run_desc(nx, ny, DX, 1.0, 0.6, 2, [(-Q, Q, ppc), (Q, Q, ppc)], cg_rtol=1e-8,
                        bc="shock")
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 32), tile_split=1, slack=1.5,
-                                          exchange_frac=0.5, track_ids=False, solver="learned",
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(16, 32), tile_split=1, slack=1.5, track_ids=False, solver="learned",
                                           precond_slots=4))
     for s in range(2):
         d = ld[s]
@@ -207,8 +206,7 @@ def test_fullsize_tuned_schedule_full_length():
     from synth import loads
     Q = loads.macro_charge(G0, DX, DX, PPC)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=3,
-                                          exchange_frac=0.5, slack=0.5, track_ids=False,
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, sort_every=3, slack=0.5, track_ids=False,
                                           graph=True,
                                           solver="learned", precond_slots=8, diag_every=250,
                                           history_cap=16))

@@ -66,10 +66,13 @@ def test_large_share_fullsize_fp32():
     NX, NY, PPC, G0, ORDER, T, SEED = 8192, 2048, 64, 40.0, 3, 0.01, 0
     Q = loads.macro_charge(G0, DX, DX, PPC)
     run = pic.run_desc(NX, NY, DX, 1.0, 0.6, ORDER, [(-Q, Q, PPC), (Q, Q, PPC)], cg_rtol=1e-8)
-    # the learned aid as the timed configuration uses it: plain CG first,
-    # recording training pairs, then the trained network
-    opts = pic.make_options("fp32", tile=(16, 32), tile_split=1, track_ids=False,
-                            solver="learned", precond_slots=4)
+    # the launch configuration and the learned aid as the timed form uses
+    # them (2 x 64 tiles, one work-group per tile, reordering every 4 steps,
+    # slack 0.5; plain CG first, recording training pairs, then the trained
+    # network): the fourth step ends with a reordering, so the learned step
+    # runs on a reordered store
+    opts = pic.make_options("fp32", tile=(2, 64), tile_split=1, track_ids=False,
+                            solver="learned", precond_slots=4, sort_every=4, slack=0.5)
     _say(f"large share: workspace {pic.plan([run], opts).workspace_bytes / 1e9:.1f} GB")
     sim = pic.Sim([run], opts)
     _say(f"large share: context created ({sim.L.pic_last_error(sim.ctx).decode() or 'ok'})")

@@ -63,7 +63,7 @@ class Shock:
                            [(-self.Q, self.Q, self.ppc), (self.Q, self.Q, self.ppc)],
                            cg_rtol=self.rtol if rtol is None else rtol, cg_maxit=self.maxit,
                            bc="shock")
-        sim = pic.Sim([run], pic.make_options(precision, slack=2.0, exchange_frac=0.5, **opt))
+        sim = pic.Sim([run], pic.make_options(precision, slack=2.0, **opt))
         for s, d in enumerate(self.load):
             sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
                                d["uz"])
@@ -212,7 +212,7 @@ def test_device_inflow_matches_host_slabs(precision):
     run = pic.run_desc(case.nx, case.ny, 0.1, case.cfl, case.theta, case.order,
                        [(-case.Q, case.Q, case.ppc), (case.Q, case.Q, case.ppc)], bc="shock")
     # no initial load: every particle of the run comes from the inflow
-    sim = pic.Sim([run], pic.make_options(precision, slack=2.0, exchange_frac=0.5))
+    sim = pic.Sim([run], pic.make_options(precision, slack=2.0))
     sim.set_inflow(0, case.ppc, case.gamma0, case.T, case.seed)
     # FP64: transcendental functions of the momentum draw differ in the last
     # bits between the device and numpy; FP32: the particle precision

@@ -34,8 +34,7 @@ def test_shock_10000_steps_learned():
     # the shock compresses the flow behind it and the reflected beam adds to
     # that: with 5x the upstream slots a tile near the wall overflowed near
     # step 6000, so tiles get 10x
-    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, slack=9.0,
-                                          exchange_frac=0.5, track_ids=False, solver="learned",
+    sim = pic.Sim([run], pic.make_options("fp32", tile=(4, 32), tile_split=2, slack=9.0, track_ids=False, solver="learned",
                                           precond_slots=16, sort_every=4, graph=True))
     for s in range(2):
         sim.load_plasma(0, s, ppc, g0, T, seed=0, direction=-1, x_cells=x_out)

@@ -44,7 +44,7 @@ def _run(golden, solver, train_after=0, **opt):
     Q = golden["macro_charge"]
     run = pic.run_desc(c["nx"], c["ny"], c["dx"], c["cfl"], c["theta"], c["order"],
                        [(-Q, Q, c["ppc"]), (Q, Q, c["ppc"])], cg_rtol=c["rtol"])
-    kw = dict(slack=1.0, exchange_frac=0.5)
+    kw = dict(slack=1.0)
     kw.update(opt)
     opts = pic.make_options("fp32", diag_every=1, history_cap=c["steps"] + 1, solver=solver,
                             precond_slots=8, **kw)
