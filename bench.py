@@ -105,8 +105,31 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
                 h.update(f.read())
         if h.hexdigest() != rec["sources_sha256"]:
             continue
-        return rec["traffic_bytes"], os.path.relpath(path, ROOT)
+        return rec, os.path.relpath(path, ROOT)
     return None, None
+
+
+# issue ceiling of the vector ALU: a wave64 instruction occupies a 16-lane
+# SIMD for 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz (packed FP32 is not used)
+VALU_CYCLES_PER_INST, N_SIMD, CLOCK_HZ = 4, 1024, 2.4e9
+
+
+def ceilings(rec, n_particles, launch_ms):
+    """The particle kernel against its issue and LDS ceilings, from the
+    instruction counts of the counter record (which are fixed by the kernel's
+    code and the particle count) and the live launch time."""
+    if rec is None or "valu_instructions_per_wavefront_of_64_particles" not in rec:
+        return None
+    vpw = rec["valu_instructions_per_wavefront_of_64_particles"]
+    valu_ms = n_particles / 64 * vpw * VALU_CYCLES_PER_INST / (N_SIMD * CLOCK_HZ) * 1e3
+    return {"valu_issue": {"ms": valu_ms, "frac": valu_ms / launch_ms,
+                           "instructions_per_wavefront": vpw},
+            "lds": {"active_fraction_counted": rec["lds_active_fraction"],
+                    "instructions_per_wavefront": rec["lds_instructions_per_wavefront_of_64_particles"]},
+            "note": "VALU: the counted instructions at one wave64 instruction per SIMD every 4 "
+                    "cycles; LDS: cycles with the LDS pipe active over the kernel's cycles "
+                    "(SQ_LDS_IDX_ACTIVE per CU / SQ_BUSY_CYCLES per shader engine), counted "
+                    "on the same launches as the traffic"}
 
 
 GRAPH = True    # pic_step replays captured two-step HIP graphs (--no-graph: plain launches)
@@ -814,8 +837,9 @@ def main():
     n_part = h["particles"]
     alg = BYTES_PER_PARTICLE["fp32"] * n_part
     achieved = alg / (t["push_ms"] * 1e-3) / 1e9
-    traffic, traffic_src = measured_traffic("fp32", C5_TILE, C5_SPLIT, C5["order"], n_part,
-                                            C5_SORT, args.warmup)
+    rec, traffic_src = measured_traffic("fp32", C5_TILE, C5_SPLIT, C5["order"], n_part,
+                                        C5_SORT, args.warmup)
+    traffic = None if rec is None else rec["traffic_bytes"]
     line = {
         "metric": "particle-steps/s + field-solve ms/step; FP32+learned vs plain FP64, same GPU",
         "value": t["particle_steps_per_s"],
@@ -840,7 +864,8 @@ def main():
                      "traffic_unit": "bytes per launch", "traffic_source": traffic_src,
                      "bytes_per_particle_step": BYTES_PER_PARTICLE["fp32"],
                      "algorithmic_bytes_per_launch": alg, "avg_launch_ms": t["push_ms"],
-                     "launches_timed": t["push_launches"]},
+                     "launches_timed": t["push_launches"],
+                     "ceilings": ceilings(rec, n_part, t["push_ms"])},
         "headline": h,
         "cpu_baseline": cpu,
     }
