@@ -19,7 +19,6 @@ within a factor 2 for the two species).
 """
 import argparse
 import json
-import math
 import sys
 import time
 
@@ -31,10 +30,14 @@ DX = 0.1
 
 
 def run(pic, sigma=1.0, t_end=177.0, nx=5650, ny=990, ppc=50, order=2, theta=0.501,
-        gamma0=GAMMA, T=T_FLOW, slack=4.0, precision="fp32", learned_pairs=8,
-        profile_times=(), tile=(4, 32), tile_split=2, sort_every=4, log=None):
+        gamma0=GAMMA, T=T_FLOW, slack=5.0, precision="fp32", learned_pairs=8,
+        profile_times=(), tile=(2, 66), tile_split=1, sort_every=8, log=None):
     """One shock run to omega_pe t = t_end; returns the profiles at t_end
-    (and at each of profile_times), particle counts and timings."""
+    (and at each of profile_times), particle counts and timings. The tile
+    height should divide ny (990 = 15 x 66): tile slots are sized for the
+    largest tile, and a last tile that absorbs a tail is taller. The shocked
+    plasma behind the front is about three times denser than the flow, and
+    filaments add to that: tiles get 6x the flow's particles (slack 5)."""
     from synth import loads
     x_out = nx - pic.PIC_WALL_GAP
     Q = loads.macro_charge(gamma0, DX, DX, ppc)
