@@ -77,13 +77,15 @@ def _upstream_b2(r):
 def test_cfl_one_keeps_the_upstream_quieter():
     """Sec. 4 runs the shock at CFL 0.5 and 1.0 and finds the flow ahead of
     the shock polluted by numerical Cherenkov radiation at 0.5 and not at 1.0:
-    the magnetic energy of the upstream flow is lower at CFL 1.0."""
+    the magnetic energy of the upstream flow is lower at CFL 1.0. The box is
+    the paper's length over 2.5 (226 c/omega_pe), so that 120 c/omega_pe of
+    flow lie ahead of the front at t = 177."""
     import paper_1412_2480_amd as pic
     from paper_1412_2480_amd import shock
     out = {}
     for sigma in (0.5, 1.0):
-        _say(f"paper shock set-up at 1130 x 198, sigma {sigma}")
-        r = shock.run(pic, sigma=sigma, t_end=177.0, nx=1130, ny=198, ppc=50, tile=(2, 66))
+        _say(f"paper shock set-up at 2260 x 198, sigma {sigma}")
+        r = shock.run(pic, sigma=sigma, t_end=177.0, nx=2260, ny=198, ppc=50, tile=(2, 66))
         p = r["profiles"][max(r["profiles"])]
         r["shock_front_x"] = shock.shock_front(p["electron_density"], p["x"])
         out[sigma] = _upstream_b2(r)
