@@ -341,10 +341,13 @@ NET_FLOP_PER_CELL = 2 * 9 * (1 * 32 + 32 * 32 + 32 * 1)   # three 3x3 layers, 1-
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def net_rate(pic, torch, cfg, reps=20):
-    """Application rate of the learned network N on one field of the workload
-    grid: the BF16 matrix-core form (19,584 FLOP per cell) against the bf16
-    dense peak, and the collapsed 7x7 form (98 FLOP per cell)."""
+def net_rate(pic, torch, cfg, reps=10):
+    """Application rate of the learned network N on one field of the headline
+    grid (16.8M cells): the BF16 matrix-core form (19,584 FLOP per cell)
+    against the bf16 dense peak, and the collapsed 7x7 form (98 FLOP per
+    cell). Timed with HIP events on the context's stream around the calls (a
+    call ends with the library's stream synchronisation, a few microseconds
+    against milliseconds of kernel time at this size)."""
     import ctypes
     run = pic.run_desc(cfg["nx"], cfg["ny"], 0.1, cfg["cfl"], cfg["theta"], cfg["order"],
                        [(-1.0, 1.0, 1), (1.0, 1.0, 1)])
@@ -361,15 +364,20 @@ def net_rate(pic, torch, cfg, reps=20):
             if rc != 0:
                 raise RuntimeError("pic_precond_apply failed")
         call()
-        t0 = time.perf_counter()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(sim.stream)
         for _ in range(reps):
             call()
-        ms = (time.perf_counter() - t0) * 1e3 / reps
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
         cells = cfg["nx"] * cfg["ny"]
         flop = (NET_FLOP_PER_CELL if name == "mfma" else 2 * 49) * cells
         out[name] = dict(ms_per_application=ms, tflops=flop / (ms * 1e-3) / 1e12)
     out["mfma"]["frac_of_bf16_peak"] = out["mfma"]["tflops"] / MFMA_BF16_PEAK_TFLOPS
-    out["note"] = "one field per call, call includes the library's stream synchronisation"
+    out["grid"] = [cfg["nx"], cfg["ny"]]
+    out["note"] = "one field per call, HIP events on the context stream"
     sim.close()
     return out
 
@@ -638,7 +646,7 @@ def c2_legs(pic, torch, args, learned):
     log(f"bench: c2 FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
         f"{fast_cg['field_solve_ms']:.3f} ms, iters {fast_cg['cg_iters']}")
     mfma = None
-    if args.also_mfma and learned is not None:
+    if not args.no_mfma and learned is not None:
         mfma = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split,
                          dict(learned, form="mfma"))
         log(f"bench: c2 FP32 + learned (mfma) {mfma['ms_per_step']:.3f} ms/step, field solve "
@@ -769,8 +777,8 @@ def main():
     ap.add_argument("--no-nci", action="store_true",
                     help="skip the paper's numerical-Cherenkov scans (Sec. 3)")
     ap.add_argument("--learned-form", default="collapsed", choices=["collapsed", "mfma"])
-    ap.add_argument("--also-mfma", action="store_true",
-                    help="also time the 1024x256 FP32 form with the BF16 matrix-core network")
+    ap.add_argument("--no-mfma", action="store_true",
+                    help="skip the 1024x256 leg with the network applied on the matrix cores")
     ap.add_argument("--no-autotune", action="store_true",
                     help="fixed schedules for the 1024x256 legs instead of the autotuner")
     ap.add_argument("--no-graph", action="store_true",
@@ -834,8 +842,7 @@ def main():
         if not args.no_shock:
             legs["shock"] = run_leg("shock workload",
                                     lambda: shock_share(pic, torch, (4, 32), 2))
-        legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch,
-                                                                       CONFIGS["c2"]))
+        legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch, C5))
         if not args.no_nci:
             legs["nci_scans"] = run_leg("NCI scans", lambda: nci_scans(pic, torch))
     cpu = None
