@@ -867,7 +867,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 particles, f64 fields/CG, learned aid (" + args.learned_form + ")",
+        "dtype": "f32/f64",
+        "dtype_detail": "f32 particle state and gather/push/deposit arithmetic, f64 current "
+                        "accumulation, fields, CG and diagnostics; learned aid ("
+                        + args.learned_form + ")",
         "data": "synthetic (seeded Maxwell-Juettner pair plasma, loaded on the device)",
         "config": {"workload": C5["label"], "particles": n_part, "cells": C5["nx"] * C5["ny"],
                    "tile": list(C5_TILE), "tile_split": C5_SPLIT, "sort_every": C5_SORT,
