@@ -148,9 +148,18 @@ typedef struct pic_options {
                             values; periodic runs, solver PIC_SOLVER_CG, and the Courant
                             condition cfl^2 (1 + dx^2/dy^2) <= 1 (dispersion Eq. (16));
                             theta and the CG fields are not used */
+  int32_t gather;        /* field interpolation to the particles: PIC_GATHER_NODAL, the
+                            momentum-conserving interpolation of Sec. 1 and Sec. 3
+                            (Birdsall & Langdon ch. 8: every component averaged from its
+                            Yee points onto the charge nodes, then interpolated with the
+                            charge-assignment weights; the default), or
+                            PIC_GATHER_STAGGERED (each component from its own Yee points
+                            with the same weights; an alternative reading, kept for
+                            comparison) */
 } pic_options;
 
 enum pic_cg_x0 { PIC_X0_ZERO = 0, PIC_X0_PREV = 1 };
+enum pic_gather { PIC_GATHER_NODAL = 0, PIC_GATHER_STAGGERED = 1 };
 enum pic_field_scheme { PIC_SCHEME_IMPLICIT = 0, PIC_SCHEME_EXPLICIT = 1 };
 
 typedef struct pic_plan_info {

@@ -134,10 +134,19 @@ class Particles:
         return (self.iy + self.fy) * dy
 
 
-def gather(nx, ny, order, fields6, p):
+GATHER_MODES = ("nodal", "staggered")
+
+
+def gather(nx, ny, order, fields6, p, mode="nodal"):
+    """E, B at the particles: "nodal" (the method's momentum-conserving
+    interpolation: fields averaged onto the charge nodes, then the
+    charge-assignment weights) or "staggered" (each component from its own
+    Yee points)."""
+    assert mode in GATHER_MODES
     out = np.zeros(6 * p.n)
-    lib().ora_gather(nx, ny, order, _dpp(fields6), ctypes.c_int64(p.n), _i(p.ix), _i(p.iy),
-                     _d(p.fx), _d(p.fy), _d(out))
+    fn = lib().ora_gather_nodal if mode == "nodal" else lib().ora_gather
+    fn(nx, ny, order, _dpp(fields6), ctypes.c_int64(p.n), _i(p.ix), _i(p.iy),
+       _d(p.fx), _d(p.fy), _d(out))
     return out.reshape(6, p.n)
 
 
@@ -224,10 +233,12 @@ def div_b(nx, ny, dx, dy, bx, by):
 
 # ---- shock set-up: conducting walls at x = 0 and x = (nx-1) dx, reflection
 # at x = 0, outflow/injection at x = (nx - WALL_GAP) dx (see oracle.h)
-def gather_wall(nx, ny, order, fields6, p):
+def gather_wall(nx, ny, order, fields6, p, mode="nodal"):
+    assert mode in GATHER_MODES
     out = np.zeros(6 * p.n)
-    lib().ora_gather_wall(nx, ny, order, _dpp(fields6), ctypes.c_int64(p.n), _i(p.ix),
-                          _i(p.iy), _d(p.fx), _d(p.fy), _d(out))
+    fn = lib().ora_gather_nodal_wall if mode == "nodal" else lib().ora_gather_wall
+    fn(nx, ny, order, _dpp(fields6), ctypes.c_int64(p.n), _i(p.ix), _i(p.iy), _d(p.fx),
+       _d(p.fy), _d(out))
     return out.reshape(6, p.n)
 
 
@@ -308,10 +319,12 @@ class Sim:
     bc: "periodic" (both directions) or "shock" (walls in x, see oracle.h).
     scheme: "implicit" (Eqs. (5)-(7), the paper's solver) or "explicit"
     (the Yee FDTD of Eqs. (3)-(4), periodic only; theta is not used).
+    gather: "nodal" (the method's momentum-conserving interpolation) or
+    "staggered" (the alternative reading, see gather()).
     """
 
     def __init__(self, nx, ny, dx, dy, cfl, theta, order, species, rtol=1e-8, maxit=200,
-                 bc="periodic", scheme="implicit"):
+                 bc="periodic", scheme="implicit", gather="nodal"):
         self.nx, self.ny, self.dx, self.dy = nx, ny, float(dx), float(dy)
         self.dt = cfl * dx        # sigma = c dt/dx with c = 1 (Sec. 3.1)
         self.theta, self.order = float(theta), int(order)
@@ -322,6 +335,8 @@ class Sim:
         assert scheme == "implicit" or bc == "periodic"
         self.bc = bc
         self.scheme = scheme
+        assert gather in GATHER_MODES
+        self.gather = gather
         self.next_id = [p.n for p in species]
         self.E = [np.zeros((ny, nx)) for _ in range(3)]
         self.B = [np.zeros((ny, nx)) for _ in range(3)]
@@ -349,7 +364,8 @@ class Sim:
         wk_minus = wk_plus = 0.0
         for p in self.species:
             wk_minus += kinetic(p)
-            f = (gather_wall if wall else gather)(nx, ny, self.order, self.E + self.B, p)
+            f = (gather_wall if wall else gather)(nx, ny, self.order, self.E + self.B, p,
+                                                  self.gather)
             boris(p, dt, f[0:3], f[3:6])
             wk_plus += kinetic(p)
             old = p.copy()

@@ -71,10 +71,10 @@ double ora_shape(int order, double d) {
 static const double STAG_X[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
 static const double STAG_Y[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
 
-/* Momentum-conserving gather (Sec. 1; Sec. 3 first paragraph): field value at
- * the particle = sum over the component's own grid points of
- * F(i+sx, j+sy) * S(X - i - sx) * S(Y - j - sy). The window i in
- * [ix-2, ix+2] contains the support of every order for both staggers. */
+/* Staggered gather (the alternative reading of the interpolation, kept for
+ * comparison): field value at the particle = sum over the component's own
+ * grid points of F(i+sx, j+sy) * S(X - i - sx) * S(Y - j - sy). The window i
+ * in [ix-2, ix+2] contains the support of every order for both staggers. */
 void ora_gather(int nx, int ny, int order, const double* const* f6,
                 int64_t np, const int32_t* ix, const int32_t* iy,
                 const double* fx, const double* fy, double* out6) {
@@ -92,6 +92,66 @@ void ora_gather(int nx, int ny, int order, const double* const* f6,
       out6[(int64_t)c * np + k] = sum;
     }
   }
+}
+
+/* Momentum-conserving gather in the sense of Birdsall & Langdon ch. 8 (the
+ * reading adopted for the paper's method, Sec. 1 and Sec. 3): the force is
+ * interpolated from the charge nodes with the charge-assignment weights, so
+ * every component is first averaged from its Yee points onto the node (i, j):
+ *   Ex, By (half-integer x): (F(i-1, j) + F(i, j)) / 2
+ *   Ey, Bx (half-integer y): (F(i, j-1) + F(i, j)) / 2
+ *   Ez (node):               F(i, j)
+ *   Bz (half-integer x, y):  (F(i-1, j-1) + F(i, j-1) + F(i-1, j) + F(i, j)) / 4
+ * and then interpolated as sum_{i,j} N(i, j) S(X - i) S(Y - j). fetch gives the
+ * Yee value at any (i, j) (periodic wrap, or the conductor images). */
+typedef double (*ora_fetch)(int nx, int ny, const double* f, int c, int i, int j);
+
+static double node_value(int nx, int ny, const double* f, int c, int i, int j, ora_fetch get) {
+  switch (c) {
+    case 0:
+    case 4:
+      return 0.5 * (get(nx, ny, f, c, i - 1, j) + get(nx, ny, f, c, i, j));
+    case 1:
+    case 3:
+      return 0.5 * (get(nx, ny, f, c, i, j - 1) + get(nx, ny, f, c, i, j));
+    case 2:
+      return get(nx, ny, f, c, i, j);
+    default:
+      return 0.25 * (get(nx, ny, f, c, i - 1, j - 1) + get(nx, ny, f, c, i, j - 1) +
+                     get(nx, ny, f, c, i - 1, j) + get(nx, ny, f, c, i, j));
+  }
+}
+
+static double periodic_field(int nx, int ny, const double* f, int c, int i, int j) {
+  (void)c;
+  return f[at(nx, ny, i, j)];
+}
+
+static void gather_nodal(int nx, int ny, int order, const double* const* f6, int64_t np,
+                         const int32_t* ix, const int32_t* iy, const double* fx,
+                         const double* fy, double* out6, ora_fetch get) {
+#pragma omp parallel for schedule(static) if (np >= ORA_PAR_MIN)
+  for (int64_t k = 0; k < np; ++k) {
+    for (int c = 0; c < 6; ++c) {
+      double sum = 0.0;
+      for (int j = iy[k] - 2; j <= iy[k] + 2; ++j) {
+        double wy = ora_shape(order, (double)(iy[k] - j) + fy[k]);
+        if (wy == 0.0) continue;
+        for (int i = ix[k] - 2; i <= ix[k] + 2; ++i) {
+          double wx = ora_shape(order, (double)(ix[k] - i) + fx[k]);
+          if (wx == 0.0) continue;
+          sum += node_value(nx, ny, f6[c], c, i, j, get) * wx * wy;
+        }
+      }
+      out6[(int64_t)c * np + k] = sum;
+    }
+  }
+}
+
+void ora_gather_nodal(int nx, int ny, int order, const double* const* f6,
+                      int64_t np, const int32_t* ix, const int32_t* iy,
+                      const double* fx, const double* fy, double* out6) {
+  gather_nodal(nx, ny, order, f6, np, ix, iy, fx, fy, out6, periodic_field);
 }
 
 /* Relativistic Boris push, c = 1:
@@ -572,6 +632,12 @@ void ora_gather_wall(int nx, int ny, int order, const double* const* f6,
       out6[(int64_t)c * np + k] = sum;
     }
   }
+}
+
+void ora_gather_nodal_wall(int nx, int ny, int order, const double* const* f6,
+                           int64_t np, const int32_t* ix, const int32_t* iy,
+                           const double* fx, const double* fy, double* out6) {
+  gather_nodal(nx, ny, order, f6, np, ix, iy, fx, fy, out6, wall_field);
 }
 
 /* add v to component c (0 Jx, 1 Jy, 2 Jz, 3 rho) at column i, folding a

@@ -41,9 +41,18 @@ int ora_get_threads(void);
 double ora_shape(int order, double d);
 
 /* Momentum-conserving gather (Sec. 1 and Sec. 3, citing Birdsall & Langdon
- * ch. 8): every field component is interpolated from its own staggered
- * points with the same order-p shape in x and y as the charge assignment.
- * f6 = {Ex, Ey, Ez, Bx, By, Bz}, each [ny][nx]. out6[c*np + k]. */
+ * ch. 8), the method's reading: the force is interpolated from the charge
+ * nodes with the charge-assignment weights, every component first averaged
+ * from its Yee points onto the nodes (Ex, By along x; Ey, Bx along y; Bz over
+ * the four surrounding points; Ez is a node value). f6 = {Ex, Ey, Ez, Bx, By,
+ * Bz}, each [ny][nx]. out6[c*np + k]. */
+void ora_gather_nodal(int nx, int ny, int order, const double* const* f6,
+                      int64_t np, const int32_t* ix, const int32_t* iy,
+                      const double* fx, const double* fy, double* out6);
+
+/* The alternative reading, kept for comparison: every field component is
+ * interpolated from its own staggered points with the same order-p shape in
+ * x and y as the charge assignment (no averaging onto the nodes). */
 void ora_gather(int nx, int ny, int order, const double* const* f6,
                 int64_t np, const int32_t* ix, const int32_t* iy,
                 const double* fx, const double* fy, double* out6);
@@ -129,6 +138,11 @@ void ora_div_b(int nx, int ny, double dx, double dy, const double* bx, const dou
 void ora_gather_wall(int nx, int ny, int order, const double* const* f6,
                      int64_t np, const int32_t* ix, const int32_t* iy,
                      const double* fx, const double* fy, double* out6);
+
+/* the node-averaged gather with the same conductor images */
+void ora_gather_nodal_wall(int nx, int ny, int order, const double* const* f6,
+                           int64_t np, const int32_t* ix, const int32_t* iy,
+                           const double* fx, const double* fy, double* out6);
 
 /* Esirkepov deposit of the unreflected displacement; columns behind the wall
  * fold onto their mirrors (rho, Jy, Jz with their sign, Jx negated) */

@@ -25,6 +25,7 @@ NET_NW = 9792
 PIC_BC_PERIODIC, PIC_BC_SHOCK = 0, 1
 PIC_X0_ZERO, PIC_X0_PREV = 0, 1
 PIC_SCHEME_IMPLICIT, PIC_SCHEME_EXPLICIT = 0, 1
+PIC_GATHER_NODAL, PIC_GATHER_STAGGERED = 0, 1
 PIC_WALL_GAP = 4
 FIELD_IDS = {"Ex": 0, "Ey": 1, "Ez": 2, "Bx": 3, "By": 4, "Bz": 5, "Jx": 6, "Jy": 7, "Jz": 8,
              "rho": 9, "n0": 10, "n1": 11}
@@ -64,7 +65,8 @@ class Options(ctypes.Structure):
                 ("tile_split", ctypes.c_int32), ("learned_form", ctypes.c_int32),
                 ("learned_maxit", ctypes.c_int32), ("precond_slots", ctypes.c_int32),
                 ("graph", ctypes.c_int32), ("sort_every", ctypes.c_int32),
-                ("cg_x0", ctypes.c_int32), ("field_scheme", ctypes.c_int32)]
+                ("cg_x0", ctypes.c_int32), ("field_scheme", ctypes.c_int32),
+                ("gather", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -231,10 +233,12 @@ def run_desc(nx, ny, dx, cfl, theta, order, species, dy=None, cg_rtol=1e-8, cg_m
 def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25,
                  diag_every=0, history_cap=1, cg_blocks=0, track_ids=True, tile_split=0,
                  solver="cg", learned_form="collapsed", learned_maxit=0, precond_slots=0,
-                 graph=False, sort_every=0, cg_x0="zero", scheme="implicit"):
+                 graph=False, sort_every=0, cg_x0="zero", scheme="implicit", gather="nodal"):
     """solver: "cg" or "learned"; learned_form: "collapsed" or "mfma";
     cg_x0: "zero" or "prev" (plain CG from the previous step's dB);
-    scheme: "implicit" (Eqs. (5)-(7)) or "explicit" (Yee FDTD, Eqs. (3)-(4))."""
+    scheme: "implicit" (Eqs. (5)-(7)) or "explicit" (Yee FDTD, Eqs. (3)-(4));
+    gather: "nodal" (momentum-conserving: fields averaged onto the charge nodes,
+    the default) or "staggered" (each component from its own Yee points)."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
     o.solver = PIC_SOLVER_LEARNED_PCG if solver in ("learned", PIC_SOLVER_LEARNED_PCG) \
@@ -248,6 +252,10 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     o.cg_x0 = PIC_X0_PREV if cg_x0 in ("prev", PIC_X0_PREV) else PIC_X0_ZERO
     o.field_scheme = PIC_SCHEME_EXPLICIT if scheme in ("explicit", PIC_SCHEME_EXPLICIT) \
         else PIC_SCHEME_IMPLICIT
+    if gather not in ("nodal", "staggered", PIC_GATHER_NODAL, PIC_GATHER_STAGGERED):
+        raise ValueError(f"gather must be 'nodal' or 'staggered', not {gather!r}")
+    o.gather = PIC_GATHER_STAGGERED if gather in ("staggered", PIC_GATHER_STAGGERED) \
+        else PIC_GATHER_NODAL
     o.tile_x, o.tile_y = int(tile[0]), int(tile[1])
     o.slack, o.exchange_frac = float(slack), float(exchange_frac)
     o.diag_every, o.history_cap = int(diag_every), int(history_cap)

@@ -193,6 +193,10 @@ int validate(const pic_run_desc* runs, int n_runs, const pic_options* o, std::st
     *msg = "sort_every must be >= 0";
     return PIC_E_INVAL;
   }
+  if (o->gather != PIC_GATHER_NODAL && o->gather != PIC_GATHER_STAGGERED) {
+    *msg = "gather must be PIC_GATHER_NODAL or PIC_GATHER_STAGGERED";
+    return PIC_E_INVAL;
+  }
   if (o->field_scheme != PIC_SCHEME_IMPLICIT && o->field_scheme != PIC_SCHEME_EXPLICIT) {
     *msg = "field_scheme must be PIC_SCHEME_IMPLICIT or PIC_SCHEME_EXPLICIT";
     return PIC_E_INVAL;
@@ -1274,6 +1278,7 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
     carve<double>(c->ws, c->tl, c->plan, n_runs, false, c->split, c->ids, c->opt.history_cap,
                   c->pair_slots, net_cells, ic, c, &c->sd);
   c->next_id.assign(n_runs, std::array<long long, PIC_MAXS>{0, 0});
+  c->sf.nodal = c->sd.nodal = opt->gather == PIC_GATHER_NODAL ? 1 : 0;
   c->fa.learned_form = opt->learned_form;
   c->fa.cg_x0 = opt->cg_x0 == PIC_X0_PREV ? 1 : 0;
   c->fa.explicit_fdtd = opt->field_scheme == PIC_SCHEME_EXPLICIT ? 1 : 0;

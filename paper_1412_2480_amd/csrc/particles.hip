@@ -153,7 +153,7 @@ __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
   return slot;
 }
 
-template <typename R, typename F, int P, int MODE, bool DIAG>
+template <typename R, typename F, int P, int MODE, bool DIAG, bool NODAL>
 __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, int tx, int ty,
                           int x0, int y0, int tw, int th, const F* sF, double* sJ, int part,
                           int sel, double (&wk)[PIC_MAXS][2]) {
@@ -231,18 +231,30 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
         }
 
         if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
-          // ---- gather (each component from its own staggered points)
-          R whx[P + 1], why[P + 1];
-          const int fhx = bspline_weights<P, R>(fx - R(0.5), whx);
-          const int fhy = bspline_weights<P, R>(fy - R(0.5), why);
+          // ---- gather: NODAL, every component from the charge nodes (staged
+          // node averages) with the charge-assignment weights; otherwise each
+          // component from its own staggered points
           const int gx0 = lx + f0x + G, gy0 = ly + f0y + G;
-          const int gxh = lx + fhx + G, gyh = ly + fhy + G;
-          const R ex = interp<P, R, F>(sF + 0 * plane, PW, gxh, gy0, whx, w0y);
-          const R ey = interp<P, R, F>(sF + 1 * plane, PW, gx0, gyh, w0x, why);
-          const R ez = interp<P, R, F>(sF + 2 * plane, PW, gx0, gy0, w0x, w0y);
-          const R bx = interp<P, R, F>(sF + 3 * plane, PW, gx0, gyh, w0x, why);
-          const R by = interp<P, R, F>(sF + 4 * plane, PW, gxh, gy0, whx, w0y);
-          const R bz = interp<P, R, F>(sF + 5 * plane, PW, gxh, gyh, whx, why);
+          R ex, ey, ez, bx, by, bz;
+          if constexpr (NODAL) {
+            ex = interp<P, R, F>(sF + 0 * plane, PW, gx0, gy0, w0x, w0y);
+            ey = interp<P, R, F>(sF + 1 * plane, PW, gx0, gy0, w0x, w0y);
+            ez = interp<P, R, F>(sF + 2 * plane, PW, gx0, gy0, w0x, w0y);
+            bx = interp<P, R, F>(sF + 3 * plane, PW, gx0, gy0, w0x, w0y);
+            by = interp<P, R, F>(sF + 4 * plane, PW, gx0, gy0, w0x, w0y);
+            bz = interp<P, R, F>(sF + 5 * plane, PW, gx0, gy0, w0x, w0y);
+          } else {
+            R whx[P + 1], why[P + 1];
+            const int fhx = bspline_weights<P, R>(fx - R(0.5), whx);
+            const int fhy = bspline_weights<P, R>(fy - R(0.5), why);
+            const int gxh = lx + fhx + G, gyh = ly + fhy + G;
+            ex = interp<P, R, F>(sF + 0 * plane, PW, gxh, gy0, whx, w0y);
+            ey = interp<P, R, F>(sF + 1 * plane, PW, gx0, gyh, w0x, why);
+            ez = interp<P, R, F>(sF + 2 * plane, PW, gx0, gy0, w0x, w0y);
+            bx = interp<P, R, F>(sF + 3 * plane, PW, gx0, gyh, w0x, why);
+            by = interp<P, R, F>(sF + 4 * plane, PW, gxh, gy0, whx, w0y);
+            bz = interp<P, R, F>(sF + 5 * plane, PW, gxh, gyh, whx, why);
+          }
           if constexpr (DIAG)
             wk[s][0] += mass * (sqrt(1.0 + (double)ux * ux + (double)uy * uy +
                                      (double)uz * uz) - 1.0);
@@ -454,7 +466,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
 
 // DIAG: the step records the kinetic energies W_K(n -/+ 1/2) (a compile-time
 // variant, so that the ordinary step carries no FP64 accumulators)
-template <typename R, typename F, int MODE, bool DIAG>
+template <typename R, typename F, int MODE, bool DIAG, bool NODAL>
 __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int sel) {
   // XCD-aware order: consecutive (tile, part) items go to the same XCD
   const int per = gridDim.x / 8;
@@ -479,36 +491,53 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int sel) {
   __shared__ double s_red[4][PIC_MAXS * 2];
 
   if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
-    for (int e = threadIdx.x; e < plane; e += blockDim.x) {
-      const int ly = e / PW - G, lx = e % PW - G;
-      bool in = lx <= tw + PIC_GUARD_HI - 1 && ly <= th + PIC_GUARD_HI - 1;
-      const int gx = x0 + lx;
-      // column read by integer-x (Ey, Ez, Bx) and half-integer-x (Ex, By, Bz)
-      // components; behind a shock run's wall at x = 0 the conductor images
-      // are used: integer-x components odd, half-integer ones even
-      int colI = pic_wrap(gx, run.nx), colH = colI;
-      F signI = F(1);
+    // Yee value of component c at column gx, row gy: periodic wrap, or behind
+    // a shock run's wall at x = 0 the conductor images (integer-x components
+    // Ey, Ez, Bx odd, half-integer ones Ex, By, Bz even); columns at or beyond
+    // the far wall's outside column hold zero
+    auto yee = [&](int c, int gx, int gy) -> F {
+      const bool half = c == 0 || c >= 4;
+      int col = pic_wrap(gx, run.nx);
+      F sign = F(1);
       if (run.bc == 1) {
         if (gx < 0) {
-          colI = -gx;
-          colH = -gx - 1;
-          signI = F(-1);
+          col = half ? -gx - 1 : -gx;
+          if (!half) sign = F(-1);
         } else if (gx >= run.nx) {
-          in = false;
+          return F(0);
         }
       }
-      const long long row = run.cell0 + (long long)pic_wrap(y0 + ly, run.ny) * run.nx;
+      const long long g = run.cell0 + (long long)pic_wrap(gy, run.ny) * run.nx + col;
+      F v;
+      if constexpr (sizeof(F) == 4)
+        v = st.Ef[c][g];
+      else
+        v = (c < 3) ? st.E[c][g] : st.B[c - 3][g];
+      return sign * v;
+    };
+    for (int e = threadIdx.x; e < plane; e += blockDim.x) {
+      const int ly = e / PW - G, lx = e % PW - G;
+      const bool in = lx <= tw + PIC_GUARD_HI - 1 && ly <= th + PIC_GUARD_HI - 1;
+      const int gx = x0 + lx, gy = y0 + ly;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const bool half = c == 0 || c >= 4;
-        const long long g = row + (half ? colH : colI);
         F v = F(0);
         if (in) {
-          if constexpr (sizeof(F) == 4)
-            v = st.Ef[c][g];
-          else
-            v = (c < 3) ? st.E[c][g] : st.B[c - 3][g];
-          if (!half) v *= signI;
+          if constexpr (NODAL) {
+            // momentum-conserving interpolation: the component averaged from
+            // its Yee points onto the charge node (gx, gy)
+            if (c == 0 || c == 4)
+              v = F(0.5) * (yee(c, gx - 1, gy) + yee(c, gx, gy));
+            else if (c == 1 || c == 3)
+              v = F(0.5) * (yee(c, gx, gy - 1) + yee(c, gx, gy));
+            else if (c == 2)
+              v = yee(c, gx, gy);
+            else
+              v = F(0.25) * (yee(c, gx - 1, gy - 1) + yee(c, gx, gy - 1) + yee(c, gx - 1, gy) +
+                             yee(c, gx, gy));
+          } else {
+            v = yee(c, gx, gy);
+          }
         }
         sF[c * plane + e] = v;
       }
@@ -520,13 +549,13 @@ __global__ void __launch_bounds__(256) k_particles(DevState<R> st, int sel) {
   double wk[PIC_MAXS][2] = {{0.0, 0.0}, {0.0, 0.0}};
   switch (run.order) {
     case 1:
-      tile_body<R, F, 1, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
+      tile_body<R, F, 1, MODE, DIAG, NODAL>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
     case 2:
-      tile_body<R, F, 2, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
+      tile_body<R, F, 2, MODE, DIAG, NODAL>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
     default:
-      tile_body<R, F, 3, MODE, DIAG>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
+      tile_body<R, F, 3, MODE, DIAG, NODAL>(st, run, tile, tx, ty, x0, y0, tw, th, sF, sJ, part, sel, wk);
       break;
   }
   __syncthreads();
@@ -974,24 +1003,35 @@ hipError_t pic_launch_particles(const DevState<R>& st, int mode, int diag, int t
   using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
   const size_t smem = pic_particle_smem(st, mode);
   const dim3 grid(grid_tiles(st.n_tiles * st.K)), block(threads);
+  // the gather variant (node-averaged or staggered) is a compile-time choice
+  // of the gathering modes
+  auto gathering = [&](auto mode_c, auto diag_c) {
+    constexpr int M = decltype(mode_c)::value;
+    constexpr bool D = decltype(diag_c)::value;
+    if (st.nodal)
+      k_particles<R, F, M, D, true><<<grid, block, smem, s>>>(st, -1);
+    else
+      k_particles<R, F, M, D, false><<<grid, block, smem, s>>>(st, -1);
+  };
+  using std::integral_constant;
   switch (mode) {
     case MODE_FUSED:
       if (diag)
-        k_particles<R, F, MODE_FUSED, true><<<grid, block, smem, s>>>(st, -1);
+        gathering(integral_constant<int, MODE_FUSED>{}, integral_constant<bool, true>{});
       else
-        k_particles<R, F, MODE_FUSED, false><<<grid, block, smem, s>>>(st, -1);
+        gathering(integral_constant<int, MODE_FUSED>{}, integral_constant<bool, false>{});
       break;
     case MODE_PUSH:
       if (diag)
-        k_particles<R, F, MODE_PUSH, true><<<grid, block, smem, s>>>(st, -1);
+        gathering(integral_constant<int, MODE_PUSH>{}, integral_constant<bool, true>{});
       else
-        k_particles<R, F, MODE_PUSH, false><<<grid, block, smem, s>>>(st, -1);
+        gathering(integral_constant<int, MODE_PUSH>{}, integral_constant<bool, false>{});
       break;
     case MODE_DEPOSIT:
-      k_particles<R, F, MODE_DEPOSIT, false><<<grid, block, smem, s>>>(st, -1);
+      k_particles<R, F, MODE_DEPOSIT, false, false><<<grid, block, smem, s>>>(st, -1);
       break;
     default:
-      k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st, -1);
+      k_particles<R, F, MODE_CHARGE, false, false><<<grid, block, smem, s>>>(st, -1);
       break;
   }
   return hipGetLastError();
@@ -1002,7 +1042,7 @@ hipError_t pic_launch_density(const DevState<R>& st, int species, int threads, h
   using F = typename std::conditional<sizeof(R) == 4, float, double>::type;
   const size_t smem = pic_particle_smem(st, MODE_CHARGE);
   const dim3 grid(grid_tiles(st.n_tiles * st.K)), block(threads);
-  k_particles<R, F, MODE_CHARGE, false><<<grid, block, smem, s>>>(st, species);
+  k_particles<R, F, MODE_CHARGE, false, false><<<grid, block, smem, s>>>(st, species);
   return hipGetLastError();
 }
 

@@ -42,6 +42,7 @@ struct DevState {
   int TX, TY, TXA, TYA, PW, PH;  // tile shape, widest tile, patch pitch/rows
   int tile_slots[PIC_MAXS];
   int K;                          // work-groups per tile (each takes 1/K of its particles)
+  int nodal;                      // 1: gather from node-averaged fields (momentum-conserving)
   const DevRun* runs;
   const int* tile_run;            // run index of each global tile
 

@@ -2,7 +2,7 @@
 of a whole run in which the numerical Cherenkov instability grows from noise
 and saturates, plus the growth rate measured from it.
 
-Run: python tests/golden/make_nci_history.py [128x64|1024x256]
+Run: python tests/golden/make_nci_history.py [128x64|1024x256] [nodal|staggered]
   128x64    about a minute on one CPU core
   1024x256  hours of CPU time: run it with the oracle's OpenMP threads
             (OMP_NUM_THREADS = the host's cores; about half an hour on 8)
@@ -15,6 +15,10 @@ theta = 0.6, field CG to 1e-8, seed 0.
             workload on a smaller grid (same physics per cell);
   1024x256  64 particles/cell/species, 300 steps: the single-run workload
             itself, through the growth and saturation of the instability.
+The gather is the method's node-averaged momentum-conserving interpolation
+("nodal", written to nci_history_<case>_nodal.json) or the staggered
+alternative ("staggered", written to nci_history_<case>.json, the files that
+predate the nodal reading; their case records no "gather" key).
 Only the oracle and the seeded input generator are used.
 """
 import json
@@ -39,15 +43,16 @@ CASES = {
 }
 
 
-def main(name="128x64"):
-    c = CASES[name]
-    out_path = os.path.join(HERE, f"nci_history_{name}.json")
+def main(name="128x64", gather="nodal"):
+    c = dict(CASES[name], gather=gather)
+    suffix = "_nodal" if gather == "nodal" else ""
+    out_path = os.path.join(HERE, f"nci_history_{name}{suffix}.json")
     Q = loads.macro_charge(c["gamma0"], c["dx"], c["dx"], c["ppc"])
     ld = loads.pair_plasma_cells(c["nx"], c["ny"], c["ppc"], c["gamma0"], c["T"], c["seed"])
     sp = [oracle.Particles(d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"], q, Q)
           for d, q in zip(ld, (-Q, Q))]
     sim = oracle.Sim(c["nx"], c["ny"], c["dx"], c["dx"], c["cfl"], c["theta"], c["order"], sp,
-                     rtol=c["rtol"])
+                     rtol=c["rtol"], gather=gather)
     recs = []
     t0 = time.time()
     for n in range(c["steps"]):
@@ -68,4 +73,5 @@ def main(name="128x64"):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "128x64")
+    main(sys.argv[1] if len(sys.argv) > 1 else "128x64",
+         sys.argv[2] if len(sys.argv) > 2 else "nodal")

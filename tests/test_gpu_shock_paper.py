@@ -67,12 +67,13 @@ def test_shock_forms_and_compresses():
 
 
 def _upstream_b2(r):
+    """Mean <B_z^2> of the flow that nothing from the shock has reached: beyond
+    x = t (a particle reflected at the wall at t = 0 and moving at c since),
+    short of the entry edge (its last 1.5 c/omega_pe)."""
     p = r["profiles"][max(r["profiles"])]
     x = np.asarray(p["x"])
-    xf = r["shock_front_x"]
-    # the flow between the front and the injection edge (the last 1.5
-    # c/omega_pe hold the boundary layer of the entering flow)
-    m = (x > xf + 15.0) & (x < x[-1] - 15.0)
+    m = (x > r["t_end"] + 5.0) & (x < x[-1] - 15.0)
+    assert m.sum() >= 100
     return float(np.asarray(p["bz2_mean"])[m].mean())
 
 
@@ -80,9 +81,12 @@ def _upstream_b2(r):
 def test_cfl_one_keeps_the_upstream_quieter():
     """Sec. 4 runs the shock at CFL 0.5 and 1.0 and finds the flow ahead of
     the shock polluted by numerical Cherenkov radiation at 0.5 and not at 1.0:
-    the magnetic energy of the upstream flow is lower at CFL 1.0. The box is
-    the paper's length over 2.5 (226 c/omega_pe), so that 120 c/omega_pe of
-    flow lie ahead of the front at t = 177."""
+    the magnetic energy of the undisturbed flow (beyond the reach of anything
+    the shock reflects) is much lower at CFL 1.0. The box is the paper's
+    length over 2.5 (226 c/omega_pe), so that 30 c/omega_pe of such flow
+    remain at t = 177. (Closer to the shock, the particles it reflects drive
+    filaments in the flow: physical, and sharper at CFL 1.0, as the paper
+    notes.)"""
     import paper_1412_2480_amd as pic
     from paper_1412_2480_amd import shock
     out = {}
@@ -95,4 +99,4 @@ def test_cfl_one_keeps_the_upstream_quieter():
         _say(f"  front {r['shock_front_x']:.1f}, upstream <Bz^2>/Gamma^2 {out[sigma]:.3e}, "
              f"fallbacks {r['fallbacks']}")
         assert r["fallbacks"] == 0
-    assert out[1.0] < 0.5 * out[0.5]
+    assert out[1.0] < 0.01 * out[0.5]

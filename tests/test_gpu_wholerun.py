@@ -1,9 +1,12 @@
 """Whole-run parity of the FP32 fast form (FP32 particles, FP64 fields and CG)
 against the FP64 oracle: a drifting pair plasma at gamma0 = 40 in which the
-numerical Cherenkov instability grows from noise and saturates (Sec. 3).
+numerical Cherenkov instability grows from noise (Sec. 3): fast, to
+saturation, with the staggered gather; slowly with the method's node-averaged
+(momentum-conserving) gather at CFL 1, the paper's finding.
 
-The stored history was written by tests/golden/make_nci_history.py from the
-oracle alone. Bars: the field-energy history within 1e-3, measured against
+The stored histories were written by tests/golden/make_nci_history.py from
+the oracle alone; each case records its gather (files without the key were
+written with the staggered one). Bars: the field-energy history within 1e-3, measured against
 the largest oracle field energy so far, e(n) = |W_F(n) - W_F^ora(n)| /
 max_{m <= n} W_F^ora(m), because FP32 and FP64 trajectories cannot agree
 pointwise at the noise floor; the total energy within 1e-3 relative; the
@@ -23,8 +26,10 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 GOLDEN = os.path.join(HERE, "golden", "nci_history_128x64.json")
+GOLDEN_NODAL = os.path.join(HERE, "golden", "nci_history_128x64_nodal.json")
 # the single-run workload itself (1024 x 256, 64 ppc/species, 300 steps)
 GOLDEN_FULL = os.path.join(HERE, "golden", "nci_history_1024x256.json")
+GOLDEN_FULL_NODAL = os.path.join(HERE, "golden", "nci_history_1024x256_nodal.json")
 
 
 def _say(msg):
@@ -32,10 +37,14 @@ def _say(msg):
     sys.stdout.flush()
 
 
-@pytest.fixture(scope="module")
-def golden():
-    with open(GOLDEN) as f:
+@pytest.fixture(scope="module", params=[GOLDEN, GOLDEN_NODAL], ids=["staggered", "nodal"])
+def golden(request):
+    with open(request.param) as f:
         return json.load(f)
+
+
+def _gather(golden):
+    return golden["case"].get("gather", "staggered")
 
 
 def _run(golden, solver, train_after=0, **opt):
@@ -47,7 +56,7 @@ def _run(golden, solver, train_after=0, **opt):
     kw = dict(slack=1.0)
     kw.update(opt)
     opts = pic.make_options("fp32", diag_every=1, history_cap=c["steps"] + 1, solver=solver,
-                            precond_slots=8, **kw)
+                            precond_slots=8, gather=_gather(golden), **kw)
     sim = pic.Sim([run], opts)
     if c["nx"] * c["ny"] * c["ppc"] > 1 << 22:
         # the device loader draws the same seeded items as the host generator
@@ -120,19 +129,22 @@ def test_fp32_learned_whole_run_matches_oracle(golden):
     assert it >= 1
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN_FULL), reason="1024x256 oracle history not written")
-@pytest.mark.parametrize("tile,sort_every", [((2, 64), 3), ((4, 32), 4)])
-def test_fp32_learned_whole_run_matches_oracle_full_size(tile, sort_every):
+@pytest.mark.parametrize("path,tile,sort_every",
+                         [(GOLDEN_FULL_NODAL, (2, 64), 3), (GOLDEN_FULL, (2, 64), 3),
+                          (GOLDEN_FULL, (4, 32), 4)],
+                         ids=["nodal-2x64", "staggered-2x64", "staggered-4x32"])
+def test_fp32_learned_whole_run_matches_oracle_full_size(path, tile, sort_every):
     """The single-run workload at its own size (1024 x 256, 64 ppc/species,
-    order 3, gamma0 = 40) through the growth and saturation of the numerical
-    Cherenkov instability, 300 steps, in the configurations the tuner picks
+    order 3, gamma0 = 40), 300 steps, in the configurations the tuner picks
     between (FP32 particles, learned aid trained on the first 20 steps'
     pairs, 2 x 64 or 4 x 32 tiles, two work-groups per tile, reordering every
-    3 or 4 steps), against the FP64 oracle's history: the 1e-3 history bars
-    and the 5 % growth-rate bar."""
-    with open(GOLDEN_FULL) as f:
+    3 or 4 steps), against the FP64 oracle's history with the same gather:
+    the 1e-3 history bars and the 5 % growth-rate bar."""
+    if not os.path.exists(path):
+        pytest.skip(f"{os.path.basename(path)} not written")
+    with open(path) as f:
         golden = json.load(f)
-    _say(f"whole run 1024x256, FP32 form, learned CG aid, tile {tile}")
+    _say(f"whole run 1024x256, FP32 form, learned CG aid, {_gather(golden)} gather, tile {tile}")
     a, it = _run(golden, "learned", train_after=20, tile=tile, tile_split=2,
                  sort_every=sort_every, slack=0.5, track_ids=False)
     _check(golden, a)

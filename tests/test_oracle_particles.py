@@ -68,12 +68,12 @@ def _second_moment(order, t):
 
 @pytest.mark.parametrize("order", ORDERS)
 def test_gather_quadratic_pins_shape_order_per_axis(ora, order):
-    """A field quadratic in one coordinate of each component's own staggered
-    points gathers to t^2 + m_p(t) along that axis, with m_p the order-p
-    second moment: every component must use the full order-p shape in both
-    directions (momentum-conserving interpolation, the same shape as the
-    deposit). A component interpolated with a lower order along its staggered
-    direction, or a wrong stagger offset, fails."""
+    """Staggered gather (the alternative reading): a field quadratic in one
+    coordinate of each component's own staggered points gathers to
+    t^2 + m_p(t) along that axis, with m_p the order-p second moment: every
+    component must use the full order-p shape in both directions. A component
+    interpolated with a lower order along its staggered direction, or a wrong
+    stagger offset, fails."""
     nx = ny = 20
     rng = np.random.default_rng(40 + order)
     p = _particles(ora, rng, 300, nx, ny, lo=4, hi=nx - 4)
@@ -85,7 +85,7 @@ def test_gather_quadratic_pins_shape_order_per_axis(ora, order):
         for sx, sy in STAG:
             t = (I + sx) if axis == 0 else (J + sy)
             f.append(0.2 + t * t)
-        g = ora.gather(nx, ny, order, f, p)
+        g = ora.gather(nx, ny, order, f, p, mode="staggered")
         for c, (sx, sy) in enumerate(STAG):
             # sum_i S(P - s - i) (i + s)^2 = P^2 + m_p(P - s), P the particle's
             # coordinate and s the component's stagger along the axis
@@ -94,26 +94,80 @@ def test_gather_quadratic_pins_shape_order_per_axis(ora, order):
             assert np.allclose(g[c], want, rtol=0, atol=1e-11), (axis, c)
 
 
+@pytest.mark.parametrize("mode", ["nodal", "staggered"])
 @pytest.mark.parametrize("order", ORDERS)
-def test_gather_uniform_and_linear(ora, order):
-    """Uniform fields are reproduced exactly; a field linear in the physical
-    coordinate of each component's own staggered points is reproduced at the
-    particle position (so a wrong stagger offset is caught)."""
+def test_gather_uniform_and_linear(ora, order, mode):
+    """Both gathers: uniform fields are reproduced exactly; a field linear in
+    the physical coordinate of each component's own staggered points is
+    reproduced at the particle position (a wrong stagger offset, or an
+    average onto the nodes taken with the wrong neighbour, is caught)."""
     nx = ny = 16
     rng = np.random.default_rng(10 + order)
     p = _particles(ora, rng, 200, nx, ny)
     consts = [1.5, -2.0, 0.25, 3.0, -0.5, 7.0]
     f = [np.full((ny, nx), c) for c in consts]
-    g = ora.gather(nx, ny, order, f, p)
+    g = ora.gather(nx, ny, order, f, p, mode=mode)
     for c in range(6):
         assert np.allclose(g[c], consts[c], rtol=0, atol=1e-13)
     J, I = np.mgrid[0:ny, 0:nx].astype(float)
     f = [0.3 + 0.7 * (I + sx) - 1.1 * (J + sy) for sx, sy in STAG]
-    g = ora.gather(nx, ny, order, f, p)
+    g = ora.gather(nx, ny, order, f, p, mode=mode)
     X = p.ix + p.fx
     Y = p.iy + p.fy
     for c in range(6):
         assert np.allclose(g[c], 0.3 + 0.7 * X - 1.1 * Y, rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_nodal_gather_quadratic_pins_averaging(ora, order):
+    """Node-averaged gather (the method's momentum-conserving interpolation):
+    a field quadratic in one coordinate t of each component's own Yee points
+    averages onto node i as i^2 + 1/4 along an axis where the component is
+    staggered (((i - 1/2)^2 + (i + 1/2)^2)/2) and i^2 where it is not, and the
+    node-centred order-p shape then adds its second moment m_p(P): the
+    gathered value is c + P^2 + m_p(P) + (1/4 if staggered along that axis).
+    An average taken along the wrong axis, with the wrong neighbour (i + 1
+    instead of i - 1 shifts the value by 2P + 1), over two instead of four
+    points for Bz, or a shape of another order fails."""
+    nx = ny = 20
+    rng = np.random.default_rng(70 + order)
+    p = _particles(ora, rng, 300, nx, ny, lo=4, hi=nx - 4)
+    J, I = np.mgrid[0:ny, 0:nx].astype(float)
+    X = p.ix + p.fx
+    Y = p.iy + p.fy
+    for axis in (0, 1):
+        f = []
+        for sx, sy in STAG:
+            t = (I + sx) if axis == 0 else (J + sy)
+            f.append(0.2 + t * t)
+        g = ora.gather(nx, ny, order, f, p, mode="nodal")
+        for c, (sx, sy) in enumerate(STAG):
+            P, sh = (X, sx) if axis == 0 else (Y, sy)
+            want = 0.2 + P ** 2 + _second_moment(order, P) + (0.25 if sh else 0.0)
+            assert np.allclose(g[c], want, rtol=0, atol=1e-11), (axis, c)
+
+
+@pytest.mark.parametrize("order", ORDERS)
+def test_nodal_gather_periodic_translation(ora, order):
+    """Periodic wrap of the averages: shifting the fields by (mx, my) cells and
+    every particle by the same amount leaves the gathered values unchanged,
+    also for particles whose shape or averages reach across the edges."""
+    nx, ny = 12, 10
+    rng = np.random.default_rng(90 + order)
+    f = [rng.normal(size=(ny, nx)) for _ in range(6)]
+    x = rng.uniform(0, nx, 200)
+    y = rng.uniform(0, ny, 200)
+    x[:20] = rng.uniform(0, 1.5, 20)           # near the low edges
+    y[20:40] = rng.uniform(ny - 1.5, ny, 20)    # near the high edges
+    u = np.zeros((3, 200))
+    p = ora.Particles.from_xy(x, y, u[0], u[1], u[2], 1.0, 1.0, 1.0, 1.0)
+    g0 = ora.gather(nx, ny, order, f, p, mode="nodal")
+    for mx, my in ((3, 0), (0, 4), (5, 7)):
+        fs = [np.roll(np.roll(a, my, axis=0), mx, axis=1) for a in f]
+        ps = ora.Particles.from_xy((x + mx) % nx, (y + my) % ny, u[0], u[1], u[2], 1.0, 1.0,
+                                   1.0, 1.0)
+        g1 = ora.gather(nx, ny, order, fs, ps, mode="nodal")
+        assert np.allclose(g1, g0, rtol=0, atol=1e-12), (mx, my)
 
 
 # ---------------------------------------------------------------- push

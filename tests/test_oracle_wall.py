@@ -226,7 +226,7 @@ def test_wall_gather_odd_images(order):
     f = []
     for (sx, sy), odd in zip(STAG, ODD):
         f.append(0.7 * (I + sx) * (J + sy + 1.0) if odd else np.zeros((ny, nx)))
-    g = oracle.gather_wall(nx, ny, order, f, p)
+    g = oracle.gather_wall(nx, ny, order, f, p, mode="staggered")
     for c, odd in enumerate(ODD):
         if odd:
             assert np.allclose(g[c], 0.7 * X * (Y + 1.0), rtol=0, atol=1e-12), c
@@ -255,7 +255,7 @@ def test_wall_gather_even_images(order):
     f = []
     for (sx, sy), odd in zip(STAG, ODD):
         f.append(np.zeros((ny, nx)) if odd else 0.4 + (I + sx) ** 2)
-    g = oracle.gather_wall(nx, ny, order, f, p)
+    g = oracle.gather_wall(nx, ny, order, f, p, mode="staggered")
     t = X - 0.5
     fr = t - np.floor(t)
     m = (order + 1) / 12.0 if order >= 2 else fr * (1 - fr)
@@ -264,7 +264,7 @@ def test_wall_gather_even_images(order):
         if not odd:
             assert np.allclose(g[c], want, rtol=0, atol=1e-11), c
     u = [np.zeros((ny, nx)) if odd else np.full((ny, nx), -1.3) for odd in ODD]
-    gu = oracle.gather_wall(nx, ny, order, u, p)
+    gu = oracle.gather_wall(nx, ny, order, u, p, mode="staggered")
     for c, odd in enumerate(ODD):
         if not odd:
             assert np.allclose(gu[c], -1.3, rtol=0, atol=1e-13), c
@@ -278,3 +278,29 @@ def test_wall_gather_even_images(order):
     for wrong in (lambda i: val(i) if i >= 0 else -val(-i - 1),
                   lambda i: val(i) if i >= 0 else val(-i)):
         assert np.abs(_interp_x(order, X, 0.5, wrong) - want).max() > 1e-2
+
+
+@pytest.mark.parametrize("order", [1, 2, 3])
+def test_wall_nodal_gather_images(order):
+    """The node-averaged gather with the conductor images: the odd components
+    (Ey, Ez, Bx) of a field a x (y + 1) in their own coordinates average onto
+    the nodes as a x (y + 1) (linear; the y average of Ey and Bx is exact) and
+    are reproduced at every particle near the wall; the even components (Ex,
+    By, Bz) of b + x^2 average onto node i as b + i^2 + 1/4, behind the wall
+    too (their even image is the same function of the position), and gather
+    to b + X^2 + m_p(X) + 1/4. An odd image of an even component, or a
+    mirror one column off, changes the averages of the first columns and
+    fails."""
+    nx, ny = 24, 10
+    p = _near_wall(order, seed=20)
+    X, Y = p.ix + p.fx, p.iy + p.fy
+    J, I = np.mgrid[0:ny, 0:nx].astype(float)
+    f = []
+    for (sx, sy), odd in zip(STAG, ODD):
+        f.append(0.7 * (I + sx) * (J + sy + 1.0) if odd else 0.4 + (I + sx) ** 2)
+    g = oracle.gather_wall(nx, ny, order, f, p, mode="nodal")
+    fr = X - np.floor(X)
+    m = (order + 1) / 12.0 if order >= 2 else fr * (1 - fr)
+    for c, odd in enumerate(ODD):
+        want = 0.7 * X * (Y + 1.0) if odd else 0.4 + X ** 2 + m + 0.25
+        assert np.allclose(g[c], want, rtol=0, atol=1e-11), c
