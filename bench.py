@@ -16,9 +16,9 @@ one-time set-up, timed and reported on its own and folded into a whole-run
 figure. Then --warmup untimed steps and --steps timed steps; the particle
 kernel's launches inside the timed region are timed with HIP events on the
 context's stream (the roofline's achieved bandwidth). The same workload is
-then taken on, untimed, past the saturation of the numerical Cherenkov
-instability (--saturated-after steps) and timed again: the state in which a
-long run spends most of its steps.
+then taken on, untimed, for --later-after more steps and timed again: the
+state in which a long run spends most of its steps (the beam has spread and
+the density has bunched, which costs the particle kernel LDS conflicts).
 
 Further legs: the 1024 x 256 single run (FP32 + learned, FP32 with plain CG,
 and the plain FP64 form on a schedule tuned for it: the FP32-vs-FP64 factor
@@ -92,8 +92,8 @@ def measured_traffic(precision, tile, tile_split, order, n_particles, sort_every
         with open(path) as f:
             rec = json.load(f)
         cfg = rec["config"]
-        # the warm-up length counts: the hot, bunched plasma after the
-        # instability saturates moves other bytes than the cold start
+        # the warm-up length counts: the spread, bunched plasma of a long run
+        # moves other bytes than the cold start
         if (cfg["precision"], list(cfg["tile"]), cfg["tile_split"], cfg["order"],
                 cfg["particles"], cfg.get("sort_every", 0),
                 cfg.get("warmup", 0)) != (precision, list(tile), tile_split, order, n_particles,
@@ -136,9 +136,10 @@ GRAPH = True    # pic_step replays captured two-step HIP graphs (--no-graph: pla
 SORT = 0        # pic_options.sort_every of the timed forms (autotuned, or --sort-every)
 # (tile shape, reordering period) candidates of the 48-run sweep
 SWEEP_SCHEDULES = (((16, 16), 0), ((4, 32), 8), ((8, 16), 8), ((2, 32), 8))
-SLACK = 0.5     # tile slots over ppc*cells: once the numerical Cherenkov instability has
-                # saturated (near step 300) the densities bunch and a tile of the default
-                # 0.25 overflows within the 2000-step run
+SLACK = 0.5     # tile slots over ppc*cells: the densities of the drifting plasma bunch
+                # over a long run; with the staggered gather (where the numerical
+                # Cherenkov instability grows at CFL 1) a tile of the default 0.25
+                # overflowed within the 2000-step run
 
 
 def make_sim(pic, cfg, load, precision, tile, cg_blocks=0, tile_split=0, solver="cg",
@@ -164,9 +165,9 @@ def time_form(pic, torch, cfg, load, precision, tile, steps, warmup, cg_blocks=0
               learned=None, retune=False, sort_every=None):
     """learned: None (plain CG) or dict(form, pairs, epochs, lr): collect that
     many pairs with plain CG in the first steps, train, then take the learned
-    path for the warm-up and the timed steps (as a run would: trained on
-    the first steps' pairs the network needs 3 iterations per component after
-    the instability has saturated, trained on pairs taken there 4)."""
+    path for the warm-up and the timed steps (as a run would: the network
+    trained on the first steps' pairs keeps 3 iterations per component over a
+    long run)."""
     solver = "learned" if learned else "cg"
     sim = make_sim(pic, cfg, load, precision, tile, cg_blocks, tile_split, solver,
                    learned["form"] if learned else "collapsed",
@@ -382,12 +383,12 @@ def net_rate(pic, torch, cfg, reps=10):
     return out
 
 
-def headline(pic, torch, steps, warmup, saturated_after=300, pairs=8, epochs=50):
+def headline(pic, torch, steps, warmup, later_after=300, pairs=8, epochs=50):
     """The headline workload (C5 dict): 2^31 particles loaded on the device,
     FP32 particles with the learned aid. Returns the timed figures: wall
     clock over `steps` steps after `warmup` untimed ones, the particle
     kernel's average launch time from HIP events on the context stream over
-    the same launches, the field solve, and (if saturated_after > 0) the
+    the same launches, the field solve, and (if later_after > 0) the
     same after that many further untimed steps."""
     from synth import loads
     c = C5
@@ -448,15 +449,15 @@ def headline(pic, torch, steps, warmup, saturated_after=300, pairs=8, epochs=50)
         sim.step(warmup)
     main_t = timed(steps)
     sat = None
-    if saturated_after > 0:
-        log(f"bench: headline: {saturated_after} more untimed steps (saturated phase)")
-        sim.step(saturated_after)
-        sat = dict(timed(min(steps, 10)), after_steps=pairs + warmup + steps + saturated_after)
+    if later_after > 0:
+        log(f"bench: headline: {later_after} more untimed steps (later phase)")
+        sim.step(later_after)
+        sat = dict(timed(min(steps, 10)), after_steps=pairs + warmup + steps + later_after)
     d = sim.diag(0)
     out = dict(workload=c["label"] + " (FP32 particles, learned aid)", particles=n,
                workspace_gb=sim.info.workspace_bytes / 1e9, load_seconds=load_s,
                tile=list(C5_TILE), tile_split=C5_SPLIT, sort_every=C5_SORT,
-               cg_blocks=retune["cg_blocks"], timed=main_t, saturated=sat,
+               cg_blocks=retune["cg_blocks"], timed=main_t, later=sat,
                training=dict(pairs=pairs, epochs=epochs, seconds=train_s, tune_seconds=tune_s,
                              loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
                plain_cg=dict(ms_per_step=plain_s * 1e3 / pairs,
@@ -465,19 +466,18 @@ def headline(pic, torch, steps, warmup, saturated_after=300, pairs=8, epochs=50)
                              note=f"the first {pairs} steps (plain CG, pairs recorded)"),
                gauss_max=d["gauss_max"], n_particles=d["n_particles"][:2])
     # a 1000-step run (the workload's length): collection steps, training,
-    # then the steps up to the saturated measurement at the timed rate and the
-    # rest at the saturated rate (the numerical Cherenkov instability
-    # saturates near step 300 and the plasma stays hot and bunched)
+    # then the steps up to the later measurement at the timed rate and the
+    # rest at the later rate
     if sat is not None:
         n_cold = sat["after_steps"] - pairs
         run_s = plain_s + train_s + tune_s + (n_cold * main_t["ms_per_step"] + (
             1000 - sat["after_steps"]) * sat["ms_per_step"]) * 1e-3
         note = (f"the {pairs} collection steps, training, tuning, {n_cold} steps at the timed "
-                f"rate and {1000 - sat['after_steps']} at the saturated-phase rate")
+                f"rate and {1000 - sat['after_steps']} at the later-phase rate")
     else:
         run_s = plain_s + train_s + tune_s + (1000 - pairs) * main_t["ms_per_step"] * 1e-3
         note = (f"the {pairs} collection steps, training, tuning and {1000 - pairs} steps at "
-                "the timed rate (saturated phase not measured)")
+                "the timed rate (later phase not measured)")
     out["whole_run_1000_steps"] = dict(seconds=run_s, ms_per_step=run_s * 1e3 / 1000,
                                        particle_steps_per_s=n * 1000 / run_s, note=note)
     sim.close()
@@ -760,10 +760,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--saturated-after", type=int, default=300,
-                    help="untimed headline steps before the saturated-phase timing (0 = skip): "
-                         "by step ~300 the numerical Cherenkov instability of the drifting "
-                         "pair plasma has saturated, the state a long run spends most steps in")
+    ap.add_argument("--later-after", type=int, default=300,
+                    help="untimed headline steps before the later-phase timing (0 = skip): "
+                         "the state a long run spends most steps in")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload (for profiling runs)")
     ap.add_argument("--no-c2", action="store_true", help="skip the 1024x256 legs")
@@ -816,15 +815,15 @@ def main():
                    lr=1e-3)
     log(f"bench: headline {C5['label']}")
     h = headline(pic, torch, args.steps, args.warmup,
-                 0 if args.headline_only else args.saturated_after, args.train_pairs,
+                 0 if args.headline_only else args.later_after, args.train_pairs,
                  args.train_epochs)
     t = h["timed"]
     log(f"bench: headline {t['ms_per_step']:.2f} ms/step ({t['particle_steps_per_s']:.3g} "
         f"particle-steps/s), push {t['push_ms']:.2f} ms, field solve {t['field_solve_ms']:.2f} ms "
         f"(plain CG {h['plain_cg']['field_solve_ms']:.2f} ms)")
-    if h["saturated"]:
-        sa = h["saturated"]
-        log(f"bench: headline saturated phase {sa['ms_per_step']:.2f} ms/step, push "
+    if h["later"]:
+        sa = h["later"]
+        log(f"bench: headline later phase {sa['ms_per_step']:.2f} ms/step, push "
             f"{sa['push_ms']:.2f} ms")
     gc.collect()
     torch.cuda.empty_cache()
