@@ -15,8 +15,10 @@ def relerr(a, b):
 
 class Case:
     def __init__(self, nx, ny, order, ppc, gamma0=20.0, T=0.01, cfl=1.0, theta=0.6, seed=0,
-                 dx=0.1, dy=None, field_amp=0.0, n_species=2, rtol=1e-8, maxit=200):
+                 dx=0.1, dy=None, field_amp=0.0, n_species=2, rtol=1e-8, maxit=200,
+                 gather="nodal"):
         self.nx, self.ny, self.order, self.ppc = nx, ny, order, ppc
+        self.gather = gather
         self.dx, self.dy = dx, (dx if dy is None else dy)
         self.cfl, self.theta, self.rtol, self.maxit = cfl, theta, rtol, maxit
         Q = loads.macro_charge(max(gamma0, 1.0), self.dx, self.dy, ppc)
@@ -38,7 +40,8 @@ class Case:
     def oracle_sim(self, rtol=None):
         sim = oracle.Sim(self.nx, self.ny, self.dx, self.dy, self.cfl, self.theta, self.order,
                          [p.copy() for p in self.species],
-                         rtol=self.rtol if rtol is None else rtol, maxit=self.maxit)
+                         rtol=self.rtol if rtol is None else rtol, maxit=self.maxit,
+                         gather=self.gather)
         for k, n in enumerate(("Ex", "Ey", "Ez")):
             sim.E[k][...] = self.fields[n]
         for k, n in enumerate(("Bx", "By", "Bz")):
@@ -59,6 +62,7 @@ class Case:
 
     def gpu_sim(self, precision="fp64", tile=(16, 16), rtol=None, **opt):
         import paper_1412_2480_amd as pic
+        opt.setdefault("gather", self.gather)
         sim = pic.Sim([self.run_desc(rtol)], pic.make_options(precision, tile=tile, **opt))
         self.load_into(sim)
         return sim

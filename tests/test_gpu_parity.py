@@ -26,13 +26,14 @@ def _say(msg):
 GRIDS = [(40, 36), (34, 12)]
 
 
+@pytest.mark.parametrize("gather", ["nodal", "staggered"])
 @pytest.mark.parametrize("order", [1, 2, 3])
 @pytest.mark.parametrize("grid", GRIDS)
-def test_split_step_parity_fp64(order, grid):
+def test_split_step_parity_fp64(order, grid, gather):
     nx, ny = grid
-    _say(f"split parity fp64 order={order} grid={grid}")
+    _say(f"split parity fp64 order={order} grid={grid} gather={gather}")
     case = Case(nx, ny, order, ppc=3, gamma0=5.0, T=0.05, field_amp=0.5, seed=order,
-                rtol=1e-14, maxit=500)
+                rtol=1e-14, maxit=500, gather=gather)
     sim = case.gpu_sim("fp64", tile=(16, 16))
     ref = case.oracle_sim()
     # gather + push + move
@@ -42,7 +43,7 @@ def test_split_step_parity_fp64(order, grid):
     ref_f = []
     for p in ref.species:
         import oracle
-        f = oracle.gather(nx, ny, order, ref.E + ref.B, p)
+        f = oracle.gather(nx, ny, order, ref.E + ref.B, p, gather)
         oracle.boris(p, ref.dt, f[0:3], f[3:6])
         olds.append(p.copy())
         oracle.move(p, ref.dt, ref.dx, ref.dy)
@@ -127,13 +128,14 @@ def test_multistep_c1_fp64_energy_history():
     sim.close()
 
 
+@pytest.mark.parametrize("gather", ["nodal", "staggered"])
 @pytest.mark.parametrize("order", [1, 2, 3])
-def test_one_step_fp32_fast_form(order):
+def test_one_step_fp32_fast_form(order, gather):
     """FP32 particles (int cell + FP32 offset, FP32 current) against the FP64
     oracle after one step; bounds from FP32 rounding (unit roundoff 6e-8)."""
-    _say(f"fp32 one step order={order}")
+    _say(f"fp32 one step order={order} gather={gather}")
     case = Case(40, 36, order, ppc=4, gamma0=20.0, T=0.01, field_amp=0.5, seed=11,
-                rtol=1e-12)
+                rtol=1e-12, gather=gather)
     import oracle
     sim = case.gpu_sim("fp32")
     ref = case.oracle_sim()
@@ -142,7 +144,7 @@ def test_one_step_fp32_fast_form(order):
     jabs = [np.zeros((case.ny, case.nx)) for _ in range(3)]
     for p in ref.species:
         a = p.copy()
-        f = oracle.gather(case.nx, case.ny, order, ref.E + ref.B, a)
+        f = oracle.gather(case.nx, case.ny, order, ref.E + ref.B, a, gather)
         oracle.boris(a, ref.dt, f[0:3], f[3:6])
         old = a.copy()
         oracle.move(a, ref.dt, ref.dx, ref.dy)

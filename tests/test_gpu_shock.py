@@ -22,8 +22,9 @@ def _say(msg):
 
 class Shock:
     def __init__(self, nx, ny, order, ppc, gamma0=5.0, T=0.05, cfl=1.0, theta=0.6, seed=0,
-                 field_amp=0.0, rtol=1e-8, maxit=300):
+                 field_amp=0.0, rtol=1e-8, maxit=300, gather="nodal"):
         self.nx, self.ny, self.order, self.ppc = nx, ny, order, ppc
+        self.gather = gather
         self.gamma0, self.T, self.cfl, self.theta, self.seed = gamma0, T, cfl, theta, seed
         self.rtol, self.maxit = rtol, maxit
         self.x_out = nx - oracle.WALL_GAP
@@ -50,7 +51,8 @@ class Shock:
         sp = [oracle.Particles(d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"],
                                q, self.Q) for d, q in zip(self.load, (-self.Q, self.Q))]
         sim = oracle.Sim(self.nx, self.ny, 0.1, 0.1, self.cfl, self.theta, self.order, sp,
-                         rtol=self.rtol if rtol is None else rtol, maxit=self.maxit, bc="shock")
+                         rtol=self.rtol if rtol is None else rtol, maxit=self.maxit, bc="shock",
+                         gather=self.gather)
         for k, n in enumerate(EN):
             sim.E[k][...] = self.fields[n]
         for k, n in enumerate(BN):
@@ -63,6 +65,7 @@ class Shock:
                            [(-self.Q, self.Q, self.ppc), (self.Q, self.Q, self.ppc)],
                            cg_rtol=self.rtol if rtol is None else rtol, cg_maxit=self.maxit,
                            bc="shock")
+        opt.setdefault("gather", self.gather)
         sim = pic.Sim([run], pic.make_options(precision, slack=2.0, **opt))
         for s, d in enumerate(self.load):
             sim.load_particles(0, s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"],
@@ -82,14 +85,16 @@ def _inject_both(case, step, gpu, ref):
             ref.inject(s, d["ix"], d["iy"], d["fx"], d["fy"], d["ux"], d["uy"], d["uz"])
 
 
-@pytest.mark.parametrize("order,tile", [(1, (16, 16)), (2, (16, 16)), (3, (16, 16)),
-                                        (2, (2, 8)), (3, (2, 4))])
-def test_shock_steps_match_oracle_fp64(order, tile):
+@pytest.mark.parametrize("order,tile,gather",
+                         [(1, (16, 16), "nodal"), (2, (16, 16), "nodal"), (3, (16, 16), "nodal"),
+                          (2, (2, 8), "nodal"), (3, (2, 4), "nodal"),
+                          (1, (16, 16), "staggered"), (3, (2, 4), "staggered")])
+def test_shock_steps_match_oracle_fp64(order, tile, gather):
     """Split steps with reflection, outflow and injection against the oracle;
     the 2-cell-wide tiles put the wall's ghost columns and the patches that
     reach two tiles out through the current reduction."""
-    _say(f"shock split steps vs oracle, order {order}, tile {tile}")
-    case = Shock(40, 20, order, ppc=3, seed=order, field_amp=0.3, rtol=1e-14)
+    _say(f"shock split steps vs oracle, order {order}, tile {tile}, gather {gather}")
+    case = Shock(40, 20, order, ppc=3, seed=order, field_amp=0.3, rtol=1e-14, gather=gather)
     ref = case.oracle_sim()
     sim = case.gpu_sim("fp64", tile=tile)
     reflected = 0
