@@ -349,8 +349,15 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             dsy[a] = (double)DSy[a];
           }
           const double cx = (double)cjx, cy = (double)cjy, cz = (double)cjz * (double)vz;
+          // The window's last row (column) holds weights only for a lane
+          // whose support moved along y (x) this step; when no lane of the
+          // wavefront did, its Jx and Jz row (Jy and Jz column) is exactly
+          // zero and the wavefront skips those atomics as a whole.
+          const bool row_last = __any(o0y != o1y);
+          const bool col_last = __any(o0x != o1x);
 #pragma unroll
           for (int b = 0; b < W; ++b) {
+            if (b == W - 1 && !row_last) break;
             const double wy = (s0y[b] + 0.5 * dsy[b]) * cx;
             double acc = 0.0;
 #pragma unroll
@@ -371,6 +378,7 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           }
 #pragma unroll
           for (int a = 0; a < W; ++a) {
+            if (a == W - 1 && !col_last) break;
             double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) {
@@ -379,12 +387,15 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             }
           }
 #pragma unroll
-          for (int b = 0; b < W; ++b)
+          for (int b = 0; b < W; ++b) {
+            if (b == W - 1 && !row_last) break;
 #pragma unroll
             for (int a = 0; a < W; ++a) {
+              if (a == W - 1 && !col_last) break;
               const double wz = hz[a] * s0y[b] + zz[a] * dsy[b];
               if (wz != 0.0) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], wz);
             }
+          }
 
           // ---- boundaries: a shock run reflects at x = 0 (after the deposit
           // of the unreflected displacement, whose ghost columns the current
