@@ -355,17 +355,21 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           // zero and the wavefront skips those atomics as a whole.
           const bool row_last = __any(o0y != o1y);
           const bool col_last = __any(o0x != o1x);
-#pragma unroll
-          for (int b = 0; b < W; ++b) {
-            if (b == W - 1 && !row_last) break;
+          double* const bx_ = jx + ay0 * PW + ax0;
+          double* const by_ = jy + ay0 * PW + ax0;
+          double* const bz_ = jz + ay0 * PW + ax0;
+          auto jx_row = [&](int b) {
             const double wy = (s0y[b] + 0.5 * dsy[b]) * cx;
             double acc = 0.0;
 #pragma unroll
             for (int a = 0; a < W - 1; ++a) {
               acc += dsx[a] * wy;
-              if (acc != 0.0) atomicAdd(&jx[(ay0 + b) * PW + ax0 + a], acc);
+              if (acc != 0.0) atomicAdd(&bx_[b * PW + a], acc);
             }
-          }
+          };
+#pragma unroll
+          for (int b = 0; b < W - 1; ++b) jx_row(b);
+          if (row_last) jx_row(W - 1);
           // Wz = S0x S0y + DSx S0y/2 + S0x DSy/2 + DSx DSy/3, grouped as
           // (S0x + DSx/2) S0y + (S0x/2 + DSx/3) DSy; the first factor is Jy's
           double hy[W], hz[W], zz[W];
@@ -376,25 +380,33 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
             hz[a] = hx * cz;
             zz[a] = (0.5 * s0x[a] + dsx[a] * (1.0 / 3.0)) * cz;
           }
-#pragma unroll
-          for (int a = 0; a < W; ++a) {
-            if (a == W - 1 && !col_last) break;
+          auto jy_col = [&](int a) {
             double acc = 0.0;
 #pragma unroll
             for (int b = 0; b < W - 1; ++b) {
               acc += dsy[b] * hy[a];
-              if (acc != 0.0) atomicAdd(&jy[(ay0 + b) * PW + ax0 + a], acc);
+              if (acc != 0.0) atomicAdd(&by_[b * PW + a], acc);
             }
+          };
+#pragma unroll
+          for (int a = 0; a < W - 1; ++a) jy_col(a);
+          if (col_last) jy_col(W - 1);
+          auto jz_at = [&](int a, int b) {
+            const double wz = hz[a] * s0y[b] + zz[a] * dsy[b];
+            if (wz != 0.0) atomicAdd(&bz_[b * PW + a], wz);
+          };
+#pragma unroll
+          for (int b = 0; b < W - 1; ++b)
+#pragma unroll
+            for (int a = 0; a < W - 1; ++a) jz_at(a, b);
+          if (col_last) {
+#pragma unroll
+            for (int b = 0; b < W - 1; ++b) jz_at(W - 1, b);
           }
+          if (row_last) {
 #pragma unroll
-          for (int b = 0; b < W; ++b) {
-            if (b == W - 1 && !row_last) break;
-#pragma unroll
-            for (int a = 0; a < W; ++a) {
-              if (a == W - 1 && !col_last) break;
-              const double wz = hz[a] * s0y[b] + zz[a] * dsy[b];
-              if (wz != 0.0) atomicAdd(&jz[(ay0 + b) * PW + ax0 + a], wz);
-            }
+            for (int a = 0; a < W - 1; ++a) jz_at(a, W - 1);
+            if (col_last) jz_at(W - 1, W - 1);
           }
 
           // ---- boundaries: a shock run reflects at x = 0 (after the deposit
