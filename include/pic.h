@@ -121,7 +121,8 @@ typedef struct pic_options {
                             the destination tile's slots, so no exchange buffer exists */
   int32_t diag_every;    /* record energies every n steps into the history (0 = never) */
   int32_t history_cap;   /* history records kept per run (ring buffer) */
-  int32_t cg_blocks;     /* work-groups of the persistent field solve; 0 = automatic */
+  int32_t cg_blocks;     /* work-groups of the persistent field solve; 0 = as many as
+                            can be co-resident (at most one per 512 cells of a run) */
   int32_t track_ids;     /* 1: particles carry ids and reads return them ordered by id;
                             0: no ids (8 B less traffic per particle-step), reads return
                             storage order */

@@ -19,9 +19,6 @@
 namespace {
 
 constexpr int kMaxCgBlocks = 4096;
-// grid-barrier latency grows with the number of work-groups (about 30 ns
-// each), so the default keeps the persistent grid small; pic_tune measures
-constexpr int kDefaultCgBlocks = 128;
 constexpr int kDivBlocks = 512;
 constexpr int kDivWords = 4;          // per-block words of the divergence diagnostics
 constexpr int kTimingClasses = 9;
@@ -1360,7 +1357,12 @@ int32_t pic_init(const pic_run_desc* runs, int32_t n_runs, const pic_options* op
       h.m[s] = d.species[s].m;
     }
   }
-  assign_cg_blocks(c, opt->cg_blocks > 0 ? opt->cg_blocks : kDefaultCgBlocks);
+  // By default the field solve launches every work-group that can be
+  // co-resident (at most one per PIC_CG_THREADS cells of each run): its
+  // sweeps stream some twenty arrays and need the whole chip (plain CG at
+  // 8192 x 2048: 18.7 ms with 256 work-groups, 31.2 ms with 128), while the
+  // grid barrier costs about 5.5 us at 256. pic_tune measures other counts.
+  assign_cg_blocks(c, opt->cg_blocks > 0 ? opt->cg_blocks : c->max_cg_blocks);
   std::vector<int> tile_run(c->tl.n_tiles);
   for (int r = 0; r < n_runs; ++r)
     for (int t = 0; t < c->tl.ntx[r] * c->tl.nty[r]; ++t) tile_run[c->tl.tile0[r] + t] = r;

@@ -113,6 +113,15 @@ __device__ __forceinline__ void grid_barrier(unsigned* bar, unsigned nb, unsigne
 }
 
 // deterministic block reduction of N doubles; result valid in all threads
+// Every lane of the block holds the same value: tell the compiler so (scalar
+// registers and branches for the solve's coefficients and decisions).
+__device__ __forceinline__ double uniform(double x) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* sm) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -127,7 +136,7 @@ __device__ __forceinline__ void block_sum(double (&v)[N], double* sm) {
   for (int k = 0; k < N; ++k) {
     double s = 0.0;
     for (int w = 0; w < kWaves; ++w) s += sm[w * N + k];
-    v[k] = s;
+    v[k] = uniform(s);
   }
   __syncthreads();
 }
@@ -178,7 +187,7 @@ k_field_solve(FieldArgs a) {
     s_run = r;
   }
   __syncthreads();
-  const int run = s_run;
+  const int run = __builtin_amdgcn_readfirstlane(s_run);
   const DevRun& R = a.runs[run];
   const int blo = R.cg_blk_lo, bhi = R.cg_blk_hi;
   const int lb = blockIdx.x - blo, nb = bhi - blo;
@@ -249,7 +258,7 @@ k_field_solve(FieldArgs a) {
     const int t = __hip_atomic_load(&a.g_active[round % 3], __ATOMIC_RELAXED,
                                     __HIP_MEMORY_SCOPE_AGENT);
     ++round;
-    return t;
+    return __builtin_amdgcn_readfirstlane(t);
   };
   // z = N(v) over every tile of every active component, items spread over the
   // run's blocks: rd(c, i, j) gives the input at any cell, wr(c, i, j, z) sees
