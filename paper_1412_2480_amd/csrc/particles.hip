@@ -37,7 +37,11 @@ template <> __device__ __forceinline__ double max_disp<double>() { return 1.0 - 
 
 // B-spline weights of degree P for a point at offset t (in cells) from node 0
 // of the component's grid, t in [-1/2, 1). Returns the first node index
-// (relative to node 0) and the P+1 non-trivial weights.
+// (relative to node 0) and the P+1 non-trivial weights. Every sum is an
+// explicit fused multiply-add, so the weights of a position round the same
+// way wherever the function is inlined: the new shape a step deposits with is
+// then bit for bit the old shape of the next step (and of the charge
+// density), which the discrete continuity equation needs.
 template <int P, typename R>
 __device__ __forceinline__ int bspline_weights(R t, R (&w)[P + 1]) {
   if constexpr (P == 1) {
@@ -51,7 +55,7 @@ __device__ __forceinline__ int bspline_weights(R t, R (&w)[P + 1]) {
     const R d = t - R(r);                  // in [-1/2, 1/2)
     const R a = R(0.5) - d, b = R(0.5) + d;
     w[0] = R(0.5) * a * a;
-    w[1] = R(0.75) - d * d;
+    w[1] = fma(-d, d, R(0.75));
     w[2] = R(0.5) * b * b;
     return r - 1;
   } else {
@@ -60,8 +64,8 @@ __device__ __forceinline__ int bspline_weights(R t, R (&w)[P + 1]) {
     const R d2 = d * d, d3 = d2 * d, e = R(1) - d;
     const R sixth = R(1) / R(6);
     w[0] = e * e * e * sixth;
-    w[1] = (R(4) - R(6) * d2 + R(3) * d3) * sixth;
-    w[2] = (R(1) + R(3) * d + R(3) * d2 - R(3) * d3) * sixth;
+    w[1] = fma(R(3), d3, fma(R(-6), d2, R(4))) * sixth;
+    w[2] = fma(R(-3), d3, fma(R(3), d2, fma(R(3), d, R(1)))) * sixth;
     w[3] = d3 * sixth;
     return fl - 1;
   }
