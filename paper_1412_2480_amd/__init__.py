@@ -238,7 +238,8 @@ def make_options(precision="fp64", tile=(16, 16), slack=0.25, exchange_frac=0.25
     cg_x0: "zero" or "prev" (plain CG from the previous step's dB);
     scheme: "implicit" (Eqs. (5)-(7)) or "explicit" (Yee FDTD, Eqs. (3)-(4));
     gather: "nodal" (momentum-conserving: fields averaged onto the charge nodes,
-    the default) or "staggered" (each component from its own Yee points)."""
+    the default) or "staggered" (each component from its own Yee points);
+    exchange_frac: ignored by the library (kept in pic_options)."""
     o = Options()
     o.precision = PIC_FP32_FAST if precision in ("fp32", PIC_FP32_FAST) else PIC_FP64
     o.solver = PIC_SOLVER_LEARNED_PCG if solver in ("learned", PIC_SOLVER_LEARNED_PCG) \

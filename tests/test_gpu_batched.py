@@ -166,8 +166,8 @@ def test_batched_learned_solver_one_network_per_operator():
 def test_sweep_table_full_length():
     """The 48-run sweep at its full size and length (8-32 ppc/species, 500
     steps) in one context on the schedule the sweep benchmark uses (4 x 32
-    tiles, reordering every 8 steps, inboxes of half the tile slots, slack
-    0.5): no tile or inbox overflows, every run keeps its particles, the last
+    tiles, reordering every 8 steps, slack 0.5): no tile overflows, every
+    run keeps its particles, the last
     solve of every run meets the 1e-8 residual and the field energies stay
     finite."""
     import paper_1412_2480_amd as pic

@@ -112,7 +112,7 @@ def test_offset_rounding_up_keeps_cell_and_tile(precision):
     """An FP64 offset of 1 - 2^-26 rounds to 1 in FP32: it is clamped below 1,
     so the particle keeps its cell (the last cell of the last tile, whose
     neighbour across the periodic edge is tile 0). A step afterwards keeps
-    Gauss's law and raises no exchange overflow."""
+    Gauss's law and raises no tile overflow."""
     _say(f"offset clamp {precision}")
     import paper_1412_2480_amd as pic
     from synth import loads

@@ -195,11 +195,11 @@ def test_fullsize_shock_fp32_learned():
 def test_fullsize_tuned_schedule_full_length():
     """The benchmark workload for its full run length (2000 steps) in the
     timed configuration: 4 x 32 tiles, two work-groups per tile, half again
-    the mean tile occupancy as slots (the bunching after the numerical
-    Cherenkov instability saturates near step 300 overflows the default
-    quarter), reordering every 3 steps,
-    graph replay, the learned aid trained on the first 8 solves. No inbox or
-    tile overflows in 2000 steps, the last solve of every 249-step stretch meets
+    the mean tile occupancy as slots (the bunching of the later phase, where
+    the slow numerical instability of this set-up has grown, overflows the
+    default quarter), reordering every 3 steps,
+    graph replay, the learned aid trained on the first 8 solves. No tile
+    overflows in 2000 steps, the last solve of every 249-step stretch meets
     the plain-CG residual without the fallback, every particle is kept, Gauss's
     law holds at FP32 roundoff and the energies stay finite."""
     import paper_1412_2480_amd as pic

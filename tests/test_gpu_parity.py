@@ -190,7 +190,7 @@ def test_one_step_fp32_fast_form(order, gather):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_exchange_keeps_every_particle(precision):
     """Thirty steps of a gamma0 = 40 drift (about one cell per step in x): no
-    particle is lost or duplicated by the tile exchange, and positions follow
+    particle is lost or duplicated moving between tiles, and positions follow
     the oracle."""
     _say(f"exchange {precision}")
     case = Case(48, 40, 2, ppc=4, gamma0=40.0, T=0.05, seed=3, rtol=1e-10)

@@ -1,6 +1,6 @@
 """Host logic of the launch-schedule autotuner (paper_1412_2480_amd/tune.py):
-shapes whose LDS staging does not fit are skipped, shapes whose tile or inbox
-slots overflow while being timed are skipped, any other library error is
+shapes whose LDS staging does not fit are skipped, shapes whose tile slots
+overflow while being timed are skipped, any other library error is
 raised, every context is closed, and within the 2% tie the earlier candidate
 wins. A stand-in for the library context supplies the timings, so this runs
 without a GPU; the GPU test of the tuner times real steps."""
@@ -69,7 +69,7 @@ def fake(monkeypatch):
 def test_shape_search_skips_misfits_and_overflows_and_breaks_ties_early(fake):
     ms = {(4, 32): 2.00, (8, 32): 1.99, (16, 32): 1.0, (16, 16): 1.5, (8, 16): 2.5}
     fake.ms_of = lambda o: ms[(o.tile_x, o.tile_y)]
-    fake.fail = {(16, 16): -5}          # a tile or inbox overflows while timed
+    fake.fail = {(16, 16): -5}          # a tile's slots overflow while timed
     best, table = tune.autotune([None], lambda sim: None, {"precision": "fp32"},
                                 shapes=((4, 32), (8, 32), (16, 32), (16, 16), (8, 16)))
     assert [r["tile"] for r in table] == [(4, 32), (8, 32), (8, 16)]
