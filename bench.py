@@ -789,7 +789,7 @@ def main():
                          "size, for scaling HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: multi-GPU runs are not part of this build "
+        print("bench.py measures one GPU: the path has no multi-GPU form "
               f"(asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 

@@ -13,8 +13,9 @@ the cell size; 0.1 c/omega_pe is taken (that of the other workloads).
 
 Outputs (Figs. 7-8): transverse averages of the electron density and of B_z,
 normalised by the upstream density and by sqrt(4 pi n m Gamma c^2) (= Gamma
-in the units of this build), and the transverse mean of B_z^2 in the same
-normalisation (the magnetic energy density over the upstream kinetic one,
+in the code units, where c = 1, |q| = m and the flow's plasma frequency
+sqrt(4 pi n q^2 / (m Gamma)) is one), and the transverse mean of B_z^2 in
+the same normalisation (the magnetic energy density over the upstream kinetic one,
 within a factor 2 for the two species).
 """
 import argparse
