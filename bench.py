@@ -43,23 +43,23 @@ sys.path.insert(0, ROOT)
 BYTES_PER_PARTICLE = {"fp32": 2 * (4 + 5 * 4), "fp64": 2 * (4 + 5 * 8)}
 HBM_PEAK_GBS = 8000.0
 
-C5 = dict(nx=8192, ny=2048, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
-          label="periodic 8192x2048, pair gamma0=40, 64 ppc/species (2^31 particles), "
-                "order 3, CFL 1.0, theta 0.6")
+HEADLINE = dict(nx=8192, ny=2048, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
+                label="periodic 8192x2048, pair gamma0=40, 64 ppc/species (2^31 particles), "
+                      "order 3, CFL 1.0, theta 0.6")
 # schedule of the headline workload, measured on it (particle kernel, current
 # reduction and reordering per step at the cold start): 2x64 tiles, one
 # work-group per tile, reordering every 4 steps 65.3 ms; 2x64 with two
 # work-groups 70.6; 4x32 with two 80.6; 4x64 78.7; 2x128 96.0
-C5_TILE, C5_SPLIT, C5_SORT = (2, 64), 1, 4
+HEADLINE_TILE, HEADLINE_SPLIT, HEADLINE_SORT = (2, 64), 1, 4
 
 CONFIGS = {
     # name: nx, ny, ppc, gamma0, order, cfl, theta
-    "c2": dict(nx=1024, ny=256, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
-               label="periodic 1024x256, pair gamma0=40, 64 ppc/species, order 3, "
-                     "CFL 1.0, theta 0.6"),
-    "c1": dict(nx=64, ny=64, ppc=16, gamma0=20.0, order=1, cfl=1.0, theta=0.6,
-               label="periodic 64x64, pair gamma0=20, 16 ppc/species, order 1, "
-                     "CFL 1.0, theta 0.6"),
+    "1024x256": dict(nx=1024, ny=256, ppc=64, gamma0=40.0, order=3, cfl=1.0, theta=0.6,
+                     label="periodic 1024x256, pair gamma0=40, 64 ppc/species, order 3, "
+                           "CFL 1.0, theta 0.6"),
+    "64x64": dict(nx=64, ny=64, ppc=16, gamma0=20.0, order=1, cfl=1.0, theta=0.6,
+                  label="periodic 64x64, pair gamma0=20, 16 ppc/species, order 1, "
+                        "CFL 1.0, theta 0.6"),
 }
 
 
@@ -384,21 +384,21 @@ def net_rate(pic, torch, cfg, reps=10):
 
 
 def headline(pic, torch, steps, warmup, later_after=300, pairs=8, epochs=50):
-    """The headline workload (C5 dict): 2^31 particles loaded on the device,
+    """The headline workload (HEADLINE dict): 2^31 particles loaded on the device,
     FP32 particles with the learned aid. Returns the timed figures: wall
     clock over `steps` steps after `warmup` untimed ones, the particle
     kernel's average launch time from HIP events on the context stream over
     the same launches, the field solve, and (if later_after > 0) the
     same after that many further untimed steps."""
     from synth import loads
-    c = C5
+    c = HEADLINE
     nx, ny, ppc = c["nx"], c["ny"], c["ppc"]
     Q = loads.macro_charge(c["gamma0"], 0.1, 0.1, ppc)
     run = pic.run_desc(nx, ny, 0.1, c["cfl"], c["theta"], c["order"], [(-Q, Q, ppc), (Q, Q, ppc)],
                        cg_rtol=1e-8, cg_maxit=200)
-    sim = pic.Sim([run], pic.make_options("fp32", tile=C5_TILE, tile_split=C5_SPLIT,
+    sim = pic.Sim([run], pic.make_options("fp32", tile=HEADLINE_TILE, tile_split=HEADLINE_SPLIT,
                                           track_ids=False, solver="learned",
-                                          precond_slots=pairs, sort_every=C5_SORT, slack=SLACK))
+                                          precond_slots=pairs, sort_every=HEADLINE_SORT, slack=SLACK))
     t0 = time.perf_counter()
     for s in range(2):
         sim.load_plasma(0, s, ppc, c["gamma0"], 0.01, 0)
@@ -421,7 +421,7 @@ def headline(pic, torch, steps, warmup, later_after=300, pairs=8, epochs=50):
     train_s = time.perf_counter() - t0
     sim.precond_use(True)
     t0 = time.perf_counter()
-    retune = sim.tune(1, splits=(C5_SPLIT,))
+    retune = sim.tune(1, splits=(HEADLINE_SPLIT,))
     tune_s = time.perf_counter() - t0
 
     def timed(k):
@@ -456,7 +456,7 @@ def headline(pic, torch, steps, warmup, later_after=300, pairs=8, epochs=50):
     d = sim.diag(0)
     out = dict(workload=c["label"] + " (FP32 particles, learned aid)", particles=n,
                workspace_gb=sim.info.workspace_bytes / 1e9, load_seconds=load_s,
-               tile=list(C5_TILE), tile_split=C5_SPLIT, sort_every=C5_SORT,
+               tile=list(HEADLINE_TILE), tile_split=HEADLINE_SPLIT, sort_every=HEADLINE_SORT,
                cg_blocks=retune["cg_blocks"], timed=main_t, later=sat,
                training=dict(pairs=pairs, epochs=epochs, seconds=train_s, tune_seconds=tune_s,
                              loss_first=tr["loss_first"], loss_last=tr["loss_last"]),
@@ -599,13 +599,13 @@ def cpu_baseline(cfg, seconds=10.0, rows=4):
                 nproc=nproc, cpu_model=_cpu_model())
 
 
-def c2_legs(pic, torch, args, learned):
+def single_run_legs(pic, torch, args, learned):
     """The 1024 x 256 single run: FP32 + learned, FP32 with plain CG and the
     plain FP64 form, each on its own tuned schedule; returns the three
     timings, the tuning tables and the FP32/FP64 factor."""
     from synth import loads
     global SORT
-    cfg = CONFIGS["c2"]
+    cfg = CONFIGS["1024x256"]
     log(f"bench: generating load {cfg['label']}")
     load = loads.pair_plasma_cells(cfg["nx"], cfg["ny"], cfg["ppc"], cfg["gamma0"], 0.01, seed=0)
     tile = (4, 32)
@@ -635,21 +635,21 @@ def c2_legs(pic, torch, args, learned):
                     table=[{k: r[k] for k in ("tile", "tile_split", "cg_blocks", "ms_per_step")}
                            for r in table], sort_table=sort_table,
                     seconds=time.perf_counter() - t0)
-        log(f"bench: c2 autotune: tile {tile} split {split} cg_blocks {cgb} sort_every {SORT}")
+        log(f"bench: 1024x256 autotune: tile {tile} split {split} cg_blocks {cgb} sort_every {SORT}")
     else:
         SORT = 4
     fast = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split,
                      learned, retune=not args.no_autotune)
-    log(f"bench: c2 FP32 + learned {fast['ms_per_step']:.3f} ms/step, push {fast['push_ms']:.3f}, "
+    log(f"bench: 1024x256 FP32 + learned {fast['ms_per_step']:.3f} ms/step, push {fast['push_ms']:.3f}, "
         f"field solve {fast['field_solve_ms']:.3f} ms, iters {fast['cg_iters']}")
     fast_cg = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split)
-    log(f"bench: c2 FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
+    log(f"bench: 1024x256 FP32 plain CG {fast_cg['ms_per_step']:.3f} ms/step, field solve "
         f"{fast_cg['field_solve_ms']:.3f} ms, iters {fast_cg['cg_iters']}")
     mfma = None
     if not args.no_mfma and learned is not None:
         mfma = time_form(pic, torch, cfg, load, "fp32", tile, args.steps, args.warmup, cgb, split,
                          dict(learned, form="mfma"))
-        log(f"bench: c2 FP32 + learned (mfma) {mfma['ms_per_step']:.3f} ms/step, field solve "
+        log(f"bench: 1024x256 FP32 + learned (mfma) {mfma['ms_per_step']:.3f} ms/step, field solve "
             f"{mfma['field_solve_ms']:.3f} ms")
     plain = None
     if not args.no_fp64:
@@ -669,7 +669,7 @@ def c2_legs(pic, torch, args, learned):
             tune["fp64_schedule"] = dict(t64, tile=list(t64["tile"]))
         plain = time_form(pic, torch, cfg, load, "fp64", t64["tile"], args.steps, args.warmup,
                           t64["cg_blocks"], t64["tile_split"], sort_every=t64["sort_every"])
-        log(f"bench: c2 FP64 {plain['ms_per_step']:.3f} ms/step, field solve "
+        log(f"bench: 1024x256 FP64 {plain['ms_per_step']:.3f} ms/step, field solve "
             f"{plain['field_solve_ms']:.3f} ms")
     del load
 
@@ -695,7 +695,7 @@ def explicit_vs_implicit(pic, torch, steps=20, warmup=5):
     """The explicit Yee FDTD variant (Eqs. (3)-(4)) at its stable CFL 0.5
     against the implicit scheme at CFL 1.0 on the 1024 x 256 workload (FP32
     particles): time per step and per unit of simulated time."""
-    cfg = CONFIGS["c2"]
+    cfg = CONFIGS["1024x256"]
     from synth import loads
     out = {}
     for scheme, cfl in (("explicit", 0.5), ("implicit", 1.0)):
@@ -765,7 +765,7 @@ def main():
                          "the state a long run spends most steps in")
     ap.add_argument("--headline-only", action="store_true",
                     help="only the headline workload (for profiling runs)")
-    ap.add_argument("--no-c2", action="store_true", help="skip the 1024x256 legs")
+    ap.add_argument("--no-1024", action="store_true", help="skip the 1024x256 legs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 form")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -813,7 +813,7 @@ def main():
 
     learned = dict(form=args.learned_form, pairs=args.train_pairs, epochs=args.train_epochs,
                    lr=1e-3)
-    log(f"bench: headline {C5['label']}")
+    log(f"bench: headline {HEADLINE['label']}")
     h = headline(pic, torch, args.steps, args.warmup,
                  0 if args.headline_only else args.later_after, args.train_pairs,
                  args.train_epochs)
@@ -830,8 +830,8 @@ def main():
 
     legs = {}
     if not args.headline_only:
-        if not args.no_c2:
-            legs["c2"] = run_leg("1024x256 legs", lambda: c2_legs(pic, torch, args, learned))
+        if not args.no_1024:
+            legs["single_run_1024x256"] = run_leg("1024x256 legs", lambda: single_run_legs(pic, torch, args, learned))
         if not args.no_explicit:
             legs["explicit_vs_implicit"] = run_leg("explicit scheme",
                                                    lambda: explicit_vs_implicit(pic, torch))
@@ -841,19 +841,19 @@ def main():
         if not args.no_shock:
             legs["shock"] = run_leg("shock workload",
                                     lambda: shock_share(pic, torch, (4, 32), 2))
-        legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch, C5))
+        legs["learned_net"] = run_leg("network rate", lambda: net_rate(pic, torch, HEADLINE))
         if not args.no_nci:
             legs["nci_scans"] = run_leg("NCI scans", lambda: nci_scans(pic, torch))
     cpu = None
     if not args.no_cpu and not args.headline_only:
         log("bench: oracle CPU baseline")
-        cpu = run_leg("CPU baseline", lambda: cpu_baseline(C5, args.cpu_seconds))
+        cpu = run_leg("CPU baseline", lambda: cpu_baseline(HEADLINE, args.cpu_seconds))
 
     n_part = h["particles"]
     alg = BYTES_PER_PARTICLE["fp32"] * n_part
     achieved = alg / (t["push_ms"] * 1e-3) / 1e9
-    rec, traffic_src = measured_traffic("fp32", C5_TILE, C5_SPLIT, C5["order"], n_part,
-                                        C5_SORT, args.warmup)
+    rec, traffic_src = measured_traffic("fp32", HEADLINE_TILE, HEADLINE_SPLIT, HEADLINE["order"], n_part,
+                                        HEADLINE_SORT, args.warmup)
     traffic = None if rec is None else rec["traffic_bytes"]
     line = {
         "metric": "particle-steps/s + field-solve ms/step; FP32+learned vs plain FP64, same GPU",
@@ -871,8 +871,8 @@ def main():
                         "accumulation, fields, CG and diagnostics; learned aid ("
                         + args.learned_form + ")",
         "data": "synthetic (seeded Maxwell-Juettner pair plasma, loaded on the device)",
-        "config": {"workload": C5["label"], "particles": n_part, "cells": C5["nx"] * C5["ny"],
-                   "tile": list(C5_TILE), "tile_split": C5_SPLIT, "sort_every": C5_SORT,
+        "config": {"workload": HEADLINE["label"], "particles": n_part, "cells": HEADLINE["nx"] * HEADLINE["ny"],
+                   "tile": list(HEADLINE_TILE), "tile_split": HEADLINE_SPLIT, "sort_every": HEADLINE_SORT,
                    "cg_rtol": 1e-8},
         "field_solve_ms_per_step": t["field_solve_ms"],
         "cg_iters_last_step": t["cg_iters"],

@@ -94,7 +94,7 @@ def test_headline_record_is_current_and_gives_ceilings():
         pytest.skip("the particle kernel changed since its counters were taken")
     cfg = rec["config"]
     assert (tuple(cfg["tile"]), cfg["tile_split"], cfg["sort_every"]) == \
-        (bench.C5_TILE, bench.C5_SPLIT, bench.C5_SORT)
+        (bench.HEADLINE_TILE, bench.HEADLINE_SPLIT, bench.HEADLINE_SORT)
     c = bench.ceilings(rec, cfg["particles"], 60.0)
     waves = cfg["particles"] / 64
     valu_ms = waves * rec["valu_instructions_per_wavefront_of_64_particles"] * 4 / (1024 * 2.4e9)

@@ -62,7 +62,7 @@ def test_explicit_split_step_parity_fp64(order, grid, cfl):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_explicit_run_history_and_gauss(precision):
-    """C1-like drifting pair plasma (64 x 64, order 1, gamma0 = 20) with the
+    """A drifting pair plasma (64 x 64, order 1, gamma0 = 20) with the
     explicit scheme at sigma = 0.5, 30 steps: the energy history against the
     oracle's explicit run, and Gauss's law kept at its initial value."""
     _say(f"explicit run {precision}")

@@ -104,10 +104,10 @@ def test_fused_step_equals_split(order):
     b.close()
 
 
-def test_multistep_c1_fp64_energy_history():
-    """C1 configuration (64x64, 16 ppc/species, gamma0 = 20, T = 0.01, order 1,
+def test_multistep_64x64_fp64_energy_history():
+    """The 64x64 configuration (16 ppc/species, gamma0 = 20, T = 0.01, order 1,
     sigma = 1, theta = 0.6) for 12 steps: per-step energies and final fields."""
-    _say("multistep C1 fp64")
+    _say("multistep 64x64 fp64")
     case = Case(64, 64, 1, ppc=16, gamma0=20.0, T=0.01, seed=0, rtol=1e-8)
     sim = case.gpu_sim("fp64", diag_every=1, history_cap=64)
     ref = case.oracle_sim()
@@ -296,7 +296,7 @@ def test_capacity_and_state_errors():
     sim.close()
 
 
-def test_c1_full_run_fp64():
+def test_64x64_full_run_fp64():
     """The plain-method configuration at full length: 64x64, 16 ppc/species,
     gamma0 = 20, T = 0.01, order 1, sigma = 1, theta = 0.6, 200 steps, seed 0,
     FP64 on both sides. The two CG implementations stop at 1e-8 with different
@@ -306,7 +306,7 @@ def test_c1_full_run_fp64():
     energy to the instability and the theta-damping (about 8% here), unlike the
     thermal plasma of Sec. 3 whose 1% bound the oracle tests pin; the drift is
     reported, and equal on both sides by the energy parity."""
-    _say("C1 full run, 200 steps fp64")
+    _say("64x64 full run, 200 steps fp64")
     case = Case(64, 64, 1, ppc=16, gamma0=20.0, T=0.01, seed=0, rtol=1e-8)
     sim = case.gpu_sim("fp64", diag_every=1, history_cap=256)
     ref = case.oracle_sim()
@@ -324,7 +324,7 @@ def test_c1_full_run_fp64():
     ek = np.abs(wk - wk_ref).max() / np.abs(wk_ref).max()
     tot = wf + 0.5 * np.array([h["W_K_minus"] + h["W_K_plus"] for h in hist])
     drift = np.abs(tot - tot[0]).max() / tot[0]
-    _say(f"C1 200 steps: field-energy e max {e.max():.3e}, kinetic {ek:.3e}, "
+    _say(f"64x64 200 steps: field-energy e max {e.max():.3e}, kinetic {ek:.3e}, "
          f"total-energy drift {drift:.3e}")
     assert e.max() <= 1e-10
     assert ek <= 1e-10

@@ -45,7 +45,7 @@ def test_thermal_plasma_energy_within_one_percent(ora):
 
 
 def test_drifting_pair_energy_and_cg(ora):
-    """A short C1-like run (gamma0 = 20, order 1, sigma = 1, theta = 0.6) keeps
+    """A short run like the 64x64 one (gamma0 = 20, order 1, sigma = 1, theta = 0.6) keeps
     total energy within 1 % and the CG meets 1e-8 in at most 17 iterations
     (kappa <= 1 + 8 (theta sigma)^2 bounds CG at 1e-8)."""
     sim = _pair_sim(ora, 16, 16, 4, 20.0, 0.01, 1, 1.0, 0.6, seed=0)
