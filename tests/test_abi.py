@@ -113,3 +113,18 @@ def test_library_binds_to_torchs_hip_runtime():
                          cwd=root, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1", out.stdout
+
+
+def test_plan_gather_option():
+    """Both gathers plan the same workspace; any other value is rejected
+    through the C-ABI (the binding's own check is bypassed here)."""
+    a = pic.plan([_run()], pic.make_options("fp32", gather="nodal"))
+    b = pic.plan([_run()], pic.make_options("fp32", gather="staggered"))
+    assert a.workspace_bytes == b.workspace_bytes
+    o = pic.make_options("fp32")
+    o.gather = 7
+    with pytest.raises(pic.PicError) as ei:
+        pic.plan([_run()], o)
+    assert ei.value.code == -1
+    with pytest.raises(ValueError):
+        pic.make_options("fp32", gather="cell")
