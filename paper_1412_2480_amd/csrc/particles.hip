@@ -132,6 +132,23 @@ __device__ __forceinline__ R place(const R (&w)[P + 1], int off, int a) {
   return off == 0 ? v0 : v1;
 }
 
+// The FP64 values of a shape's weights, the last taken as one minus the
+// others so that the shape sums to exactly one. The charge density and the
+// current are both formed from these: a shape whose weights summed to one
+// only to rounding (the FP32 form's, to about 6e-8) would change the
+// particle's charge from step to step, and the window's last node, where
+// the running sum of the shape change ends, would not receive it.
+template <int P, typename R>
+__device__ __forceinline__ void unit_weights(const R (&w)[P + 1], double (&d)[P + 1]) {
+  double sum = 0.0;
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
+    d[a] = (double)w[a];
+    sum += d[a];
+  }
+  d[P] = 1.0 - sum;
+}
+
 // reserve slots in counters[key] for every lane with want set, one atomic per
 // wavefront and distinct key; returns the lane's slot (or -1)
 __device__ __forceinline__ int wave_reserve(bool want, int key, int* counters) {
@@ -177,9 +194,12 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
     const int n = (int)(((long long)n_all * (part + 1)) / st.K);
     const long long base = (long long)tile * st.tile_slots[s];
     const R qdt_2m = R(run.q[s] * run.dt / (2.0 * run.m[s]));
-    const R cjx = R(-run.q[s] / (run.dy * run.dt));
-    const R cjy = R(-run.q[s] / (run.dx * run.dt));
-    const R cjz = R(run.q[s] / (run.dx * run.dy));
+    // current factors in FP64 in both forms: rounded to FP32 they would
+    // scale each species' current by its own rounding error, which Gauss's
+    // law would see at 1e-6 of the charge density per step
+    const double cjx = -run.q[s] / (run.dy * run.dt);
+    const double cjy = -run.q[s] / (run.dx * run.dt);
+    const double cjz = run.q[s] / (run.dx * run.dy);
     const double mass = run.m[s];
     for (int k0 = lo; k0 < n; k0 += blockDim.x) {
       const int k = k0 + threadIdx.x;
@@ -225,13 +245,17 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
         const int f0y = bspline_weights<P, R>(fy, w0y);
 
         if constexpr (MODE == MODE_CHARGE) {
-          const R cq = R((sel >= 0 ? 1.0 : run.q[s]) / (run.dx * run.dy));
+          // from the same unit-sum FP64 weights as the deposit
+          const double cq = (sel >= 0 ? 1.0 : run.q[s]) / (run.dx * run.dy);
           const int ax0 = lx + f0x + G, ay0 = ly + f0y + G;
+          double ux_[P + 1], uy_[P + 1];
+          unit_weights<P, R>(w0x, ux_);
+          unit_weights<P, R>(w0y, uy_);
 #pragma unroll
           for (int b = 0; b <= P; ++b)
 #pragma unroll
             for (int a = 0; a <= P; ++a)
-              atomicAdd(&sJ[(ay0 + b) * PW + ax0 + a], (double)(cq * w0x[a] * w0y[b]));
+              atomicAdd(&sJ[(ay0 + b) * PW + ax0 + a], cq * (ux_[a] * uy_[b]));
         }
 
         if constexpr (MODE == MODE_FUSED || MODE == MODE_PUSH) {
@@ -319,14 +343,11 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           const int n1x = dcx + f1x, n1y = dcy + f1y;
           const int Ax = f0x < n1x ? f0x : n1x, Ay = f0y < n1y ? f0y : n1y;
           const int o0x = f0x - Ax, o1x = n1x - Ax, o0y = f0y - Ay, o1y = n1y - Ay;
-          R S0x[W], DSx[W], S0y[W], DSy[W];
-#pragma unroll
-          for (int a = 0; a < W; ++a) {
-            S0x[a] = place<P, R>(w0x, o0x, a);
-            DSx[a] = place<P, R>(w1x, o1x, a) - S0x[a];
-            S0y[a] = place<P, R>(w0y, o0y, a);
-            DSy[a] = place<P, R>(w1y, o1y, a) - S0y[a];
-          }
+          double u0x[P + 1], u1x[P + 1], u0y[P + 1], u1y[P + 1];
+          unit_weights<P, R>(w0x, u0x);
+          unit_weights<P, R>(w1x, u1x);
+          unit_weights<P, R>(w0y, u0y);
+          unit_weights<P, R>(w1y, u1y);
           const int ax0 = lx + Ax + G, ay0 = ly + Ay + G;
           R vz;
           if constexpr (std::is_same<R, float>::value)
@@ -343,16 +364,20 @@ __device__ void tile_body(const DevState<R>& st, const DevRun& run, int tile, in
           // order-3 push from 1.3 ms to 10.3 ms, while ds_add_f64 runs near
           // the LDS bandwidth. Jx(i+1/2) is the running sum of Wx along x (the
           // last node's sum is zero); the constant factors of Jx, Jy, Jz are
-          // folded into the per-row and per-column weights.
+          // folded into the per-row and per-column weights. The shapes are
+          // the unit-sum FP64 weights the charge density uses (the next
+          // step's old shape is this step's new one bit for bit), so the
+          // current carries exactly the change of that density and Gauss's
+          // law holds to FP64 rounding in the FP32 form too.
           double s0x[W], dsx[W], s0y[W], dsy[W];
 #pragma unroll
           for (int a = 0; a < W; ++a) {
-            s0x[a] = (double)S0x[a];
-            dsx[a] = (double)DSx[a];
-            s0y[a] = (double)S0y[a];
-            dsy[a] = (double)DSy[a];
+            s0x[a] = place<P, double>(u0x, o0x, a);
+            dsx[a] = place<P, double>(u1x, o1x, a) - s0x[a];
+            s0y[a] = place<P, double>(u0y, o0y, a);
+            dsy[a] = place<P, double>(u1y, o1y, a) - s0y[a];
           }
-          const double cx = (double)cjx, cy = (double)cjy, cz = (double)cjz * (double)vz;
+          const double cx = cjx, cy = cjy, cz = cjz * (double)vz;
           // The window's last row (column) holds weights only for a lane
           // whose support moved along y (x) this step; when no lane of the
           // wavefront did, its Jx and Jz row (Jy and Jz column) is exactly

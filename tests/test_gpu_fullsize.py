@@ -201,7 +201,7 @@ def test_fullsize_tuned_schedule_full_length():
     graph replay, the learned aid trained on the first 8 solves. No tile
     overflows in 2000 steps, the last solve of every 249-step stretch meets
     the plain-CG residual without the fallback, every particle is kept, Gauss's
-    law holds at FP32 roundoff and the energies stay finite."""
+    law holds at FP64 roundoff and the energies stay finite."""
     import paper_1412_2480_amd as pic
     from synth import loads
     Q = loads.macro_charge(G0, DX, DX, PPC)
@@ -229,7 +229,8 @@ def test_fullsize_tuned_schedule_full_length():
     rho_scale = 4 * np.pi * Q / (DX * DX)
     _say(f"  gauss {d['gauss_max']:.2e} (scale {rho_scale:.2e}), particles {d['n_particles']}")
     assert d["n_particles"][:2] == [NX * NY * PPC] * 2
-    assert d["gauss_max"] <= 1e-4 * rho_scale
+    # charge and current from the same unit-sum FP64 weights: FP64 roundoff
+    assert d["gauss_max"] <= 1e-9 * rho_scale
     h = sim.history(0)
     assert len(h) >= 8
     for r in h:
